@@ -1,0 +1,143 @@
+/*
+ * refeig.h - C ABI of the MI355X (gfx950) eigenvector-refinement library.
+ *
+ * The library refines approximate eigenvectors X^ and eigenvalues D^ of a real
+ * symmetric matrix A (A X = X D, X^T X = I; Terao & Ozaki, arXiv 2602.19090,
+ * Sec. 1) until the forward error ||X - X^|| reaches a prescribed delta > u
+ * (Sec. 3.1). Each iteration is the Ogita-Aishima step of Algorithm 1
+ * (Sec. 2.4) with the paper's cost cut (Sec. 3): X^ is replaced by its first
+ * slice X^(1), whose grid is fixed by beta (the implementation rule of
+ * Sec. 4.1), and every O(n^3) product runs through the Ozaki scheme
+ * (Sec. 2.3) re-expressed for INT8 matrix cores: exponent-aligned 7-bit digit
+ * planes, exact INT32 slice products, FP64 double-word slice sums.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column-major (LAPACK): element (i, j) at i + j*ld, so
+ *    eigenvector j is the contiguous column j. ld >= n.
+ *  - "device" pointers are HIP device memory owned by the caller; the library
+ *    never frees them. "host" pointers are ordinary host memory.
+ *  - Work is enqueued on the given stream; entry points that return results
+ *    in host memory synchronise that stream before returning.
+ *  - Return values are refeig_status codes; no C++ exception crosses the ABI.
+ *  - Calls that overlap on the same stream are serialised by the stream;
+ *    calls on different streams must use different workspaces.
+ */
+#ifndef REFEIG_H
+#define REFEIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *refeig_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+    REFEIG_OK = 0,
+    REFEIG_NOT_CONVERGED = 1, /* X, D hold the last iterate; the report says why        */
+    REFEIG_E_ARG = -1,        /* bad size, pointer, leading dimension or option          */
+    REFEIG_E_NONFINITE = -2,  /* NaN or Inf in A, X or D                                 */
+    REFEIG_E_GAP = -3,        /* two eigenvalue estimates coincide (min gap 0): the
+                                 paper assumes distinct, unclustered eigenvalues (Sec. 3.2) */
+    REFEIG_E_RANGE = -4,      /* a row/column maximum outside [2^-400, 2^400]            */
+    REFEIG_E_NOMEM = -5,      /* workspace too small or device allocation failed         */
+    REFEIG_E_HIP = -6         /* a HIP runtime call failed                                */
+} refeig_status;
+
+typedef enum {
+    REFEIG_OZAKI_INT8 = 0,  /* INT8 digit planes on MFMA (the hot path)                 */
+    REFEIG_FP64_PLAIN = 2   /* the same iteration with FP64 slice products on DGEMM     */
+} refeig_mode;
+
+#define REFEIG_MAX_ITERS 32
+
+typedef struct {
+    int mode;            /* refeig_mode                                                  */
+    int max_iter;        /* iteration limit (default 8)                                  */
+    int fixed_iters;     /* > 0: run exactly this many iterations, no stop test          */
+    int stop_rule;       /* stop after an iteration whose correction eps = max|E~|
+                            satisfies eps^2 max|lambda| / (xi gap) <= target/delta_safety,
+                            the post-update error that eq. (assume2) of Sec. 3.2
+                            predicts, or eps <= target/delta_safety.
+                            0: xi as below (default); 1: strict, xi = 1              */
+    double delta_safety; /* internal delta = target / delta_safety (default 8)          */
+    double xi;           /* xi of eq. (assume2); <= 0 means n, the Sec. 4.1 choice        */
+    double theta;        /* share of the internal delta given to each product's
+                            truncation (default 0.25)                                    */
+    int ka_max;          /* maximum digit planes of A (default 18)                       */
+    int d_extra;         /* extra pair diagonals added to every product (default 0)      */
+    int verbose;         /* print per-iteration parameters to stderr                     */
+    int reserved_i[6];
+    double reserved_d[4];
+} refeig_opts;
+
+typedef struct {
+    int status;                      /* final refeig_status                             */
+    int iters;                       /* iterations performed                            */
+    int beta[REFEIG_MAX_ITERS];      /* beta of Sec. 4.1 per iteration                  */
+    int kx[REFEIG_MAX_ITERS];        /* digit planes of X^(1)                           */
+    int dv[REFEIG_MAX_ITERS];        /* last pair diagonal kept in V = A X^(1)          */
+    int dw[REFEIG_MAX_ITERS];        /* ... in W = X^(1)T (V - X^(1) D^)                */
+    int du[REFEIG_MAX_ITERS];        /* ... in X^(1) E~                                 */
+    int pairs[REFEIG_MAX_ITERS];     /* INT8 slice products (n x n x n) per iteration   */
+    double eps[REFEIG_MAX_ITERS];    /* max |E~| per iteration                          */
+    double ms_iter[REFEIG_MAX_ITERS];/* wall time per iteration (HIP events)            */
+    double ms_gemm[REFEIG_MAX_ITERS];/* time in slice products per iteration            */
+    double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
+    double max_abs_lambda;           /* max |lambda| (last)                             */
+    double ms_total;
+} refeig_report;
+
+/* Defaults as documented in refeig_opts. Returns REFEIG_OK or REFEIG_E_ARG (o NULL). */
+int refeig_default_opts(refeig_opts *o);
+
+/* Device workspace needed by refine_eigvecs for order n (host out-pointer).
+ * Returns REFEIG_E_ARG for n < 1 or n above the supported maximum (8192). */
+int refeig_workspace_bytes(int n, const refeig_opts *o, size_t *bytes);
+
+/* Refine X (n x n, device, column-major, ld ldx) and D (n, device) in place
+ * for the symmetric A (device, ld lda; must be exactly symmetric, read only)
+ * until max-abs forward error ~ target_fwd_err (Sec. 3.1; the paper's delta).
+ * D on entry holds the eigenvalue estimates of X's columns (they set beta of
+ * the first iteration); on return the Rayleigh quotients of the last X^(1).
+ * work: device buffer of work_bytes >= refeig_workspace_bytes, or NULL to let
+ * the library allocate (and free) it. report (host, may be NULL).
+ * On REFEIG_OK / REFEIG_NOT_CONVERGED, X and D hold the last iterate. On a
+ * negative status they hold the last completed iterate (unchanged if none). */
+int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int n,
+                   double target_fwd_err, const refeig_opts *o, void *work, size_t work_bytes,
+                   refeig_stream_t stream, refeig_report *report);
+
+const char *refeig_strerror(int status);
+
+/* ---- entry points for bit-exact checks of the kernels -------------------- */
+
+/* Column exponents and 7-bit digit planes of M (rows x cols, device, ld).
+ * exps (device, cols ints): e_j with max_i |M_ij| < 2^e_j <= 2 max_i |M_ij|,
+ * 0 for a zero column. planes (device, k * cols_pad * rows_pad bytes, where
+ * rows_pad and cols_pad are rows and cols rounded up to 256): digit r (1..k)
+ * of M_ij, sign(M_ij) * (floor(|M_ij| 2^(7r - e_j)) mod 128), at
+ * planes[(r-1) * cols_pad * rows_pad + j * rows_pad + i]; zero for i >= rows
+ * or j >= cols. Errors: REFEIG_E_ARG (sizes, k outside 1..18),
+ * REFEIG_E_NONFINITE (NaN/Inf in M), REFEIG_E_RANGE (e_j outside [-400, 400]).
+ * trunc (device, may be NULL, ld rows): the value of the k digits.
+ * This is the integer form of the error-free splitting of Sec. 2.3 (eq. a/x). */
+int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *exps,
+                      int8_t *planes, double *trunc, refeig_stream_t stream);
+
+/* Exact per-diagonal slice products: for q = 0..ndiag-1 and d = d_min + q,
+ *   C[q][m][p] = sum_{s + t = d, 1<=s<=kl, 1<=t<=kr} sum_k L_s[m][k] * R_t[p][k]
+ * with L_s at Lp + (s-1)*plane_stride + m*npad + k, R_t likewise, and
+ * C[q][m][p] at C + q*npad*npad + m*npad + p (int32, device). npad must be a
+ * multiple of 256 and the planes zero-padded. The pairs of one diagonal must
+ * satisfy pairs * npad * 127^2 < 2^31 (exact INT32 accumulation).  */
+int refeig_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, int npad, int kl,
+                      int kr, int d_min, int ndiag, int32_t *C, refeig_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,155 @@
+"""ctypes binding of librefeig.so (the C ABI declared in include/refeig.h).
+
+Argument marshalling only: every step of the refinement runs in the HIP
+library. torch supplies device memory and the current HIP stream. Matrices
+cross the ABI in column-major order; a column-major n x n matrix is held here
+as a C-contiguous torch tensor T of shape (n, n) with T[j, i] = X[i, j] (row j
+of T is eigenvector j). ``colmajor`` / ``from_colmajor`` convert numpy arrays.
+
+Importing this module raises if the library has not been built: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# One HIP runtime per process: torch ships its own libamdhip64 (soname
+# libamdhip64.so.7). Loading torch first makes the dynamic loader bind
+# librefeig's libamdhip64.so.7 dependency to that copy instead of mapping a
+# second runtime, which would not see the device.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librefeig.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+REFEIG_OK, REFEIG_NOT_CONVERGED = 0, 1
+REFEIG_E_ARG, REFEIG_E_NONFINITE, REFEIG_E_GAP = -1, -2, -3
+REFEIG_E_RANGE, REFEIG_E_NOMEM, REFEIG_E_HIP = -4, -5, -6
+REFEIG_OZAKI_INT8, REFEIG_FP64_PLAIN = 0, 2
+MAX_ITERS = 32
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("stop_rule", ctypes.c_int), ("delta_safety", ctypes.c_double),
+                ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
+                ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("reserved_i", ctypes.c_int * 6), ("reserved_d", ctypes.c_double * 4)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("beta", ctypes.c_int * MAX_ITERS), ("kx", ctypes.c_int * MAX_ITERS),
+                ("dv", ctypes.c_int * MAX_ITERS), ("dw", ctypes.c_int * MAX_ITERS),
+                ("du", ctypes.c_int * MAX_ITERS), ("pairs", ctypes.c_int * MAX_ITERS),
+                ("eps", ctypes.c_double * MAX_ITERS), ("ms_iter", ctypes.c_double * MAX_ITERS),
+                ("ms_gemm", ctypes.c_double * MAX_ITERS), ("min_gap", ctypes.c_double),
+                ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        k = self.iters
+        return {"status": self.status, "iters": k, "beta": list(self.beta[:k]),
+                "kx": list(self.kx[:k]), "dv": list(self.dv[:k]), "dw": list(self.dw[:k]),
+                "du": list(self.du[:k]), "pairs": list(self.pairs[:k]), "eps": list(self.eps[:k]),
+                "ms_iter": list(self.ms_iter[:k]), "ms_gemm": list(self.ms_gemm[:k]),
+                "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
+                "ms_total": self.ms_total}
+
+
+_vp, _int, _dbl, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_lib.refeig_default_opts.argtypes = [ctypes.POINTER(Opts)]
+_lib.refeig_workspace_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_lib.refine_eigvecs.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctypes.POINTER(Opts), _vp,
+                                _sz, _vp, ctypes.POINTER(Report)]
+_lib.refeig_strerror.restype = ctypes.c_char_p
+_lib.refeig_strerror.argtypes = [_int]
+_lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp]
+_lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
+
+EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
+            "refeig_split_cols", "refeig_slice_gemm"]
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _lib.refeig_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def strerror(status: int) -> str:
+    return _lib.refeig_strerror(status).decode()
+
+
+def workspace_bytes(n: int, opts: Opts | None = None) -> int:
+    b = _sz()
+    st = _lib.refeig_workspace_bytes(n, ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(b))
+    if st != 0:
+        raise ValueError(f"refeig_workspace_bytes({n}): {strerror(st)}")
+    return b.value
+
+
+def colmajor(M: np.ndarray, device="cuda"):
+    """numpy (n, m) matrix -> C-contiguous torch tensor holding it column-major."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(M, dtype=np.float64).T)).to(device)
+
+
+def from_colmajor(T) -> np.ndarray:
+    return np.asfortranarray(T.detach().cpu().numpy().T)
+
+
+def refine_eigvecs(A, X, D, target: float, opts: Opts | None = None, work=None, stream=None):
+    """Refine X (column-major tensor, see module doc) and D in place. Returns (status, report)."""
+    n = D.numel()
+    assert A.dtype == X.dtype == D.dtype and A.is_cuda and X.is_cuda and D.is_cuda
+    assert A.is_contiguous() and X.is_contiguous() and D.is_contiguous()
+    assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+    rep = Report()
+    wb = work.numel() * work.element_size() if work is not None else 0
+    st = _lib.refine_eigvecs(_ptr(A), n, _ptr(X), n, _ptr(D), n, float(target),
+                             ctypes.byref(opts) if opts is not None else None, _ptr(work), wb,
+                             _stream(stream), ctypes.byref(rep))
+    return st, rep
+
+
+def split_cols(M, rows: int, cols: int, k: int, want_trunc=True, stream=None):
+    """Debug entry point refeig_split_cols on a column-major tensor M (cols, rows)."""
+    import torch
+    rpad, cpad = -(-rows // 256) * 256, -(-cols // 256) * 256
+    exps = torch.empty(cols, dtype=torch.int32, device=M.device)
+    planes = torch.empty((k, cpad, rpad), dtype=torch.int8, device=M.device)
+    trunc = torch.empty((cols, rows), dtype=torch.float64, device=M.device) if want_trunc else None
+    st = _lib.refeig_split_cols(_ptr(M), rows, rows, cols, k, _ptr(exps), _ptr(planes), _ptr(trunc),
+                                _stream(stream))
+    return st, exps, planes, trunc
+
+
+def slice_gemm(Lp, Rp, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stream=None):
+    """Debug entry point refeig_slice_gemm. Lp: (kl, npad, npad) int8, Rp: (kr, npad, npad)."""
+    import torch
+    assert Lp.stride(0) == Rp.stride(0) == npad * npad
+    C = torch.empty((ndiag, npad, npad), dtype=torch.int32, device=Lp.device)
+    st = _lib.refeig_slice_gemm(_ptr(Lp), _ptr(Rp), npad * npad, npad, kl, kr, d_min, ndiag,
+                                _ptr(C), _stream(stream))
+    return st, C

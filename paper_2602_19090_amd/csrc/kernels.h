@@ -1,0 +1,59 @@
+// Internal interface between the host orchestrator and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace refeig {
+
+constexpr int kTile = 256;     // padding granule of every n x n operand
+constexpr int kMaxDiag = 32;   // pair diagonals per product
+constexpr int kEpiThreads = 1024;
+
+// Flags raised by kernels (bitwise OR into a device int).
+enum : int { FLAG_NONFINITE = 1, FLAG_TIE = 2, FLAG_RANGE = 4 };
+
+struct DiagOrder {
+  int q[kMaxDiag];  // launch position -> diagonal slot
+};
+
+// Column statistics of M (rows x cols, column-major, ld):
+//   e[j] = floor(log2 max_i |M_ij|) + 1 (0 for a zero column),
+//   c[j] = ceil(log2 max_i |M_ij|)      (0 for a zero column),
+//   mx[j] = max_i |M_ij|.  Columns cols..cols_pad-1 get zeros.
+void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
+                     double *mx, int *flags, hipStream_t s);
+
+// 7-bit digit planes of M with column exponents e (see refeig_split_cols).
+//  planes: k planes, plane stride pstride, element (i, j) at j*rpad + i.
+//  trunc (optional, ld ldt): value of the k digits.
+//  planesT (optional): kT planes of the transposed layout, element (i, j) at i*cpad + j.
+// The grid covers the padded rpad x cpad area and writes zero digits outside.
+void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
+                       int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
+                       int8_t *planesT, size_t pstrideT, int kT, hipStream_t s);
+
+// Per-diagonal INT8 slice products (see refeig_slice_gemm).
+void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
+                       int kr, int d_min, int ndiag, int32_t *C, hipStream_t s);
+
+// V epilogue fused with the column pass of Algorithm 1 (column j per block):
+//   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),
+//   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots),
+//   Res_ij = V_ij - x_ij lambda_j (pair arithmetic),
+//   eR_j, resmax_j, and kr digit planes of Res (layout j*npad + i).
+void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *eA, const int *eX,
+                  const double *X1, int n, double *lam, double *r, int *eR, double *resmax,
+                  int8_t *Rplanes, int kr, int *flags, hipStream_t s);
+
+// W epilogue (column j per block): W_ij = sum_d 2^(eX_i + eR_j - 7d) C_d(i, j),
+//   e_ij = W_ij / (lambda_j - lambda_i), e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
+//   eE_j (exponent of column j of E'), emax_j = max_i |e_ij|, ke digit planes of E'.
+void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *eX, const int *eR,
+                  const double *lam, const double *r, int n, int *eE, double *emax,
+                  int8_t *Eplanes, int ke, int *flags, hipStream_t s);
+
+// Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j).
+void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *eE,
+                  const double *X1, int n, double *X, int ldx, hipStream_t s);
+
+}  // namespace refeig

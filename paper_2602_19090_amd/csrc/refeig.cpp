@@ -1,0 +1,464 @@
+// Host orchestrator and C ABI of the eigenvector-refinement library.
+//
+// One call of refine_eigvecs runs, per iteration (Algorithm 1 with the first
+// slice X^(1) of Sec. 3, products by the Ozaki scheme on INT8 digit planes):
+//   colstats(X) -> beta (Sec. 4.1), kx          [host reads n exponents]
+//   split X -> X^(1), its digit planes (both layouts)
+//   V = A X^(1)          per-diagonal slice GEMMs + fused column pass
+//                        (r, lambda, residual V - X^(1) D^, residual planes)
+//                                               [host reads lambda, exponents]
+//   W = X^(1)T Res       slice GEMMs + E~ epilogue (E~ planes)
+//                                               [host reads column maxima]
+//   X <- X^(1) + X^(1) E~ slice GEMMs + update epilogue
+// The A planes are built once per call. How many pair diagonals each product
+// keeps is decided on the host from the target error and the eigenvalue gaps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/refeig.h"
+#include "kernels.h"
+
+using namespace refeig;
+
+namespace {
+
+constexpr int kMaxN = 8192;  // the column epilogues hold a whole column in registers
+constexpr int kKaMaxLimit = 18;
+constexpr int kKxMax = 9;
+constexpr int kKrMax = 12;
+constexpr int kKeMax = 12;
+
+#define HIPCHK(x)                                                        \
+  do {                                                                   \
+    hipError_t err__ = (x);                                              \
+    if (err__ != hipSuccess) {                                           \
+      fprintf(stderr, "refeig: %s failed: %s\n", #x, hipGetErrorString(err__)); \
+      return REFEIG_E_HIP;                                               \
+    }                                                                    \
+  } while (0)
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+struct Work {
+  int n = 0, npad = 0, ka = 0;
+  size_t P = 0;
+  int8_t *AP, *XP, *XPT, *RP, *EP;
+  int32_t *Cs;
+  double *X1;
+  int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
+  double *mxA, *mxX, *lam, *r, *resmax, *emax;
+};
+
+int nslots(int ka) { return std::max(ka, kKrMax + kKxMax); }
+
+// Carves the workspace; returns the bytes needed (base may be null).
+size_t carve(int n, int ka, char *base, Work *w) {
+  Work t;
+  t.n = n;
+  t.npad = round_up(n, kTile);
+  t.ka = ka;
+  t.P = (size_t)t.npad * t.npad;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  t.AP = (int8_t *)take(t.P * ka);
+  t.XP = (int8_t *)take(t.P * kKxMax);
+  t.XPT = (int8_t *)take(t.P * kKxMax);
+  t.RP = (int8_t *)take(t.P * kKrMax);
+  t.EP = (int8_t *)take(t.P * kKeMax);
+  t.Cs = (int32_t *)take(t.P * 4 * (size_t)nslots(ka));
+  t.X1 = (double *)take(sizeof(double) * (size_t)n * n);
+  const size_t vi = sizeof(int) * t.npad, vd = sizeof(double) * t.npad;
+  t.eA = (int *)take(vi);
+  t.cA = (int *)take(vi);
+  t.eX = (int *)take(vi);
+  t.cX = (int *)take(vi);
+  t.eR = (int *)take(vi);
+  t.eE = (int *)take(vi);
+  t.flags = (int *)take(256);
+  t.mxA = (double *)take(vd);
+  t.mxX = (double *)take(vd);
+  t.lam = (double *)take(vd);
+  t.r = (double *)take(vd);
+  t.resmax = (double *)take(vd);
+  t.emax = (double *)take(vd);
+  if (w) *w = t;
+  return off;
+}
+
+int ka_of(const refeig_opts *o) {
+  int ka = (o && o->ka_max > 0) ? o->ka_max : kKaMaxLimit;
+  return std::min(ka, kKaMaxLimit);
+}
+
+int npairs_of(int d, int kl, int kr) {
+  int lo = std::max(1, d - kr), hi = std::min(kl, d - 1);
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// beta of Sec. 4.1 (floor form): beta = floor(log2((1/(0.75u)) sqrt(xi delta g / (L S)))),
+// evaluated as q = ((xi*delta)*g)/(L*S), t = sqrt(q)/(0.75*2^-53), beta = exponent(t) - 1.
+// kx = ceil((54 - beta + max_j(e_j - c_j)) / 7): the X^(1) grid 2^(c_j+beta-54) is the
+// rounding bound u*ufp(tau_j) of eq. (minamihata).
+void beta_rule(int n, double xi, double delta, double g, double L, const std::vector<int> &e,
+               const std::vector<int> &c, const std::vector<double> &mx, int *beta, int *kx) {
+  double S = 0.0;
+  int extra = 0;
+  for (int j = 0; j < n; ++j) {
+    if (mx[j] == 0.0) continue;
+    S += std::ldexp(1.0, 2 * c[j]);
+    extra = std::max(extra, e[j] - c[j]);
+  }
+  double q = ((xi * delta) * g) / (L * S);
+  double t = std::sqrt(q) / (0.75 * std::ldexp(1.0, -53));
+  int ex = 0;
+  (void)std::frexp(t, &ex);
+  *beta = ex - 1;
+  int num = 54 - *beta + extra;
+  int k = num <= 0 ? 1 : (num + 6) / 7;
+  *kx = std::min(std::max(k, 1), kKxMax);
+}
+
+// Per-column distance to the nearest other eigenvalue estimate.
+void column_gaps(const std::vector<double> &lam, std::vector<double> &g, double *gmin,
+                 double *lmax) {
+  const int n = (int)lam.size();
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+  g.assign(n, INFINITY);
+  double m = INFINITY, L = 0.0;
+  for (int p = 0; p + 1 < n; ++p) {
+    double d = lam[idx[p + 1]] - lam[idx[p]];
+    g[idx[p]] = std::min(g[idx[p]], d);
+    g[idx[p + 1]] = std::min(g[idx[p + 1]], d);
+    m = std::min(m, d);
+  }
+  for (int i = 0; i < n; ++i) L = std::max(L, std::fabs(lam[i]));
+  if (n == 1) {
+    g[0] = 1.0;
+    m = 1.0;
+  }
+  *gmin = m;
+  *lmax = L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int refeig_default_opts(refeig_opts *o) {
+  if (!o) return REFEIG_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = REFEIG_OZAKI_INT8;
+  o->max_iter = 8;
+  o->fixed_iters = 0;
+  o->stop_rule = 0;
+  o->delta_safety = 8.0;
+  o->xi = 0.0;
+  o->theta = 0.25;
+  o->ka_max = kKaMaxLimit;
+  o->d_extra = 0;
+  o->verbose = 0;
+  return REFEIG_OK;
+}
+
+int refeig_workspace_bytes(int n, const refeig_opts *o, size_t *bytes) {
+  if (n < 1 || n > kMaxN || !bytes) return REFEIG_E_ARG;
+  *bytes = carve(n, ka_of(o), nullptr, nullptr);
+  return REFEIG_OK;
+}
+
+const char *refeig_strerror(int s) {
+  switch (s) {
+    case REFEIG_OK: return "ok";
+    case REFEIG_NOT_CONVERGED: return "not converged (stagnation or iteration limit)";
+    case REFEIG_E_ARG: return "invalid argument";
+    case REFEIG_E_NONFINITE: return "non-finite value in A, X or D";
+    case REFEIG_E_GAP: return "two eigenvalue estimates coincide";
+    case REFEIG_E_RANGE: return "row/column maximum outside [2^-400, 2^400]";
+    case REFEIG_E_NOMEM: return "workspace too small or allocation failed";
+    case REFEIG_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *exps,
+                      int8_t *planes, double *trunc, refeig_stream_t stream) {
+  if (!M || !exps || !planes || rows < 1 || cols < 1 || ld < rows || k < 1 || k > 18)
+    return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const int rpad = round_up(rows, kTile), cpad = round_up(cols, kTile);
+  // exponents are produced for the padded column range; copy the first cols out
+  int *cbuf = nullptr;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMalloc((void **)&cbuf, sizeof(int) * (2 * (size_t)cpad + 64)));
+  int *e_int = cbuf, *c_int = cbuf + cpad, *flags = cbuf + 2 * cpad;
+  HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), s));
+  launch_colstats(M, ld, rows, cols, cpad, e_int, c_int, nullptr, flags, s);
+  launch_split_cols(M, ld, rows, cols, e_int, k, planes, (size_t)rpad * cpad, rpad, cpad, trunc,
+                    rows, nullptr, 0, 0, s);
+  HIPCHK(hipMemcpyAsync(exps, e_int, sizeof(int) * cols, hipMemcpyDeviceToDevice, s));
+  int hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFree(cbuf));
+  HIPCHK(hipGetLastError());
+  if (hf & FLAG_NONFINITE) return REFEIG_E_NONFINITE;
+  if (hf & FLAG_RANGE) return REFEIG_E_RANGE;
+  return REFEIG_OK;
+}
+
+int refeig_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, int npad, int kl,
+                      int kr, int d_min, int ndiag, int32_t *C, refeig_stream_t stream) {
+  if (!Lp || !Rp || !C || npad < kTile || npad % kTile || kl < 1 || kr < 1 || d_min < 2 ||
+      ndiag < 1 || ndiag > kMaxDiag || d_min + ndiag - 1 > kl + kr)
+    return REFEIG_E_ARG;
+  for (int q = 0; q < ndiag; ++q)
+    if ((double)npairs_of(d_min + q, kl, kr) * npad * 127.0 * 127.0 >= 2147483648.0)
+      return REFEIG_E_ARG;
+  if (plane_stride < (size_t)npad * npad) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  launch_slice_gemm(Lp, Rp, plane_stride, npad, kl, kr, d_min, ndiag, C, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return REFEIG_OK;
+}
+
+int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int n,
+                   double target, const refeig_opts *o_in, void *work, size_t work_bytes,
+                   refeig_stream_t stream, refeig_report *rep) {
+  refeig_opts o;
+  if (o_in) o = *o_in;
+  else refeig_default_opts(&o);
+  const int verbose = o.verbose;
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
+      !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
+      o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
+    return REFEIG_E_ARG;
+  if (o.mode != REFEIG_OZAKI_INT8) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const int ka_max = ka_of(&o);
+  const size_t need = carve(n, ka_max, nullptr, nullptr);
+  bool own = false;
+  if (!work) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMalloc(&work, need));
+    own = true;
+  } else if (work_bytes < need) {
+    return REFEIG_E_NOMEM;
+  }
+  Work w;
+  carve(n, ka_max, (char *)work, &w);
+  const int npad = w.npad;
+  const size_t P = w.P;
+  const double delta_int = target / o.delta_safety;
+  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  const double theta = o.theta;
+  const double lsqn = 0.5 * std::log2((double)n);
+  auto t_start = std::chrono::steady_clock::now();
+
+  int status = REFEIG_OK;
+  std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
+  std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
+  int hflags = 0;
+  hipEvent_t ev[8];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+
+  auto cleanup = [&](int st) {
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(work);
+    }
+    if (rep) {
+      rep->status = st;
+      rep->ms_total =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+              .count();
+    }
+    return st;
+  };
+#define STEP(x)                                   \
+  do {                                            \
+    hipError_t err__ = (x);                       \
+    if (err__ != hipSuccess) {                    \
+      fprintf(stderr, "refeig: %s failed: %s\n", #x, hipGetErrorString(err__)); \
+      return cleanup(REFEIG_E_HIP);               \
+    }                                             \
+  } while (0)
+
+  // D on entry: the eigenvalue estimates that set beta of the first iteration
+  STEP(hipMemcpyAsync(lam_prev.data(), D, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  STEP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  // A: column exponents (= row exponents, A is symmetric) and its digit planes, once
+  launch_colstats(A, lda, n, n, npad, w.eA, w.cA, w.mxA, w.flags, s);
+  STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  STEP(hipMemcpyAsync(eA.data(), w.eA, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+  STEP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(lam_prev[i])) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
+  int eA_max = -100000;
+  for (int i = 0; i < n; ++i) eA_max = std::max(eA_max, eA[i]);
+  launch_split_cols(A, lda, n, n, w.eA, ka_max, w.AP, P, npad, npad, nullptr, 0, nullptr, 0, 0,
+                    s);
+  STEP(hipGetLastError());
+
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  double eps_prev = INFINITY;
+  int it = 0;
+  for (; it < iters; ++it) {
+    STEP(hipEventRecord(ev[0], s));
+    // ---- beta and kx from the previous eigenvalue estimates and column maxima of X
+    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s);
+    STEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
+    double gmin, lmax;
+    column_gaps(lam_prev, gaps, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    int beta, kx;
+    beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx);
+    // ---- X^(1) and its planes (both layouts)
+    launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s);
+    // ---- V = A X^(1): keep pair diagonals d <= dv
+    int eXmax = -100000;
+    for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
+    int dv = 2;
+    {
+      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lsqn;
+      for (int j = 0; j < n; ++j) {
+        if (mxX[j] == 0.0) continue;
+        double need = (c0 + eX[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
+        dv = std::max(dv, (int)std::ceil(need));
+      }
+      dv += o.d_extra;
+      dv = std::min(dv, std::min(ka_max + 1, kx + ka_max));
+    }
+    const int ka = std::min(ka_max, dv - 1);
+    int pairs = 0;
+    for (int d = 2; d <= dv; ++d) pairs += npairs_of(d, kx, ka);
+    STEP(hipEventRecord(ev[1], s));
+    launch_slice_gemm(w.XP, w.AP, P, npad, kx, ka, 2, dv - 1, w.Cs, s);
+    STEP(hipEventRecord(ev[2], s));
+    launch_epi_v(w.Cs, npad, 2, dv - 1, w.eA, w.eX, w.X1, n, w.lam, w.r, w.eR, w.resmax, w.RP,
+                 kKrMax, w.flags, s);
+    STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    // ---- W = X^(1)T Res -> E~
+    column_gaps(lam, gaps, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    int dw = 2;
+    {
+      const double c0 = eXmax + 7 + std::log2(1.5 * kx) + lsqn;
+      for (int j = 0; j < n; ++j) {
+        if (resmax[j] == 0.0) continue;
+        double need = (c0 + eR[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
+        dw = std::max(dw, (int)std::ceil(need));
+      }
+      dw += o.d_extra;
+      dw = std::min(dw, kKrMax + 1);
+    }
+    const int kR = std::min(kKrMax, dw - 1), kxw = std::min(kx, dw - 1);
+    dw = std::min(dw, kR + kxw);
+    for (int d = 2; d <= dw; ++d) pairs += npairs_of(d, kR, kxw);
+    STEP(hipEventRecord(ev[3], s));
+    launch_slice_gemm(w.RP, w.XP, P, npad, kR, kxw, 2, dw - 1, w.Cs, s);
+    STEP(hipEventRecord(ev[4], s));
+    launch_epi_w(w.Cs, npad, 2, dw - 1, w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP, kKeMax,
+                 w.flags, s);
+    STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_TIE) return cleanup(REFEIG_E_GAP);
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    double eps = 0.0;
+    for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
+    // ---- X <- X^(1) + X^(1) E~
+    int du = 2;
+    {
+      const double c0 = 7 + std::log2(1.008 * kx) + lsqn - std::log2(theta * delta_int);
+      for (int j = 0; j < n; ++j) {
+        if (emax[j] == 0.0) continue;
+        double need = (c0 + eE[j]) / 7.0;
+        du = std::max(du, (int)std::ceil(need));
+      }
+      du += o.d_extra;
+      du = std::min(du, kKeMax + 1);
+    }
+    const int kE = std::min(kKeMax, du - 1), kxu = std::min(kx, du - 1);
+    du = std::min(du, kE + kxu);
+    for (int d = 2; d <= du; ++d) pairs += npairs_of(d, kE, kxu);
+    STEP(hipEventRecord(ev[5], s));
+    launch_slice_gemm(w.EP, w.XPT, P, npad, kE, kxu, 2, du - 1, w.Cs, s);
+    STEP(hipEventRecord(ev[6], s));
+    launch_epi_u(w.Cs, npad, 2, du - 1, w.eE, w.X1, n, X, ldx, s);
+    STEP(hipMemcpyAsync(D, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    STEP(hipEventRecord(ev[7], s));
+    STEP(hipGetLastError());
+    STEP(hipEventSynchronize(ev[7]));
+    float t_it = 0, g1 = 0, g2 = 0, g3 = 0;
+    (void)hipEventElapsedTime(&t_it, ev[0], ev[7]);
+    (void)hipEventElapsedTime(&g1, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&g2, ev[3], ev[4]);
+    (void)hipEventElapsedTime(&g3, ev[5], ev[6]);
+    if (rep && it < REFEIG_MAX_ITERS) {
+      rep->beta[it] = beta;
+      rep->kx[it] = kx;
+      rep->dv[it] = dv;
+      rep->dw[it] = dw;
+      rep->du[it] = du;
+      rep->pairs[it] = pairs;
+      rep->eps[it] = eps;
+      rep->ms_iter[it] = t_it;
+      rep->ms_gemm[it] = g1 + g2 + g3;
+      rep->iters = it + 1;
+      rep->min_gap = gmin;
+      rep->max_abs_lambda = lmax;
+    }
+    if (verbose)
+      fprintf(stderr,
+              "refeig it %d: beta %d kx %d dv %d dw %d du %d pairs %d eps %.3e gap %.3e "
+              "ms %.2f (gemm %.2f)\n",
+              it + 1, beta, kx, dv, dw, du, pairs, eps, gmin, t_it, g1 + g2 + g3);
+    lam_prev = lam;
+    if (o.fixed_iters > 0) continue;
+    // The correction eps = max|E~| estimates the error of X^(1) (Sec. 3.2: X = X^(1)(I + E)),
+    // which never falls below the truncation grid that beta sets. The forward error after
+    // the update is modelled by eq. (assume2): eps^2 max|lambda| / (xi gap); stop once that
+    // is within the internal delta (xi from the options; strict mode takes xi = 1).
+    const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
+    if (eps <= delta_int || eps * eps * lmax / (xi_stop * gmin) <= delta_int) break;
+    if (it >= 1 && eps > 0.5 * eps_prev) {
+      status = REFEIG_NOT_CONVERGED;
+      break;
+    }
+    eps_prev = eps;
+    if (it + 1 == iters) status = REFEIG_NOT_CONVERGED;
+  }
+  return cleanup(status);
+#undef STEP
+}
+
+}  // extern "C"

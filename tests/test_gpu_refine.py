@@ -1,0 +1,169 @@
+"""Parity of the GPU refinement (C ABI refine_eigvecs) with the CPU oracle.
+
+* One iteration against the oracle's step of the proposed method (Sec. 3, exact
+  products): beta and kx equal, X within the truncation budget.
+* Full solves against X_true (the double-double fixed point of Algorithm 1):
+  max-abs forward error <= the target, on the workload families, ragged and
+  tiny sizes.
+* Error paths and run-to-run determinism.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _rb():
+    from paper_2602_19090_amd import binding
+    return binding
+
+
+def _to_dev(p):
+    import torch
+    rb = _rb()
+    return rb.colmajor(p.A), rb.colmajor(p.X0), torch.from_numpy(np.array(p.D0)).cuda()
+
+
+_XTRUE = {}
+
+
+def _xtrue(p):
+    key = (p.meta["digest"], p.n)
+    if key not in _XTRUE:
+        Xh, Xl, lh, ll, hist = oracle.refine_dd(p.A, p.X0)
+        _XTRUE[key] = (Xh, lh)
+    return _XTRUE[key]
+
+
+def _fwd(Xg, Xt):
+    return float(np.max(np.abs(Xg - oracle.sign_align(Xg, Xt))))
+
+
+@pytest.mark.parametrize("cfg,n,target", [(1, 100, 1e-10), (1, 100, 1e-14), (2, 256, 1e-12),
+                                          (2, 300, 1e-14)])
+def test_one_step_vs_oracle(cfg, n, target):
+    print(f"step cfg={cfg} n={n} target={target}", flush=True)
+    rb = _rb()
+    p = workloads.make_problem(cfg, n, x0="eigh")
+    A, X, D = _to_dev(p)
+    opts = rb.default_opts(fixed_iters=1)
+    st, rep = rb.refine_eigvecs(A, X, D, target, opts)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    ref = oracle.method_step(p.A, p.X0, p.D0, target / opts.delta_safety)
+    assert rep.beta[0] == ref.beta and rep.kx[0] == ref.kx
+    Xg = rb.from_colmajor(X)
+    diff = float(np.max(np.abs(Xg - ref.X_hi)))
+    print(f"  beta={ref.beta} kx={ref.kx} dv={rep.dv[0]} dw={rep.dw[0]} du={rep.du[0]} "
+          f"|X_gpu - X_oracle|max={diff:.3e}", flush=True)
+    assert diff <= target / opts.delta_safety
+    lam = D.cpu().numpy()
+    assert float(np.max(np.abs(lam - ref.lam_h))) <= 1e-15 * float(np.max(np.abs(ref.lam_h)))
+
+
+@pytest.mark.parametrize("cfg,n,x0,target", [
+    (1, 100, "eigh", 1e-14), (1, 100, "eigh", 1e-8),
+    (2, 512, "eigh", 1e-14), (2, 512, "eigh", 1e-11), (2, 300, "eigh", 1e-14),
+    (3, 700, "eigh", 1e-14), (1, 257, "q", 1e-12)])
+def test_refine_to_target(cfg, n, x0, target):
+    print(f"refine cfg={cfg} n={n} x0={x0} target={target}", flush=True)
+    rb = _rb()
+    p = workloads.make_problem(cfg, n, x0=x0)
+    Xt, lt = _xtrue(p)
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, target)
+    r = rep.as_dict()
+    err = _fwd(rb.from_colmajor(X), Xt)
+    print(f"  status={st} iters={r['iters']} eps={['%.1e' % e for e in r['eps']]} "
+          f"pairs={r['pairs']} fwd={err:.3e}", flush=True)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert err <= target
+    lam = D.cpu().numpy()
+    assert float(np.max(np.abs(lam - lt))) <= 1e-15 * float(np.max(np.abs(lt)))
+
+
+def test_fp32_jacobi_start():
+    """An FP32 cyclic-Jacobi start converges where FP32 resolves every eigenvalue gap
+    (cond 1e4). At cond 1e8 it cannot (column errors up to 0.65, outside the assumption
+    eps < 1/100 of Sec. 3.2): the solver must then report NOT_CONVERGED, never OK."""
+    import torch
+    rb = _rb()
+    p = workloads.make_problem(4, 100, x0="jacobi32", cond_exp=4.0)
+    Xt, _ = _xtrue(workloads.make_problem(4, 100, x0="eigh", cond_exp=4.0))
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, 1e-14)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert _fwd(rb.from_colmajor(X), Xt) <= 1e-14
+    p = workloads.make_problem(1, 100, x0="jacobi32")
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, 1e-14)
+    assert st == rb.REFEIG_NOT_CONVERGED
+    assert bool(torch.isfinite(X).all())
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_tiny_sizes(n):
+    rb = _rb()
+    if n == 1:
+        A = np.asfortranarray([[2.5]]); X0 = np.asfortranarray([[1.0]]); D0 = np.array([2.5])
+        Xt = X0
+    else:
+        p = workloads.make_problem(2, n, x0="eigh")
+        A, X0, D0 = p.A, p.X0, p.D0
+        Xt, _ = _xtrue(p)
+    import torch
+    Ad, Xd, Dd = rb.colmajor(A), rb.colmajor(X0), torch.from_numpy(np.array(D0)).cuda()
+    st, rep = rb.refine_eigvecs(Ad, Xd, Dd, 1e-14)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert _fwd(rb.from_colmajor(Xd), Xt) <= 1e-14
+
+
+def test_diagonal_matrix_stays_identity():
+    import torch
+    rb = _rb()
+    n = 64
+    A = np.asfortranarray(np.diag(np.geomspace(1.0, 1e-6, n)))
+    Ad, Xd = rb.colmajor(A), rb.colmajor(np.eye(n))
+    Dd = torch.from_numpy(np.diag(A).copy()).cuda()
+    st, rep = rb.refine_eigvecs(Ad, Xd, Dd, 1e-14)
+    assert st == rb.REFEIG_OK
+    assert np.array_equal(rb.from_colmajor(Xd), np.eye(n))
+    assert rep.eps[0] == 0.0
+
+
+def test_error_paths():
+    import torch
+    rb = _rb()
+    p = workloads.make_problem(2, 64, x0="eigh")
+    A, X, D = _to_dev(p)
+    Ab = A.clone(); Ab[3, 5] = float("nan")
+    st, _ = rb.refine_eigvecs(Ab, X.clone(), D.clone(), 1e-12)
+    assert st == rb.REFEIG_E_NONFINITE
+    Dt = D.clone(); Dt[7] = Dt[8]
+    X2 = X.clone()
+    st, _ = rb.refine_eigvecs(A, X2, Dt, 1e-12)
+    assert st == rb.REFEIG_E_GAP
+    assert torch.equal(X2, X)                      # untouched on a negative status
+    st, _ = rb.refine_eigvecs(A, X.clone(), D.clone(), -1.0)
+    assert st == rb.REFEIG_E_ARG
+    work = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    st, _ = rb.refine_eigvecs(A, X.clone(), D.clone(), 1e-12, work=work)
+    assert st == rb.REFEIG_E_NOMEM
+    with pytest.raises(ValueError):
+        rb.workspace_bytes(8193)
+
+
+def test_caller_workspace_and_determinism():
+    import torch
+    rb = _rb()
+    p = workloads.make_problem(2, 384, x0="eigh")
+    outs = []
+    work = torch.empty(rb.workspace_bytes(384), dtype=torch.uint8, device="cuda")
+    for w in (None, work):
+        A, X, D = _to_dev(p)
+        st, rep = rb.refine_eigvecs(A, X, D, 1e-13, work=w)
+        assert st == rb.REFEIG_OK
+        outs.append((X.cpu().numpy(), D.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

@@ -190,8 +190,12 @@ def jacobi_eig_fp32(A: np.ndarray, tol: float = 1e-7, max_sweeps: int = 60):
                     continue
                 app, aqq = M[p, p], M[q, q]
                 theta = np.float32(aqq - app) / np.float32(2.0 * apq)
-                t = np.float32(np.sign(theta) if theta != 0 else 1.0) / np.float32(
-                    abs(theta) + np.sqrt(np.float32(theta * theta + np.float32(1.0))))
+                sgn = np.float32(1.0) if theta >= 0 else np.float32(-1.0)
+                at = np.float32(abs(theta))
+                if at > np.float32(1e15):          # t = 1/(2 theta) to working precision
+                    t = sgn / (np.float32(2.0) * at)
+                else:
+                    t = sgn / (at + np.sqrt(at * at + np.float32(1.0)))
                 c = np.float32(1.0) / np.sqrt(np.float32(t * t + np.float32(1.0)))
                 s = np.float32(t * c)
                 Mp, Mq = M[:, p].copy(), M[:, q].copy()
