@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of Ozaki-INT8 eigenvector refinement on one MI355X.
+
+Workload: the n = 8192 symmetric matrix with a geometric spectrum from 1 to
+1e-12 (condition 1e12) and 16 clustered pairs, A = Q diag(lambda) Q^T with Q a
+product of four seeded Householder reflectors (synthetic stand-in for the
+paper's randsvd matrices, Sec. 4.2), X0 and D0 from an FP64 eigensolve (the
+paper's start, Sec. 4). Target: max-abs forward error <= 1e-14.
+
+A step is one full refinement from (X0, D0) to the target: every iteration of
+Algorithm 1 (beta rule, X^(1) split, V = A X^(1), column pass, W, E~, update),
+all in the HIP library. The iteration count K is fixed before timing: the
+first iterate whose forward error on the stored oracle columns
+(tests/golden/xtrue_*.npz, sampled columns of the double-double X_true) is
+<= target, or the library's own stop rule when no such file matches A.
+
+Output: one JSON line. value = FP64-equivalent TFLOP/s = 6 n^3 K / time
+(three n x n x n products per iteration, the algorithmic work of Algorithm 1);
+ms_per_step = time to target. roofline: the INT8 slice GEMM kernel against the
+dense INT8 MFMA peak (5.0 POP/s); cpu_baseline: the double-double oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-fwd-err≤1e-14 + FP64-equiv TFLOP/s, Ozaki-INT8 vs FP64 MFMA, n=8192"
+INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_golden(cfg, n, digest):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"xtrue_cfg{cfg}_n{n}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    if str(g["digest"]) != digest:
+        log(f"golden {path} does not match the generated matrix; ignoring it")
+        return None
+    return {"cols": g["cols"], "X": g["X_hi"], "lam": g["lam_hi"]}
+
+
+def sampled_error(Xcm, golden):
+    """max-abs error of the sampled columns (sign-aligned) of a column-major tensor."""
+    import numpy as np
+    import torch
+    cols = torch.from_numpy(golden["cols"]).to(Xcm.device)
+    Xs = Xcm[cols].cpu().numpy().T               # n x m
+    Xt = golden["X"]
+    s = np.sign(np.sum(Xs * Xt, axis=0))
+    s[s == 0] = 1.0
+    return float(np.max(np.abs(Xs - Xt * s)))
+
+
+def cpu_baseline(A, X0cm, n, cols):
+    """Time the oracle's double-double products on `cols` columns and scale to one
+    iteration (three n x n x n double-double products)."""
+    import numpy as np
+    import oracle
+    X = np.asfortranarray(X0cm[:cols].cpu().numpy().T)       # n x cols
+    Xl = np.zeros_like(X, order="F")
+    t0 = time.perf_counter()
+    oracle.dd_gemm(A, X, None, Xl)                          # V-type: FP64 x double-double
+    t1 = time.perf_counter()
+    oracle.dd_gemm(X, X, Xl, Xl, transA=True)                # W-type: double-double x double-double
+    t2 = time.perf_counter()
+    # per iteration: one V-type product and two double-double products of n x n x n
+    t_iter = ((t1 - t0) + 2 * (t2 - t1) * (n / cols)) * (n / cols)
+    tflops = 6.0 * n ** 3 / t_iter / 1e12
+    return {"value": tflops, "unit": "TFLOP/s (FP64-equivalent)", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"double-double products A*X[:, :{cols}] and X[:, :{cols}]^T X[:, :{cols}] "
+                      f"at n={n} ({t2 - t0:.1f} s), scaled to one iteration "
+                      f"(3 products of n x n x n): {t_iter:.0f} s per iteration"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--target", type=float, default=1e-14)
+    ap.add_argument("--cpu-cols", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the refinement of one matrix is not sharded "
+              "across GPUs in this build (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2602_19090_amd import binding as rb
+
+    torch.cuda.set_device(0)
+    n, target = args.n, args.target
+    log(f"generating config {args.config} n={n}")
+    p = workloads.make_problem(args.config, n, x0="none")
+    A = rb.colmajor(p.A)
+    log("FP64 eigensolve for the start (untimed input preparation)")
+    w, V = torch.linalg.eigh(A)
+    X0 = V.t().contiguous()
+    D0 = w.contiguous()
+    del V
+    golden = load_golden(args.config, n, p.meta["digest"])
+
+    # ---- untimed: iterations to the target
+    X, D = X0.clone(), D0.clone()
+    st, rep = rb.refine_eigvecs(A, X, D, target)
+    stop_iters = rep.iters
+    log(f"stop rule: status {rb.strerror(st)}, {stop_iters} iterations, eps {list(rep.as_dict()['eps'])}")
+    errs = []
+    K = stop_iters
+    if golden is not None:
+        X, D = X0.clone(), D0.clone()
+        errs.append(sampled_error(X, golden))
+        K = None
+        for k in range(1, 13):
+            st1, _ = rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=1))
+            errs.append(sampled_error(X, golden))
+            log(f"iteration {k}: sampled max-abs forward error {errs[-1]:.3e}")
+            if errs[-1] <= target and K is None:
+                K = k
+                break
+        if K is None:
+            K = stop_iters
+    opts = rb.default_opts(fixed_iters=K)
+
+    # ---- warmup and timed steps
+    for _ in range(args.warmup):
+        X, D = X0.clone(), D0.clone()
+        rb.refine_eigvecs(A, X, D, target, opts)
+    torch.cuda.synchronize()
+    ms, reps = [], []
+    Xw, Dw = torch.empty_like(X0), torch.empty_like(D0)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for s in range(args.steps):
+        Xw.copy_(X0)
+        Dw.copy_(D0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st, rep = rb.refine_eigvecs(A, Xw, Dw, target, opts)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        reps.append(rep.as_dict())
+        assert st == rb.REFEIG_OK, rb.strerror(st)
+        log(f"step {s + 1}/{args.steps}: {ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    final_err = sampled_error(Xw, golden) if golden is not None else None
+    ms_step = float(np.mean(ms))
+    value = 6.0 * n ** 3 * K / (ms_step * 1e-3) / 1e12
+
+    # ---- roofline of the INT8 slice GEMM (all its launches in the timed steps)
+    ops = sum(pp * 2.0 * n ** 3 for r in reps for it in r["pairs_p"] for pp in it)
+    gemm_ms = sum(t for r in reps for it in r["ms_p"] for t in it)
+    launches = sum(len(it) for r in reps for it in r["ms_p"])
+    achieved = ops / (gemm_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "k_slice_gemm", "achieved": achieved,
+                "peak": INT8_PEAK_TOPS, "unit": "TOP/s (INT8)", "frac": achieved / INT8_PEAK_TOPS,
+                "traffic": None, "avg_launch_ms": gemm_ms / launches,
+                "ops_per_launch": ops / launches}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle double-double products on a column sample")
+        cpu = cpu_baseline(p.A, X0, n, args.cpu_cols)
+
+    r0 = reps[0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s (FP64-equivalent)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"refine eigenvectors n={n} cond 1e12 (16 clustered pairs), "
+                               f"FP64-eigh start, max-abs fwd err <= {target:g}",
+                   "n": n, "target_fwd_err": target, "iters": K, "config_id": args.config},
+        "time_to_target_ms": ms_step, "iters_to_target": K, "stop_rule_iters": stop_iters,
+        "fwd_err_sampled": final_err, "fwd_err_per_iter": errs or None,
+        "eps_per_iter": r0["eps"], "pairs_per_iter": r0["pairs"], "ms_per_iter": r0["ms_iter"],
+        "ms_gemm_per_iter": r0["ms_gemm"], "timed_wall_s": wall,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,7 +51,9 @@ class Report(ctypes.Structure):
                 ("dv", ctypes.c_int * MAX_ITERS), ("dw", ctypes.c_int * MAX_ITERS),
                 ("du", ctypes.c_int * MAX_ITERS), ("pairs", ctypes.c_int * MAX_ITERS),
                 ("eps", ctypes.c_double * MAX_ITERS), ("ms_iter", ctypes.c_double * MAX_ITERS),
-                ("ms_gemm", ctypes.c_double * MAX_ITERS), ("min_gap", ctypes.c_double),
+                ("ms_gemm", ctypes.c_double * MAX_ITERS),
+                ("pairs_p", (ctypes.c_int * 3) * MAX_ITERS),
+                ("ms_p", (ctypes.c_double * 3) * MAX_ITERS), ("min_gap", ctypes.c_double),
                 ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
     def as_dict(self):
@@ -60,6 +62,8 @@ class Report(ctypes.Structure):
                 "kx": list(self.kx[:k]), "dv": list(self.dv[:k]), "dw": list(self.dw[:k]),
                 "du": list(self.du[:k]), "pairs": list(self.pairs[:k]), "eps": list(self.eps[:k]),
                 "ms_iter": list(self.ms_iter[:k]), "ms_gemm": list(self.ms_gemm[:k]),
+                "pairs_p": [list(self.pairs_p[i]) for i in range(k)],
+                "ms_p": [list(self.ms_p[i]) for i in range(k)],
                 "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
                 "ms_total": self.ms_total}
 

@@ -328,6 +328,128 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
       }
 }
 
+// Large-tile variant: one block computes a 256 x 256 tile with 4 waves, each
+// owning 128 x 128 (4 x 4 MFMA 32x32x32 blocks, 256 accumulator registers held
+// in the AGPR half of the register file). Each fragment read from LDS feeds 4
+// MFMAs. K advances 128 bytes per stage through two LDS buffers (147 KB of the
+// 160 KB): while the matrix cores consume stage t, stage t+1 goes from
+// registers into the other buffer and the global loads of stage t+2 are in
+// flight, with one barrier per stage.
+// Tile order: the blocks of one XCD (block id mod 8) get a contiguous range of
+// tiles, walked in groups of 4 tile-rows, so the ~32 blocks an XCD runs at once
+// cover a 4 x 8 patch and share its L and R panels in that XCD's L2.
+constexpr int HBM_ = 256, HBK = 128, HLDS = HBK + 16, HGM = 4;
+
+__global__ __launch_bounds__(256, 1) void k_slice_gemm256(const int8_t *__restrict__ Lp,
+                                                          const int8_t *__restrict__ Rp,
+                                                          size_t pstride, int npad, int kl, int kr,
+                                                          int d_min, DiagOrder order,
+                                                          int32_t *__restrict__ C) {
+  __shared__ __attribute__((aligned(16))) int8_t sL[2][HBM_ * HLDS];
+  __shared__ __attribute__((aligned(16))) int8_t sR[2][HBM_ * HLDS];
+  const int tiles_n = npad / HBM_;
+  const int G = gridDim.x;
+  int b = blockIdx.x;
+  if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
+  const int group = b / (HGM * tiles_n);
+  const int first_m = group * HGM;
+  const int gsz = min(tiles_n - first_m, HGM);
+  const int inb = b - group * HGM * tiles_n;
+  const int m0 = (first_m + inb % gsz) * HBM_;
+  const int n0 = (inb / gsz) * HBM_;
+  const int slot = order.q[blockIdx.y];
+  const int d = d_min + slot;
+  const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
+  const int npairs = s_hi - s_lo + 1;
+  const int KT = npad / HBK;
+  const int T = npairs * KT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  v16i acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][c][v] = 0;
+
+  // global -> register staging: 256 rows x 128 bytes per operand = 2048 chunks
+  // of 16 bytes, 8 per thread; 8 consecutive threads read one 128-byte row.
+  v4i gL[8], gR[8];
+  auto load = [&](int tt) {
+    const int p = tt / KT, k0 = (tt - p * KT) * HBK;
+    const int s = s_lo + p;
+    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + (size_t)m0 * npad + k0;
+    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + (size_t)n0 * npad + k0;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
+      gL[h] = *(const v4i *)(Lb + (size_t)row * npad + col);
+      gR[h] = *(const v4i *)(Rb + (size_t)row * npad + col);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
+      *(v4i *)(&sL[buf][row * HLDS + col]) = gL[h];
+      *(v4i *)(&sR[buf][row * HLDS + col]) = gR[h];
+    }
+  };
+  if (T > 0) {
+    load(0);
+    stash(0);
+    if (T > 1) load(1);
+  }
+  // Fragment addresses: lane l reads 16 bytes of row (l mod 32) of each 32-row
+  // block at K offset 16 (l / 32) within the 32-byte MFMA step.
+  const int fa_off = (wm * 128 + (lane & 31)) * HLDS + 16 * (lane >> 5);
+  const int fb_off = (wn * 128 + (lane & 31)) * HLDS + 16 * (lane >> 5);
+  for (int tt = 0; tt < T; ++tt) {
+    const int cur = tt & 1;
+    __syncthreads();                 // stage tt visible; buffer cur^1 no longer read
+    const int8_t *bL = sL[cur], *bR = sR[cur];
+    v4i fa[2][4], fb[2][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      fa[0][x] = *(const v4i *)(bL + fa_off + x * 32 * HLDS);
+      fb[0][x] = *(const v4i *)(bR + fb_off + x * 32 * HLDS);
+    }
+#pragma unroll
+    for (int ks = 0; ks < HBK / 32; ++ks) {
+      const int c = ks & 1;
+      if (ks + 1 < HBK / 32) {       // next step's fragments, in flight during the MFMAs
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          fa[c ^ 1][x] = *(const v4i *)(bL + fa_off + x * 32 * HLDS + (ks + 1) * 32);
+          fb[c ^ 1][x] = *(const v4i *)(bR + fb_off + x * 32 * HLDS + (ks + 1) * 32);
+        }
+      }
+      if (ks == 1 && tt + 1 < T) stash(cur ^ 1);              // LDS writes of stage tt+1
+      if (ks == 2 && tt + 2 < T) load(tt + 2);                // global loads of stage tt+2
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[c][x], fb[c][y], acc[x][y], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  int32_t *Cq = C + (size_t)slot * npad * npad;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 128 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = n0 + wn * 128 + y * 32 + (lane & 31);
+        Cq[(size_t)row * npad + col] = acc[x][y][v];
+      }
+}
+
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, hipStream_t s) {
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
@@ -345,9 +467,15 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
       o.q[b] = o.q[b - 1];
       o.q[b - 1] = t;
     }
-  const int tiles = (npad / GBM) * (npad / GBN);
-  hipLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, Lp, Rp, pstride, npad, kl,
-                     kr, d_min, o, C);
+  if (npad >= 1024) {
+    const int tiles = (npad / HBM_) * (npad / HBM_);
+    hipLaunchKernelGGL(k_slice_gemm256, dim3(tiles, ndiag), dim3(256), 0, s, Lp, Rp, pstride,
+                       npad, kl, kr, d_min, o, C);
+  } else {
+    const int tiles = (npad / GBM) * (npad / GBN);
+    hipLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, Lp, Rp, pstride, npad,
+                       kl, kr, d_min, o, C);
+  }
 }
 
 // ---------------------------------------------------------------- V epilogue + column pass

@@ -352,8 +352,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       dv = std::min(dv, std::min(ka_max + 1, kx + ka_max));
     }
     const int ka = std::min(ka_max, dv - 1);
-    int pairs = 0;
-    for (int d = 2; d <= dv; ++d) pairs += npairs_of(d, kx, ka);
+    int pairs = 0, pv = 0, pw = 0, pu = 0;
+    for (int d = 2; d <= dv; ++d) pv += npairs_of(d, kx, ka);
+    pairs += pv;
     STEP(hipEventRecord(ev[1], s));
     launch_slice_gemm(w.XP, w.AP, P, npad, kx, ka, 2, dv - 1, w.Cs, s);
     STEP(hipEventRecord(ev[2], s));
@@ -381,7 +382,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     }
     const int kR = std::min(kKrMax, dw - 1), kxw = std::min(kx, dw - 1);
     dw = std::min(dw, kR + kxw);
-    for (int d = 2; d <= dw; ++d) pairs += npairs_of(d, kR, kxw);
+    for (int d = 2; d <= dw; ++d) pw += npairs_of(d, kR, kxw);
+    pairs += pw;
     STEP(hipEventRecord(ev[3], s));
     launch_slice_gemm(w.RP, w.XP, P, npad, kR, kxw, 2, dw - 1, w.Cs, s);
     STEP(hipEventRecord(ev[4], s));
@@ -409,7 +411,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     }
     const int kE = std::min(kKeMax, du - 1), kxu = std::min(kx, du - 1);
     du = std::min(du, kE + kxu);
-    for (int d = 2; d <= du; ++d) pairs += npairs_of(d, kE, kxu);
+    for (int d = 2; d <= du; ++d) pu += npairs_of(d, kE, kxu);
+    pairs += pu;
     STEP(hipEventRecord(ev[5], s));
     launch_slice_gemm(w.EP, w.XPT, P, npad, kE, kxu, 2, du - 1, w.Cs, s);
     STEP(hipEventRecord(ev[6], s));
@@ -433,6 +436,12 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->eps[it] = eps;
       rep->ms_iter[it] = t_it;
       rep->ms_gemm[it] = g1 + g2 + g3;
+      rep->pairs_p[it][0] = pv;
+      rep->pairs_p[it][1] = pw;
+      rep->pairs_p[it][2] = pu;
+      rep->ms_p[it][0] = g1;
+      rep->ms_p[it][1] = g2;
+      rep->ms_p[it][2] = g3;
       rep->iters = it + 1;
       rep->min_gap = gmin;
       rep->max_abs_lambda = lmax;

@@ -83,7 +83,8 @@ def _diag_products_oracle(Lp, Rp, kl, kr, d_min, ndiag, rows=None, cols=None):
     return out
 
 
-@pytest.mark.parametrize("npad,kl,kr", [(256, 1, 1), (256, 3, 5), (512, 7, 2), (512, 4, 9)])
+@pytest.mark.parametrize("npad,kl,kr", [(256, 1, 1), (256, 3, 5), (512, 7, 2), (512, 4, 9),
+                                         (1024, 2, 3), (1536, 1, 2)])
 def test_slice_gemm_bitexact(npad, kl, kr):
     print(f"gemm npad={npad} kl={kl} kr={kr}", flush=True)
     torch = _torch()
