@@ -94,8 +94,9 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--target", type=float, default=1e-14)
-    ap.add_argument("--cpu-cols", type=int, default=96)
+    ap.add_argument("--cpu-cols", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain-form leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -179,6 +180,53 @@ def main():
                 "traffic": None, "avg_launch_ms": gemm_ms / launches,
                 "ops_per_launch": ops / launches}
 
+    # ---- the plain form: the same refinement with FP64 slices on DGEMM (FP64 MFMA)
+    plain = None
+    if not args.no_plain:
+        log("FP64 plain form: iterations to the target")
+        popts = rb.default_opts(mode=rb.REFEIG_FP64_PLAIN)
+        X, D = X0.clone(), D0.clone()
+        pst, prep = rb.refine_eigvecs(A, X, D, target, popts)
+        Kp = prep.iters
+        perrs = []
+        if golden is not None:
+            X, D = X0.clone(), D0.clone()
+            Kp = None
+            for k in range(1, 13):
+                rb.refine_eigvecs(A, X, D, target, rb.default_opts(mode=rb.REFEIG_FP64_PLAIN,
+                                                                    fixed_iters=1))
+                perrs.append(sampled_error(X, golden))
+                log(f"plain iteration {k}: sampled max-abs forward error {perrs[-1]:.3e}")
+                if perrs[-1] <= target:
+                    Kp = k
+                    break
+        if Kp is not None:
+            popts = rb.default_opts(mode=rb.REFEIG_FP64_PLAIN, fixed_iters=Kp)
+            pms, preps = [], []
+            for s in range(max(1, args.steps)):
+                Xw.copy_(X0)
+                Dw.copy_(D0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pst, prep = rb.refine_eigvecs(A, Xw, Dw, target, popts)
+                e1.record()
+                torch.cuda.synchronize()
+                pms.append(e0.elapsed_time(e1))
+                preps.append(prep.as_dict())
+                log(f"plain step {s + 1}: {pms[-1]:.1f} ms")
+            pms_step = float(np.mean(pms))
+            dg = sum(it[0] + 2 for it in preps[0]["pairs_p"])
+            plain = {"ms_to_target": pms_step, "iters": Kp,
+                     "value": 6.0 * n ** 3 * Kp / (pms_step * 1e-3) / 1e12,
+                     "unit": "TFLOP/s (FP64-equivalent)", "dgemm_per_solve": dg,
+                     "dgemm_tflops": dg * 2.0 * n ** 3 / (pms_step * 1e-3) / 1e12,
+                     "fp64_peak_tflops": 78.6, "status": rb.strerror(pst),
+                     "fwd_err_per_iter": perrs or None, "eps_per_iter": preps[0]["eps"],
+                     "speedup_int8_vs_plain": pms_step / ms_step}
+        else:
+            plain = {"ms_to_target": None, "iters": None, "status": "did not reach the target",
+                     "fwd_err_per_iter": perrs or None}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle double-double products on a column sample")
@@ -197,7 +245,7 @@ def main():
         "fwd_err_sampled": final_err, "fwd_err_per_iter": errs or None,
         "eps_per_iter": r0["eps"], "pairs_per_iter": r0["pairs"], "ms_per_iter": r0["ms_iter"],
         "ms_gemm_per_iter": r0["ms_gemm"], "timed_wall_s": wall,
-        "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": None,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": plain,
     }
     print(json.dumps(out), flush=True)
 

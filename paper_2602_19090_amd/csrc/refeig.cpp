@@ -21,8 +21,11 @@
 #include <cstring>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/refeig.h"
 #include "kernels.h"
+#include "plain.h"
 
 using namespace refeig;
 
@@ -95,6 +98,43 @@ size_t carve(int n, int ka, char *base, Work *w) {
   return off;
 }
 
+// ---- FP64 plain form: workspace
+constexpr int kPlainKaMax = 8, kPlainKxMax = 4;
+struct PlainWork {
+  double *SA, *SX, *X1, *P, *Vh, *Vl, *Res, *E;
+  int *eX, *cX, *flags;
+  double *mxX, *lam, *r;
+  unsigned long long *colmax;
+};
+size_t carve_plain(int n, char *base, PlainWork *w) {
+  PlainWork t;
+  size_t off = 0;
+  const size_t nn = (size_t)n * n * sizeof(double);
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  t.SA = (double *)take(nn * kPlainKaMax);
+  t.SX = (double *)take(nn * kPlainKxMax);
+  t.X1 = (double *)take(nn);
+  t.P = (double *)take(nn);
+  t.Vh = (double *)take(nn);
+  t.Vl = (double *)take(nn);
+  t.Res = (double *)take(nn);
+  t.E = (double *)take(nn);
+  const int npad = round_up(n, kTile);
+  t.eX = (int *)take(sizeof(int) * npad);
+  t.cX = (int *)take(sizeof(int) * npad);
+  t.flags = (int *)take(256);
+  t.mxX = (double *)take(sizeof(double) * npad);
+  t.lam = (double *)take(sizeof(double) * npad);
+  t.r = (double *)take(sizeof(double) * npad);
+  t.colmax = (unsigned long long *)take(sizeof(unsigned long long) * npad);
+  if (w) *w = t;
+  return off;
+}
+
 int ka_of(const refeig_opts *o) {
   int ka = (o && o->ka_max > 0) ? o->ka_max : kKaMaxLimit;
   return std::min(ka, kKaMaxLimit);
@@ -152,6 +192,198 @@ void column_gaps(const std::vector<double> &lam, std::vector<double> &g, double 
   *lmax = L;
 }
 
+// ---- FP64 plain form: the same iteration with FP64-slice products on DGEMM.
+// V = sum over kept pairs of A_row^(r) X^(s), every product exact in FP64 because
+// both slices carry b = 53 - alpha bits with 2 alpha >= 53 + log2 n (Sec. 2.3,
+// eq. alp_beta with alpha = beta); W and X^(1) E~ are single DGEMMs.
+int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n, double target,
+                 const refeig_opts &o, void *work, size_t work_bytes, hipStream_t s,
+                 refeig_report *rep) {
+  const int verbose = o.verbose;
+  const size_t need = carve_plain(n, nullptr, nullptr);
+  bool own = false;
+  if (!work) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMalloc(&work, need));
+    own = true;
+  } else if (work_bytes < need) {
+    return REFEIG_E_NOMEM;
+  }
+  PlainWork w;
+  carve_plain(n, (char *)work, &w);
+  const int npad = round_up(n, kTile);
+  const size_t nn = (size_t)n * n;
+  const double delta_int = target / o.delta_safety;
+  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  const double lsqn = 0.5 * std::log2((double)n);
+  const int alpha = (int)std::ceil((53.0 + std::log2((double)n)) / 2.0);
+  const int b = 53 - alpha;  // bits per FP64 slice
+  auto t_start = std::chrono::steady_clock::now();
+  rocblas_handle hb = nullptr;
+  std::vector<int> eX(npad), cX(npad), eA(npad), cA(npad);
+  std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), gaps;
+  std::vector<unsigned long long> cm(npad);
+  int hflags = 0, status = REFEIG_OK;
+  hipEvent_t ev[4];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  auto cleanup = [&](int st) {
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (hb) (void)rocblas_destroy_handle(hb);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(work);
+    }
+    if (rep) {
+      rep->status = st;
+      rep->ms_total =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+              .count();
+    }
+    return st;
+  };
+#define PSTEP(x)                                                                            \
+  do {                                                                                      \
+    hipError_t err__ = (x);                                                                 \
+    if (err__ != hipSuccess) {                                                              \
+      fprintf(stderr, "refeig: %s failed: %s\n", #x, hipGetErrorString(err__));             \
+      return cleanup(REFEIG_E_HIP);                                                         \
+    }                                                                                       \
+  } while (0)
+#define BSTEP(x)                                                                            \
+  do {                                                                                      \
+    if ((x) != rocblas_status_success) {                                                    \
+      fprintf(stderr, "refeig: %s failed\n", #x);                                           \
+      return cleanup(REFEIG_E_HIP);                                                         \
+    }                                                                                       \
+  } while (0)
+  BSTEP(rocblas_create_handle(&hb));
+  BSTEP(rocblas_set_stream(hb, s));
+  const double one = 1.0, zero = 0.0;
+
+  PSTEP(hipMemcpyAsync(lam_prev.data(), D, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  PSTEP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  // A: its columns are its rows (symmetric); kPlainKaMax FP64 slices per column
+  launch_colstats(A, lda, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s);
+  PSTEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PSTEP(hipMemcpyAsync(eA.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+  PSTEP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(lam_prev[i])) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
+  int eA_max = -100000;
+  for (int i = 0; i < n; ++i) eA_max = std::max(eA_max, eA[i]);
+  launch_sigma_split_cols(A, lda, n, alpha, kPlainKaMax, w.SA, s);
+
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  double eps_prev = INFINITY;
+  for (int it = 0; it < iters; ++it) {
+    PSTEP(hipEventRecord(ev[0], s));
+    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s);
+    PSTEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    PSTEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    PSTEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    PSTEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PSTEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    double gmin, lmax;
+    column_gaps(lam_prev, gaps, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    int beta, kx_unused;
+    beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx_unused);
+    launch_x1_rn(X, ldx, n, w.cX, w.mxX, beta, w.X1, s);
+    const int kx = std::min(kPlainKxMax, std::max(1, (54 - beta + b - 1) / b));
+    launch_sigma_split_cols(w.X1, n, n, alpha, kx, w.SX, s);
+    int eXmax = -100000;
+    for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
+    int dv = 2;
+    for (int j = 0; j < n; ++j) {
+      if (mxX[j] == 0.0) continue;
+      double need_bits = eA_max + eX[j] + b + std::log2(1.5 * kx) + lsqn -
+                         std::log2(o.theta * delta_int * gaps[j]);
+      dv = std::max(dv, (int)std::ceil(need_bits / b));
+    }
+    dv = std::min(dv + o.d_extra, kPlainKaMax + kx);
+    // V: pairs (r, s) with r + s <= dv, summed from the smallest weight up
+    PSTEP(hipEventRecord(ev[1], s));
+    int pv = 0;
+    for (int d = dv; d >= 2; --d)
+      for (int sx = 1; sx <= kx; ++sx) {
+        const int ra = d - sx;
+        if (ra < 1 || ra > kPlainKaMax) continue;
+        BSTEP(rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one,
+                            w.SA + (size_t)(ra - 1) * nn, n, w.SX + (size_t)(sx - 1) * nn, n,
+                            &zero, w.P, n));
+        launch_dd_accum(w.P, w.Vh, w.Vl, nn, pv == 0, s);
+        ++pv;
+      }
+    PSTEP(hipEventRecord(ev[2], s));
+    launch_colpass_dd(w.Vh, w.Vl, w.X1, n, w.lam, w.r, w.Res, w.flags, s);
+    // W = X1^T Res, E~, U = X1 E~, X = X1 + U
+    BSTEP(rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one,
+                        w.X1, n, w.Res, n, &zero, w.P, n));
+    PSTEP(hipMemsetAsync(w.colmax, 0, sizeof(unsigned long long) * npad, s));
+    launch_etilde(w.P, w.lam, w.r, n, w.E, w.colmax, w.flags, s);
+    BSTEP(rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, w.X1, n,
+                        w.E, n, &zero, w.P, n));
+    launch_update(w.X1, w.P, n, X, ldx, s);
+    PSTEP(hipMemcpyAsync(D, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    PSTEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    PSTEP(hipMemcpyAsync(cm.data(), w.colmax, sizeof(unsigned long long) * n,
+                         hipMemcpyDeviceToHost, s));
+    PSTEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PSTEP(hipEventRecord(ev[3], s));
+    PSTEP(hipGetLastError());
+    PSTEP(hipStreamSynchronize(s));
+    if (hflags & 2) return cleanup(REFEIG_E_GAP);
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    double eps = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double v;
+      std::memcpy(&v, &cm[j], sizeof(v));
+      eps = std::max(eps, v);
+    }
+    float t_it = 0, tv = 0;
+    (void)hipEventElapsedTime(&t_it, ev[0], ev[3]);
+    (void)hipEventElapsedTime(&tv, ev[1], ev[2]);
+    column_gaps(lam, gaps, &gmin, &lmax);
+    if (rep && it < REFEIG_MAX_ITERS) {
+      rep->beta[it] = beta;
+      rep->kx[it] = kx;
+      rep->dv[it] = dv;
+      rep->dw[it] = 0;
+      rep->du[it] = 0;
+      rep->pairs[it] = pv + 2;
+      rep->pairs_p[it][0] = pv;
+      rep->pairs_p[it][1] = 1;
+      rep->pairs_p[it][2] = 1;
+      rep->ms_p[it][0] = tv;
+      rep->eps[it] = eps;
+      rep->ms_iter[it] = t_it;
+      rep->ms_gemm[it] = tv;
+      rep->iters = it + 1;
+      rep->min_gap = gmin;
+      rep->max_abs_lambda = lmax;
+    }
+    if (verbose)
+      fprintf(stderr, "refeig plain it %d: beta %d slices A %d X %d (b=%d) dv %d dgemm %d eps %.3e "
+                      "ms %.2f (V %.2f)\n", it + 1, beta, kPlainKaMax, kx, b, dv, pv + 2, eps, t_it, tv);
+    lam_prev = lam;
+    if (o.fixed_iters > 0) continue;
+    const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
+    if (eps <= delta_int || eps * eps * lmax / (xi_stop * gmin) <= delta_int) break;
+    if (it >= 1 && eps > 0.5 * eps_prev) {
+      status = REFEIG_NOT_CONVERGED;
+      break;
+    }
+    eps_prev = eps;
+    if (it + 1 == iters) status = REFEIG_NOT_CONVERGED;
+  }
+  return cleanup(status);
+#undef PSTEP
+#undef BSTEP
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,7 +406,8 @@ int refeig_default_opts(refeig_opts *o) {
 
 int refeig_workspace_bytes(int n, const refeig_opts *o, size_t *bytes) {
   if (n < 1 || n > kMaxN || !bytes) return REFEIG_E_ARG;
-  *bytes = carve(n, ka_of(o), nullptr, nullptr);
+  *bytes = (o && o->mode == REFEIG_FP64_PLAIN) ? carve_plain(n, nullptr, nullptr)
+                                               : carve(n, ka_of(o), nullptr, nullptr);
   return REFEIG_OK;
 }
 
@@ -246,8 +479,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
-  if (o.mode != REFEIG_OZAKI_INT8) return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if (o.mode == REFEIG_FP64_PLAIN)
+    return refine_plain(A, lda, X, ldx, D, n, target, o, work, work_bytes, s, rep);
+  if (o.mode != REFEIG_OZAKI_INT8) return REFEIG_E_ARG;
   const int ka_max = ka_of(&o);
   const size_t need = carve(n, ka_max, nullptr, nullptr);
   bool own = false;
