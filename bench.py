@@ -194,7 +194,7 @@ def main():
     value = 6.0 * n ** 3 * K / (ms_step * 1e-3) / 1e12
 
     # ---- roofline of the INT8 slice GEMM (all its launches in the timed steps)
-    ops = sum(pp * 2.0 * n ** 3 for r in reps for it in r["pairs_p"] for pp in it)
+    ops = sum(pp * 2.0 * n ** 3 for r in reps for it in r["pairs_f"] for pp in it)
     gemm_ms = sum(t for r in reps for it in r["ms_p"] for t in it)
     launches = sum(len(it) for r in reps for it in r["ms_p"])
     achieved = ops / (gemm_ms * 1e-3) / 1e12
@@ -266,7 +266,7 @@ def main():
                    "n": n, "target_fwd_err": target, "iters": K, "config_id": args.config},
         "time_to_target_ms": ms_step, "iters_to_target": K, "stop_rule_iters": stop_iters,
         "fwd_err_sampled": final_err, "fwd_err_per_iter": errs or None,
-        "eps_per_iter": r0["eps"], "pairs_per_iter": r0["pairs"], "ms_per_iter": r0["ms_iter"],
+        "eps_per_iter": r0["eps"], "pairs_per_iter": [round(sum(x), 2) for x in r0["pairs_f"]], "ms_per_iter": r0["ms_iter"],
         "ms_gemm_per_iter": r0["ms_gemm"], "timed_wall_s": wall,
         "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": plain,
     }

@@ -86,6 +86,8 @@ typedef struct {
     double ms_iter[REFEIG_MAX_ITERS];/* wall time per iteration (HIP events)            */
     double ms_gemm[REFEIG_MAX_ITERS];/* time in slice products per iteration            */
     int pairs_p[REFEIG_MAX_ITERS][3];   /* slice products of V, W, X^(1)E~ per iteration  */
+    double pairs_f[REFEIG_MAX_ITERS][3];/* the same in units of one n x n x n product,
+                                           counting per-column-block cutoffs exactly      */
     double ms_p[REFEIG_MAX_ITERS][3];   /* launch time of those three products (events)    */
     double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
     double max_abs_lambda;           /* max |lambda| (last)                             */

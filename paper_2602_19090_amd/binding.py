@@ -53,6 +53,7 @@ class Report(ctypes.Structure):
                 ("eps", ctypes.c_double * MAX_ITERS), ("ms_iter", ctypes.c_double * MAX_ITERS),
                 ("ms_gemm", ctypes.c_double * MAX_ITERS),
                 ("pairs_p", (ctypes.c_int * 3) * MAX_ITERS),
+                ("pairs_f", (ctypes.c_double * 3) * MAX_ITERS),
                 ("ms_p", (ctypes.c_double * 3) * MAX_ITERS), ("min_gap", ctypes.c_double),
                 ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
@@ -64,6 +65,7 @@ class Report(ctypes.Structure):
                 "ms_iter": list(self.ms_iter[:k]), "ms_gemm": list(self.ms_gemm[:k]),
                 "pairs_p": [list(self.pairs_p[i]) for i in range(k)],
                 "ms_p": [list(self.ms_p[i]) for i in range(k)],
+                "pairs_f": [list(self.pairs_f[i]) for i in range(k)],
                 "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
                 "ms_total": self.ms_total}
 

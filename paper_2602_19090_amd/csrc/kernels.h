@@ -32,28 +32,43 @@ void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
                        int8_t *planesT, size_t pstrideT, int kT, hipStream_t s);
 
-// Per-diagonal INT8 slice products (see refeig_slice_gemm).
-void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
-                       int kr, int d_min, int ndiag, int32_t *C, hipStream_t s);
+constexpr int kMaxRowBlocks = 64;
+struct RowBlocks {
+  int count;               // number of L row blocks (tile rows) in this launch
+  int m[kMaxRowBlocks];    // their indices (units of gemm_tile_rows(npad) rows)
+};
 
+// Per-diagonal INT8 slice products (see refeig_slice_gemm) for diagonals
+// d_min .. d_min + ndiag - 1, restricted to the L row blocks in rb (all row
+// blocks when rb is null). The host issues one launch per group of row blocks
+// that need the same diagonals, so every block of a diagonal does real work.
+// ev_start / ev_stop (may be null) take the dispatch's own start / end times.
+void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
+                       int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
+                       hipStream_t s, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
+// L rows per block tile of launch_slice_gemm for this npad.
+int gemm_tile_rows(int npad);
+
+// Epilogues sum, for output column j, the diagonals d_min .. min(d_min+ndiag-1, dcut[j]).
 // V epilogue fused with the column pass of Algorithm 1 (column j per block):
 //   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),
 //   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots),
 //   Res_ij = V_ij - x_ij lambda_j (pair arithmetic),
 //   eR_j, resmax_j, and kr digit planes of Res (layout j*npad + i).
-void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *eA, const int *eX,
-                  const double *X1, int n, double *lam, double *r, int *eR, double *resmax,
-                  int8_t *Rplanes, int kr, int *flags, hipStream_t s);
+void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
+                  int *eR, double *resmax, int8_t *Rplanes, int kr, int *flags, hipStream_t s);
 
 // W epilogue (column j per block): W_ij = sum_d 2^(eX_i + eR_j - 7d) C_d(i, j),
 //   e_ij = W_ij / (lambda_j - lambda_i), e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
 //   eE_j (exponent of column j of E'), emax_j = max_i |e_ij|, ke digit planes of E'.
-void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *eX, const int *eR,
-                  const double *lam, const double *r, int n, int *eE, double *emax,
-                  int8_t *Eplanes, int ke, int *flags, hipStream_t s);
+void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
+                  double *emax, int8_t *Eplanes, int ke, int *flags, hipStream_t s);
 
 // Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j).
-void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *eE,
-                  const double *X1, int n, double *X, int ldx, hipStream_t s);
+void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s);
 
 }  // namespace refeig

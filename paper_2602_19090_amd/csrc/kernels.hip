@@ -11,6 +11,7 @@
 // -ffp-contract=off: the error-free transformations (TwoSum, the exact product
 // via fma) must not be contracted or reassociated.
 #include "kernels.h"
+#include <hip/hip_ext.h>
 
 #include <float.h>
 
@@ -253,11 +254,11 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
                                                        const int8_t *__restrict__ Rp,
                                                        size_t pstride, int npad, int kl, int kr,
                                                        int d_min, DiagOrder order,
-                                                       int32_t *__restrict__ C) {
+                                                       int32_t *__restrict__ C, RowBlocks rb) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
   const int tiles_n = npad / GBN;
-  const int m0 = (blockIdx.x / tiles_n) * GBM;
+  const int m0 = rb.m[blockIdx.x / tiles_n] * GBM;
   const int n0 = (blockIdx.x % tiles_n) * GBN;
   const int slot = order.q[blockIdx.y];
   const int d = d_min + slot;
@@ -328,40 +329,73 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
       }
 }
 
-// Large-tile variant: one block computes a 256 x 256 tile with 4 waves, each
-// owning 128 x 128 (4 x 4 MFMA 32x32x32 blocks, 256 accumulator registers held
-// in the AGPR half of the register file). Each fragment read from LDS feeds 4
-// MFMAs. K advances 128 bytes per stage through two LDS buffers (147 KB of the
-// 160 KB): while the matrix cores consume stage t, stage t+1 goes from
-// registers into the other buffer and the global loads of stage t+2 are in
-// flight, with one barrier per stage.
-// Tile order: the blocks of one XCD (block id mod 8) get a contiguous range of
-// tiles, walked in groups of 4 tile-rows, so the ~32 blocks an XCD runs at once
-// cover a 4 x 8 patch and share its L and R panels in that XCD's L2.
-constexpr int HBM_ = 256, HBK = 128, HLDS = HBK + 16, HGM = 4;
+constexpr int HBM_ = 256, HGM = 4;
 
-__global__ __launch_bounds__(256, 1) void k_slice_gemm256(const int8_t *__restrict__ Lp,
-                                                          const int8_t *__restrict__ Rp,
-                                                          size_t pstride, int npad, int kl, int kr,
-                                                          int d_min, DiagOrder order,
-                                                          int32_t *__restrict__ C) {
-  __shared__ __attribute__((aligned(16))) int8_t sL[2][HBM_ * HLDS];
-  __shared__ __attribute__((aligned(16))) int8_t sR[2][HBM_ * HLDS];
+// Block -> (row-block index, column offset) for the 256 x 256 kernel over a
+// launch of tiles_m row blocks x tiles_n column blocks. Blocks are dispatched
+// round-robin over the 8 XCDs (block id mod 8), and each XCD has its own L2, so
+// the blocks one XCD runs at once should form a compact patch that shares
+// operand panels. With tiles_n a multiple of 8 each XCD owns a column band;
+// else with tiles_m a multiple of 8 it takes row blocks x, x + 8, ...; otherwise
+// blocks walk groups of 4 row blocks.
+__device__ __forceinline__ void tile_of_block(int bid, int tiles_m, int tiles_n, int &mi, int &n0) {
+  if (tiles_n % 8 == 0) {
+    // XCD x owns the column band [x cb, (x + 1) cb) and walks it in groups of up
+    // to 8 row blocks: its ~32 resident blocks form an 8 x 4 patch.
+    const int xcd = bid & 7, local = bid >> 3;
+    const int cb = tiles_n >> 3;
+    const int rg = local / (8 * cb), rem = local - rg * 8 * cb;
+    const int gs = min(8, tiles_m - rg * 8);
+    mi = rg * 8 + rem % gs;
+    n0 = (xcd * cb + rem / gs) * HBM_;
+  } else if (tiles_m % 8 == 0) {
+    const int xcd = bid & 7, local = bid >> 3;
+    const int rows = tiles_m >> 3;
+    mi = xcd + 8 * (local % rows);
+    n0 = (local / rows) * HBM_;
+  } else {
+    const int group = bid / (HGM * tiles_n);
+    const int first_m = group * HGM;
+    const int gsz = min(tiles_m - first_m, HGM);
+    const int inb = bid - group * HGM * tiles_n;
+    mi = first_m + inb % gsz;
+    n0 = (inb / gsz) * HBM_;
+  }
+}
+
+// Direct-to-LDS variant (the default for npad >= 1024). Same 256 x 256 tile and
+// 4 waves x (4 x 4) MFMA 32x32x32 blocks, but operands move from global memory
+// straight into a 4-stage LDS ring (global_load_lds_dwordx4: 64 lanes x 16 bytes
+// land contiguously, 16 rows of 64 bytes per instruction), three K-stages ahead
+// of the matrix cores, with no register staging. Within a 64-byte row the 16-byte
+// chunk c is stored at chunk position c ^ ((row >> 2) & 3), which makes the
+// fragment reads (16 consecutive rows, one chunk) hit 16 distinct bank groups.
+constexpr int DBK = 64, DSTAGES = 4, DSTAGE_BYTES = 2 * 256 * DBK;
+
+// Wait until at most N vector-memory operations of this wave are outstanding,
+// then barrier; the memory clobber keeps LDS reads on their side of it.
+// Also waits for this wave's LDS reads, so no wave still reads a slot that the
+// DMA issued after the barrier overwrites.
+template <int N>
+__device__ __forceinline__ void wait_vm_lds_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restrict__ Lp,
+                                                           const int8_t *__restrict__ Rp,
+                                                           size_t pstride, int npad, int kl,
+                                                           int kr, int d_min, DiagOrder order,
+                                                           int32_t *__restrict__ C, RowBlocks rb) {
+  __shared__ __attribute__((aligned(1024))) int8_t ring[DSTAGES * DSTAGE_BYTES];
   const int tiles_n = npad / HBM_;
-  const int G = gridDim.x;
-  int b = blockIdx.x;
-  if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
-  const int group = b / (HGM * tiles_n);
-  const int first_m = group * HGM;
-  const int gsz = min(tiles_n - first_m, HGM);
-  const int inb = b - group * HGM * tiles_n;
-  const int m0 = (first_m + inb % gsz) * HBM_;
-  const int n0 = (inb / gsz) * HBM_;
+  int mi, n0;
+  tile_of_block(blockIdx.x, rb.count, tiles_n, mi, n0);
+  const int m0 = rb.m[mi] * HBM_;
   const int slot = order.q[blockIdx.y];
   const int d = d_min + slot;
   const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
   const int npairs = s_hi - s_lo + 1;
-  const int KT = npad / HBK;
+  const int KT = npad / DBK;
   const int T = npairs * KT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -374,66 +408,67 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256(const int8_t *__restri
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][c][v] = 0;
 
-  // global -> register staging: 256 rows x 128 bytes per operand = 2048 chunks
-  // of 16 bytes, 8 per thread; 8 consecutive threads read one 128-byte row.
-  v4i gL[8], gR[8];
-  auto load = [&](int tt) {
-    const int p = tt / KT, k0 = (tt - p * KT) * HBK;
+  // this lane's share of a stage: wave w fills rows [64w, 64w + 64) of both
+  // operands, 16 rows per instruction; lane -> row 16i + lane/4, position lane%4
+  const int lrow = lane >> 2, lpos = lane & 3;
+  auto issue = [&](int tt) {
+    const int p = tt / KT, k0 = (tt - p * KT) * DBK;
     const int s = s_lo + p;
     const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + (size_t)m0 * npad + k0;
     const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + (size_t)n0 * npad + k0;
+    int8_t *st = ring + (tt % DSTAGES) * DSTAGE_BYTES;
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
-      gL[h] = *(const v4i *)(Lb + (size_t)row * npad + col);
-      gR[h] = *(const v4i *)(Rb + (size_t)row * npad + col);
+    for (int i = 0; i < 4; ++i) {
+      const int row = wave * 64 + i * 16 + lrow;
+      const int chunk = lpos ^ ((row >> 2) & 3);
+      __builtin_amdgcn_global_load_lds((const void *)(Lb + (size_t)row * npad + chunk * 16),
+                                       (void __attribute__((address_space(3))) *)(st + (wave * 64 + i * 16) * DBK),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(Rb + (size_t)row * npad + chunk * 16),
+                                       (void __attribute__((address_space(3))) *)(st + 256 * DBK + (wave * 64 + i * 16) * DBK),
+                                       16, 0, 0);
     }
   };
-  auto stash = [&](int buf) {
+  // fragment offsets (before the stage base): row r, 16-byte chunk c -> r*64 + 16*(c ^ ((r>>2)&3))
+  int fa_row[4], fb_row[4];
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
-      *(v4i *)(&sL[buf][row * HLDS + col]) = gL[h];
-      *(v4i *)(&sR[buf][row * HLDS + col]) = gR[h];
-    }
-  };
-  if (T > 0) {
-    load(0);
-    stash(0);
-    if (T > 1) load(1);
+  for (int x = 0; x < 4; ++x) {
+    fa_row[x] = wm * 128 + x * 32 + (lane & 31);
+    fb_row[x] = wn * 128 + x * 32 + (lane & 31);
   }
-  // Fragment addresses: lane l reads 16 bytes of row (l mod 32) of each 32-row
-  // block at K offset 16 (l / 32) within the 32-byte MFMA step.
-  const int fa_off = (wm * 128 + (lane & 31)) * HLDS + 16 * (lane >> 5);
-  const int fb_off = (wn * 128 + (lane & 31)) * HLDS + 16 * (lane >> 5);
+  const int cgrp = lane >> 5;
+
+  for (int q = 0; q < DSTAGES - 1 && q < T; ++q) issue(q);
   for (int tt = 0; tt < T; ++tt) {
-    const int cur = tt & 1;
-    __syncthreads();                 // stage tt visible; buffer cur^1 no longer read
-    const int8_t *bL = sL[cur], *bR = sR[cur];
+    const int ahead = min(T - 1, tt + DSTAGES - 2) - tt;   // stages issued after tt
+    // stage tt complete for every wave; every wave's reads of stage tt-1's slot
+    // (which the DMA below refills) have returned
+    if (ahead >= 2) wait_vm_lds_barrier<16>();
+    else if (ahead == 1) wait_vm_lds_barrier<8>();
+    else wait_vm_lds_barrier<0>();
+    if (tt + DSTAGES - 1 < T) issue(tt + DSTAGES - 1);
+    const int8_t *sL = ring + (tt % DSTAGES) * DSTAGE_BYTES;
+    const int8_t *sR = sL + 256 * DBK;
     v4i fa[2][4], fb[2][4];
+    auto frags = [&](int ks) {
+      const int c = 2 * ks + cgrp;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      fa[0][x] = *(const v4i *)(bL + fa_off + x * 32 * HLDS);
-      fb[0][x] = *(const v4i *)(bR + fb_off + x * 32 * HLDS);
-    }
-#pragma unroll
-    for (int ks = 0; ks < HBK / 32; ++ks) {
-      const int c = ks & 1;
-      if (ks + 1 < HBK / 32) {       // next step's fragments, in flight during the MFMAs
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          fa[c ^ 1][x] = *(const v4i *)(bL + fa_off + x * 32 * HLDS + (ks + 1) * 32);
-          fb[c ^ 1][x] = *(const v4i *)(bR + fb_off + x * 32 * HLDS + (ks + 1) * 32);
-        }
+      for (int x = 0; x < 4; ++x) {
+        fa[ks][x] = *(const v4i *)(sL + fa_row[x] * DBK + 16 * (c ^ ((fa_row[x] >> 2) & 3)));
+        fb[ks][x] = *(const v4i *)(sR + fb_row[x] * DBK + 16 * (c ^ ((fb_row[x] >> 2) & 3)));
       }
-      if (ks == 1 && tt + 1 < T) stash(cur ^ 1);              // LDS writes of stage tt+1
-      if (ks == 2 && tt + 2 < T) load(tt + 2);                // global loads of stage tt+2
-      __builtin_amdgcn_sched_barrier(0);
+    };
+    frags(0);
+    __builtin_amdgcn_sched_barrier(0);
+    frags(1);                                  // in flight during the first 16 MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < DBK / 32; ++ks) {
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[c][x], fb[c][y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks][x], fb[ks][y], acc[x][y], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -451,7 +486,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256(const int8_t *__restri
 }
 
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
-                       int kr, int d_min, int ndiag, int32_t *C, hipStream_t s) {
+                       int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
+                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
   int cnt[kMaxDiag];
@@ -467,23 +503,34 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
       o.q[b] = o.q[b - 1];
       o.q[b - 1] = t;
     }
-  if (npad >= 1024) {
-    const int tiles = (npad / HBM_) * (npad / HBM_);
-    hipLaunchKernelGGL(k_slice_gemm256, dim3(tiles, ndiag), dim3(256), 0, s, Lp, Rp, pstride,
-                       npad, kl, kr, d_min, o, C);
+  const int tr = gemm_tile_rows(npad);
+  RowBlocks rb;
+  if (rbp) {
+    rb = *rbp;
   } else {
-    const int tiles = (npad / GBM) * (npad / GBN);
-    hipLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, Lp, Rp, pstride, npad,
-                       kl, kr, d_min, o, C);
+    rb.count = npad / tr;
+    for (int i = 0; i < rb.count; ++i) rb.m[i] = i;
   }
+  if (rb.count <= 0) return;
+  const int tiles = rb.count * (npad / tr);
+  if (npad >= 1024)
+    hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
+                          Lp, Rp, pstride,
+                       npad, kl, kr, d_min, o, C, rb);
+  else
+    hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
+                          Lp, Rp, pstride, npad,
+                       kl, kr, d_min, o, C, rb);
 }
+
+int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
 
 // ---------------------------------------------------------------- V epilogue + column pass
 template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
-    const int32_t *__restrict__ C, int npad, int d_min, int ndiag, const int *__restrict__ eA,
-    const int *__restrict__ eX, const double *__restrict__ X1, int n, double *lam, double *r,
-    int *eR, double *resmax, int8_t *__restrict__ Rpl, int kr, int *flags) {
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
+    double *lam, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl, int kr, int *flags) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -497,6 +544,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     return;
   }
   const int ej = eX[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad;
   const double *xcol = X1 + (size_t)j * n;
   double vh[EPT], vl[EPT];
@@ -572,29 +620,30 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
 }
 
 template <int EPT>
-static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *eA, const int *eX,
-                    const double *X1, int n, double *lam, double *r, int *eR, double *resmax,
-                    int8_t *Rpl, int kr, int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_v<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, eA,
-                     eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags);
+static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                    const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
+                    int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_epi_v<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
+                     eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags);
 }
 
-void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *eA, const int *eX,
-                  const double *X1, int n, double *lam, double *r, int *eR, double *resmax,
-                  int8_t *Rpl, int kr, int *flags, hipStream_t s) {
+void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
+                  int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else epi_v_t<8>(C, npad, d_min, ndiag, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
+  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
+  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
+  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
+  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
 }
 
 // ---------------------------------------------------------------- W epilogue -> E~
 template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
-    const int32_t *__restrict__ C, int npad, int d_min, int ndiag, const int *__restrict__ eX,
-    const int *__restrict__ eR, const double *__restrict__ lam, const double *__restrict__ r,
-    int n, int *eE, double *emax, int8_t *__restrict__ Epl, int ke, int *flags) {
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
+    const double *__restrict__ r, int n, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
+    int *flags) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -609,6 +658,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   }
   const int ej = eR[j];
   const double lj = lam[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad;
   double ev[EPT];
   double ms = 0.0, mr = 0.0;
@@ -668,26 +718,27 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 }
 
 template <int EPT>
-static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *eX, const int *eR,
-                    const double *lam, const double *r, int n, int *eE, double *emax,
-                    int8_t *Epl, int ke, int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, eX,
-                     eR, lam, r, n, eE, emax, Epl, ke, flags);
+static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                    const int *eX, const int *eR, const double *lam, const double *r, int n,
+                    int *eE, double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
+                     eX, eR, lam, r, n, eE, emax, Epl, ke, flags);
 }
 
-void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *eX, const int *eR,
-                  const double *lam, const double *r, int n, int *eE, double *emax,
-                  int8_t *Epl, int ke, int *flags, hipStream_t s) {
+void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
+                  double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
+  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
+  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
 }
 
 // ---------------------------------------------------------------- update X <- X1 + X1 E~
 __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, int npad, int d_min,
-                                               int ndiag, const int *__restrict__ eE,
+                                               int ndiag_all, const int *__restrict__ dcut,
+                                               const int *__restrict__ eE,
                                                const double *__restrict__ X1, int n,
                                                double *__restrict__ X, int ldx) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
@@ -695,16 +746,17 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
   const size_t P = (size_t)npad * npad;
   const int32_t *Ccol = C + (size_t)j * npad;
   const int ej = eE[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   double u = 0.0;
   for (int qq = ndiag - 1; qq >= 0; --qq)
     u += ldexp((double)Ccol[(size_t)qq * P + i], ej - 7 * (d_min + qq));
   X[(size_t)j * ldx + i] = X1[(size_t)j * n + i] + u;
 }
 
-void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *eE,
-                  const double *X1, int n, double *X, int ldx, hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_u, dim3((n + 255) / 256, n), dim3(256), 0, s, C, npad, d_min, ndiag, eE,
-                     X1, n, X, ldx);
+void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s) {
+  hipLaunchKernelGGL(k_epi_u, dim3((n + 255) / 256, n), dim3(256), 0, s, C, npad, d_min, ndiag, dcut,
+                     eE, X1, n, X, ldx);
 }
 
 }  // namespace refeig

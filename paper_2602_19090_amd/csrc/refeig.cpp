@@ -55,6 +55,7 @@ struct Work {
   int32_t *Cs;
   double *X1;
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
+  int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
   double *mxA, *mxX, *lam, *r, *resmax, *emax;
 };
 
@@ -88,6 +89,7 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.eR = (int *)take(vi);
   t.eE = (int *)take(vi);
   t.flags = (int *)take(256);
+  for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
   t.mxA = (double *)take(vd);
   t.mxX = (double *)take(vd);
   t.lam = (double *)take(vd);
@@ -143,6 +145,54 @@ int ka_of(const refeig_opts *o) {
 int npairs_of(int d, int kl, int kr) {
   int lo = std::max(1, d - kr), hi = std::min(kl, d - 1);
   return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// Per-column pair cutoffs -> per GEMM tile (max over its columns, the block
+// computes those diagonals anyway), expanded back to every column and uploaded
+// for the epilogues; tiles with equal cutoffs are grouped for one launch each.
+// *pairs_eff = kept slice products in units of one n x n x n product.
+struct CutPlan {
+  int dmax = 2;
+  double pairs_eff = 0.0;
+  std::vector<std::pair<int, RowBlocks>> groups;  // (last diagonal, row blocks)
+};
+bool plan_cutoffs(const std::vector<int> &dcol, int n, int npad, int kl, int kr, int dmax_allowed,
+                  int *dev, std::vector<int> &host, hipStream_t s, CutPlan &plan) {
+  const int tr = gemm_tile_rows(npad);
+  host.assign(npad, 2);
+  plan = CutPlan();
+  std::vector<int> dtile;
+  for (int t0 = 0; t0 < npad; t0 += tr) {
+    int dt = 2;
+    for (int j = t0; j < std::min(t0 + tr, n); ++j) dt = std::max(dt, dcol[j]);
+    dt = std::min(dt, dmax_allowed);
+    for (int j = t0; j < t0 + tr; ++j) host[j] = dt;
+    dtile.push_back(dt);
+    plan.dmax = std::max(plan.dmax, dt);
+    int pr = 0;
+    for (int d = 2; d <= dt; ++d) pr += npairs_of(d, kl, kr);
+    plan.pairs_eff += pr * (double)tr / npad;
+  }
+  for (int dv = plan.dmax; dv >= 2; --dv) {
+    RowBlocks rb;
+    rb.count = 0;
+    for (int t = 0; t < (int)dtile.size(); ++t)
+      if (dtile[t] == dv) rb.m[rb.count++] = t;
+    if (rb.count) plan.groups.emplace_back(dv, rb);
+  }
+  return hipMemcpyAsync(dev, host.data(), sizeof(int) * npad, hipMemcpyHostToDevice, s) ==
+         hipSuccess;
+}
+
+// One launch per group; ev_start is taken by the first dispatch, ev_stop by the last.
+void launch_plan(const CutPlan &plan, const int8_t *Lp, const int8_t *Rp, size_t P, int npad,
+                 int kl, int kr, int32_t *C, hipStream_t s, hipEvent_t ev_start,
+                 hipEvent_t ev_stop) {
+  const size_t ng = plan.groups.size();
+  for (size_t q = 0; q < ng; ++q)
+    launch_slice_gemm(Lp, Rp, P, npad, kl, kr, 2, plan.groups[q].first - 1, C,
+                      &plan.groups[q].second, s, q == 0 ? ev_start : nullptr,
+                      q + 1 == ng ? ev_stop : nullptr);
 }
 
 // beta of Sec. 4.1 (floor form): beta = floor(log2((1/(0.75u)) sqrt(xi delta g / (L S)))),
@@ -357,6 +407,9 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
       rep->pairs_p[it][0] = pv;
       rep->pairs_p[it][1] = 1;
       rep->pairs_p[it][2] = 1;
+      rep->pairs_f[it][0] = pv;
+      rep->pairs_f[it][1] = 1;
+      rep->pairs_f[it][2] = 1;
       rep->ms_p[it][0] = tv;
       rep->eps[it] = eps;
       rep->ms_iter[it] = t_it;
@@ -461,7 +514,7 @@ int refeig_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, i
       return REFEIG_E_ARG;
   if (plane_stride < (size_t)npad * npad) return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  launch_slice_gemm(Lp, Rp, plane_stride, npad, kl, kr, d_min, ndiag, C, s);
+  launch_slice_gemm(Lp, Rp, plane_stride, npad, kl, kr, d_min, ndiag, C, nullptr, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return REFEIG_OK;
@@ -572,29 +625,28 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx);
     // ---- X^(1) and its planes (both layouts)
     launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s);
-    // ---- V = A X^(1): keep pair diagonals d <= dv
+    // ---- V = A X^(1): per column j keep pair diagonals d <= dv(j)
     int eXmax = -100000;
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
-    int dv = 2;
+    std::vector<int> dcol(npad, 2), dhost;
     {
       const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lsqn;
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
         double need = (c0 + eX[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
-        dv = std::max(dv, (int)std::ceil(need));
+        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
-      dv += o.d_extra;
-      dv = std::min(dv, std::min(ka_max + 1, kx + ka_max));
     }
-    const int ka = std::min(ka_max, dv - 1);
-    int pairs = 0, pv = 0, pw = 0, pu = 0;
-    for (int d = 2; d <= dv; ++d) pv += npairs_of(d, kx, ka);
-    pairs += pv;
-    STEP(hipEventRecord(ev[1], s));
-    launch_slice_gemm(w.XP, w.AP, P, npad, kx, ka, 2, dv - 1, w.Cs, s);
-    STEP(hipEventRecord(ev[2], s));
-    launch_epi_v(w.Cs, npad, 2, dv - 1, w.eA, w.eX, w.X1, n, w.lam, w.r, w.eR, w.resmax, w.RP,
-                 kKrMax, w.flags, s);
+    const int dv_allowed = std::min(ka_max + 1, kx + ka_max);
+    const int ka = ka_max;
+    CutPlan plan;
+    if (!plan_cutoffs(dcol, n, npad, kx, ka, dv_allowed, w.dcut[0], dhost, s, plan))
+      return cleanup(REFEIG_E_HIP);
+    const int dv = plan.dmax;
+    const double pv = plan.pairs_eff;
+    launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
+    launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.r, w.eR, w.resmax,
+                 w.RP, kKrMax, w.flags, s);
     STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -604,26 +656,24 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     // ---- W = X^(1)T Res -> E~
     column_gaps(lam, gaps, &gmin, &lmax);
     if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
-    int dw = 2;
     {
       const double c0 = eXmax + 7 + std::log2(1.5 * kx) + lsqn;
+      std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (resmax[j] == 0.0) continue;
         double need = (c0 + eR[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
-        dw = std::max(dw, (int)std::ceil(need));
+        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
-      dw += o.d_extra;
-      dw = std::min(dw, kKrMax + 1);
     }
-    const int kR = std::min(kKrMax, dw - 1), kxw = std::min(kx, dw - 1);
-    dw = std::min(dw, kR + kxw);
-    for (int d = 2; d <= dw; ++d) pw += npairs_of(d, kR, kxw);
-    pairs += pw;
-    STEP(hipEventRecord(ev[3], s));
-    launch_slice_gemm(w.RP, w.XP, P, npad, kR, kxw, 2, dw - 1, w.Cs, s);
-    STEP(hipEventRecord(ev[4], s));
-    launch_epi_w(w.Cs, npad, 2, dw - 1, w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP, kKeMax,
-                 w.flags, s);
+    const int kR = kKrMax, kxw = kx;
+    if (!plan_cutoffs(dcol, n, npad, kR, kxw, std::min(kKrMax + 1, kR + kxw), w.dcut[1], dhost, s,
+                      plan))
+      return cleanup(REFEIG_E_HIP);
+    const int dw = plan.dmax;
+    const double pw = plan.pairs_eff;
+    launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
+    launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP,
+                 kKeMax, w.flags, s);
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -633,25 +683,22 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     double eps = 0.0;
     for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
     // ---- X <- X^(1) + X^(1) E~
-    int du = 2;
     {
       const double c0 = 7 + std::log2(1.008 * kx) + lsqn - std::log2(theta * delta_int);
+      std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (emax[j] == 0.0) continue;
-        double need = (c0 + eE[j]) / 7.0;
-        du = std::max(du, (int)std::ceil(need));
+        dcol[j] = std::max(2, (int)std::ceil((c0 + eE[j]) / 7.0) + o.d_extra);
       }
-      du += o.d_extra;
-      du = std::min(du, kKeMax + 1);
     }
-    const int kE = std::min(kKeMax, du - 1), kxu = std::min(kx, du - 1);
-    du = std::min(du, kE + kxu);
-    for (int d = 2; d <= du; ++d) pu += npairs_of(d, kE, kxu);
-    pairs += pu;
-    STEP(hipEventRecord(ev[5], s));
-    launch_slice_gemm(w.EP, w.XPT, P, npad, kE, kxu, 2, du - 1, w.Cs, s);
-    STEP(hipEventRecord(ev[6], s));
-    launch_epi_u(w.Cs, npad, 2, du - 1, w.eE, w.X1, n, X, ldx, s);
+    const int kE = kKeMax, kxu = kx;
+    if (!plan_cutoffs(dcol, n, npad, kE, kxu, std::min(kKeMax + 1, kE + kxu), w.dcut[2], dhost, s,
+                      plan))
+      return cleanup(REFEIG_E_HIP);
+    const int du = plan.dmax;
+    const double pu = plan.pairs_eff;
+    launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6]);
+    launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s);
     STEP(hipMemcpyAsync(D, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     STEP(hipEventRecord(ev[7], s));
     STEP(hipGetLastError());
@@ -667,13 +714,16 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->dv[it] = dv;
       rep->dw[it] = dw;
       rep->du[it] = du;
-      rep->pairs[it] = pairs;
+      rep->pairs[it] = (int)std::lround(pv + pw + pu);
       rep->eps[it] = eps;
       rep->ms_iter[it] = t_it;
       rep->ms_gemm[it] = g1 + g2 + g3;
-      rep->pairs_p[it][0] = pv;
-      rep->pairs_p[it][1] = pw;
-      rep->pairs_p[it][2] = pu;
+      rep->pairs_p[it][0] = (int)std::lround(pv);
+      rep->pairs_p[it][1] = (int)std::lround(pw);
+      rep->pairs_p[it][2] = (int)std::lround(pu);
+      rep->pairs_f[it][0] = pv;
+      rep->pairs_f[it][1] = pw;
+      rep->pairs_f[it][2] = pu;
       rep->ms_p[it][0] = g1;
       rep->ms_p[it][1] = g2;
       rep->ms_p[it][2] = g3;
@@ -685,7 +735,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       fprintf(stderr,
               "refeig it %d: beta %d kx %d dv %d dw %d du %d pairs %d eps %.3e gap %.3e "
               "ms %.2f (gemm %.2f)\n",
-              it + 1, beta, kx, dv, dw, du, pairs, eps, gmin, t_it, g1 + g2 + g3);
+              it + 1, beta, kx, dv, dw, du, (int)std::lround(pv + pw + pu), eps, gmin, t_it,
+              g1 + g2 + g3);
     lam_prev = lam;
     if (o.fixed_iters > 0) continue;
     // The correction eps = max|E~| estimates the error of X^(1) (Sec. 3.2: X = X^(1)(I + E)),

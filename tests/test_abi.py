@@ -49,3 +49,32 @@ def test_host_only_entry_points(lib):
     assert 8e9 < b < 16e9
     with pytest.raises(ValueError):
         rb.workspace_bytes(0)
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, from a C program that gcc builds."""
+    import subprocess
+    import tempfile
+    lines = [f'printf("%zu\\n", sizeof({struct}));']
+    lines += [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"refeig.h\"\nint main(void) {\n"
+           + "\n".join(lines) + "\nreturn 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("cname,pyname", [("refeig_opts", "Opts"), ("refeig_report", "Report")])
+def test_binding_struct_layout_matches_header(lib, cname, pyname):
+    """Every ctypes field sits at the offset the C compiler gives it in the header."""
+    from paper_2602_19090_amd import binding as rb
+    py = getattr(rb, pyname)
+    fields = [f for f, _ in py._fields_]
+    size, offs = _c_layout(cname, fields)
+    assert ctypes.sizeof(py) == size
+    for f, off in zip(fields, offs):
+        assert getattr(py, f).offset == off, f

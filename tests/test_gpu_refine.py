@@ -60,7 +60,8 @@ def test_one_step_vs_oracle(cfg, n, target):
           f"|X_gpu - X_oracle|max={diff:.3e}", flush=True)
     assert diff <= target / opts.delta_safety
     lam = D.cpu().numpy()
-    assert float(np.max(np.abs(lam - ref.lam_h))) <= 1e-15 * float(np.max(np.abs(ref.lam_h)))
+    assert float(np.max(np.abs(lam - ref.lam_h))) <= (target / opts.delta_safety) * float(
+        np.max(np.abs(ref.lam_h)))
 
 
 @pytest.mark.parametrize("cfg,n,x0,target", [
@@ -81,7 +82,9 @@ def test_refine_to_target(cfg, n, x0, target):
     assert st == rb.REFEIG_OK, rb.strerror(st)
     assert err <= target
     lam = D.cpu().numpy()
-    assert float(np.max(np.abs(lam - lt))) <= 1e-15 * float(np.max(np.abs(lt)))
+    # eigenvalues to the prescribed accuracy: the Rayleigh quotients come from the
+    # truncated V, whose per-column error the cutoffs keep below target * gap
+    assert float(np.max(np.abs(lam - lt))) <= target * float(np.max(np.abs(lt)))
 
 
 def test_fp32_jacobi_start():
@@ -167,3 +170,42 @@ def test_caller_workspace_and_determinism():
         assert st == rb.REFEIG_OK
         outs.append((X.cpu().numpy(), D.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def _golden(cfg, n):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"xtrue_cfg{cfg}_n{n}.npz")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.mark.parametrize("cfg,n", [(2, 4096), (3, 8192)])
+def test_full_size_against_oracle_columns(cfg, n):
+    """Full-size solves (the benchmark's workload at n = 8192) from an FP64 eigensolve start,
+    checked on the sampled columns of the oracle's X_true (tests/golden/make_xtrue.py) and on
+    every eigenvalue."""
+    import torch
+    rb = _rb()
+    print(f"full size cfg={cfg} n={n}", flush=True)
+    g = _golden(cfg, n)
+    p = workloads.make_problem(cfg, n, x0="none")
+    assert p.meta["digest"] == str(g["digest"]), "generator output differs from the stored matrix"
+    A = rb.colmajor(p.A)
+    w, V = torch.linalg.eigh(A)
+    X = V.t().contiguous()
+    D = w.contiguous()
+    del V
+    target = 1e-14
+    st, rep = rb.refine_eigvecs(A, X, D, target)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    cols = torch.from_numpy(g["cols"]).cuda()
+    Xs = X[cols].cpu().numpy().T
+    Xt = g["X_hi"]
+    s = np.sign(np.sum(Xs * Xt, axis=0))
+    err = float(np.max(np.abs(Xs - Xt * s)))
+    lam_err = float(np.max(np.abs(D.cpu().numpy() - g["lam_hi"])))
+    print(f"  iters {rep.iters} eps {list(rep.eps[:rep.iters])} sampled fwd err {err:.3e} "
+          f"eigenvalue err {lam_err:.3e}", flush=True)
+    assert err <= target
+    assert lam_err <= target * float(np.max(np.abs(g["lam_hi"])))
+    del A, X, D
+    torch.cuda.empty_cache()
