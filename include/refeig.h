@@ -123,8 +123,10 @@ const char *refeig_strerror(int status);
  * 0 for a zero column. planes (device, k * cols_pad * rows_pad bytes, where
  * rows_pad and cols_pad are rows and cols rounded up to 256): digit r (1..k)
  * of M_ij, sign(M_ij) * (floor(|M_ij| 2^(7r - e_j)) mod 128), at
- * planes[(r-1) * cols_pad * rows_pad + j * rows_pad + i]; zero for i >= rows
- * or j >= cols. Errors: REFEIG_E_ARG (sizes, k outside 1..18),
+ * planes[(r-1) * cols_pad * rows_pad + ((i / 64) * cols_pad + j) * 64 + i % 64]
+ * (the K-blocked form: a plane is an operand with cols_pad rows j, each of
+ * rows_pad entries i, cut into 64-entry blocks stored block by block); zero for
+ * i >= rows or j >= cols. Errors: REFEIG_E_ARG (sizes, k outside 1..18),
  * REFEIG_E_NONFINITE (NaN/Inf in M), REFEIG_E_RANGE (e_j outside [-400, 400]).
  * trunc (device, may be NULL, ld rows): the value of the k digits.
  * This is the integer form of the error-free splitting of Sec. 2.3 (eq. a/x). */
@@ -133,7 +135,8 @@ int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *e
 
 /* Exact per-diagonal slice products: for q = 0..ndiag-1 and d = d_min + q,
  *   C[q][m][p] = sum_{s + t = d, 1<=s<=kl, 1<=t<=kr} sum_k L_s[m][k] * R_t[p][k]
- * with L_s at Lp + (s-1)*plane_stride + m*npad + k, R_t likewise, and
+ * with L_s[m][k] at Lp + (s-1)*plane_stride + ((k / 64) * npad + m) * 64 + k % 64
+ * (K-blocked, as refeig_split_cols writes), R_t likewise, and
  * C[q][m][p] at C + q*npad*npad + m*npad + p (int32, device). npad must be a
  * multiple of 256 and the planes zero-padded. The pairs of one diagonal must
  * satisfy pairs * npad * 127^2 < 2^31 (exact INT32 accumulation).  */

@@ -139,8 +139,23 @@ def refine_eigvecs(A, X, D, target: float, opts: Opts | None = None, work=None, 
     return st, rep
 
 
+def rows_to_kblocked(P):
+    """Planes (k, R, K), row m holding its K entries in order, rearranged into the
+    K-blocked memory order the kernels use (same shape): element (m, kk) of a plane
+    at ((kk // 64) * R + m) * 64 + kk % 64."""
+    k, R, K = P.shape
+    return P.reshape(k, R, K // 64, 64).permute(0, 2, 1, 3).contiguous().view(k, R, K)
+
+
+def kblocked_to_rows(P):
+    """Inverse of rows_to_kblocked (a view where possible)."""
+    k, R, K = P.shape
+    return P.reshape(k, K // 64, R, 64).permute(0, 2, 1, 3).reshape(k, R, K)
+
+
 def split_cols(M, rows: int, cols: int, k: int, want_trunc=True, stream=None):
-    """Debug entry point refeig_split_cols on a column-major tensor M (cols, rows)."""
+    """Debug entry point refeig_split_cols on a column-major tensor M (cols, rows).
+    The planes come back K-blocked, shape (k, cols_pad, rows_pad)."""
     import torch
     rpad, cpad = -(-rows // 256) * 256, -(-cols // 256) * 256
     exps = torch.empty(cols, dtype=torch.int32, device=M.device)
@@ -152,7 +167,8 @@ def split_cols(M, rows: int, cols: int, k: int, want_trunc=True, stream=None):
 
 
 def slice_gemm(Lp, Rp, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stream=None):
-    """Debug entry point refeig_slice_gemm. Lp: (kl, npad, npad) int8, Rp: (kr, npad, npad)."""
+    """Debug entry point refeig_slice_gemm. Lp: (kl, npad, npad) int8, Rp: (kr, npad, npad),
+    both K-blocked (see rows_to_kblocked)."""
     import torch
     assert Lp.stride(0) == Rp.stride(0) == npad * npad
     C = torch.empty((ndiag, npad, npad), dtype=torch.int32, device=Lp.device)

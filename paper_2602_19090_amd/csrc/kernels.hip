@@ -1,8 +1,12 @@
 // gfx950 (MI355X) kernels for Ozaki-scheme eigenvector refinement.
 //
 // Data layout (npad = n rounded up to 256, P = npad * npad):
-//   digit planes   int8, plane-major; in plane t, element (row m, k) at m*npad + k
-//                  so every GEMM operand row is K-contiguous (the "TN" form).
+//   digit planes   int8, plane-major. A plane holds a GEMM operand of R rows
+//                  (row m, reduction index k) K-blocked: K is cut into 64-byte
+//                  blocks and block b stores its 64 bytes of every row in turn,
+//                  element (m, k) at ((k >> 6) * R + m) * 64 + (k & 63). The
+//                  64-byte K-slice of 256 consecutive rows that one GEMM stage
+//                  needs is then one contiguous 16 KB run (full cache lines).
 //   slot C_d       int32 n x n per pair diagonal d, element (i, j) at j*npad + i,
 //                  i.e. column-major, so the column epilogues read columns
 //                  contiguously.
@@ -14,11 +18,17 @@
 #include <hip/hip_ext.h>
 
 #include <float.h>
+#include <type_traits>
 
 namespace refeig {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Offset of element (row m, reduction index k) in a K-blocked plane of `rows` rows.
+__device__ __forceinline__ size_t kb_off(int m, int k, int rows) {
+  return ((size_t)(k >> 6) * rows + m) * 64 + (k & 63);
+}
 
 // ---------------------------------------------------------------- scalar helpers
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
@@ -218,14 +228,14 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
 #pragma unroll
     for (int t = 0; t < kMaxPlanesSplit; ++t)
       if (t < k)
-        *(unsigned *)(planes + (size_t)t * pstride + (size_t)j * rpad + i0 + 4 * ig) = packed[t];
+        *(unsigned *)(planes + (size_t)t * pstride + kb_off(j, i0 + 4 * ig, cpad)) = packed[t];
   }
   if (WITH_T) {
     __syncthreads();
     const int ii = threadIdx.x >> 2, jq = (threadIdx.x & 3) * 16;
     for (int t = 0; t < kT; ++t) {
       v4i w = *(const v4i *)(sT + (t * 64 + ii) * kTStride + jq);
-      *(v4i *)(planesT + (size_t)t * pstrideT + (size_t)(i0 + ii) * cpad + j0 + jq) = w;
+      *(v4i *)(planesT + (size_t)t * pstrideT + kb_off(i0 + ii, j0 + jq, rpad)) = w;
     }
   }
 }
@@ -281,13 +291,13 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
   auto load = [&](int t) {
     const int p = t / KT, k0 = (t - p * KT) * GBK;
     const int s = s_lo + p;
-    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + (size_t)m0 * npad + k0;
-    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + (size_t)n0 * npad + k0;
+    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride;
+    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
-      gL[h] = *(const v4i *)(Lb + (size_t)row * npad + col);
-      gR[h] = *(const v4i *)(Rb + (size_t)row * npad + col);
+      gL[h] = *(const v4i *)(Lb + kb_off(m0 + row, k0 + col, npad));
+      gR[h] = *(const v4i *)(Rb + kb_off(n0 + row, k0 + col, npad));
     }
   };
   if (npairs > 0) load(0);
@@ -363,13 +373,17 @@ __device__ __forceinline__ void tile_of_block(int bid, int tiles_m, int tiles_n,
   }
 }
 
-// Direct-to-LDS variant (the default for npad >= 1024). Same 256 x 256 tile and
-// 4 waves x (4 x 4) MFMA 32x32x32 blocks, but operands move from global memory
-// straight into a 4-stage LDS ring (global_load_lds_dwordx4: 64 lanes x 16 bytes
-// land contiguously, 16 rows of 64 bytes per instruction), three K-stages ahead
-// of the matrix cores, with no register staging. Within a 64-byte row the 16-byte
-// chunk c is stored at chunk position c ^ ((row >> 2) & 3), which makes the
-// fragment reads (16 consecutive rows, one chunk) hit 16 distinct bank groups.
+// 256 x 256 tile kernel (npad >= 1024). 4 waves in a 2 x 2 arrangement, each
+// 128 x 128 = 4 x 4 MFMA 32x32x32 blocks held in AGPRs. Operands move from
+// global memory straight into a 4-stage LDS ring (global_load_lds_dwordx4:
+// 64 lanes x 16 bytes land contiguously, 16 rows of 64 bytes per instruction);
+// with K-blocked planes each instruction reads one contiguous kilobyte. Within a
+// 64-byte row the 16-byte chunk c sits at chunk position c ^ ((row >> 2) & 3),
+// so a fragment read (16 consecutive rows, one chunk) hits 16 distinct bank
+// groups. Software pipeline: while the 32 MFMAs of stage t run from registers,
+// the wave reads the fragments of stage t+1 from LDS into a second register set
+// and issues the DMA of stage t+3, so the matrix cores are not left idle
+// between stages; one barrier per stage.
 constexpr int DBK = 64, DSTAGES = 4, DSTAGE_BYTES = 2 * 256 * DBK;
 
 // Wait until at most N vector-memory operations of this wave are outstanding,
@@ -386,7 +400,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
                                                            size_t pstride, int npad, int kl,
                                                            int kr, int d_min, DiagOrder order,
                                                            int32_t *__restrict__ C, RowBlocks rb) {
-  __shared__ __attribute__((aligned(1024))) int8_t ring[DSTAGES * DSTAGE_BYTES];
+  constexpr int S = DSTAGES;
+  __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
   const int tiles_n = npad / HBM_;
   int mi, n0;
   tile_of_block(blockIdx.x, rb.count, tiles_n, mi, n0);
@@ -396,7 +411,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
   const int npairs = s_hi - s_lo + 1;
   const int KT = npad / DBK;
-  const int T = npairs * KT;
+  const int T = npairs * KT;   // K-stages over all pairs of this diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -414,63 +429,103 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   auto issue = [&](int tt) {
     const int p = tt / KT, k0 = (tt - p * KT) * DBK;
     const int s = s_lo + p;
-    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + (size_t)m0 * npad + k0;
-    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + (size_t)n0 * npad + k0;
-    int8_t *st = ring + (tt % DSTAGES) * DSTAGE_BYTES;
+    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + kb_off(m0, k0, npad);
+    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + kb_off(n0, k0, npad);
+    int8_t *st = ring + (tt % S) * DSTAGE_BYTES;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wave * 64 + i * 16 + lrow;
       const int chunk = lpos ^ ((row >> 2) & 3);
-      __builtin_amdgcn_global_load_lds((const void *)(Lb + (size_t)row * npad + chunk * 16),
+      __builtin_amdgcn_global_load_lds((const void *)(Lb + row * 64 + chunk * 16),
                                        (void __attribute__((address_space(3))) *)(st + (wave * 64 + i * 16) * DBK),
                                        16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void *)(Rb + (size_t)row * npad + chunk * 16),
+      __builtin_amdgcn_global_load_lds((const void *)(Rb + row * 64 + chunk * 16),
                                        (void __attribute__((address_space(3))) *)(st + 256 * DBK + (wave * 64 + i * 16) * DBK),
                                        16, 0, 0);
     }
   };
-  // fragment offsets (before the stage base): row r, 16-byte chunk c -> r*64 + 16*(c ^ ((r>>2)&3))
-  int fa_row[4], fb_row[4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    fa_row[x] = wm * 128 + x * 32 + (lane & 31);
-    fb_row[x] = wn * 128 + x * 32 + (lane & 31);
-  }
+  // fragment offsets within a stage: row r, 16-byte chunk c -> r*64 + 16*(c ^ ((r>>2)&3))
+  int fa_off[2][4], fb_off[2][4];
   const int cgrp = lane >> 5;
-
-  for (int q = 0; q < DSTAGES - 1 && q < T; ++q) issue(q);
-  for (int tt = 0; tt < T; ++tt) {
-    const int ahead = min(T - 1, tt + DSTAGES - 2) - tt;   // stages issued after tt
-    // stage tt complete for every wave; every wave's reads of stage tt-1's slot
-    // (which the DMA below refills) have returned
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int ra = wm * 128 + x * 32 + (lane & 31), rbr = wn * 128 + x * 32 + (lane & 31);
+      const int c = 2 * ks + cgrp;
+      fa_off[ks][x] = ra * DBK + 16 * (c ^ ((ra >> 2) & 3));
+      fb_off[ks][x] = 256 * DBK + rbr * DBK + 16 * (c ^ ((rbr >> 2) & 3));
+    }
+  v4i fA[2][2][4], fB[2][2][4];   // [register set][k half][block]
+  auto load_frags = [&](int tt, v4i (&fa)[2][4], v4i (&fb)[2][4]) {
+    const int8_t *sb = ring + (tt % S) * DSTAGE_BYTES;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        fa[ks][x] = *(const v4i *)(sb + fa_off[ks][x]);
+        fb[ks][x] = *(const v4i *)(sb + fb_off[ks][x]);
+      }
+  };
+  // Wait until stage `need` has landed for every wave, given that stages up to
+  // `last` have been issued (8 DMA instructions per stage and wave), then barrier.
+  auto wait_stage = [&](int need, int last) {
+    const int ahead = last - need;
     if (ahead >= 2) wait_vm_lds_barrier<16>();
     else if (ahead == 1) wait_vm_lds_barrier<8>();
     else wait_vm_lds_barrier<0>();
-    if (tt + DSTAGES - 1 < T) issue(tt + DSTAGES - 1);
-    const int8_t *sL = ring + (tt % DSTAGES) * DSTAGE_BYTES;
-    const int8_t *sR = sL + 256 * DBK;
-    v4i fa[2][4], fb[2][4];
-    auto frags = [&](int ks) {
-      const int c = 2 * ks + cgrp;
+  };
+  // prologue: stages 0..S-2 in flight, stage 0 landed, its fragments in set 0
+  for (int q = 0; q < S - 1 && q < T; ++q) issue(q);
+  wait_stage(0, min(T - 1, S - 2));
+  load_frags(0, fA[0], fB[0]);
+
+  // One stage: wait for stage tt+1 (which also guarantees that every wave has
+  // read stage tt-1 from the slot the new DMA refills), issue the DMA of stage
+  // tt+S-1, read stage tt+1 into the other register set, and run the MFMAs of
+  // stage tt. Steady stages (tt+S-1 < T) are branch-free so the scheduler can
+  // interleave the three instruction streams.
+  auto stage = [&](auto steady, int tt, v4i (&ca)[2][4], v4i (&cb)[2][4], v4i (&na)[2][4],
+                   v4i (&nb)[2][4]) {
+    if constexpr (decltype(steady)::value) {
+      wait_vm_lds_barrier<8 * (S - 3)>();
+      issue(tt + S - 1);
+      load_frags(tt + 1, na, nb);
+    } else if (tt + 1 < T) {
+      wait_stage(tt + 1, min(T - 1, tt + S - 2));
+      if (tt + S - 1 < T) issue(tt + S - 1);
+      load_frags(tt + 1, na, nb);
+    }
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        fa[ks][x] = *(const v4i *)(sL + fa_row[x] * DBK + 16 * (c ^ ((fa_row[x] >> 2) & 3)));
-        fb[ks][x] = *(const v4i *)(sR + fb_row[x] * DBK + 16 * (c ^ ((fb_row[x] >> 2) & 3)));
-      }
-    };
-    frags(0);
-    __builtin_amdgcn_sched_barrier(0);
-    frags(1);                                  // in flight during the first 16 MFMAs
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int ks = 0; ks < DBK / 32; ++ks) {
+    for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks][x], fb[ks][y], acc[x][y], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
+          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[ks][x], cb[ks][y], acc[x][y], 0, 0, 0);
+    if constexpr (decltype(steady)::value) {
+      // per 4 MFMAs: one DMA instruction and two fragment reads
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  using Steady = std::integral_constant<bool, true>;
+  using Tail = std::integral_constant<bool, false>;
+  const int t_steady = T - S + 1;   // stages tt < t_steady are steady
+  int tt = 0;
+  for (; tt + 1 < t_steady; tt += 2) {
+    stage(Steady(), tt, fA[0], fB[0], fA[1], fB[1]);
+    stage(Steady(), tt + 1, fA[1], fB[1], fA[0], fB[0]);
+  }
+  for (; tt < T; tt += 2) {   // tt is even here, so register set 0 holds stage tt
+    stage(Tail(), tt, fA[0], fB[0], fA[1], fB[1]);
+    if (tt + 1 < T) stage(Tail(), tt + 1, fA[1], fB[1], fA[0], fB[0]);
   }
   int32_t *Cq = C + (size_t)slot * npad * npad;
 #pragma unroll
@@ -534,12 +589,11 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
-  int8_t *Rcol = Rpl + (size_t)j * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
       const int i = tid + kEpiThreads * q;
       if (i < npad)
-        for (int t = 0; t < kr; ++t) Rcol[t * P + i] = 0;
+        for (int t = 0; t < kr; ++t) Rpl[t * P + kb_off(j, i, npad)] = 0;
     }
     return;
   }
@@ -606,7 +660,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
         double t128 = y * 128.0;
         double dgt = floor(t128);
         y = t128 - dgt;
-        Rcol[t * P + i] = (int8_t)(sg * (int)dgt);
+        Rpl[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
       }
     }
   }
@@ -647,12 +701,11 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
-  int8_t *Ecol = Epl + (size_t)j * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
       const int i = tid + kEpiThreads * q;
       if (i < npad)
-        for (int t = 0; t < ke; ++t) Ecol[t * P + i] = 0;
+        for (int t = 0; t < ke; ++t) Epl[t * P + kb_off(j, i, npad)] = 0;
     }
     return;
   }
@@ -706,7 +759,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
         double t128 = y * 128.0;
         double dgt = floor(t128);
         y = t128 - dgt;
-        Ecol[t * P + i] = (int8_t)(sg * (int)dgt);
+        Epl[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
       }
     }
   }

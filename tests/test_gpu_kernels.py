@@ -48,7 +48,7 @@ def test_split_bitexact(rows, cols, k):
     assert st == 0, rb.strerror(st)
     e_o, pl_o, tr_o = oracle.split_s7(M, k)
     np.testing.assert_array_equal(e.cpu().numpy(), e_o)
-    P = pl.cpu().numpy()
+    P = rb.kblocked_to_rows(pl).cpu().numpy()
     np.testing.assert_array_equal(P[:, :cols, :rows], pl_o)
     assert not P[:, cols:, :].any() and not P[:, :, rows:].any()
     np.testing.assert_array_equal(rb.from_colmajor(tr), tr_o)
@@ -93,8 +93,8 @@ def test_slice_gemm_bitexact(npad, kl, kr):
     Lp = rng.integers(-127, 128, (kl, npad, npad)).astype(np.int8)
     Rp = rng.integers(-127, 128, (kr, npad, npad)).astype(np.int8)
     ndiag = kl + kr - 1
-    st, C = rb.slice_gemm(torch.from_numpy(Lp).cuda(), torch.from_numpy(Rp).cuda(), npad, kl, kr, 2,
-                          ndiag)
+    st, C = rb.slice_gemm(rb.rows_to_kblocked(torch.from_numpy(Lp).cuda()),
+                          rb.rows_to_kblocked(torch.from_numpy(Rp).cuda()), npad, kl, kr, 2, ndiag)
     assert st == 0
     Cg = C.cpu().numpy()
     ref = _diag_products_oracle(Lp, Rp, kl, kr, 2, ndiag)
@@ -120,8 +120,8 @@ def test_slice_gemm_full_size_sampled():
     rows[0], cols[-1] = 0, npad - 1
     ridx = torch.from_numpy(rows).cuda()
     cidx = torch.from_numpy(cols).cuda()
-    Ls = Lp[:, ridx, :].cpu().numpy()
-    Rs = Rp[:, cidx, :].cpu().numpy()
+    Ls = rb.kblocked_to_rows(Lp)[:, ridx, :].cpu().numpy()   # the planes are read K-blocked
+    Rs = rb.kblocked_to_rows(Rp)[:, cidx, :].cpu().numpy()
     ref = _diag_products_oracle(Ls, Rs, kl, kr, 2, ndiag)
     Cs = C[:, ridx][:, :, cidx].cpu().numpy()
     for q in range(ndiag):
