@@ -68,7 +68,7 @@ def measured_traffic():
     """HBM bytes per slice-GEMM launch from the profiler's FETCH_SIZE / WRITE_SIZE passes
     (scaled by a copy kernel of known size), if they were taken on the current kernels."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_slice_gemm256_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_slice_gemm256d_traffic.json")
     src = os.path.join(ROOT, "paper_2602_19090_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
@@ -196,9 +196,9 @@ def main():
     # ---- roofline of the INT8 slice GEMM (all its launches in the timed steps)
     ops = sum(pp * 2.0 * n ** 3 for r in reps for it in r["pairs_f"] for pp in it)
     gemm_ms = sum(t for r in reps for it in r["ms_p"] for t in it)
-    launches = sum(len(it) for r in reps for it in r["ms_p"])
+    launches = sum(c for r in reps for it in r["launches_p"] for c in it)
     achieved = ops / (gemm_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "k_slice_gemm256", "achieved": achieved,
+    roofline = {"bound": "mfma", "kernel": "k_slice_gemm256d", "achieved": achieved,
                 "peak": INT8_PEAK_TOPS, "unit": "TOP/s (INT8)", "frac": achieved / INT8_PEAK_TOPS,
                 "traffic": measured_traffic(), "avg_launch_ms": gemm_ms / launches,
                 "ops_per_launch": ops / launches}

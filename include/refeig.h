@@ -88,7 +88,10 @@ typedef struct {
     int pairs_p[REFEIG_MAX_ITERS][3];   /* slice products of V, W, X^(1)E~ per iteration  */
     double pairs_f[REFEIG_MAX_ITERS][3];/* the same in units of one n x n x n product,
                                            counting per-column-block cutoffs exactly      */
-    double ms_p[REFEIG_MAX_ITERS][3];   /* launch time of those three products (events)    */
+    double ms_p[REFEIG_MAX_ITERS][3];   /* time of those three products, from the start of
+                                           their first kernel dispatch to the end of their
+                                           last (events taken by the dispatches)          */
+    int launches_p[REFEIG_MAX_ITERS][3];/* slice-GEMM kernel dispatches of each product    */
     double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
     double max_abs_lambda;           /* max |lambda| (last)                             */
     double ms_total;

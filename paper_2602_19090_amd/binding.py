@@ -54,7 +54,8 @@ class Report(ctypes.Structure):
                 ("ms_gemm", ctypes.c_double * MAX_ITERS),
                 ("pairs_p", (ctypes.c_int * 3) * MAX_ITERS),
                 ("pairs_f", (ctypes.c_double * 3) * MAX_ITERS),
-                ("ms_p", (ctypes.c_double * 3) * MAX_ITERS), ("min_gap", ctypes.c_double),
+                ("ms_p", (ctypes.c_double * 3) * MAX_ITERS),
+                ("launches_p", (ctypes.c_int * 3) * MAX_ITERS), ("min_gap", ctypes.c_double),
                 ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
     def as_dict(self):
@@ -66,6 +67,7 @@ class Report(ctypes.Structure):
                 "pairs_p": [list(self.pairs_p[i]) for i in range(k)],
                 "ms_p": [list(self.ms_p[i]) for i in range(k)],
                 "pairs_f": [list(self.pairs_f[i]) for i in range(k)],
+                "launches_p": [list(self.launches_p[i]) for i in range(k)],
                 "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
                 "ms_total": self.ms_total}
 

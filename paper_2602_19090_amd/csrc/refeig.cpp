@@ -644,6 +644,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       return cleanup(REFEIG_E_HIP);
     const int dv = plan.dmax;
     const double pv = plan.pairs_eff;
+    const int lv = (int)plan.groups.size();
     launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
     launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.r, w.eR, w.resmax,
                  w.RP, kKrMax, w.flags, s);
@@ -671,6 +672,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       return cleanup(REFEIG_E_HIP);
     const int dw = plan.dmax;
     const double pw = plan.pairs_eff;
+    const int lw = (int)plan.groups.size();
     launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
     launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP,
                  kKeMax, w.flags, s);
@@ -697,6 +699,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       return cleanup(REFEIG_E_HIP);
     const int du = plan.dmax;
     const double pu = plan.pairs_eff;
+    const int lu = (int)plan.groups.size();
     launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6]);
     launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s);
     STEP(hipMemcpyAsync(D, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -727,6 +730,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->ms_p[it][0] = g1;
       rep->ms_p[it][1] = g2;
       rep->ms_p[it][2] = g3;
+      rep->launches_p[it][0] = lv;
+      rep->launches_p[it][1] = lw;
+      rep->launches_p[it][2] = lu;
       rep->iters = it + 1;
       rep->min_gap = gmin;
       rep->max_abs_lambda = lmax;
