@@ -20,17 +20,20 @@ struct DiagOrder {
 //   e[j] = floor(log2 max_i |M_ij|) + 1 (0 for a zero column),
 //   c[j] = ceil(log2 max_i |M_ij|)      (0 for a zero column),
 //   mx[j] = max_i |M_ij|.  Columns cols..cols_pad-1 get zeros.
+// colmap (device, may be null): column j of the result is column colmap[j] of M.
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
-                     double *mx, int *flags, hipStream_t s);
+                     double *mx, int *flags, hipStream_t s, const int *colmap = nullptr);
 
 // 7-bit digit planes of M with column exponents e (see refeig_split_cols).
 //  planes: k planes, plane stride pstride, element (i, j) at j*rpad + i.
 //  trunc (optional, ld ldt): value of the k digits.
 //  planesT (optional): kT planes of the transposed layout, element (i, j) at i*cpad + j.
 // The grid covers the padded rpad x cpad area and writes zero digits outside.
+// colmap (device, may be null): column j is read from column colmap[j] of M.
 void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
-                       int8_t *planesT, size_t pstrideT, int kT, hipStream_t s);
+                       int8_t *planesT, size_t pstrideT, int kT, hipStream_t s,
+                       const int *colmap = nullptr);
 
 constexpr int kMaxRowBlocks = 64;
 struct RowBlocks {
@@ -67,8 +70,13 @@ void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *d
                   const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
                   double *emax, int8_t *Eplanes, int ke, int *flags, hipStream_t s);
 
-// Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j).
+// Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j); column j
+// is written to column colmap[j] of X (colmap may be null).
 void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s);
+                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s,
+                  const int *colmap = nullptr);
+
+// out[colmap[p]] = v[p] for p < n (colmap may be null).
+void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s);
 
 }  // namespace refeig

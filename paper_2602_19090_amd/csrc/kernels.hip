@@ -143,7 +143,7 @@ __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
 // ---------------------------------------------------------------- column statistics
 __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, int ld, int rows,
                                                   int cols, int *e, int *c, double *mx,
-                                                  int *flags) {
+                                                  int *flags, const int *__restrict__ colmap) {
   __shared__ double scratch[4];
   const int j = blockIdx.x;
   if (j >= cols) {
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, 
     }
     return;
   }
-  const double *col = M + (size_t)j * ld;
+  const double *col = M + (size_t)(colmap ? colmap[j] : j) * ld;
   double m = 0.0;
   int bad = 0;
   for (int i = threadIdx.x; i < rows; i += 256) {
@@ -174,9 +174,9 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, 
 }
 
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
-                     double *mx, int *flags, hipStream_t s) {
+                     double *mx, int *flags, hipStream_t s, const int *colmap) {
   hipLaunchKernelGGL(k_colstats, dim3(cols_pad), dim3(256), 0, s, M, ld, rows, cols, e, c, mx,
-                     flags);
+                     flags, colmap);
 }
 
 // ---------------------------------------------------------------- digit planes
@@ -190,7 +190,8 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
                                                     int8_t *__restrict__ planes, size_t pstride,
                                                     int rpad, int cpad, double *__restrict__ trunc,
                                                     int ldt, int8_t *__restrict__ planesT,
-                                                    size_t pstrideT, int kT) {
+                                                    size_t pstrideT, int kT,
+                                                    const int *__restrict__ colmap) {
   __shared__ __attribute__((aligned(16))) int8_t sT[WITH_T ? kMaxPlanesT * 64 * kTStride : 16];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int ig = threadIdx.x & 15, jl = threadIdx.x >> 4;
@@ -199,13 +200,14 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
   for (int q = 0; q < 4; ++q) {
     const int jj = jl + 16 * q, j = j0 + jj;
     const int ej = (j < cols) ? e[j] : 0;
+    const size_t mcol = (j < cols) ? (size_t)(colmap ? colmap[j] : j) * ld : 0;
     unsigned packed[kMaxPlanesSplit];
 #pragma unroll
     for (int t = 0; t < kMaxPlanesSplit; ++t) packed[t] = 0u;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int ii = 4 * ig + u, i = i0 + ii;
-      const double a = (i < rows && j < cols) ? M[(size_t)j * ld + i] : 0.0;
+      const double a = (i < rows && j < cols) ? M[mcol + i] : 0.0;
       double y = ldexp(fabs(a), -ej);
       const int sg = (a < 0.0) ? -1 : 1;
       double val = 0.0;
@@ -242,14 +244,15 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
 
 void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
-                       int8_t *planesT, size_t pstrideT, int kT, hipStream_t s) {
+                       int8_t *planesT, size_t pstrideT, int kT, hipStream_t s,
+                       const int *colmap) {
   dim3 grid(rpad / 64, cpad / 64);
   if (planesT && kT > 0)
     hipLaunchKernelGGL(k_split_cols<true>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
-                       pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT);
+                       pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT, colmap);
   else
     hipLaunchKernelGGL(k_split_cols<false>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
-                       pstride, rpad, cpad, trunc, ldt, (int8_t *)nullptr, (size_t)0, 0);
+                       pstride, rpad, cpad, trunc, ldt, (int8_t *)nullptr, (size_t)0, 0, colmap);
 }
 
 // ---------------------------------------------------------------- INT8 slice GEMM
@@ -793,7 +796,8 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
                                                int ndiag_all, const int *__restrict__ dcut,
                                                const int *__restrict__ eE,
                                                const double *__restrict__ X1, int n,
-                                               double *__restrict__ X, int ldx) {
+                                               double *__restrict__ X, int ldx,
+                                               const int *__restrict__ colmap) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
   const size_t P = (size_t)npad * npad;
@@ -803,13 +807,24 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
   double u = 0.0;
   for (int qq = ndiag - 1; qq >= 0; --qq)
     u += ldexp((double)Ccol[(size_t)qq * P + i], ej - 7 * (d_min + qq));
-  X[(size_t)j * ldx + i] = X1[(size_t)j * n + i] + u;
+  X[(size_t)(colmap ? colmap[j] : j) * ldx + i] = X1[(size_t)j * n + i] + u;
 }
 
 void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s) {
+                  const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s,
+                  const int *colmap) {
   hipLaunchKernelGGL(k_epi_u, dim3((n + 255) / 256, n), dim3(256), 0, s, C, npad, d_min, ndiag, dcut,
-                     eE, X1, n, X, ldx);
+                     eE, X1, n, X, ldx, colmap);
+}
+
+__global__ void k_scatter(const double *__restrict__ v, const int *__restrict__ colmap, int n,
+                          double *__restrict__ out) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < n) out[colmap ? colmap[p] : p] = v[p];
+}
+
+void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, v, colmap, n, out);
 }
 
 }  // namespace refeig

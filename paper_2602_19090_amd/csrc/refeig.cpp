@@ -56,6 +56,7 @@ struct Work {
   double *X1;
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
   int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
+  int *colmap;   // working column p holds column colmap[p] of the caller's X
   double *mxA, *mxX, *lam, *r, *resmax, *emax;
 };
 
@@ -90,6 +91,7 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.eE = (int *)take(vi);
   t.flags = (int *)take(256);
   for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
+  t.colmap = (int *)take(vi);
   t.mxA = (double *)take(vd);
   t.mxX = (double *)take(vd);
   t.lam = (double *)take(vd);
@@ -559,6 +561,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   int status = REFEIG_OK;
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
   std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
+  std::vector<double> gaps_nat;
+  std::vector<int> cmap(n);
   int hflags = 0;
   hipEvent_t ev[8];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -609,8 +613,23 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   int it = 0;
   for (; it < iters; ++it) {
     STEP(hipEventRecord(ev[0], s));
+    // ---- working column order: widest gap first. The iteration is equivariant under a
+    // column permutation (each column keeps its own arithmetic), and a GEMM block spans
+    // 256 columns and computes the pair diagonals its neediest column requires, so columns
+    // that need similar diagonal counts (set by their gaps) are placed together. Column p
+    // of every working array is column cmap[p] of X and D.
+    double gmin, lmax;
+    column_gaps(lam_prev, gaps_nat, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    for (int p = 0; p < n; ++p) cmap[p] = p;
+    // ties (two columns share a gap) go by eigenvalue, so the order does not depend on
+    // where the caller put the columns
+    std::sort(cmap.begin(), cmap.end(), [&](int a, int b) {
+      return gaps_nat[a] != gaps_nat[b] ? gaps_nat[a] > gaps_nat[b] : lam_prev[a] < lam_prev[b];
+    });
+    STEP(hipMemcpyAsync(w.colmap, cmap.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     // ---- beta and kx from the previous eigenvalue estimates and column maxima of X
-    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s);
+    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap);
     STEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -618,13 +637,13 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     STEP(hipStreamSynchronize(s));
     if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
     if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
-    double gmin, lmax;
-    column_gaps(lam_prev, gaps, &gmin, &lmax);
-    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    gaps.resize(n);
+    for (int p = 0; p < n; ++p) gaps[p] = gaps_nat[cmap[p]];
     int beta, kx;
     beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx);
     // ---- X^(1) and its planes (both layouts)
-    launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s);
+    launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s,
+                      w.colmap);
     // ---- V = A X^(1): per column j keep pair diagonals d <= dv(j)
     int eXmax = -100000;
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
@@ -701,8 +720,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const double pu = plan.pairs_eff;
     const int lu = (int)plan.groups.size();
     launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6]);
-    launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s);
-    STEP(hipMemcpyAsync(D, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s, w.colmap);
+    launch_scatter(w.lam, w.colmap, n, D, s);
     STEP(hipEventRecord(ev[7], s));
     STEP(hipGetLastError());
     STEP(hipEventSynchronize(ev[7]));
@@ -743,7 +762,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
               "ms %.2f (gemm %.2f)\n",
               it + 1, beta, kx, dv, dw, du, (int)std::lround(pv + pw + pu), eps, gmin, t_it,
               g1 + g2 + g3);
-    lam_prev = lam;
+    for (int p = 0; p < n; ++p) lam_prev[cmap[p]] = lam[p];
     if (o.fixed_iters > 0) continue;
     // The correction eps = max|E~| estimates the error of X^(1) (Sec. 3.2: X = X^(1)(I + E)),
     // which never falls below the truncation grid that beta sets. The forward error after

@@ -172,6 +172,27 @@ def test_caller_workspace_and_determinism():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_column_order_of_the_input_does_not_matter():
+    """The library works on the columns in an order of its own (by gap), and every column's
+    arithmetic is independent of where it sits, so permuting the input columns permutes the
+    output bit for bit (n = 700 spans three 256-column blocks and a ragged tail)."""
+    import torch
+    rb = _rb()
+    n = 700
+    p = workloads.make_problem(2, n, x0="eigh")
+    perm = np.random.default_rng(7).permutation(n)
+    A, X, D = _to_dev(p)
+    st, _ = rb.refine_eigvecs(A, X, D, 1e-13)
+    assert st == rb.REFEIG_OK
+    Xp = rb.colmajor(np.asfortranarray(p.X0[:, perm]))
+    Dp = torch.from_numpy(np.array(p.D0)[perm].copy()).cuda()
+    st, _ = rb.refine_eigvecs(A, Xp, Dp, 1e-13)
+    assert st == rb.REFEIG_OK
+    X0n, Xpn = rb.from_colmajor(X), rb.from_colmajor(Xp)
+    assert np.array_equal(Xpn, X0n[:, perm])
+    assert np.array_equal(Dp.cpu().numpy(), D.cpu().numpy()[perm])
+
+
 def _golden(cfg, n):
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", f"xtrue_cfg{cfg}_n{n}.npz")
