@@ -117,6 +117,26 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
                    double target_fwd_err, const refeig_opts *o, void *work, size_t work_bytes,
                    refeig_stream_t stream, refeig_report *report);
 
+/* Batched form of refine_eigvecs for `count` independent problems (the
+ * serving and many-small-matrices workloads of Sec. 4's setting, one matrix
+ * per request). Host arrays of length count hold each problem's order n[i],
+ * device pointers A[i], X[i], D[i], leading dimensions and target_fwd_err[i];
+ * o applies to all. Problems run concurrently on up to REFEIG_BATCH_LANES
+ * internal streams, each with its own slice of the workspace; the caller's
+ * stream is joined to them on entry and exit. Every problem's result is bit
+ * for bit what refine_eigvecs returns for it alone. work: device buffer of
+ * work_bytes >= refeig_batched_workspace_bytes, or NULL (the library allocates
+ * and frees it). reports (host, count entries, may be NULL) receive each
+ * problem's report and status. Returns REFEIG_OK when every problem did, else
+ * the first negative per-problem status, else REFEIG_NOT_CONVERGED;
+ * REFEIG_E_ARG for count < 1 or a NULL array. */
+#define REFEIG_BATCH_LANES 4
+int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes);
+int refine_eigvecs_batched(int count, const int *n, const double *const *A, const int *lda,
+                           double *const *X, const int *ldx, double *const *D,
+                           const double *target_fwd_err, const refeig_opts *o, void *work,
+                           size_t work_bytes, refeig_stream_t stream, refeig_report *reports);
+
 const char *refeig_strerror(int status);
 
 /* ---- entry points for bit-exact checks of the kernels -------------------- */

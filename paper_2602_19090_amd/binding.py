@@ -82,8 +82,14 @@ _lib.refeig_strerror.argtypes = [_int]
 _lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 
+_lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
+                                                ctypes.POINTER(_sz)]
+_lib.refine_eigvecs_batched.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.POINTER(Opts), _vp, _sz, _vp, _vp]
+
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
-            "refeig_split_cols", "refeig_slice_gemm"]
+            "refeig_split_cols", "refeig_slice_gemm", "refeig_batched_workspace_bytes",
+            "refine_eigvecs_batched"]
 
 
 def _stream(stream=None):
@@ -139,6 +145,42 @@ def refine_eigvecs(A, X, D, target: float, opts: Opts | None = None, work=None, 
                              ctypes.byref(opts) if opts is not None else None, _ptr(work), wb,
                              _stream(stream), ctypes.byref(rep))
     return st, rep
+
+
+def batched_workspace_bytes(ns, opts: Opts | None = None) -> int:
+    arr = (ctypes.c_int * len(ns))(*[int(v) for v in ns])
+    out = _sz(0)
+    st = _lib.refeig_batched_workspace_bytes(len(ns), ctypes.cast(arr, _vp),
+                                             ctypes.byref(opts) if opts is not None else None,
+                                             ctypes.byref(out))
+    if st != 0:
+        raise ValueError(strerror(st))
+    return out.value
+
+
+def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=None, stream=None):
+    """Batched refine_eigvecs over lists of (A, X, D) tensors (each as for refine_eigvecs).
+    Returns (status, [report per problem])."""
+    count = len(As)
+    assert len(Xs) == len(Ds) == len(targets) == count
+    ns = []
+    for A, X, D in zip(As, Xs, Ds):
+        n = D.numel()
+        assert A.is_cuda and X.is_cuda and D.is_cuda and A.is_contiguous() and X.is_contiguous()
+        assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+        ns.append(n)
+    ci = ctypes.c_int * count
+    cp = ctypes.c_void_p * count
+    n_a, ld_a = ci(*ns), ci(*ns)
+    A_a, X_a, D_a = (cp(*[t.data_ptr() for t in ts]) for ts in (As, Xs, Ds))
+    t_a = (ctypes.c_double * count)(*[float(t) for t in targets])
+    reps = (Report * count)()
+    wb = work.numel() * work.element_size() if work is not None else 0
+    c = lambda a: ctypes.cast(a, _vp)
+    st = _lib.refine_eigvecs_batched(count, c(n_a), c(A_a), c(ld_a), c(X_a), c(ld_a), c(D_a), c(t_a),
+                                     ctypes.byref(opts) if opts is not None else None, _ptr(work),
+                                     wb, _stream(stream), c(reps))
+    return st, list(reps)
 
 
 def rows_to_kblocked(P):

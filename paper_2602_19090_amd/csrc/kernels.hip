@@ -605,23 +605,39 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
   const int32_t *Ccol = C + (size_t)j * npad;
   const double *xcol = X1 + (size_t)j * n;
   double vh[EPT], vl[EPT];
-  ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
+  int eiq[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
     vh[q] = vl[q] = 0.0;
-    if (i < n) {
-      const int ei = eA[i];
-      double h = 0.0, l = 0.0;
+    eiq[q] = (i < n) ? eA[i] + ej : 0;
+  }
+  // slice sum, smallest scale first; diagonals outermost so each thread keeps EPT
+  // independent loads in flight
 #pragma unroll 1
-      for (int qq = ndiag - 1; qq >= 0; --qq) {
-        const double tv = ldexp((double)Ccol[(size_t)qq * P + i], ei + ej - 7 * (d_min + qq));
-        double s, e;
-        two_sum(h, tv, s, e);
-        h = s;
-        l += e;
-      }
-      fast_two_sum(h, l, vh[q], vl[q]);
+  for (int qq = ndiag - 1; qq >= 0; --qq) {
+    const int32_t *Cq = Ccol + (size_t)qq * P;
+    int32_t cv[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int i = tid + kEpiThreads * q;
+      cv[q] = (i < n) ? Cq[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double tv = ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+      double s, e;
+      two_sum(vh[q], tv, s, e);
+      vh[q] = s;
+      vl[q] += e;
+    }
+  }
+  ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    if (i < n) {
+      fast_two_sum(vh[q], vl[q], vh[q], vl[q]);
       const double x = xcol[i];
       double p, pe;
       two_prod(x, x, p, pe);
@@ -716,7 +732,26 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   const double lj = lam[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad;
-  double ev[EPT];
+  double ev[EPT], wq[EPT];
+  int eiq[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    wq[q] = 0.0;
+    eiq[q] = (i < n) ? eX[i] + ej : 0;
+  }
+#pragma unroll 1
+  for (int qq = ndiag - 1; qq >= 0; --qq) {
+    const int32_t *Cq = Ccol + (size_t)qq * P;
+    int32_t cv[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int i = tid + kEpiThreads * q;
+      cv[q] = (i < n) ? Cq[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+  }
   double ms = 0.0, mr = 0.0;
   int tie = 0;
 #pragma unroll
@@ -725,10 +760,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     ev[q] = 0.0;
     if (i < n) {
       const int ei = eX[i];
-      double w = 0.0;
-#pragma unroll 1
-      for (int qq = ndiag - 1; qq >= 0; --qq)
-        w += ldexp((double)Ccol[(size_t)qq * P + i], ei + ej - 7 * (d_min + qq));
+      const double w = wq[q];
       double e;
       if (i == j) {
         e = 0.5 * r[j];

@@ -15,10 +15,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include <rocblas/rocblas.h>
@@ -779,6 +781,85 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   }
   return cleanup(status);
 #undef STEP
+}
+
+int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes) {
+  if (count < 1 || !n || !bytes) return REFEIG_E_ARG;
+  int nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kMaxN) return REFEIG_E_ARG;
+    nmax = std::max(nmax, n[i]);
+  }
+  size_t one = 0;
+  const int st = refeig_workspace_bytes(nmax, o, &one);
+  if (st != REFEIG_OK) return st;
+  *bytes = (size_t)std::min(count, REFEIG_BATCH_LANES) * ((one + 255) / 256 * 256);
+  return REFEIG_OK;
+}
+
+int refine_eigvecs_batched(int count, const int *n, const double *const *A, const int *lda,
+                           double *const *X, const int *ldx, double *const *D,
+                           const double *target, const refeig_opts *o, void *work,
+                           size_t work_bytes, refeig_stream_t stream, refeig_report *reports) {
+  if (count < 1 || !n || !A || !lda || !X || !ldx || !D || !target) return REFEIG_E_ARG;
+  size_t need = 0;
+  int st = refeig_batched_workspace_bytes(count, n, o, &need);
+  if (st != REFEIG_OK) return st;
+  const int lanes = std::min(count, REFEIG_BATCH_LANES);
+  const size_t slice = need / lanes;
+  hipStream_t s = (hipStream_t)stream;
+  bool own = false;
+  if (!work) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMalloc(&work, need));
+    own = true;
+  } else if (work_bytes < need) {
+    return REFEIG_E_NOMEM;
+  }
+  // lanes: own streams (default priority), joined to the caller's stream by events
+  std::vector<hipStream_t> ls(lanes, nullptr);
+  std::vector<hipEvent_t> le(lanes + 1, nullptr);
+  bool ok = hipEventCreateWithFlags(&le[lanes], hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(le[lanes], s) == hipSuccess;
+  for (int l = 0; l < lanes && ok; ++l)
+    ok = hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&le[l], hipEventDisableTiming) == hipSuccess &&
+         hipStreamWaitEvent(ls[l], le[lanes], 0) == hipSuccess;
+  std::vector<int> status(count, REFEIG_E_HIP);
+  if (ok) {
+    // each lane takes the next unstarted problem until none is left
+    std::atomic<int> next{0};
+    auto run_lane = [&](int l) {
+      char *wl = (char *)work + (size_t)l * slice;
+      for (int i = next++; i < count; i = next++)
+        status[i] = refine_eigvecs(A[i], lda[i], X[i], ldx[i], D[i], n[i], target[i], o, wl,
+                                   slice, (refeig_stream_t)ls[l], reports ? &reports[i] : nullptr);
+    };
+    std::vector<std::thread> th;
+    for (int l = 1; l < lanes; ++l) th.emplace_back(run_lane, l);
+    run_lane(0);
+    for (auto &t : th) t.join();
+    for (int l = 0; l < lanes; ++l)
+      ok = ok && hipEventRecord(le[l], ls[l]) == hipSuccess &&
+           hipStreamWaitEvent(s, le[l], 0) == hipSuccess;
+  }
+  for (int l = 0; l < lanes; ++l) {
+    if (ls[l]) (void)hipStreamSynchronize(ls[l]);
+    if (ls[l]) (void)hipStreamDestroy(ls[l]);
+    if (le[l]) (void)hipEventDestroy(le[l]);
+  }
+  if (le[lanes]) (void)hipEventDestroy(le[lanes]);
+  if (own) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(work);
+  }
+  if (!ok) return REFEIG_E_HIP;
+  int worst = REFEIG_OK;
+  for (int i = 0; i < count; ++i) {
+    if (status[i] < 0) return status[i];
+    if (status[i] != REFEIG_OK) worst = status[i];
+  }
+  return worst;
 }
 
 }  // extern "C"

@@ -230,3 +230,52 @@ def test_full_size_against_oracle_columns(cfg, n):
     assert lam_err <= target * float(np.max(np.abs(g["lam_hi"])))
     del A, X, D
     torch.cuda.empty_cache()
+
+
+def test_batched_matches_single_calls_config4():
+    """Config-4 style batch (n log-uniform in [32, 1024], cond 10^U(4,12), FP64-eigh start,
+    exactly 3 iterations): the batched entry point gives each problem bit for bit what a
+    single call gives, and the small members meet the target against the oracle's X_true."""
+    import torch
+    rb = _rb()
+    ns, cs = workloads.config4_sizes(20)
+    probs = [workloads.make_problem(4, int(n), index=i, cond_exp=float(c))
+             for i, (n, c) in enumerate(zip(ns, cs))]
+    print("batch n:", [p.n for p in probs], flush=True)
+    opts = rb.default_opts(fixed_iters=3)
+    target = 1e-14
+    singles = []
+    for p in probs:
+        A, X, D = _to_dev(p)
+        st, _ = rb.refine_eigvecs(A, X, D, target, opts)
+        assert st == rb.REFEIG_OK, (p.n, rb.strerror(st))
+        singles.append((X.cpu().numpy(), D.cpu().numpy()))
+    dev = [_to_dev(p) for p in probs]
+    st, reps = rb.refine_eigvecs_batched([d[0] for d in dev], [d[1] for d in dev],
+                                         [d[2] for d in dev], [target] * len(probs), opts)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    torch.cuda.synchronize()
+    for (A, X, D), (Xs, Ds), r in zip(dev, singles, reps):
+        assert r.status == rb.REFEIG_OK and r.iters == 3
+        assert np.array_equal(X.cpu().numpy(), Xs) and np.array_equal(D.cpu().numpy(), Ds)
+    errs = []
+    for p, (A, X, D) in zip(probs, dev):
+        if p.n <= 160:
+            Xt, _ = _xtrue(p)
+            errs.append((p.n, _fwd(rb.from_colmajor(X), Xt)))
+    print("3-iteration errors (n, err):", errs, flush=True)
+    assert errs and all(e <= target for _, e in errs)
+
+
+def test_batched_error_paths():
+    import torch
+    rb = _rb()
+    p = workloads.make_problem(1, 64)
+    A, X, D = _to_dev(p)
+    Xbad = X.clone()
+    Xbad[0, 0] = float("nan")
+    st, reps = rb.refine_eigvecs_batched([A, A], [X, Xbad], [D, D.clone()], [1e-13, 1e-13])
+    assert st == rb.REFEIG_E_NONFINITE
+    assert reps[0].status == rb.REFEIG_OK and reps[1].status == rb.REFEIG_E_NONFINITE
+    with pytest.raises(ValueError):
+        rb.batched_workspace_bytes([64, 0])

@@ -141,6 +141,16 @@ def spectrum_for_config(config_id: int, n: int, rng: np.random.Generator, cond_e
     return geometric_spectrum(n, float(cond_exp))
 
 
+def config4_sizes(count: int, batch: int = 0):
+    """Orders and condition exponents of the many-small-matrices workload (config 4):
+    n = round(exp(U(ln 32, ln 1024))), cond = 10^c with c ~ U(4, 12), seeded per batch.
+    Matrix i of the batch is make_problem(4, n[i], index=i, cond_exp=c[i])."""
+    rng = rng_for(4, 1_000_000 + batch)
+    ns = np.rint(np.exp(rng.uniform(np.log(32.0), np.log(1024.0), count))).astype(int)
+    cs = rng.uniform(4.0, 12.0, count)
+    return ns, cs
+
+
 def make_problem(config_id: int, n: int, index: int = 0, x0: str = "eigh",
                  cond_exp: float | None = None) -> Problem:
     """Build (A, X0, D0) for a workload family.
