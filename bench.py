@@ -78,6 +78,41 @@ def measured_traffic():
     return t["traffic_bytes_per_launch"]
 
 
+def config4_leg(count):
+    """Many small matrices (config 4): one batched call, exactly 3 iterations each, inputs
+    resident on the device; matrices/s and FP64-equivalent TFLOP/s (6 n^3 per iteration)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2602_19090_amd import binding as rb
+    ns, cs = workloads.config4_sizes(count)
+    log(f"config 4: {count} matrices, n {ns.min()}..{ns.max()}, FP64 eigensolves on the host")
+    probs = [workloads.make_problem(4, int(nn), index=i, cond_exp=float(c))
+             for i, (nn, c) in enumerate(zip(ns, cs))]
+    As = [rb.colmajor(q.A) for q in probs]
+    X0s = [rb.colmajor(q.X0) for q in probs]
+    D0s = [torch.from_numpy(np.array(q.D0)).cuda() for q in probs]
+    opts = rb.default_opts(fixed_iters=3)
+    work = torch.empty(rb.batched_workspace_bytes([q.n for q in probs], opts), dtype=torch.uint8,
+                       device="cuda")
+    times = []
+    for rep in range(3):
+        Xs = [x.clone() for x in X0s]
+        Ds = [d.clone() for d in D0s]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, reps = rb.refine_eigvecs_batched(As, Xs, Ds, [1e-14] * count, opts, work=work)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert st == rb.REFEIG_OK, rb.strerror(st)
+        log(f"config 4 batch {rep + 1}: {times[-1] * 1e3:.1f} ms")
+    t = float(np.median(times))
+    flops = sum(6.0 * float(q.n) ** 3 * 3 for q in probs)
+    return {"matrices": count, "n_range": [int(ns.min()), int(ns.max())], "iters": 3,
+            "ms": t * 1e3, "matrices_per_s": count / t, "tflops_fp64_equiv": flops / t / 1e12,
+            "lanes": 8}
+
+
 def cpu_baseline(A, X0cm, n, cols):
     """Time the oracle's double-double products on `cols` columns and scale to one
     iteration (three n x n x n double-double products)."""
@@ -111,6 +146,9 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain-form leg")
+    ap.add_argument("--config4", type=int, default=0, metavar="COUNT",
+                    help="also time a batch of COUNT config-4 matrices (n log-uniform in "
+                         "[32, 1024], cond 10^U(4,12), 3 iterations) through the batched entry point")
     ap.add_argument("--calibrate", action="store_true",
                     help="run one elementwise kernel of known traffic (for profiler byte counters)")
     args = ap.parse_args()
@@ -250,6 +288,8 @@ def main():
             plain = {"ms_to_target": None, "iters": None, "status": "did not reach the target",
                      "fwd_err_per_iter": perrs or None}
 
+    batch = config4_leg(args.config4) if args.config4 > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle double-double products on a column sample")
@@ -270,6 +310,8 @@ def main():
         "ms_gemm_per_iter": r0["ms_gemm"], "timed_wall_s": wall,
         "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": plain,
     }
+    if batch is not None:
+        out["config4_batched"] = batch
     print(json.dumps(out), flush=True)
 
 

@@ -130,7 +130,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
  * problem's report and status. Returns REFEIG_OK when every problem did, else
  * the first negative per-problem status, else REFEIG_NOT_CONVERGED;
  * REFEIG_E_ARG for count < 1 or a NULL array. */
-#define REFEIG_BATCH_LANES 4
+#define REFEIG_BATCH_LANES 8
 int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes);
 int refine_eigvecs_batched(int count, const int *n, const double *const *A, const int *lda,
                            double *const *X, const int *ldx, double *const *D,
