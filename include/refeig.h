@@ -70,7 +70,15 @@ typedef struct {
     int d_extra;         /* extra pair diagonals added to every product (default 0)      */
     int verbose;         /* print per-iteration parameters to stderr                     */
     int reserved_i[6];
-    double reserved_d[4];
+    double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
+                            method (which assumes well-separated eigenvalues, Sec. 3.2):
+                            a column whose largest first-order correction |e_ij|, i != j,
+                            exceeds group_tau is linked to row i; each linked group of
+                            2..32 columns is corrected by the Rayleigh-Ritz problem on its
+                            span (T y = mu G y, G = X_C^T X_C, T = X_C^T A X_C), which
+                            resolves badly mixed or near-tied eigenvectors in one step.
+                            0 (default): off, the paper's method.                       */
+    double reserved_d[3];
 } refeig_opts;
 
 typedef struct {
@@ -92,6 +100,7 @@ typedef struct {
                                            their first kernel dispatch to the end of their
                                            last (events taken by the dispatches)          */
     int launches_p[REFEIG_MAX_ITERS][3];/* slice-GEMM kernel dispatches of each product    */
+    int groups[REFEIG_MAX_ITERS];    /* groups corrected by Rayleigh-Ritz (group_tau > 0) */
     double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
     double max_abs_lambda;           /* max |lambda| (last)                             */
     double ms_total;

@@ -56,6 +56,11 @@ def _load():
                                      _D, _D, _D]
         lib.or_method_step.argtypes = [_c_int, _D, _D, _D, _c_double, _c_double, _c_int, _c_int,
                                        _D, _D, _D, _D, _D, _D, _D, _I, _I]
+        lib.or_method_step_grouped.argtypes = [_c_int, _D, _D, _D, _c_double, _c_double, _c_int,
+                                               _c_int, _D, _D, _D, _D, _D, _D, _D, _I, _I,
+                                               _c_double, _I]
+        lib.or_refine_dd_step_grouped.argtypes = [_c_int, _D, _D, _D, _D, _D, _D, _D, _D,
+                                                  _c_double, _I]
         lib.or_secular_rank1.argtypes = [_c_int, _D, _D, _c_double, _D, _D, _D, _D, _D, _c_int,
                                          _c_int]
         lib.or_two_sum.argtypes = [_c_double, _c_double, _D, _D]
@@ -129,17 +134,23 @@ class DDStep:
         self.lam_h, self.lam_l, self.r, self.emax, self.E = lam_h, lam_l, r, emax, E
 
 
-def refine_dd_step(A, X_hi, X_lo, want_E=False):
-    """One iteration of Algorithm 1 in double-double. X_hi/X_lo updated in place."""
+def refine_dd_step(A, X_hi, X_lo, want_E=False, tau=0.0):
+    """One iteration of Algorithm 1 in double-double. X_hi/X_lo updated in place.
+    tau > 0: columns whose largest first-order correction exceeds tau are grouped and
+    corrected by the Rayleigh-Ritz problem on their span (or_refine_dd_step_grouped);
+    the number of groups is returned in .groups."""
     n = A.shape[0]
     A = _f64(A)
     lam_h = np.empty(n); lam_l = np.empty(n); r = np.empty(n); em = np.zeros(1)
     E = np.empty((n, n), order="F") if want_E else None
-    st = _load().or_refine_dd_step(n, _p(A), _p(X_hi), _p(X_lo), _p(lam_h), _p(lam_l), _p(r),
-                                   _p(E), _p(em))
+    g = ctypes.c_int(0)
+    st = _load().or_refine_dd_step_grouped(n, _p(A), _p(X_hi), _p(X_lo), _p(lam_h), _p(lam_l),
+                                           _p(r), _p(E), _p(em), float(tau), ctypes.byref(g))
     if st != 0:
         raise RuntimeError(f"or_refine_dd_step status {st}")
-    return DDStep(lam_h, lam_l, r, float(em[0]), E)
+    out = DDStep(lam_h, lam_l, r, float(em[0]), E)
+    out.groups = g.value
+    return out
 
 
 def refine_dd(A, X0, max_iter=12, tol=1e-28, verbose=False):
@@ -227,8 +238,9 @@ class MethodStep:
     pass
 
 
-def method_step(A, X, lam_prev, delta, xi=0.0, kx_max=9, kx_force=0):
-    """One iteration of the proposed method with exact (double-double) products."""
+def method_step(A, X, lam_prev, delta, xi=0.0, kx_max=9, kx_force=0, tau=0.0):
+    """One iteration of the proposed method with exact (double-double) products
+    (tau > 0: with the grouped correction, see refine_dd_step)."""
     A = _f64(A); X = _f64(X)
     lam_prev = np.ascontiguousarray(lam_prev, dtype=np.float64)
     n = A.shape[0]
@@ -236,14 +248,15 @@ def method_step(A, X, lam_prev, delta, xi=0.0, kx_max=9, kx_force=0):
     out.X1 = np.empty((n, n), order="F")
     out.X_hi = np.empty((n, n), order="F"); out.X_lo = np.empty((n, n), order="F")
     out.lam_h = np.empty(n); out.lam_l = np.empty(n); out.r = np.empty(n)
-    em = np.zeros(1); b = ctypes.c_int(); k = ctypes.c_int()
-    st = _load().or_method_step(n, _p(A), _p(X), _p(lam_prev), float(delta), float(xi),
-                                int(kx_max), int(kx_force), _p(out.X1), _p(out.X_hi),
-                                _p(out.X_lo), _p(out.lam_h), _p(out.lam_l), _p(out.r), _p(em),
-                                ctypes.byref(b), ctypes.byref(k))
+    em = np.zeros(1); b = ctypes.c_int(); k = ctypes.c_int(); g = ctypes.c_int(0)
+    st = _load().or_method_step_grouped(n, _p(A), _p(X), _p(lam_prev), float(delta), float(xi),
+                                        int(kx_max), int(kx_force), _p(out.X1), _p(out.X_hi),
+                                        _p(out.X_lo), _p(out.lam_h), _p(out.lam_l), _p(out.r),
+                                        _p(em), ctypes.byref(b), ctypes.byref(k), float(tau),
+                                        ctypes.byref(g))
     if st != 0:
         raise RuntimeError(f"or_method_step status {st}")
-    out.emax, out.beta, out.kx = float(em[0]), b.value, k.value
+    out.emax, out.beta, out.kx, out.groups = float(em[0]), b.value, k.value, g.value
     return out
 
 

@@ -15,6 +15,16 @@
  *                      e_ij = w_ij / (lambda_j - lambda_i), e_ii = r_i / 2,
  *                      X <- X + X E. Iterated to its fixed point this gives
  *                      X_true, the eigenvectors of the stored matrix.
+ *  or_refine_dd_step_grouped
+ *                      The same step with strongly coupled columns grouped (an
+ *                      extension for near-tied or badly mixed eigenvectors,
+ *                      which the paper leaves for future work, Sec. 5): where
+ *                      the first-order correction of column j is large
+ *                      (max_i |e_ij| > tau), j is linked to that i; for each
+ *                      linked group C the exact Rayleigh-Ritz problem on
+ *                      span(X_C), T y = mu G y with G = X_C^T X_C and
+ *                      T = X_C^T A X_C = W_CC + G_CC D_C, replaces the
+ *                      first-order entries of the group's columns.
  *  or_method_step      One iteration of the proposed method (Sec. 3): beta
  *                      from the implementation rule of Sec. 4.1 (floor form,
  *                      xi = n), X^(1) = truncation of X to the grid that beta
@@ -150,8 +160,22 @@ static dd_t dd_dot_cols(int n, const double *xh, const double *xl, const double 
 /*   emax: max |e_ij| (output).                                              */
 /* Returns 0, or -3 when two Rayleigh quotients coincide exactly.            */
 /* ------------------------------------------------------------------------ */
+static int grouped_correction(int n, const double *Xh, const double *Xl, const dd_t *lam,
+                              const double *Wh, const double *Wl, double *Eh, double *El,
+                              double tau, int *groups_out);
+int or_refine_dd_step_grouped(int n, const double *A, double *Xh, double *Xl,
+                              double *lam_h, double *lam_l, double *r_h, double *E_h,
+                              double *emax, double tau, int *groups_out);
+
 int or_refine_dd_step(int n, const double *A, double *Xh, double *Xl,
                       double *lam_h, double *lam_l, double *r_h, double *E_h, double *emax)
+{
+    return or_refine_dd_step_grouped(n, A, Xh, Xl, lam_h, lam_l, r_h, E_h, emax, 0.0, NULL);
+}
+
+int or_refine_dd_step_grouped(int n, const double *A, double *Xh, double *Xl,
+                              double *lam_h, double *lam_l, double *r_h, double *E_h,
+                              double *emax, double tau, int *groups_out)
 {
     size_t nn = (size_t)n * n;
     double *Vh = (double *)malloc(sizeof(double) * nn), *Vl = (double *)malloc(sizeof(double) * nn);
@@ -185,8 +209,14 @@ int or_refine_dd_step(int n, const double *A, double *Xh, double *Xl,
         }
     or_dd_gemm(1, n, n, n, Xh, Xl, n, Vh, Vl, n, Wh, Wl, n);
 
-    /* the correction matrix E (stored in W) */
-    double m = 0.0;
+    /* the correction matrix E (first order; stored in W unless groups are formed,
+       which need W itself) */
+    double *Eh = Wh, *El = Wl;
+    if (tau > 0.0) {
+        Eh = (double *)malloc(sizeof(double) * nn);
+        El = (double *)malloc(sizeof(double) * nn);
+        if (!Eh || !El) return -5;
+    }
     for (int j = 0; j < n && status == 0; ++j)
         for (int i = 0; i < n; ++i) {
             size_t q = IX(i, j, n);
@@ -200,10 +230,21 @@ int or_refine_dd_step(int n, const double *A, double *Xh, double *Xl,
                 dd_t w = { Wh[q], Wl[q] };
                 e = dd_div(w, den);
             }
-            Wh[q] = e.hi; Wl[q] = e.lo;
-            if (E_h) E_h[q] = e.hi;
-            if (fabs(e.hi) > m) m = fabs(e.hi);
+            Eh[q] = e.hi; El[q] = e.lo;
         }
+    if (groups_out) *groups_out = 0;
+    if (status == 0 && tau > 0.0)
+        status = grouped_correction(n, Xh, Xl, lam, Wh, Wl, Eh, El, tau, groups_out);
+    double m = 0.0;
+    for (size_t q = 0; q < nn; ++q) {
+        if (E_h) E_h[q] = Eh[q];
+        if (fabs(Eh[q]) > m) m = fabs(Eh[q]);
+    }
+    if (Eh != Wh) {
+        memcpy(Wh, Eh, sizeof(double) * nn);
+        memcpy(Wl, El, sizeof(double) * nn);
+        free(Eh); free(El);
+    }
 
     if (status == 0) {
         /* X <- X + X E (products and sum in double-double) */
@@ -223,6 +264,231 @@ int or_refine_dd_step(int n, const double *A, double *Xh, double *Xl,
     }
     if (emax) *emax = m;
     free(Vh); free(Vl); free(Wh); free(Wl); free(lam); free(rr);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grouped correction (Rayleigh-Ritz on strongly coupled columns).           */
+/* ------------------------------------------------------------------------ */
+#define OR_GROUP_MAX 32
+
+static int uf_find(int *par, int a)
+{
+    while (par[a] != a) { par[a] = par[par[a]]; a = par[a]; }
+    return a;
+}
+
+/* Symmetric eigenproblem of the k x k DD matrix M (row-major, overwritten):
+   cyclic Jacobi rotations until every off-diagonal entry is below 1e-32 of
+   the largest diagonal entry. Q (row-major) receives the eigenvectors as
+   columns; the eigenvalues are left on M's diagonal. */
+static void dd_jacobi(int k, dd_t *M, dd_t *Q)
+{
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) Q[a * k + b] = dd_from(a == b ? 1.0 : 0.0);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double dmax = 0.0, off = 0.0;
+        for (int a = 0; a < k; ++a) dmax = fmax(dmax, fabs(M[a * k + a].hi));
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b) off = fmax(off, fabs(M[a * k + b].hi));
+        if (off <= 1e-32 * dmax || off == 0.0) break;
+        for (int p = 0; p < k; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                dd_t apq = M[p * k + q];
+                if (apq.hi == 0.0) continue;
+                /* theta = (a_qq - a_pp) / (2 a_pq); t = sign(theta) / (|theta| + sqrt(theta^2 + 1)) */
+                dd_t theta = dd_div(dd_sub(M[q * k + q], M[p * k + p]), dd_mul_d(apq, 2.0));
+                dd_t at = theta.hi < 0.0 ? dd_neg(theta) : theta;
+                dd_t t;
+                if (at.hi > 1e30) t = dd_div(dd_from(0.5), at);
+                else t = dd_div(dd_from(1.0), dd_add(at, dd_sqrt(dd_add(dd_mul(at, at), dd_from(1.0)))));
+                if (theta.hi < 0.0) t = dd_neg(t);
+                dd_t c = dd_div(dd_from(1.0), dd_sqrt(dd_add(dd_mul(t, t), dd_from(1.0))));
+                dd_t sn = dd_mul(t, c);
+                for (int r = 0; r < k; ++r) {          /* M <- M J (columns p, q) */
+                    dd_t mp = M[r * k + p], mq = M[r * k + q];
+                    M[r * k + p] = dd_sub(dd_mul(c, mp), dd_mul(sn, mq));
+                    M[r * k + q] = dd_add(dd_mul(sn, mp), dd_mul(c, mq));
+                }
+                for (int r = 0; r < k; ++r) {          /* M <- J^T M (rows p, q) */
+                    dd_t mp = M[p * k + r], mq = M[q * k + r];
+                    M[p * k + r] = dd_sub(dd_mul(c, mp), dd_mul(sn, mq));
+                    M[q * k + r] = dd_add(dd_mul(sn, mp), dd_mul(c, mq));
+                }
+                for (int r = 0; r < k; ++r) {          /* Q <- Q J */
+                    dd_t qp = Q[r * k + p], qq = Q[r * k + q];
+                    Q[r * k + p] = dd_sub(dd_mul(c, qp), dd_mul(sn, qq));
+                    Q[r * k + q] = dd_add(dd_mul(sn, qp), dd_mul(c, qq));
+                }
+            }
+    }
+}
+
+/* Replaces the first-order columns of E for every linked group (see the file
+   header). Group members are kept in ascending index order c_0 < ... < c_{k-1};
+   each member column receives the Ritz vector closest to it (largest entry
+   first) with the sign that makes its own entry positive. For a member column
+   c_b with Ritz vector y and
+   value mu:  e_{c_a c_b} = y_a - [a == b]  and, for rows i outside the group,
+   e_{i c_b} = (sum_a w_{i c_a} y_a) / (mu - lambda_i). */
+static int grouped_correction(int n, const double *Xh, const double *Xl, const dd_t *lam,
+                              const double *Wh, const double *Wl, double *Eh, double *El,
+                              double tau, int *groups_out)
+{
+    int *par = (int *)malloc(sizeof(int) * n);
+    int *size = (int *)calloc((size_t)n, sizeof(int));
+    if (!par || !size) return -5;
+    for (int j = 0; j < n; ++j) par[j] = j;
+    /* link column j to the row of its largest off-diagonal |e_ij| (first index on ties) */
+    for (int j = 0; j < n; ++j) {
+        int best = -1;
+        double bv = -1.0;
+        for (int i = 0; i < n; ++i) {
+            if (i == j) continue;
+            double v = fabs(Eh[IX(i, j, n)]);
+            if (v > bv) { bv = v; best = i; }
+        }
+        if (best >= 0 && bv > tau) {
+            int a = uf_find(par, j), b = uf_find(par, best);
+            if (a != b) par[a < b ? b : a] = a < b ? a : b;
+        }
+    }
+    for (int j = 0; j < n; ++j) size[uf_find(par, j)]++;
+    int ngroups = 0, status = 0;
+    int *mem = (int *)malloc(sizeof(int) * OR_GROUP_MAX);
+    dd_t *G = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *T = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *L = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *M = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *Q = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *Y = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *mu = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX);
+    dd_t *Ynew = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX * OR_GROUP_MAX);
+    dd_t *munew = (dd_t *)malloc(sizeof(dd_t) * OR_GROUP_MAX);
+    dd_t *Ecol = (dd_t *)malloc(sizeof(dd_t) * (size_t)n * OR_GROUP_MAX);
+    if (!mem || !G || !T || !L || !M || !Q || !Y || !mu || !Ynew || !munew || !Ecol) return -5;
+    for (int root = 0; root < n && status == 0; ++root) {
+        if (uf_find(par, root) != root || size[root] < 2 || size[root] > OR_GROUP_MAX) continue;
+        int k = 0;
+        for (int j = 0; j < n; ++j)
+            if (uf_find(par, j) == root) mem[k++] = j;
+        ++ngroups;
+        /* G = X_C^T X_C and T = W_CC + G_CC D_C, symmetrised */
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                const size_t ca = IX(0, mem[a], n), cb = IX(0, mem[b], n);
+                G[a * k + b] = dd_dot_cols(n, Xh + ca, Xl + ca, Xh + cb, Xl + cb);
+            }
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                size_t q = IX(mem[a], mem[b], n);
+                dd_t w = { Wh[q], Wl[q] };
+                T[a * k + b] = dd_add(w, dd_mul(G[a * k + b], lam[mem[b]]));
+            }
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b) {
+                dd_t avg = dd_add(T[a * k + b], T[b * k + a]);
+                avg.hi *= 0.5; avg.lo *= 0.5;
+                T[a * k + b] = avg; T[b * k + a] = avg;
+            }
+        /* Cholesky G = L L^T */
+        for (int a = 0; a < k * k; ++a) L[a] = dd_from(0.0);
+        for (int a = 0; a < k && status == 0; ++a) {
+            dd_t d = G[a * k + a];
+            for (int c = 0; c < a; ++c) d = dd_sub(d, dd_mul(L[a * k + c], L[a * k + c]));
+            if (!(d.hi > 0.0)) { status = -3; break; }
+            L[a * k + a] = dd_sqrt(d);
+            for (int b = a + 1; b < k; ++b) {
+                dd_t v = G[b * k + a];
+                for (int c = 0; c < a; ++c) v = dd_sub(v, dd_mul(L[b * k + c], L[a * k + c]));
+                L[b * k + a] = dd_div(v, L[a * k + a]);
+            }
+        }
+        if (status != 0) break;
+        /* M = L^-1 T L^-T: forward substitution on the columns, then on the rows */
+        for (int b = 0; b < k; ++b)
+            for (int a = 0; a < k; ++a) {
+                dd_t v = T[a * k + b];
+                for (int c = 0; c < a; ++c) v = dd_sub(v, dd_mul(L[a * k + c], M[c * k + b]));
+                M[a * k + b] = dd_div(v, L[a * k + a]);
+            }
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                dd_t v = M[a * k + b];
+                for (int c = 0; c < b; ++c) v = dd_sub(v, dd_mul(T[a * k + c], L[b * k + c]));
+                T[a * k + b] = dd_div(v, L[b * k + b]);   /* T now holds M */
+            }
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) M[a * k + b] = T[a * k + b];
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b) {
+                dd_t avg = dd_add(M[a * k + b], M[b * k + a]);
+                avg.hi *= 0.5; avg.lo *= 0.5;
+                M[a * k + b] = avg; M[b * k + a] = avg;
+            }
+        dd_jacobi(k, M, Q);
+        /* Y = L^-T Q: back substitution */
+        for (int b = 0; b < k; ++b)
+            for (int a = k - 1; a >= 0; --a) {
+                dd_t v = Q[a * k + b];
+                for (int c = a + 1; c < k; ++c) v = dd_sub(v, dd_mul(L[c * k + a], Y[c * k + b]));
+                Y[a * k + b] = dd_div(v, L[a * k + a]);
+            }
+        for (int b = 0; b < k; ++b) mu[b] = M[b * k + b];
+        /* assignment: repeatedly give the Ritz vector with the largest remaining entry
+           |y_a| (over unassigned members a and vectors) to member a, so that each column
+           keeps the Ritz vector closest to it (first indices on ties) */
+        int used_v[OR_GROUP_MAX], used_c[OR_GROUP_MAX];
+        for (int a = 0; a < k; ++a) { used_v[a] = 0; used_c[a] = 0; }
+        for (int step = 0; step < k; ++step) {
+            int ba = -1, bv = -1;
+            double best = -1.0;
+            for (int a = 0; a < k; ++a) {
+                if (used_c[a]) continue;
+                for (int v = 0; v < k; ++v) {
+                    if (used_v[v]) continue;
+                    double x = fabs(Y[a * k + v].hi);
+                    if (x > best) { best = x; ba = a; bv = v; }
+                }
+            }
+            used_c[ba] = 1; used_v[bv] = 1;
+            munew[ba] = mu[bv];
+            const int flip = Y[ba * k + bv].hi < 0.0;
+            for (int r = 0; r < k; ++r) Ynew[r * k + ba] = flip ? dd_neg(Y[r * k + bv]) : Y[r * k + bv];
+        }
+        /* new columns of E for the members */
+        for (int b = 0; b < k; ++b) {
+            dd_t *ec = Ecol + (size_t)b * n;
+            for (int i = 0; i < n; ++i) {
+                int in_group = -1;
+                for (int a = 0; a < k; ++a)
+                    if (mem[a] == i) in_group = a;
+                if (in_group >= 0) {
+                    dd_t y = Ynew[in_group * k + b];
+                    ec[i] = (in_group == b) ? dd_sub(y, dd_from(1.0)) : y;
+                } else {
+                    dd_t num = dd_from(0.0);
+                    for (int a = 0; a < k; ++a) {
+                        size_t q = IX(i, mem[a], n);
+                        dd_t w = { Wh[q], Wl[q] };
+                        num = dd_add(num, dd_mul(w, Ynew[a * k + b]));
+                    }
+                    dd_t den = dd_sub(munew[b], lam[i]);
+                    if (den.hi == 0.0) { status = -3; break; }
+                    ec[i] = dd_div(num, den);
+                }
+            }
+        }
+        for (int b = 0; b < k && status == 0; ++b)
+            for (int i = 0; i < n; ++i) {
+                size_t q = IX(i, mem[b], n);
+                Eh[q] = Ecol[(size_t)b * n + i].hi;
+                El[q] = Ecol[(size_t)b * n + i].lo;
+            }
+    }
+    if (groups_out) *groups_out = ngroups;
+    free(par); free(size); free(mem); free(G); free(T); free(L); free(M); free(Q); free(Y);
+    free(mu); free(Ynew); free(munew); free(Ecol);
     return status;
 }
 
@@ -424,10 +690,26 @@ int or_beta_rule(int n, const double *lam, const double *X, int ldx, double delt
 /* Outputs: X1 (FP64), Xnew_h/Xnew_l, lam_h/lam_l (Rayleigh quotients of     */
 /* X^(1)), r_h, emax, beta, kx.                                              */
 /* ------------------------------------------------------------------------ */
+int or_method_step_grouped(int n, const double *A, const double *X, const double *lam_prev,
+                           double delta, double xi, int kx_max, int kx_force,
+                           double *X1, double *Xnew_h, double *Xnew_l, double *lam_h,
+                           double *lam_l, double *r_h, double *emax, int *beta_out, int *kx_out,
+                           double tau, int *groups_out);
+
 int or_method_step(int n, const double *A, const double *X, const double *lam_prev,
                    double delta, double xi, int kx_max, int kx_force,
                    double *X1, double *Xnew_h, double *Xnew_l, double *lam_h, double *lam_l,
                    double *r_h, double *emax, int *beta_out, int *kx_out)
+{
+    return or_method_step_grouped(n, A, X, lam_prev, delta, xi, kx_max, kx_force, X1, Xnew_h,
+                                  Xnew_l, lam_h, lam_l, r_h, emax, beta_out, kx_out, 0.0, NULL);
+}
+
+int or_method_step_grouped(int n, const double *A, const double *X, const double *lam_prev,
+                           double delta, double xi, int kx_max, int kx_force,
+                           double *X1, double *Xnew_h, double *Xnew_l, double *lam_h,
+                           double *lam_l, double *r_h, double *emax, int *beta_out, int *kx_out,
+                           double tau, int *groups_out)
 {
     int beta = 0, kx = 0;
     int st = or_beta_rule(n, lam_prev, X, n, delta, xi, kx_max, &beta, &kx, NULL, NULL, NULL);
@@ -442,7 +724,8 @@ int or_method_step(int n, const double *A, const double *X, const double *lam_pr
     free(ex); free(pl);
     if (st != 0) return st;
     for (size_t q = 0; q < nn; ++q) { Xnew_h[q] = X1[q]; Xnew_l[q] = 0.0; }
-    return or_refine_dd_step(n, A, Xnew_h, Xnew_l, lam_h, lam_l, r_h, NULL, emax);
+    return or_refine_dd_step_grouped(n, A, Xnew_h, Xnew_l, lam_h, lam_l, r_h, NULL, emax, tau,
+                                     groups_out);
 }
 
 /* ------------------------------------------------------------------------ */

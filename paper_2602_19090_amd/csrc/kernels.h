@@ -66,9 +66,30 @@ void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *d
 // W epilogue (column j per block): W_ij = sum_d 2^(eX_i + eR_j - 7d) C_d(i, j),
 //   e_ij = W_ij / (lambda_j - lambda_i), e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
 //   eE_j (exponent of column j of E'), emax_j = max_i |e_ij|, ke digit planes of E'.
+// eb_idx / eb_val (may be null): per column j the row i != j of the largest |e_ij| (smallest
+// row on ties; -1 if none) and that value.
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
-                  double *emax, int8_t *Eplanes, int ke, int *flags, hipStream_t s);
+                  double *emax, int8_t *Eplanes, int ke, int *flags, hipStream_t s,
+                  int *eb_idx = nullptr, double *eb_val = nullptr);
+
+// Grouped correction (Rayleigh-Ritz on strongly coupled columns). Groups hold at most
+// kGroupMax members.
+constexpr int kGroupMax = 32;
+// For listed pairs q: gh/gl[q] = x_a^T x_b (double-word, columns of X1), wab[q] = w_ab
+// (entry of W from the slots, as the W epilogue sums it), a = pa[q], b = pb[q].
+void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                       const int *eX, const int *eR, const double *X1, int n, const int *pa,
+                       const int *pb, int npairs, double *gh, double *gl, double *wab,
+                       hipStream_t s);
+// For each of nmem member slots m: column gcol[m], the group's slots start at gfirst[m],
+// it has gk[m] members, this member is number gpos[m]; Ritz vectors row-major at
+// Y + gbase[m], Ritz value mu[m]. Rewrites that column's E' planes, eE and emax.
+void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                      const int *eX, const int *eR, const double *lam, int n, const int *gcol,
+                      const int *gfirst, const int *gk, const int *gpos, const int *gbase,
+                      const double *Y, const double *mu, int nmem, int *eE, double *emax,
+                      int8_t *Eplanes, int ke, int *flags, hipStream_t s);
 
 // Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j); column j
 // is written to column colmap[j] of X (colmap may be null).

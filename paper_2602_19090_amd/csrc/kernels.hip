@@ -18,6 +18,7 @@
 #include <hip/hip_ext.h>
 
 #include <float.h>
+#include <limits.h>
 #include <type_traits>
 
 namespace refeig {
@@ -138,6 +139,20 @@ __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
 #pragma unroll
   for (int q = 1; q < NT / 64; ++q) s = dd_add(s, ddv{scratch[2 * q], scratch[2 * q + 1]});
   return s;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_min_int(int v, int *scratch) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[w] = v;
+  __syncthreads();
+  int m = scratch[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) m = min(m, scratch[q]);
+  return m;
 }
 
 // ---------------------------------------------------------------- column statistics
@@ -583,6 +598,31 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
 
 int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
 
+// Digit planes of one operand row j (an output column of a column epilogue): the values
+// v (EPT per thread, row i = tid + kEpiThreads q; zero beyond n) with column maximum ms,
+// exponent exp_above(ms), written K-blocked for rows i < npad.
+template <int EPT>
+__device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double ms, int j, int npad,
+                                                 int8_t *__restrict__ planes, int k) {
+  const size_t P = (size_t)npad * npad;
+  const int ee = exp_above(ms);
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = threadIdx.x + kEpiThreads * q;
+    if (i < npad) {
+      const double a = v[q];
+      double y = ldexp(fabs(a), -ee);
+      const int sg = (a < 0.0) ? -1 : 1;
+      for (int t = 0; t < k; ++t) {
+        double t128 = y * 128.0;
+        double dgt = floor(t128);
+        y = t128 - dgt;
+        planes[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- V epilogue + column pass
 template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
@@ -716,8 +756,9 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ r, int n, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
-    int *flags) {
+    int *flags, int *eb_idx, double *eb_val) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
+  __shared__ int iscratch[kEpiThreads / 64];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
@@ -752,8 +793,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 #pragma unroll
     for (int q = 0; q < EPT; ++q) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
   }
-  double ms = 0.0, mr = 0.0;
-  int tie = 0;
+  double ms = 0.0, mr = 0.0, bv = -1.0;
+  int tie = 0, bi = INT_MAX;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
@@ -772,6 +813,10 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
         } else {
           e = w / den;
         }
+        if (fabs(e) > bv) {   // rows visited in ascending order: first index on ties
+          bv = fabs(e);
+          bi = i;
+        }
       }
       mr = fmax(mr, fabs(e));
       const double es = ldexp(e, ei);
@@ -782,24 +827,18 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   if (tie) atomicOr(flags, FLAG_TIE);
   ms = block_max<kEpiThreads>(ms, scratch);
   mr = block_max<kEpiThreads>(mr, scratch);
-  const int ee = exp_above(ms);
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
-    if (i < npad) {
-      const double a = ev[q];
-      double y = ldexp(fabs(a), -ee);
-      const int sg = (a < 0.0) ? -1 : 1;
-      for (int t = 0; t < ke; ++t) {
-        double t128 = y * 128.0;
-        double dgt = floor(t128);
-        y = t128 - dgt;
-        Epl[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
-      }
+  if (eb_idx) {
+    // largest off-diagonal |e_ij| of the column and its row (smallest row on ties)
+    const double bmax = block_max<kEpiThreads>(bv, scratch);
+    const int cand = block_min_int<kEpiThreads>(bv == bmax ? bi : INT_MAX, iscratch);
+    if (tid == 0) {
+      eb_idx[j] = cand == INT_MAX ? -1 : cand;
+      eb_val[j] = bmax;
     }
   }
+  write_col_planes<EPT>(ev, ms, j, npad, Epl, ke);
   if (tid == 0) {
-    eE[j] = ee;
+    eE[j] = exp_above(ms);
     emax[j] = mr;
     if (!(mr <= DBL_MAX)) atomicOr(flags, FLAG_NONFINITE);
   }
@@ -808,19 +847,160 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 template <int EPT>
 static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eX, const int *eR, const double *lam, const double *r, int n,
-                    int *eE, double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s) {
+                    int *eE, double *emax, int8_t *Epl, int ke, int *flags, int *eb_idx,
+                    double *eb_val, hipStream_t s) {
   hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
-                     eX, eR, lam, r, n, eE, emax, Epl, ke, flags);
+                     eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val);
 }
 
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
-                  double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s) {
+                  double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, int *eb_idx,
+                  double *eb_val) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, s);
+  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+}
+
+// ---------------------------------------------------------------- grouped correction
+// Entry w_ij of W = X^(1)T Res, summed from the slots exactly as the W epilogue sums it
+// (smallest scale first, FP64), so both see the same value.
+__device__ __forceinline__ double w_entry(const int32_t *__restrict__ C, size_t P, int npad,
+                                          int d_min, int ndiag, int scale, int i, int j) {
+  const int32_t *Ccol = C + (size_t)j * npad + i;
+  double w = 0.0;
+  for (int qq = ndiag - 1; qq >= 0; --qq)
+    w += ldexp((double)Ccol[(size_t)qq * P], scale - 7 * (d_min + qq));
+  return w;
+}
+
+// One block per listed pair (a, b): the double-word dot product x_a^T x_b of two columns
+// of X^(1) and the entry w_ab.
+__global__ __launch_bounds__(256) void k_group_gram(
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ X1, int n,
+    const int *__restrict__ pa, const int *__restrict__ pb, double *gh, double *gl, double *wab) {
+  __shared__ double scratch[2 * 4];
+  const int q = blockIdx.x, a = pa[q], b = pb[q];
+  const double *xa = X1 + (size_t)a * n, *xb = X1 + (size_t)b * n;
+  ddv acc = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double p, pe;
+    two_prod(xa[i], xb[i], p, pe);
+    acc = dd_add_prod(acc, p, pe);
+  }
+  acc = block_dd_sum<256>(acc, scratch);
+  if (threadIdx.x == 0) {
+    gh[q] = acc.h;
+    gl[q] = acc.l;
+    const int nd = dcut ? min(ndiag_all, dcut[b] - d_min + 1) : ndiag_all;
+    wab[q] = w_entry(C, (size_t)npad * npad, npad, d_min, nd, eX[a] + eR[b], a, b);
+  }
+}
+
+void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                       const int *eX, const int *eR, const double *X1, int n, const int *pa,
+                       const int *pb, int npairs, double *gh, double *gl, double *wab,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_group_gram, dim3(npairs), dim3(256), 0, s, C, npad, d_min, ndiag, dcut, eX,
+                     eR, X1, n, pa, pb, gh, gl, wab);
+}
+
+// One block per group member: its new correction column, from the group's Ritz vectors
+// Y (row-major k x k at Y + base) and Ritz values mu (per member):
+//   e_{c_a, c_pos} = Y[a][pos] - [a == pos]                       (rows in the group)
+//   e_{i, c_pos} = (sum_a w_{i c_a} Y[a][pos]) / (mu - lambda_i)    (other rows)
+// then, as in the W epilogue, E' = 2^(eX_i) e, its exponent, maximum and digit planes.
+template <int EPT>
+__global__ __launch_bounds__(kEpiThreads) void k_group_fix(
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam, int n,
+    const int *__restrict__ gcol, const int *__restrict__ gfirst, const int *__restrict__ gk,
+    const int *__restrict__ gpos, const int *__restrict__ gbase, const double *__restrict__ Y,
+    const double *__restrict__ mu, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
+    int *flags) {
+  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  __shared__ int smem[kGroupMax], snd[kGroupMax], ser[kGroupMax];
+  __shared__ double sy[kGroupMax];
+  const int m = blockIdx.x, tid = threadIdx.x;
+  const int j = gcol[m], k = gk[m], pos = gpos[m], first = gfirst[m];
+  const double muj = mu[m];
+  if (tid < k) {
+    const int c = gcol[first + tid];
+    smem[tid] = c;
+    snd[tid] = dcut ? min(ndiag_all, dcut[c] - d_min + 1) : ndiag_all;
+    ser[tid] = eR[c];
+    sy[tid] = Y[gbase[m] + tid * k + pos];
+  }
+  __syncthreads();
+  const size_t P = (size_t)npad * npad;
+  double ev[EPT];
+  double ms = 0.0, mr = 0.0;
+  int tie = 0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    ev[q] = 0.0;
+    if (i < n) {
+      int in = -1;
+      for (int a = 0; a < k; ++a)
+        if (smem[a] == i) in = a;
+      double e;
+      if (in >= 0) {
+        e = (in == pos) ? sy[in] - 1.0 : sy[in];
+      } else {
+        double num = 0.0;
+        const int ei = eX[i];
+        for (int a = 0; a < k; ++a)
+          num += w_entry(C, P, npad, d_min, snd[a], ei + ser[a], i, smem[a]) * sy[a];
+        const double den = muj - lam[i];
+        if (den == 0.0) {
+          tie = 1;
+          e = 0.0;
+        } else {
+          e = num / den;
+        }
+      }
+      mr = fmax(mr, fabs(e));
+      const double es = ldexp(e, eX[i]);
+      ev[q] = es;
+      ms = fmax(ms, fabs(es));
+    }
+  }
+  if (tie) atomicOr(flags, FLAG_TIE);
+  ms = block_max<kEpiThreads>(ms, scratch);
+  mr = block_max<kEpiThreads>(mr, scratch);
+  write_col_planes<EPT>(ev, ms, j, npad, Epl, ke);
+  if (tid == 0) {
+    eE[j] = exp_above(ms);
+    emax[j] = mr;
+    if (!(mr <= DBL_MAX)) atomicOr(flags, FLAG_NONFINITE);
+  }
+}
+
+template <int EPT>
+static void group_fix_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                        const int *eX, const int *eR, const double *lam, int n, const int *gcol,
+                        const int *gfirst, const int *gk, const int *gpos, const int *gbase,
+                        const double *Y, const double *mu, int nmem, int *eE, double *emax,
+                        int8_t *Epl, int ke, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_fix<EPT>, dim3(nmem), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag,
+                     dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, eE, emax, Epl, ke,
+                     flags);
+}
+
+void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
+                      const int *eX, const int *eR, const double *lam, int n, const int *gcol,
+                      const int *gfirst, const int *gk, const int *gpos, const int *gbase,
+                      const double *Y, const double *mu, int nmem, int *eE, double *emax,
+                      int8_t *Epl, int ke, int *flags, hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+  if (ept <= 1) group_fix_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 2) group_fix_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 4) group_fix_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
+  else group_fix_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
 }
 
 // ---------------------------------------------------------------- update X <- X1 + X1 E~

@@ -59,10 +59,15 @@ struct Work {
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
   int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
   int *colmap;   // working column p holds column colmap[p] of the caller's X
+  // grouped correction: per column argmax of |e_ij|, pair list, member table, Ritz data
+  int *eb_idx, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;
+  double *eb_val, *g_gh, *g_gl, *g_w, *g_Y, *g_mu;
   double *mxA, *mxX, *lam, *r, *resmax, *emax;
 };
 
 int nslots(int ka) { return std::max(ka, kKrMax + kKxMax); }
+
+constexpr int kGroupColsMax = 1024;   // group members corrected per iteration (at most)
 
 // Carves the workspace; returns the bytes needed (base may be null).
 size_t carve(int n, int ka, char *base, Work *w) {
@@ -94,6 +99,21 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.flags = (int *)take(256);
   for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
   t.colmap = (int *)take(vi);
+  t.eb_idx = (int *)take(vi);
+  t.eb_val = (double *)take(vd);
+  const size_t npr = (size_t)kGroupColsMax * kGroupMax;
+  t.g_pa = (int *)take(sizeof(int) * npr);
+  t.g_pb = (int *)take(sizeof(int) * npr);
+  t.g_gh = (double *)take(sizeof(double) * npr);
+  t.g_gl = (double *)take(sizeof(double) * npr);
+  t.g_w = (double *)take(sizeof(double) * npr);
+  t.g_Y = (double *)take(sizeof(double) * npr);
+  t.g_col = (int *)take(sizeof(int) * kGroupColsMax);
+  t.g_first = (int *)take(sizeof(int) * kGroupColsMax);
+  t.g_k = (int *)take(sizeof(int) * kGroupColsMax);
+  t.g_pos = (int *)take(sizeof(int) * kGroupColsMax);
+  t.g_base = (int *)take(sizeof(int) * kGroupColsMax);
+  t.g_mu = (double *)take(sizeof(double) * kGroupColsMax);
   t.mxA = (double *)take(vd);
   t.mxX = (double *)take(vd);
   t.lam = (double *)take(vd);
@@ -197,6 +217,175 @@ void launch_plan(const CutPlan &plan, const int8_t *Lp, const int8_t *Rp, size_t
     launch_slice_gemm(Lp, Rp, P, npad, kl, kr, 2, plan.groups[q].first - 1, C,
                       &plan.groups[q].second, s, q == 0 ? ev_start : nullptr,
                       q + 1 == ng ? ev_stop : nullptr);
+}
+
+// ---------------------------------------------------------------- grouped correction (host)
+// Double-word arithmetic for the small Rayleigh-Ritz problems (k <= kGroupMax).
+struct HD {
+  double h, l;
+};
+inline HD hd(double a) { return {a, 0.0}; }
+inline HD hd_two_sum(double a, double b) {
+  double s = a + b, z = s - a;
+  return {s, (a - (s - z)) + (b - z)};
+}
+inline HD hd_norm(double h, double l) {
+  double s = h + l;
+  return {s, l - (s - h)};
+}
+inline HD hd_add(HD a, HD b) {
+  HD s = hd_two_sum(a.h, b.h);
+  HD t = hd_two_sum(a.l, b.l);
+  s.l += t.h;
+  s = hd_norm(s.h, s.l);
+  s.l += t.l;
+  return hd_norm(s.h, s.l);
+}
+inline HD hd_neg(HD a) { return {-a.h, -a.l}; }
+inline HD hd_sub(HD a, HD b) { return hd_add(a, hd_neg(b)); }
+inline HD hd_mul(HD a, HD b) {
+  double p = a.h * b.h;
+  double e = std::fma(a.h, b.h, -p);
+  e += a.h * b.l + a.l * b.h;
+  return hd_norm(p, e);
+}
+inline HD hd_div(HD a, HD b) {
+  double q1 = a.h / b.h;
+  HD r = hd_sub(a, hd_mul(b, hd(q1)));
+  double q2 = r.h / b.h;
+  r = hd_sub(r, hd_mul(b, hd(q2)));
+  double q3 = r.h / b.h;
+  return hd_add(hd_norm(q1, q2), hd(q3));
+}
+inline HD hd_sqrt(HD a) {
+  if (!(a.h > 0.0)) return hd(0.0);
+  double x = std::sqrt(a.h);
+  HD r = hd_sub(a, hd_mul(hd(x), hd(x)));
+  return hd_norm(x, r.h / (2.0 * x));
+}
+inline bool hd_less(HD a, HD b) { return a.h < b.h || (a.h == b.h && a.l < b.l); }
+
+// Ritz pairs of one group: G (k x k, double-word Gram matrix of the members' columns),
+// Wg (k x k, w_ab), lamg (current eigenvalue estimates). T = W + G diag(lambda),
+// symmetrised; T y = mu G y through the Cholesky factor of G and cyclic Jacobi
+// rotations. Each member keeps the Ritz vector with its largest entry (greedily, first
+// indices on ties), signed so that entry is positive. Y row-major, Y[a][b] = entry a of
+// member b's vector. Returns false if G is not positive definite.
+bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
+                const std::vector<double> &lamg, double *Y, double *mu) {
+  std::vector<HD> T(k * k), L(k * k, hd(0.0)), M(k * k), Q(k * k), Z(k * k);
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) T[a * k + b] = hd_add(hd(Wg[a * k + b]), hd_mul(G[a * k + b], hd(lamg[b])));
+  for (int a = 0; a < k; ++a)
+    for (int b = a + 1; b < k; ++b) {
+      HD m = hd_add(T[a * k + b], T[b * k + a]);
+      m = {0.5 * m.h, 0.5 * m.l};
+      T[a * k + b] = T[b * k + a] = m;
+    }
+  for (int a = 0; a < k; ++a) {
+    HD d = G[a * k + a];
+    for (int c = 0; c < a; ++c) d = hd_sub(d, hd_mul(L[a * k + c], L[a * k + c]));
+    if (!(d.h > 0.0)) return false;
+    L[a * k + a] = hd_sqrt(d);
+    for (int b = a + 1; b < k; ++b) {
+      HD v = G[b * k + a];
+      for (int c = 0; c < a; ++c) v = hd_sub(v, hd_mul(L[b * k + c], L[a * k + c]));
+      L[b * k + a] = hd_div(v, L[a * k + a]);
+    }
+  }
+  // Z = L^-1 T, then M = Z L^-T
+  for (int b = 0; b < k; ++b)
+    for (int a = 0; a < k; ++a) {
+      HD v = T[a * k + b];
+      for (int c = 0; c < a; ++c) v = hd_sub(v, hd_mul(L[a * k + c], Z[c * k + b]));
+      Z[a * k + b] = hd_div(v, L[a * k + a]);
+    }
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) {
+      HD v = Z[a * k + b];
+      for (int c = 0; c < b; ++c) v = hd_sub(v, hd_mul(M[a * k + c], L[b * k + c]));
+      M[a * k + b] = hd_div(v, L[b * k + b]);
+    }
+  for (int a = 0; a < k; ++a)
+    for (int b = a + 1; b < k; ++b) {
+      HD m = hd_add(M[a * k + b], M[b * k + a]);
+      m = {0.5 * m.h, 0.5 * m.l};
+      M[a * k + b] = M[b * k + a] = m;
+    }
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) Q[a * k + b] = hd(a == b ? 1.0 : 0.0);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double dmax = 0.0, off = 0.0;
+    for (int a = 0; a < k; ++a) dmax = std::max(dmax, std::fabs(M[a * k + a].h));
+    for (int a = 0; a < k; ++a)
+      for (int b = a + 1; b < k; ++b) off = std::max(off, std::fabs(M[a * k + b].h));
+    if (off == 0.0 || off <= 1e-32 * dmax) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const HD apq = M[p * k + q];
+        if (apq.h == 0.0) continue;
+        const HD th = hd_div(hd_sub(M[q * k + q], M[p * k + p]), {2.0 * apq.h, 2.0 * apq.l});
+        const HD at = th.h < 0.0 ? hd_neg(th) : th;
+        HD t = at.h > 1e30 ? hd_div(hd(0.5), at)
+                           : hd_div(hd(1.0), hd_add(at, hd_sqrt(hd_add(hd_mul(at, at), hd(1.0)))));
+        if (th.h < 0.0) t = hd_neg(t);
+        const HD c = hd_div(hd(1.0), hd_sqrt(hd_add(hd_mul(t, t), hd(1.0))));
+        const HD sn = hd_mul(t, c);
+        for (int r = 0; r < k; ++r) {
+          const HD mp = M[r * k + p], mq = M[r * k + q];
+          M[r * k + p] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
+          M[r * k + q] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
+        }
+        for (int r = 0; r < k; ++r) {
+          const HD mp = M[p * k + r], mq = M[q * k + r];
+          M[p * k + r] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
+          M[q * k + r] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
+        }
+        for (int r = 0; r < k; ++r) {
+          const HD qp = Q[r * k + p], qq = Q[r * k + q];
+          Q[r * k + p] = hd_sub(hd_mul(c, qp), hd_mul(sn, qq));
+          Q[r * k + q] = hd_add(hd_mul(sn, qp), hd_mul(c, qq));
+        }
+      }
+  }
+  // Ritz vectors V = L^-T Q (columns), by back substitution
+  std::vector<HD> V(k * k);
+  for (int b = 0; b < k; ++b)
+    for (int a = k - 1; a >= 0; --a) {
+      HD v = Q[a * k + b];
+      for (int c = a + 1; c < k; ++c) v = hd_sub(v, hd_mul(L[c * k + a], V[c * k + b]));
+      V[a * k + b] = hd_div(v, L[a * k + a]);
+    }
+  std::vector<char> used_v(k, 0), used_c(k, 0);
+  for (int step = 0; step < k; ++step) {
+    int ba = -1, bv = -1;
+    double best = -1.0;
+    for (int a = 0; a < k; ++a) {
+      if (used_c[a]) continue;
+      for (int v = 0; v < k; ++v) {
+        if (used_v[v]) continue;
+        const double x = std::fabs(V[a * k + v].h);
+        if (x > best) {
+          best = x;
+          ba = a;
+          bv = v;
+        }
+      }
+    }
+    used_c[ba] = used_v[bv] = 1;
+    mu[ba] = M[bv * k + bv].h;
+    const double sg = V[ba * k + bv].h < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < k; ++r) Y[r * k + ba] = sg * V[r * k + bv].h;
+  }
+  return true;
+}
+
+int uf_root(std::vector<int> &par, int a) {
+  while (par[a] != a) {
+    par[a] = par[par[a]];
+    a = par[a];
+  }
+  return a;
 }
 
 // beta of Sec. 4.1 (floor form): beta = floor(log2((1/(0.75u)) sqrt(xi delta g / (L S)))),
@@ -534,6 +723,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   if (rep) std::memset(rep, 0, sizeof(*rep));
   if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
+      !(o.group_tau >= 0.0) ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -563,8 +753,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   int status = REFEIG_OK;
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
   std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
-  std::vector<double> gaps_nat;
-  std::vector<int> cmap(n);
+  std::vector<double> gaps_nat, eb_val(n);
+  std::vector<int> cmap(n), eb_idx(n);
   int hflags = 0;
   hipEvent_t ev[8];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -695,14 +885,97 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const double pw = plan.pairs_eff;
     const int lw = (int)plan.groups.size();
     launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
+    const bool grouping = o.group_tau > 0.0;
     launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP,
-                 kKeMax, w.flags, s);
+                 kKeMax, w.flags, s, grouping ? w.eb_idx : nullptr,
+                 grouping ? w.eb_val : nullptr);
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (grouping) {
+      STEP(hipMemcpyAsync(eb_idx.data(), w.eb_idx, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+      STEP(hipMemcpyAsync(eb_val.data(), w.eb_val, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    }
     STEP(hipStreamSynchronize(s));
     if (hflags & FLAG_TIE) return cleanup(REFEIG_E_GAP);
     if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    // ---- grouped correction (opt-in; not part of the paper's method): columns whose
+    // largest first-order correction exceeds group_tau are linked to that row; each linked
+    // group gets the Rayleigh-Ritz solution on its span instead of the first-order entries
+    int ngroups = 0;
+    if (grouping) {
+      std::vector<int> par(n);
+      for (int j = 0; j < n; ++j) par[j] = j;
+      for (int j = 0; j < n; ++j)
+        if (eb_idx[j] >= 0 && eb_val[j] > o.group_tau) {
+          int a = uf_root(par, j), b = uf_root(par, eb_idx[j]);
+          if (a != b) par[std::max(a, b)] = std::min(a, b);
+        }
+      std::vector<std::vector<int>> comp(n);
+      for (int j = 0; j < n; ++j) comp[uf_root(par, j)].push_back(j);
+      std::vector<int> gcol, gfirst, gk, gpos, gbase, pa, pb;
+      std::vector<int> gstart;   // first member slot of each group
+      int ybase = 0;
+      for (int root = 0; root < n; ++root) {
+        const int k = (int)comp[root].size();
+        if (k < 2 || k > kGroupMax || (int)gcol.size() + k > kGroupColsMax) continue;
+        const int first = (int)gcol.size();
+        gstart.push_back(first);
+        for (int a = 0; a < k; ++a) {
+          gcol.push_back(comp[root][a]);
+          gfirst.push_back(first);
+          gk.push_back(k);
+          gpos.push_back(a);
+          gbase.push_back(ybase);
+          for (int b = 0; b < k; ++b) {
+            pa.push_back(comp[root][a]);
+            pb.push_back(comp[root][b]);
+          }
+        }
+        ybase += k * k;
+      }
+      ngroups = (int)gstart.size();
+      if (ngroups > 0) {
+        const int nmem = (int)gcol.size(), npr = (int)pa.size();
+        STEP(hipMemcpyAsync(w.g_pa, pa.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_pb, pb.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
+        launch_group_gram(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.X1, n, w.g_pa, w.g_pb,
+                          npr, w.g_gh, w.g_gl, w.g_w, s);
+        std::vector<double> gh(npr), gl(npr), gw(npr), Yh(npr), muh(nmem);
+        STEP(hipMemcpyAsync(gh.data(), w.g_gh, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
+        STEP(hipMemcpyAsync(gl.data(), w.g_gl, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
+        STEP(hipMemcpyAsync(gw.data(), w.g_w, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
+        STEP(hipStreamSynchronize(s));
+        for (int g = 0; g < ngroups; ++g) {
+          const int first = gstart[g], k = gk[first], base = gbase[first];
+          std::vector<HD> G(k * k);
+          std::vector<double> Wg(k * k), lamg(k);
+          for (int q = 0; q < k * k; ++q) {
+            G[q] = {gh[base + q], gl[base + q]};
+            Wg[q] = gw[base + q];
+          }
+          for (int a = 0; a < k; ++a) lamg[a] = lam[gcol[first + a]];
+          if (!group_ritz(k, G, Wg, lamg, Yh.data() + base, muh.data() + first))
+            return cleanup(REFEIG_E_GAP);
+        }
+        STEP(hipMemcpyAsync(w.g_Y, Yh.data(), sizeof(double) * npr, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_mu, muh.data(), sizeof(double) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_col, gcol.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_first, gfirst.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_k, gk.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_pos, gpos.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_base, gbase.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
+        launch_group_fix(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, n, w.g_col,
+                         w.g_first, w.g_k, w.g_pos, w.g_base, w.g_Y, w.g_mu, nmem, w.eE, w.emax,
+                         w.EP, kKeMax, w.flags, s);
+        STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+        STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+        STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        STEP(hipStreamSynchronize(s));
+        if (hflags & FLAG_TIE) return cleanup(REFEIG_E_GAP);
+        if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+      }
+    }
     double eps = 0.0;
     for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
     // ---- X <- X^(1) + X^(1) E~
@@ -754,6 +1027,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->launches_p[it][0] = lv;
       rep->launches_p[it][1] = lw;
       rep->launches_p[it][2] = lu;
+      rep->groups[it] = ngroups;
       rep->iters = it + 1;
       rep->min_gap = gmin;
       rep->max_abs_lambda = lmax;

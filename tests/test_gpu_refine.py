@@ -279,3 +279,65 @@ def test_batched_error_paths():
     assert reps[0].status == rb.REFEIG_OK and reps[1].status == rb.REFEIG_E_NONFINITE
     with pytest.raises(ValueError):
         rb.batched_workspace_bytes([64, 0])
+
+
+def _mixed_start(p, pairs, angles):
+    """The FP64 eigensolve's start with some neighbouring column pairs rotated in their
+    plane: strongly mixed eigenvector pairs, as a badly resolved start has."""
+    X0 = p.X0.copy(order="F")
+    for (a, b), t in zip(pairs, angles):
+        c, s = np.cos(t), np.sin(t)
+        xa, xb = X0[:, a].copy(), X0[:, b].copy()
+        X0[:, a], X0[:, b] = c * xa + s * xb, -s * xa + c * xb
+    return X0
+
+
+@pytest.mark.parametrize("cfg,n", [(2, 300), (2, 1100)])
+def test_grouped_step_vs_oracle(cfg, n):
+    """One step with the grouped correction (group_tau = 1e-3) against the oracle's grouped
+    method step on a start with three badly mixed column pairs; spans npad < 1024 and the
+    256 x 256 kernel."""
+    import torch
+    rb = _rb()
+    target, tau = 1e-14, 1e-3
+    p = workloads.make_problem(cfg, n, x0="eigh")
+    pairs = [(5, 6), (n // 2, n // 2 + 1), (n - 3, n - 2)]
+    X0 = _mixed_start(p, pairs, [0.3, 0.2, 0.1])
+    A = rb.colmajor(p.A)
+    X = rb.colmajor(X0)
+    D = torch.from_numpy(np.array(p.D0)).cuda()
+    opts = rb.default_opts(fixed_iters=1, group_tau=tau)
+    st, rep = rb.refine_eigvecs(A, X, D, target, opts)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    ref = oracle.method_step(p.A, X0, p.D0, target / opts.delta_safety, tau=tau)
+    print(f"  groups gpu={rep.groups[0]} oracle={ref.groups} beta={ref.beta} kx={ref.kx}",
+          flush=True)
+    assert rep.groups[0] == ref.groups >= 3   # the three mixed pairs, plus any the start has
+    Xg = rb.from_colmajor(X)
+    diff = float(np.max(np.abs(Xg - ref.X_hi)))
+    print(f"  |X_gpu - X_oracle|max={diff:.3e}", flush=True)
+    assert diff <= target / opts.delta_safety
+
+
+def test_grouped_solve_from_mixed_start():
+    """Full solves from a start with badly mixed pairs: with grouping the target is met
+    against X_true in a few iterations; the paper's first-order step needs more."""
+    import torch
+    rb = _rb()
+    target = 1e-14
+    p = workloads.make_problem(3, 700, x0="eigh")
+    Xt, lt = _xtrue(p)
+    X0 = _mixed_start(p, [(10, 11), (300, 301), (650, 651)], [0.35, 0.25, 0.15])
+    res = {}
+    for tau in (0.0, 1e-3):
+        A, X = rb.colmajor(p.A), rb.colmajor(X0)
+        D = torch.from_numpy(np.array(p.D0)).cuda()
+        st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(group_tau=tau, max_iter=12))
+        r = rep.as_dict()
+        err = _fwd(rb.from_colmajor(X), Xt)
+        res[tau] = (st, r["iters"], err)
+        print(f"  tau={tau}: status={st} iters={r['iters']} groups={r['groups']} "
+              f"eps={['%.1e' % e for e in r['eps']]} fwd={err:.2e}", flush=True)
+    st, iters, err = res[1e-3]
+    assert st == rb.REFEIG_OK and err <= target
+    assert iters < res[0.0][1] or res[0.0][0] != rb.REFEIG_OK
