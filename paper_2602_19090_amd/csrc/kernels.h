@@ -56,21 +56,24 @@ int gemm_tile_rows(int npad);
 // Epilogues sum, for output column j, the diagonals d_min .. min(d_min+ndiag-1, dcut[j]).
 // V epilogue fused with the column pass of Algorithm 1 (column j per block):
 //   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),
-//   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots),
-//   Res_ij = V_ij - x_ij lambda_j (pair arithmetic),
+//   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots; lam gets
+//   the FP64 value, lam_lo its low word), Res_ij = V_ij - x_ij lambda_j (pair arithmetic),
 //   eR_j, resmax_j, and kr digit planes of Res (layout j*npad + i).
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
-                  int *eR, double *resmax, int8_t *Rplanes, int kr, int *flags, hipStream_t s);
+                  const int *eA, const int *eX, const double *X1, int n, double *lam,
+                  double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rplanes, int kr,
+                  int *flags, hipStream_t s);
 
 // W epilogue (column j per block): W_ij = sum_d 2^(eX_i + eR_j - 7d) C_d(i, j),
-//   e_ij = W_ij / (lambda_j - lambda_i), e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
+//   e_ij = W_ij / (lambda_j - lambda_i) (difference of the double-word values),
+//   e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
 //   eE_j (exponent of column j of E'), emax_j = max_i |e_ij|, ke digit planes of E'.
 // eb_idx / eb_val (may be null): per column j the row i != j of the largest |e_ij| (smallest
 // row on ties; -1 if none) and that value.
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
-                  double *emax, int8_t *Eplanes, int ke, int *flags, hipStream_t s,
+                  const int *eX, const int *eR, const double *lam, const double *lam_lo,
+                  const double *r, int n, int *eE, double *emax, int8_t *Eplanes, int ke,
+                  int *flags, hipStream_t s,
                   int *eb_idx = nullptr, double *eb_val = nullptr);
 
 // Grouped correction (Rayleigh-Ritz on strongly coupled columns). Groups hold at most
@@ -84,12 +87,13 @@ void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const i
                        hipStream_t s);
 // For each of nmem member slots m: column gcol[m], the group's slots start at gfirst[m],
 // it has gk[m] members, this member is number gpos[m]; Ritz vectors row-major at
-// Y + gbase[m], Ritz value mu[m]. Rewrites that column's E' planes, eE and emax.
+// Y + gbase[m], Ritz value mu[m] + mu_lo[m]. Rewrites that column's E' planes, eE and emax.
 void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                      const int *eX, const int *eR, const double *lam, int n, const int *gcol,
-                      const int *gfirst, const int *gk, const int *gpos, const int *gbase,
-                      const double *Y, const double *mu, int nmem, int *eE, double *emax,
-                      int8_t *Eplanes, int ke, int *flags, hipStream_t s);
+                      const int *eX, const int *eR, const double *lam, const double *lam_lo,
+                      int n, const int *gcol, const int *gfirst, const int *gk, const int *gpos,
+                      const int *gbase, const double *Y, const double *mu, const double *mu_lo,
+                      int nmem, int *eE, double *emax, int8_t *Eplanes, int ke, int *flags,
+                      hipStream_t s);
 
 // Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j); column j
 // is written to column colmap[j] of X (colmap may be null).

@@ -79,6 +79,27 @@ __device__ __forceinline__ double dd_div_to_d(ddv a, ddv b) {
   return q1 + q2;
 }
 
+// a / b to double-word: the FP64 quotient q1 (as dd_div_to_d) and its correction q2.
+__device__ __forceinline__ ddv dd_div_to_dd(ddv a, ddv b) {
+  double q1 = a.h / b.h;
+  double p, pe;
+  two_prod(q1, b.h, p, pe);
+  double s, e;
+  two_sum(a.h, -p, s, e);
+  e = ((e - pe) + a.l) - q1 * b.l;
+  double rem = s + e;
+  double q2 = rem / b.h;
+  ddv r;
+  fast_two_sum(q1, q2, r.h, r.l);
+  return r;
+}
+// (a_h + a_l) - (b_h + b_l) rounded to FP64, with the high parts subtracted exactly.
+__device__ __forceinline__ double dd_diff(double ah, double al, double bh, double bl) {
+  double s, e;
+  two_sum(ah, -bh, s, e);
+  return s + (e + (al - bl));
+}
+
 // floor(log2 v) + 1 for v > 0 (so v < 2^e), 0 for v == 0.
 __device__ __forceinline__ int exp_above(double v) {
   if (v == 0.0) return 0;
@@ -628,7 +649,8 @@ template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
-    double *lam, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl, int kr, int *flags) {
+    double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
+    int kr, int *flags) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -691,17 +713,19 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
   // r_j = 1 - x^T x,  lambda_j = x^T v / (1 - r_j)
   ddv rj = dd_add(ddv{1.0, 0.0}, ddv{-sx.h, -sx.l});
   ddv den = dd_add(ddv{1.0, 0.0}, ddv{-rj.h, -rj.l});
-  const double lj = dd_div_to_d(sv, den);
-  // residual in pair arithmetic: (vh + vl) - x * lambda
+  const ddv ljd = dd_div_to_dd(sv, den);
+  const double lj = ljd.h;
+  // residual in pair arithmetic: (vh + vl) - x * (lambda_hi + lambda_lo)
   double rmax = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
     if (i < n) {
       double p, pe, s, e;
-      two_prod(xcol[i], lj, p, pe);
+      const double x = xcol[i];
+      two_prod(x, lj, p, pe);
       two_sum(vh[q], -p, s, e);
-      const double res = s + ((e + vl[q]) - pe);
+      const double res = s + (((e + vl[q]) - pe) - x * ljd.l);
       vh[q] = res;
       rmax = fmax(rmax, fabs(res));
     }
@@ -725,6 +749,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
   }
   if (tid == 0) {
     lam[j] = lj;
+    lam_lo[j] = ljd.l;
     r[j] = rj.h;
     eR[j] = er;
     resmax[j] = rmax;
@@ -734,20 +759,20 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
 
 template <int EPT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                    const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
+                    const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                     int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
   hipLaunchKernelGGL(k_epi_v<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
-                     eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags);
+                     eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags);
 }
 
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eA, const int *eX, const double *X1, int n, double *lam, double *r,
+                  const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                   int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
-  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, r, eR, resmax, Rpl, kr, flags, s);
+  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
+  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
+  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
+  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
 }
 
 // ---------------------------------------------------------------- W epilogue -> E~
@@ -755,8 +780,8 @@ template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
-    const double *__restrict__ r, int n, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
-    int *flags, int *eb_idx, double *eb_val) {
+    const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
+    double *emax, int8_t *__restrict__ Epl, int ke, int *flags, int *eb_idx, double *eb_val) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   __shared__ int iscratch[kEpiThreads / 64];
   const int j = blockIdx.x, tid = threadIdx.x;
@@ -770,7 +795,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     return;
   }
   const int ej = eR[j];
-  const double lj = lam[j];
+  const double lj = lam[j], ljl = lam_lo[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad;
   double ev[EPT], wq[EPT];
@@ -806,7 +831,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
       if (i == j) {
         e = 0.5 * r[j];
       } else {
-        const double den = lj - lam[i];
+        const double den = dd_diff(lj, ljl, lam[i], lam_lo[i]);
         if (den == 0.0) {
           tie = 1;
           e = 0.0;
@@ -846,22 +871,22 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 
 template <int EPT>
 static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                    const int *eX, const int *eR, const double *lam, const double *r, int n,
+                    const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n,
                     int *eE, double *emax, int8_t *Epl, int ke, int *flags, int *eb_idx,
                     double *eb_val, hipStream_t s) {
   hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
-                     eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val);
+                     eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val);
 }
 
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                  const int *eX, const int *eR, const double *lam, const double *r, int n, int *eE,
+                  const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n, int *eE,
                   double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, int *eb_idx,
                   double *eb_val) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
 }
 
 // ---------------------------------------------------------------- grouped correction
@@ -916,17 +941,18 @@ void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const i
 template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
-    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam, int n,
-    const int *__restrict__ gcol, const int *__restrict__ gfirst, const int *__restrict__ gk,
-    const int *__restrict__ gpos, const int *__restrict__ gbase, const double *__restrict__ Y,
-    const double *__restrict__ mu, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
+    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
+    const double *__restrict__ lam_lo, int n, const int *__restrict__ gcol,
+    const int *__restrict__ gfirst, const int *__restrict__ gk, const int *__restrict__ gpos,
+    const int *__restrict__ gbase, const double *__restrict__ Y, const double *__restrict__ mu,
+    const double *__restrict__ mu_lo, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
     int *flags) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   __shared__ int smem[kGroupMax], snd[kGroupMax], ser[kGroupMax];
   __shared__ double sy[kGroupMax];
   const int m = blockIdx.x, tid = threadIdx.x;
   const int j = gcol[m], k = gk[m], pos = gpos[m], first = gfirst[m];
-  const double muj = mu[m];
+  const double muj = mu[m], mujl = mu_lo[m];
   if (tid < k) {
     const int c = gcol[first + tid];
     smem[tid] = c;
@@ -955,7 +981,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
         const int ei = eX[i];
         for (int a = 0; a < k; ++a)
           num += w_entry(C, P, npad, d_min, snd[a], ei + ser[a], i, smem[a]) * sy[a];
-        const double den = muj - lam[i];
+        const double den = dd_diff(muj, mujl, lam[i], lam_lo[i]);
         if (den == 0.0) {
           tie = 1;
           e = 0.0;
@@ -982,25 +1008,25 @@ __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
 
 template <int EPT>
 static void group_fix_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                        const int *eX, const int *eR, const double *lam, int n, const int *gcol,
+                        const int *eX, const int *eR, const double *lam, const double *lam_lo, int n, const int *gcol,
                         const int *gfirst, const int *gk, const int *gpos, const int *gbase,
-                        const double *Y, const double *mu, int nmem, int *eE, double *emax,
+                        const double *Y, const double *mu, const double *mu_lo, int nmem, int *eE, double *emax,
                         int8_t *Epl, int ke, int *flags, hipStream_t s) {
   hipLaunchKernelGGL(k_group_fix<EPT>, dim3(nmem), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag,
-                     dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, eE, emax, Epl, ke,
+                     dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, eE, emax, Epl, ke,
                      flags);
 }
 
 void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
-                      const int *eX, const int *eR, const double *lam, int n, const int *gcol,
+                      const int *eX, const int *eR, const double *lam, const double *lam_lo, int n, const int *gcol,
                       const int *gfirst, const int *gk, const int *gpos, const int *gbase,
-                      const double *Y, const double *mu, int nmem, int *eE, double *emax,
+                      const double *Y, const double *mu, const double *mu_lo, int nmem, int *eE, double *emax,
                       int8_t *Epl, int ke, int *flags, hipStream_t s) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) group_fix_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 2) group_fix_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 4) group_fix_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
-  else group_fix_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, n, gcol, gfirst, gk, gpos, gbase, Y, mu, nmem, eE, emax, Epl, ke, flags, s);
+  if (ept <= 1) group_fix_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 2) group_fix_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
+  else if (ept <= 4) group_fix_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
+  else group_fix_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
 }
 
 // ---------------------------------------------------------------- update X <- X1 + X1 E~

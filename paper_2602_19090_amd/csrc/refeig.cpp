@@ -61,8 +61,8 @@ struct Work {
   int *colmap;   // working column p holds column colmap[p] of the caller's X
   // grouped correction: per column argmax of |e_ij|, pair list, member table, Ritz data
   int *eb_idx, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;
-  double *eb_val, *g_gh, *g_gl, *g_w, *g_Y, *g_mu;
-  double *mxA, *mxX, *lam, *r, *resmax, *emax;
+  double *eb_val, *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
+  double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
 };
 
 int nslots(int ka) { return std::max(ka, kKrMax + kKxMax); }
@@ -114,9 +114,11 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.g_pos = (int *)take(sizeof(int) * kGroupColsMax);
   t.g_base = (int *)take(sizeof(int) * kGroupColsMax);
   t.g_mu = (double *)take(sizeof(double) * kGroupColsMax);
+  t.g_mul = (double *)take(sizeof(double) * kGroupColsMax);
   t.mxA = (double *)take(vd);
   t.mxX = (double *)take(vd);
   t.lam = (double *)take(vd);
+  t.lam_lo = (double *)take(vd);
   t.r = (double *)take(vd);
   t.resmax = (double *)take(vd);
   t.emax = (double *)take(vd);
@@ -266,16 +268,16 @@ inline HD hd_sqrt(HD a) {
 inline bool hd_less(HD a, HD b) { return a.h < b.h || (a.h == b.h && a.l < b.l); }
 
 // Ritz pairs of one group: G (k x k, double-word Gram matrix of the members' columns),
-// Wg (k x k, w_ab), lamg (current eigenvalue estimates). T = W + G diag(lambda),
+// Wg (k x k, w_ab), lamg (current double-word eigenvalue estimates). T = W + G diag(lambda),
 // symmetrised; T y = mu G y through the Cholesky factor of G and cyclic Jacobi
 // rotations. Each member keeps the Ritz vector with its largest entry (greedily, first
 // indices on ties), signed so that entry is positive. Y row-major, Y[a][b] = entry a of
 // member b's vector. Returns false if G is not positive definite.
 bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
-                const std::vector<double> &lamg, double *Y, double *mu) {
+                const std::vector<HD> &lamg, double *Y, double *mu, double *mu_lo) {
   std::vector<HD> T(k * k), L(k * k, hd(0.0)), M(k * k), Q(k * k), Z(k * k);
   for (int a = 0; a < k; ++a)
-    for (int b = 0; b < k; ++b) T[a * k + b] = hd_add(hd(Wg[a * k + b]), hd_mul(G[a * k + b], hd(lamg[b])));
+    for (int b = 0; b < k; ++b) T[a * k + b] = hd_add(hd(Wg[a * k + b]), hd_mul(G[a * k + b], lamg[b]));
   for (int a = 0; a < k; ++a)
     for (int b = a + 1; b < k; ++b) {
       HD m = hd_add(T[a * k + b], T[b * k + a]);
@@ -374,6 +376,7 @@ bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
     }
     used_c[ba] = used_v[bv] = 1;
     mu[ba] = M[bv * k + bv].h;
+    mu_lo[ba] = M[bv * k + bv].l;
     const double sg = V[ba * k + bv].h < 0.0 ? -1.0 : 1.0;
     for (int r = 0; r < k; ++r) Y[r * k + ba] = sg * V[r * k + bv].h;
   }
@@ -857,8 +860,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const double pv = plan.pairs_eff;
     const int lv = (int)plan.groups.size();
     launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
-    launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.r, w.eR, w.resmax,
-                 w.RP, kKrMax, w.flags, s);
+    launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
+                 w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
     STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -886,8 +889,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int lw = (int)plan.groups.size();
     launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
     const bool grouping = o.group_tau > 0.0;
-    launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.r, n, w.eE, w.emax, w.EP,
-                 kKeMax, w.flags, s, grouping ? w.eb_idx : nullptr,
+    launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n, w.eE,
+                 w.emax, w.EP, kKeMax, w.flags, s, grouping ? w.eb_idx : nullptr,
                  grouping ? w.eb_val : nullptr);
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -941,7 +944,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         STEP(hipMemcpyAsync(w.g_pb, pb.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
         launch_group_gram(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.X1, n, w.g_pa, w.g_pb,
                           npr, w.g_gh, w.g_gl, w.g_w, s);
-        std::vector<double> gh(npr), gl(npr), gw(npr), Yh(npr), muh(nmem);
+        std::vector<double> gh(npr), gl(npr), gw(npr), Yh(npr), muh(nmem), mul(nmem), laml(n);
+        STEP(hipMemcpyAsync(laml.data(), w.lam_lo, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(gh.data(), w.g_gh, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(gl.data(), w.g_gl, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(gw.data(), w.g_w, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
@@ -949,25 +953,28 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         for (int g = 0; g < ngroups; ++g) {
           const int first = gstart[g], k = gk[first], base = gbase[first];
           std::vector<HD> G(k * k);
-          std::vector<double> Wg(k * k), lamg(k);
+          std::vector<double> Wg(k * k);
+          std::vector<HD> lamg(k);
           for (int q = 0; q < k * k; ++q) {
             G[q] = {gh[base + q], gl[base + q]};
             Wg[q] = gw[base + q];
           }
-          for (int a = 0; a < k; ++a) lamg[a] = lam[gcol[first + a]];
-          if (!group_ritz(k, G, Wg, lamg, Yh.data() + base, muh.data() + first))
+          for (int a = 0; a < k; ++a) lamg[a] = {lam[gcol[first + a]], laml[gcol[first + a]]};
+          if (!group_ritz(k, G, Wg, lamg, Yh.data() + base, muh.data() + first,
+                          mul.data() + first))
             return cleanup(REFEIG_E_GAP);
         }
         STEP(hipMemcpyAsync(w.g_Y, Yh.data(), sizeof(double) * npr, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_mu, muh.data(), sizeof(double) * nmem, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.g_mul, mul.data(), sizeof(double) * nmem, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_col, gcol.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_first, gfirst.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_k, gk.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_pos, gpos.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_base, gbase.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
-        launch_group_fix(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, n, w.g_col,
-                         w.g_first, w.g_k, w.g_pos, w.g_base, w.g_Y, w.g_mu, nmem, w.eE, w.emax,
-                         w.EP, kKeMax, w.flags, s);
+        launch_group_fix(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, n,
+                         w.g_col, w.g_first, w.g_k, w.g_pos, w.g_base, w.g_Y, w.g_mu, w.g_mul,
+                         nmem, w.eE, w.emax, w.EP, kKeMax, w.flags, s);
         STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -43,7 +43,7 @@ def _fwd(Xg, Xt):
 
 
 @pytest.mark.parametrize("cfg,n,target", [(1, 100, 1e-10), (1, 100, 1e-14), (2, 256, 1e-12),
-                                          (2, 300, 1e-14)])
+                                          (2, 300, 1e-14), (3, 1100, 1e-14)])
 def test_one_step_vs_oracle(cfg, n, target):
     print(f"step cfg={cfg} n={n} target={target}", flush=True)
     rb = _rb()
@@ -292,7 +292,7 @@ def _mixed_start(p, pairs, angles):
     return X0
 
 
-@pytest.mark.parametrize("cfg,n", [(2, 300), (2, 1100)])
+@pytest.mark.parametrize("cfg,n", [(2, 300), (2, 1100), (3, 1100)])
 def test_grouped_step_vs_oracle(cfg, n):
     """One step with the grouped correction (group_tau = 1e-3) against the oracle's grouped
     method step on a start with three badly mixed column pairs; spans npad < 1024 and the
