@@ -64,16 +64,26 @@ def sampled_error(Xcm, golden):
     return float(np.max(np.abs(Xs - Xt * s)))
 
 
-def measured_traffic():
-    """HBM bytes per slice-GEMM launch from the profiler's FETCH_SIZE / WRITE_SIZE passes
-    (scaled by a copy kernel of known size), if they were taken on the current kernels."""
+def gemm_source_digest():
+    """SHA-256 of the slice GEMM's source: the K-blocked offset helper and everything from
+    the 256 x 256 tile constants to the launcher (tile order, pipeline, kernel)."""
     import hashlib
+    src = open(os.path.join(ROOT, "paper_2602_19090_amd", "csrc", "kernels.hip")).read()
+    a = src.index("__device__ __forceinline__ size_t kb_off(")
+    b = src.index("\n}\n", a) + 3
+    c = src.index("constexpr int HBM_ = 256")
+    d = src.index("void launch_slice_gemm(")
+    return hashlib.sha256((src[a:b] + src[c:d]).encode()).hexdigest()
+
+
+def measured_traffic():
+    """Mean HBM bytes per slice-GEMM dispatch from the profiler's FETCH_SIZE / WRITE_SIZE
+    passes (scaled by a copy kernel of known size), if they were taken on this kernel."""
     path = os.path.join(ROOT, "profiles", "k_slice_gemm256d_traffic.json")
-    src = os.path.join(ROOT, "paper_2602_19090_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["kernels_hip_sha256"]:
+    if t.get("gemm_source_sha256") != gemm_source_digest():
         return None
     return t["traffic_bytes_per_launch"]
 
