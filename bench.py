@@ -123,6 +123,74 @@ def config4_leg(count):
             "lanes": 8}
 
 
+def serve_leg(rates, nreq, pool_size=16):
+    """Serving (config 5): requests arrive as a Poisson process and draw a problem from a
+    pool (n = round(exp(U(ln 128, ln 8192))), cond 10^U(4,12), target from {1e-8, 1e-11,
+    1e-14}, FP64-eigh start), all resident on the device. One server loop takes every
+    request that has arrived (up to 8) and refines them in one batched call; latency =
+    completion - arrival. Reports p50/p99 latency and completed matrices/s per rate."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2602_19090_amd import binding as rb
+    rng = workloads.rng_for(5, 2_000_000)
+    ns = np.rint(np.exp(rng.uniform(np.log(128.0), np.log(8192.0), pool_size))).astype(int)
+    cs = rng.uniform(4.0, 12.0, pool_size)
+    ts = rng.choice([1e-8, 1e-11, 1e-14], pool_size)
+    log(f"serving pool: {pool_size} problems, n {ns.min()}..{ns.max()}")
+    pool = []
+    for i, (n, c, t) in enumerate(zip(ns, cs, ts)):
+        q = workloads.make_problem(5, int(n), index=i, x0="none", cond_exp=float(c))
+        A = rb.colmajor(q.A)
+        w, V = torch.linalg.eigh(A)
+        pool.append((A, V.t().contiguous(), w.contiguous(), float(t)))
+        del V
+    torch.cuda.synchronize()
+    work = torch.empty(rb.batched_workspace_bytes([int(n) for n in ns]), dtype=torch.uint8,
+                       device="cuda")
+    # warm the path once per pool entry
+    st, _ = rb.refine_eigvecs_batched([e[0] for e in pool], [e[1].clone() for e in pool],
+                                      [e[2].clone() for e in pool], [e[3] for e in pool],
+                                      work=work)
+    out = []
+    for rate in rates:
+        arr_rng = np.random.default_rng([2602, 19090, 5, int(rate * 1000)])
+        arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, nreq))
+        picks = arr_rng.integers(0, pool_size, nreq)
+        done = np.zeros(nreq)
+        batches = []
+        t0 = time.perf_counter()
+        nxt = 0
+        while nxt < nreq:
+            now = time.perf_counter() - t0
+            if arrivals[nxt] > now:
+                time.sleep(arrivals[nxt] - now)
+                continue
+            take = []
+            while nxt < nreq and arrivals[nxt] <= time.perf_counter() - t0 and len(take) < 8:
+                take.append(nxt)
+                nxt += 1
+            Xs = [pool[picks[i]][1].clone() for i in take]
+            Ds = [pool[picks[i]][2].clone() for i in take]
+            st, _ = rb.refine_eigvecs_batched([pool[picks[i]][0] for i in take], Xs, Ds,
+                                              [pool[picks[i]][3] for i in take], work=work)
+            torch.cuda.synchronize()
+            tdone = time.perf_counter() - t0
+            for i in take:
+                done[i] = tdone
+            batches.append(len(take))
+            assert st in (rb.REFEIG_OK, rb.REFEIG_NOT_CONVERGED), rb.strerror(st)
+        lat = (done - arrivals) * 1e3
+        span = done.max() - arrivals[0]
+        out.append({"rate_req_s": rate, "requests": nreq, "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "matrices_per_s": nreq / span,
+                    "mean_batch": float(np.mean(batches))})
+        log(f"serving at {rate:g} req/s: p50 {out[-1]['p50_ms']:.0f} ms, p99 "
+            f"{out[-1]['p99_ms']:.0f} ms, {out[-1]['matrices_per_s']:.1f} matrices/s, "
+            f"mean batch {out[-1]['mean_batch']:.2f}")
+    return {"pool": {"size": pool_size, "n": [int(n) for n in ns]}, "rates": out}
+
+
 def cpu_baseline(A, X0cm, n, cols):
     """Time the oracle's double-double products on `cols` columns and scale to one
     iteration (three n x n x n double-double products)."""
@@ -159,6 +227,10 @@ def main():
     ap.add_argument("--config4", type=int, default=0, metavar="COUNT",
                     help="also time a batch of COUNT config-4 matrices (n log-uniform in "
                          "[32, 1024], cond 10^U(4,12), 3 iterations) through the batched entry point")
+    ap.add_argument("--serve", type=str, default="", metavar="RATES",
+                    help="also run the serving workload (config 5) at these Poisson arrival "
+                         "rates, comma-separated requests/s, e.g. 2,5,10,20")
+    ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--group-tau", type=float, default=0.0, metavar="TAU",
                     help="also time the solve with the grouped correction (an extension beyond "
                          "the paper's method) at this threshold, e.g. 1e-3")
@@ -302,6 +374,8 @@ def main():
                      "fwd_err_per_iter": perrs or None}
 
     batch = config4_leg(args.config4) if args.config4 > 0 else None
+    serve = serve_leg([float(r) for r in args.serve.split(",")], args.serve_requests) \
+        if args.serve else None
     grouped = None
     if args.group_tau > 0.0 and golden is not None:
         log(f"grouped correction (group_tau {args.group_tau:g}): iterations to the target")
@@ -363,6 +437,8 @@ def main():
         out["config4_batched"] = batch
     if grouped is not None:
         out["grouped_correction"] = grouped
+    if serve is not None:
+        out["serving"] = serve
     print(json.dumps(out), flush=True)
 
 
