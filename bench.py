@@ -231,6 +231,9 @@ def main():
                     help="also run the serving workload (config 5) at these Poisson arrival "
                          "rates, comma-separated requests/s, e.g. 2,5,10,20")
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--ab-kx", type=int, default=0, metavar="K",
+                    help="also time the solve with X-hat's digit planes fixed at K (9 = the "
+                         "previous study's untruncated X-hat) for the paper's A/B")
     ap.add_argument("--group-tau", type=float, default=0.0, metavar="TAU",
                     help="also time the solve with the grouped correction (an extension beyond "
                          "the paper's method) at this threshold, e.g. 1e-3")
@@ -376,6 +379,39 @@ def main():
     batch = config4_leg(args.config4) if args.config4 > 0 else None
     serve = serve_leg([float(r) for r in args.serve.split(",")], args.serve_requests) \
         if args.serve else None
+    ab = None
+    if args.ab_kx > 0 and golden is not None:
+        log(f"A/B: X-hat planes fixed at {args.ab_kx}: iterations to the target")
+        X, D = X0.clone(), D0.clone()
+        aerrs, aK = [sampled_error(X, golden)], None
+        for k in range(1, 13):
+            rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=1, kx_force=args.ab_kx))
+            aerrs.append(sampled_error(X, golden))
+            if aerrs[-1] <= target:
+                aK = k
+                break
+        if aK is not None:
+            aopts = rb.default_opts(fixed_iters=aK, kx_force=args.ab_kx)
+            ams, areps = [], []
+            for s_ in range(args.warmup + max(1, args.steps)):
+                Xw.copy_(X0)
+                Dw.copy_(D0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ast_, arep = rb.refine_eigvecs(A, Xw, Dw, target, aopts)
+                e1.record()
+                torch.cuda.synchronize()
+                if s_ >= args.warmup:
+                    ams.append(e0.elapsed_time(e1))
+                    areps.append(arep.as_dict())
+            ams_step = float(np.mean(ams))
+            ab = {"kx": args.ab_kx, "ms_to_target": ams_step, "iters": aK,
+                  "pairs_per_iter": [round(sum(x), 2) for x in areps[0]["pairs_f"]],
+                  "ms_per_iter": areps[0]["ms_iter"],
+                  "fwd_err_per_iter": aerrs, "paper_method_speedup": ams_step / ms_step,
+                  "paper_method_kx": list(reps[0]["kx"])}
+        else:
+            ab = {"kx": args.ab_kx, "ms_to_target": None, "fwd_err_per_iter": aerrs}
     grouped = None
     if args.group_tau > 0.0 and golden is not None:
         log(f"grouped correction (group_tau {args.group_tau:g}): iterations to the target")
@@ -439,6 +475,8 @@ def main():
         out["grouped_correction"] = grouped
     if serve is not None:
         out["serving"] = serve
+    if ab is not None:
+        out["ab_full_x_planes"] = ab
     print(json.dumps(out), flush=True)
 
 

@@ -69,7 +69,11 @@ typedef struct {
     int ka_max;          /* maximum digit planes of A (default 18)                       */
     int d_extra;         /* extra pair diagonals added to every product (default 0)      */
     int verbose;         /* print per-iteration parameters to stderr                     */
-    int reserved_i[6];
+    int kx_force;        /* > 0: digit planes of X^(1) fixed at this count (1..9) instead of
+                            the beta rule of Sec. 4.1; 9 keeps X-hat at full FP64 precision,
+                            the previous study's form without the X^(1) cut of Sec. 3.3
+                            (an A/B for the paper's cost claim). 0: the beta rule.        */
+    int reserved_i[5];
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
                             a column whose largest first-order correction |e_ij|, i != j,

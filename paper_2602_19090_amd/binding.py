@@ -42,7 +42,8 @@ class Opts(ctypes.Structure):
                 ("stop_rule", ctypes.c_int), ("delta_safety", ctypes.c_double),
                 ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
                 ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("reserved_i", ctypes.c_int * 6), ("group_tau", ctypes.c_double),
+                ("kx_force", ctypes.c_int), ("reserved_i", ctypes.c_int * 5),
+                ("group_tau", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 3)]
 
 

@@ -726,7 +726,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   if (rep) std::memset(rep, 0, sizeof(*rep));
   if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
-      !(o.group_tau >= 0.0) ||
+      !(o.group_tau >= 0.0) || o.kx_force < 0 || o.kx_force > kKxMax ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -836,6 +836,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     for (int p = 0; p < n; ++p) gaps[p] = gaps_nat[cmap[p]];
     int beta, kx;
     beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx);
+    if (o.kx_force > 0) kx = o.kx_force;
     // ---- X^(1) and its planes (both layouts)
     launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s,
                       w.colmap);

@@ -45,14 +45,25 @@ def _fwd(Xg, Xt):
 @pytest.mark.parametrize("cfg,n,target", [(1, 100, 1e-10), (1, 100, 1e-14), (2, 256, 1e-12),
                                           (2, 300, 1e-14), (3, 1100, 1e-14)])
 def test_one_step_vs_oracle(cfg, n, target):
-    print(f"step cfg={cfg} n={n} target={target}", flush=True)
+    _one_step_vs_oracle(cfg, n, target, 0)
+
+
+@pytest.mark.parametrize("cfg,n,target", [(2, 300, 1e-14), (1, 600, 1e-8)])
+def test_one_step_full_x_planes_vs_oracle(cfg, n, target):
+    """kx_force = 9: X-hat kept at full precision (no X^(1) cut), against the oracle's step
+    with the same plane count."""
+    _one_step_vs_oracle(cfg, n, target, 9)
+
+
+def _one_step_vs_oracle(cfg, n, target, kx_force):
+    print(f"step cfg={cfg} n={n} target={target} kx_force={kx_force}", flush=True)
     rb = _rb()
     p = workloads.make_problem(cfg, n, x0="eigh")
     A, X, D = _to_dev(p)
-    opts = rb.default_opts(fixed_iters=1)
+    opts = rb.default_opts(fixed_iters=1, kx_force=kx_force)
     st, rep = rb.refine_eigvecs(A, X, D, target, opts)
     assert st == rb.REFEIG_OK, rb.strerror(st)
-    ref = oracle.method_step(p.A, p.X0, p.D0, target / opts.delta_safety)
+    ref = oracle.method_step(p.A, p.X0, p.D0, target / opts.delta_safety, kx_force=kx_force)
     assert rep.beta[0] == ref.beta and rep.kx[0] == ref.kx
     Xg = rb.from_colmajor(X)
     diff = float(np.max(np.abs(Xg - ref.X_hi)))
