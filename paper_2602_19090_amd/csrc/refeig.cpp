@@ -2,6 +2,7 @@
 //
 // One call of refine_eigvecs runs, per iteration (Algorithm 1 with the first
 // slice X^(1) of Sec. 3, products by the Ozaki scheme on INT8 digit planes):
+//   working column order (by gap), folded into the reads and writes of X and D
 //   colstats(X) -> beta (Sec. 4.1), kx          [host reads n exponents]
 //   split X -> X^(1), its digit planes (both layouts)
 //   V = A X^(1)          per-diagonal slice GEMMs + fused column pass
@@ -9,6 +10,7 @@
 //                                               [host reads lambda, exponents]
 //   W = X^(1)T Res       slice GEMMs + E~ epilogue (E~ planes)
 //                                               [host reads column maxima]
+//   (opt-in) grouped correction: Rayleigh-Ritz on strongly coupled columns
 //   X <- X^(1) + X^(1) E~ slice GEMMs + update epilogue
 // The A planes are built once per call. How many pair diagonals each product
 // keeps is decided on the host from the target error and the eigenvalue gaps.
@@ -939,6 +941,19 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         ybase += k * k;
       }
       ngroups = (int)gstart.size();
+      if (verbose) {
+        int linked = 0, biggest = 0, skipped = 0;
+        for (int root = 0; root < n; ++root) {
+          const int k = (int)comp[root].size();
+          if (k < 2) continue;
+          linked += k;
+          biggest = std::max(biggest, k);
+        }
+        for (int root = 0; root < n; ++root)
+          if ((int)comp[root].size() > kGroupMax) ++skipped;
+        fprintf(stderr, "refeig it %d: %d groups (%d linked columns, largest %d, %d too large)\n",
+                it + 1, ngroups, linked, biggest, skipped);
+      }
       if (ngroups > 0) {
         const int nmem = (int)gcol.size(), npr = (int)pa.size();
         STEP(hipMemcpyAsync(w.g_pa, pa.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
