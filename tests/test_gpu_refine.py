@@ -352,3 +352,19 @@ def test_grouped_solve_from_mixed_start():
     st, iters, err = res[1e-3]
     assert st == rb.REFEIG_OK and err <= target
     assert iters < res[0.0][1] or res[0.0][0] != rb.REFEIG_OK
+
+
+@pytest.mark.parametrize("n", [255, 256, 257, 1023, 1024, 1025])
+def test_tile_boundaries(n):
+    """Orders on either side of the 256-column block and of the switch between the
+    128 x 128 and 256 x 256 GEMM kernels (npad 1024), to target against X_true."""
+    rb = _rb()
+    target = 1e-13
+    p = workloads.make_problem(2, n, x0="eigh")
+    Xt, lt = _xtrue(p)
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, target)
+    err = _fwd(rb.from_colmajor(X), Xt)
+    print(f"  n={n} status={st} iters={rep.iters} fwd={err:.2e}", flush=True)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert err <= target
