@@ -152,6 +152,33 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
 
 const char *refeig_strerror(int status);
 
+/* ---- host-only entry points: the planning the library does on the host, exposed
+ * for checks on a machine without a GPU (no device memory is touched) ----------- */
+
+/* beta of Sec. 4.1 (floor form, xi from o or n) and the digit-plane count of
+ * X^(1), from the eigenvalue estimates lam (host, n) and the column statistics of
+ * X (host arrays of n): e_j = floor(log2 max_i |x_ij|) + 1, c_j = ceil(log2 max_i
+ * |x_ij|), mx_j = max_i |x_ij|. target_fwd_err as for refine_eigvecs (the rule
+ * uses target / delta_safety). REFEIG_E_GAP if two estimates coincide. */
+int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const double *mx,
+                     double target_fwd_err, const refeig_opts *o, int *beta, int *kx);
+
+/* Working column order of an iteration: columns by the gap of their eigenvalue
+ * estimate to its nearest neighbour, widest first, ties by eigenvalue.
+ * order[p] = the column placed at working position p (host arrays of n). */
+int refeig_host_column_order(int n, const double *lam, int *order);
+
+/* The Rayleigh-Ritz problem of one group of k (2..32) columns, as the grouped
+ * correction solves it: G (double-word Gram matrix, hi and lo parts, k x k
+ * row-major), W (k x k row-major, w_ab), lam (double-word eigenvalue estimates).
+ * T = W + G diag(lam), symmetrised; T y = mu G y. Y (k x k row-major) receives
+ * the Ritz vector of member b in column b (the greedy largest-entry assignment,
+ * signed so that its own entry is positive), mu_hi / mu_lo the Ritz values.
+ * REFEIG_E_GAP if G is not positive definite, REFEIG_E_ARG for k out of range. */
+int refeig_host_group_ritz(int k, const double *G_hi, const double *G_lo, const double *W,
+                           const double *lam_hi, const double *lam_lo, double *Y,
+                           double *mu_hi, double *mu_lo);
+
 /* ---- entry points for bit-exact checks of the kernels -------------------- */
 
 /* Column exponents and 7-bit digit planes of M (rows x cols, device, ld).

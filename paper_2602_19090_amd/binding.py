@@ -91,9 +91,15 @@ _lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
 _lib.refine_eigvecs_batched.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.POINTER(Opts), _vp, _sz, _vp, _vp]
 
+_lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(_int), ctypes.POINTER(_int)]
+_lib.refeig_host_column_order.argtypes = [_int, _vp, _vp]
+_lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
             "refeig_split_cols", "refeig_slice_gemm", "refeig_batched_workspace_bytes",
-            "refine_eigvecs_batched"]
+            "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
+            "refeig_host_group_ritz"]
 
 
 def _stream(stream=None):
@@ -185,6 +191,40 @@ def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=N
                                      ctypes.byref(opts) if opts is not None else None, _ptr(work),
                                      wb, _stream(stream), c(reps))
     return st, list(reps)
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def host_beta(lam, e, c, mx, target, opts: Opts | None = None):
+    """Host entry point refeig_host_beta: (status, beta, kx)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    mx = np.ascontiguousarray(mx, dtype=np.float64)
+    b, k = _int(0), _int(0)
+    st = _lib.refeig_host_beta(len(lam), _np_ptr(lam), _np_ptr(e), _np_ptr(c), _np_ptr(mx),
+                               float(target), ctypes.byref(opts) if opts is not None else None,
+                               ctypes.byref(b), ctypes.byref(k))
+    return st, b.value, k.value
+
+
+def host_column_order(lam):
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.empty(len(lam), dtype=np.int32)
+    st = _lib.refeig_host_column_order(len(lam), _np_ptr(lam), _np_ptr(out))
+    return st, out
+
+
+def host_group_ritz(G_hi, G_lo, W, lam_hi, lam_lo):
+    """Host entry point refeig_host_group_ritz: (status, Y, mu_hi, mu_lo)."""
+    k = len(lam_hi)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (G_hi, G_lo, W, lam_hi, lam_lo)]
+    Y = np.empty((k, k)); mh = np.empty(k); ml = np.empty(k)
+    st = _lib.refeig_host_group_ritz(k, *[_np_ptr(a) for a in arrs], _np_ptr(Y), _np_ptr(mh),
+                                     _np_ptr(ml))
+    return st, Y, mh, ml
 
 
 def rows_to_kblocked(P):

@@ -416,6 +416,18 @@ void beta_rule(int n, double xi, double delta, double g, double L, const std::ve
   *kx = std::min(std::max(k, 1), kKxMax);
 }
 
+// Working column order: by gap, widest first; ties (two columns share a gap) go by
+// eigenvalue, so the order does not depend on where the caller put the columns.
+void working_order(const std::vector<double> &lam, const std::vector<double> &gaps,
+                   std::vector<int> &order) {
+  const int n = (int)lam.size();
+  order.resize(n);
+  for (int p = 0; p < n; ++p) order[p] = p;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return gaps[a] != gaps[b] ? gaps[a] > gaps[b] : lam[a] < lam[b];
+  });
+}
+
 // Per-column distance to the nearest other eigenvalue estimate.
 void column_gaps(const std::vector<double> &lam, std::vector<double> &g, double *gmin,
                  double *lmax) {
@@ -818,12 +830,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     double gmin, lmax;
     column_gaps(lam_prev, gaps_nat, &gmin, &lmax);
     if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
-    for (int p = 0; p < n; ++p) cmap[p] = p;
-    // ties (two columns share a gap) go by eigenvalue, so the order does not depend on
-    // where the caller put the columns
-    std::sort(cmap.begin(), cmap.end(), [&](int a, int b) {
-      return gaps_nat[a] != gaps_nat[b] ? gaps_nat[a] > gaps_nat[b] : lam_prev[a] < lam_prev[b];
-    });
+    working_order(lam_prev, gaps_nat, cmap);
     STEP(hipMemcpyAsync(w.colmap, cmap.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     // ---- beta and kx from the previous eigenvalue estimates and column maxima of X
     launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap);
@@ -1078,6 +1085,46 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   }
   return cleanup(status);
 #undef STEP
+}
+
+int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const double *mx,
+                     double target, const refeig_opts *o_in, int *beta, int *kx) {
+  if (n < 1 || !lam || !e || !c || !mx || !beta || !kx || !(target > 0.0)) return REFEIG_E_ARG;
+  refeig_opts o;
+  if (o_in) o = *o_in;
+  else refeig_default_opts(&o);
+  std::vector<double> l(lam, lam + n), g, m(mx, mx + n);
+  std::vector<int> ev(e, e + n), cv(c, c + n);
+  double gmin, lmax;
+  column_gaps(l, g, &gmin, &lmax);
+  if (!(gmin > 0.0)) return REFEIG_E_GAP;
+  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  beta_rule(n, xi, target / o.delta_safety, gmin, lmax, ev, cv, m, beta, kx);
+  return REFEIG_OK;
+}
+
+int refeig_host_column_order(int n, const double *lam, int *order) {
+  if (n < 1 || !lam || !order) return REFEIG_E_ARG;
+  std::vector<double> l(lam, lam + n), g;
+  double gmin, lmax;
+  column_gaps(l, g, &gmin, &lmax);
+  std::vector<int> cm(n);
+  working_order(l, g, cm);
+  for (int p = 0; p < n; ++p) order[p] = cm[p];
+  return REFEIG_OK;
+}
+
+int refeig_host_group_ritz(int k, const double *G_hi, const double *G_lo, const double *W,
+                           const double *lam_hi, const double *lam_lo, double *Y, double *mu_hi,
+                           double *mu_lo) {
+  if (k < 2 || k > kGroupMax || !G_hi || !G_lo || !W || !lam_hi || !lam_lo || !Y || !mu_hi ||
+      !mu_lo)
+    return REFEIG_E_ARG;
+  std::vector<HD> G(k * k), lg(k);
+  std::vector<double> Wg(W, W + k * k);
+  for (int q = 0; q < k * k; ++q) G[q] = {G_hi[q], G_lo[q]};
+  for (int a = 0; a < k; ++a) lg[a] = {lam_hi[a], lam_lo[a]};
+  return group_ritz(k, G, Wg, lg, Y, mu_hi, mu_lo) ? REFEIG_OK : REFEIG_E_GAP;
 }
 
 int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes) {
