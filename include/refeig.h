@@ -76,9 +76,9 @@ typedef struct {
     int reserved_i[5];
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
-                            a column whose largest first-order correction |e_ij|, i != j,
-                            exceeds group_tau is linked to row i; each linked group of
-                            2..32 columns is corrected by the Rayleigh-Ritz problem on its
+                            every pair of columns whose first-order correction |e_ij|,
+                            i != j, exceeds group_tau is linked; each linked group of
+                            2..128 columns is corrected by the Rayleigh-Ritz problem on its
                             span (T y = mu G y, G = X_C^T X_C, T = X_C^T A X_C), which
                             resolves badly mixed or near-tied eigenvectors in one step.
                             0 (default): off, the paper's method.                       */
@@ -168,7 +168,7 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
  * order[p] = the column placed at working position p (host arrays of n). */
 int refeig_host_column_order(int n, const double *lam, int *order);
 
-/* The Rayleigh-Ritz problem of one group of k (2..32) columns, as the grouped
+/* The Rayleigh-Ritz problem of one group of k (2..128) columns, as the grouped
  * correction solves it: G (double-word Gram matrix, hi and lo parts, k x k
  * row-major), W (k x k row-major, w_ab), lam (double-word eigenvalue estimates).
  * T = W + G diag(lam), symmetrised; T y = mu G y. Y (k x k row-major) receives

@@ -18,10 +18,10 @@
  *  or_refine_dd_step_grouped
  *                      The same step with strongly coupled columns grouped (an
  *                      extension for near-tied or badly mixed eigenvectors,
- *                      which the paper leaves for future work, Sec. 5): where
- *                      the first-order correction of column j is large
- *                      (max_i |e_ij| > tau), j is linked to that i; for each
- *                      linked group C the exact Rayleigh-Ritz problem on
+ *                      which the paper leaves for future work, Sec. 5): columns
+ *                      i and j are linked when their first-order correction is
+ *                      large (|e_ij| > tau); for each linked group C (2..128
+ *                      columns) the exact Rayleigh-Ritz problem on
  *                      span(X_C), T y = mu G y with G = X_C^T X_C and
  *                      T = X_C^T A X_C = W_CC + G_CC D_C, replaces the
  *                      first-order entries of the group's columns.
@@ -270,7 +270,7 @@ int or_refine_dd_step_grouped(int n, const double *A, double *Xh, double *Xl,
 /* ------------------------------------------------------------------------ */
 /* Grouped correction (Rayleigh-Ritz on strongly coupled columns).           */
 /* ------------------------------------------------------------------------ */
-#define OR_GROUP_MAX 32
+#define OR_GROUP_MAX 128
 
 static int uf_find(int *par, int a)
 {
@@ -339,20 +339,13 @@ static int grouped_correction(int n, const double *Xh, const double *Xl, const d
     int *size = (int *)calloc((size_t)n, sizeof(int));
     if (!par || !size) return -5;
     for (int j = 0; j < n; ++j) par[j] = j;
-    /* link column j to the row of its largest off-diagonal |e_ij| (first index on ties) */
-    for (int j = 0; j < n; ++j) {
-        int best = -1;
-        double bv = -1.0;
+    /* link columns i and j whenever |e_ij| > tau (i != j) */
+    for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) {
-            if (i == j) continue;
-            double v = fabs(Eh[IX(i, j, n)]);
-            if (v > bv) { bv = v; best = i; }
-        }
-        if (best >= 0 && bv > tau) {
-            int a = uf_find(par, j), b = uf_find(par, best);
+            if (i == j || !(fabs(Eh[IX(i, j, n)]) > tau)) continue;
+            int a = uf_find(par, j), b = uf_find(par, i);
             if (a != b) par[a < b ? b : a] = a < b ? a : b;
         }
-    }
     for (int j = 0; j < n; ++j) size[uf_find(par, j)]++;
     int ngroups = 0, status = 0;
     int *mem = (int *)malloc(sizeof(int) * OR_GROUP_MAX);

@@ -68,17 +68,19 @@ void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *d
 //   e_ij = W_ij / (lambda_j - lambda_i) (difference of the double-word values),
 //   e_jj = r_j / 2,  E'_ij = 2^eX_i e_ij,
 //   eE_j (exponent of column j of E'), emax_j = max_i |e_ij|, ke digit planes of E'.
-// eb_idx / eb_val (may be null): per column j the row i != j of the largest |e_ij| (smallest
-// row on ties; -1 if none) and that value.
+// cpl_count (may be null; the caller zeroes it): every pair (i, j), i != j, with
+// |e_ij| > tau is counted, and the first cpl_cap are listed as (i, j) in cpl_pairs (in no
+// particular order).
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eX, const int *eR, const double *lam, const double *lam_lo,
                   const double *r, int n, int *eE, double *emax, int8_t *Eplanes, int ke,
                   int *flags, hipStream_t s,
-                  int *eb_idx = nullptr, double *eb_val = nullptr);
+                  double tau = 0.0, int *cpl_count = nullptr, int *cpl_pairs = nullptr,
+                  int cpl_cap = 0);
 
 // Grouped correction (Rayleigh-Ritz on strongly coupled columns). Groups hold at most
 // kGroupMax members.
-constexpr int kGroupMax = 32;
+constexpr int kGroupMax = 128;
 // For listed pairs q: gh/gl[q] = x_a^T x_b (double-word, columns of X1), wab[q] = w_ab
 // (entry of W from the slots, as the W epilogue sums it), a = pa[q], b = pb[q].
 void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,

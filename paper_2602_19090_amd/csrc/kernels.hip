@@ -781,9 +781,9 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
-    double *emax, int8_t *__restrict__ Epl, int ke, int *flags, int *eb_idx, double *eb_val) {
+    double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
+    int *cpl_pairs, int cpl_cap) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
-  __shared__ int iscratch[kEpiThreads / 64];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
@@ -818,8 +818,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 #pragma unroll
     for (int q = 0; q < EPT; ++q) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
   }
-  double ms = 0.0, mr = 0.0, bv = -1.0;
-  int tie = 0, bi = INT_MAX;
+  double ms = 0.0, mr = 0.0;
+  int tie = 0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
@@ -838,9 +838,12 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
         } else {
           e = w / den;
         }
-        if (fabs(e) > bv) {   // rows visited in ascending order: first index on ties
-          bv = fabs(e);
-          bi = i;
+        if (cpl_count && fabs(e) > tau) {   // a strong coupling: list the pair (i, j)
+          const int q = atomicAdd(cpl_count, 1);
+          if (q < cpl_cap) {
+            cpl_pairs[2 * q] = i;
+            cpl_pairs[2 * q + 1] = j;
+          }
         }
       }
       mr = fmax(mr, fabs(e));
@@ -852,15 +855,6 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   if (tie) atomicOr(flags, FLAG_TIE);
   ms = block_max<kEpiThreads>(ms, scratch);
   mr = block_max<kEpiThreads>(mr, scratch);
-  if (eb_idx) {
-    // largest off-diagonal |e_ij| of the column and its row (smallest row on ties)
-    const double bmax = block_max<kEpiThreads>(bv, scratch);
-    const int cand = block_min_int<kEpiThreads>(bv == bmax ? bi : INT_MAX, iscratch);
-    if (tid == 0) {
-      eb_idx[j] = cand == INT_MAX ? -1 : cand;
-      eb_val[j] = bmax;
-    }
-  }
   write_col_planes<EPT>(ev, ms, j, npad, Epl, ke);
   if (tid == 0) {
     eE[j] = exp_above(ms);
@@ -872,21 +866,22 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
 template <int EPT>
 static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n,
-                    int *eE, double *emax, int8_t *Epl, int ke, int *flags, int *eb_idx,
-                    double *eb_val, hipStream_t s) {
+                    int *eE, double *emax, int8_t *Epl, int ke, int *flags, double tau,
+                    int *cpl_count, int *cpl_pairs, int cpl_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
-                     eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val);
+                     eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs,
+                     cpl_cap);
 }
 
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n, int *eE,
-                  double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, int *eb_idx,
-                  double *eb_val) {
+                  double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, double tau,
+                  int *cpl_count, int *cpl_pairs, int cpl_cap) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, eb_idx, eb_val, s);
+  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
+  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
+  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
+  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
 }
 
 // ---------------------------------------------------------------- grouped correction

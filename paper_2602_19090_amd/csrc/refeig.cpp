@@ -62,14 +62,15 @@ struct Work {
   int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
   int *colmap;   // working column p holds column colmap[p] of the caller's X
   // grouped correction: per column argmax of |e_ij|, pair list, member table, Ritz data
-  int *eb_idx, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;
-  double *eb_val, *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
+  int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
+  double *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
   double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
 };
 
 int nslots(int ka) { return std::max(ka, kKrMax + kKxMax); }
 
 constexpr int kGroupColsMax = 1024;   // group members corrected per iteration (at most)
+constexpr int kCouplingsMax = 1 << 16; // strong couplings listed per iteration (at most)
 
 // Carves the workspace; returns the bytes needed (base may be null).
 size_t carve(int n, int ka, char *base, Work *w) {
@@ -101,8 +102,7 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.flags = (int *)take(256);
   for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
   t.colmap = (int *)take(vi);
-  t.eb_idx = (int *)take(vi);
-  t.eb_val = (double *)take(vd);
+  t.cpl = (int *)take(sizeof(int) * (2 * (size_t)kCouplingsMax + 64));
   const size_t npr = (size_t)kGroupColsMax * kGroupMax;
   t.g_pa = (int *)take(sizeof(int) * npr);
   t.g_pb = (int *)take(sizeof(int) * npr);
@@ -271,8 +271,8 @@ inline bool hd_less(HD a, HD b) { return a.h < b.h || (a.h == b.h && a.l < b.l);
 
 // Ritz pairs of one group: G (k x k, double-word Gram matrix of the members' columns),
 // Wg (k x k, w_ab), lamg (current double-word eigenvalue estimates). T = W + G diag(lambda),
-// symmetrised; T y = mu G y through the Cholesky factor of G and cyclic Jacobi
-// rotations. Each member keeps the Ritz vector with its largest entry (greedily, first
+// symmetrised; T y = mu G y through the Cholesky factor of G and Jacobi rotations (FP64,
+// then double-word). Each member keeps the Ritz vector with its largest entry (greedily, first
 // indices on ties), signed so that entry is positive. Y row-major, Y[a][b] = entry a of
 // member b's vector. Returns false if G is not positive definite.
 bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
@@ -316,19 +316,88 @@ bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
       m = {0.5 * m.h, 0.5 * m.l};
       M[a * k + b] = M[b * k + a] = m;
     }
+  // Eigenvectors of M. Cyclic Jacobi in FP64 on the high parts first; its basis Qf is made
+  // orthonormal to double-word accuracy by one Newton-Schulz step, Q1 = Qf (3I - Qf^T Qf) / 2;
+  // then double-word Jacobi sweeps on the nearly diagonal Q1^T M Q1 finish the job (one or two
+  // sweeps), and Q = Q1 Qd.
+  std::vector<double> Mf(k * k), Qf(k * k);
+  for (int q = 0; q < k * k; ++q) Mf[q] = M[q].h;
   for (int a = 0; a < k; ++a)
-    for (int b = 0; b < k; ++b) Q[a * k + b] = hd(a == b ? 1.0 : 0.0);
+    for (int b = 0; b < k; ++b) Qf[a * k + b] = a == b ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double dmax = 0.0, off = 0.0;
-    for (int a = 0; a < k; ++a) dmax = std::max(dmax, std::fabs(M[a * k + a].h));
+    for (int a = 0; a < k; ++a) dmax = std::max(dmax, std::fabs(Mf[a * k + a]));
     for (int a = 0; a < k; ++a)
-      for (int b = a + 1; b < k; ++b) off = std::max(off, std::fabs(M[a * k + b].h));
+      for (int b = a + 1; b < k; ++b) off = std::max(off, std::fabs(Mf[a * k + b]));
+    if (off == 0.0 || off <= 1e-17 * dmax) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = Mf[p * k + q];
+        if (apq == 0.0) continue;
+        const double th = (Mf[q * k + q] - Mf[p * k + p]) / (2.0 * apq);
+        const double at = std::fabs(th);
+        double t = at > 1e150 ? 0.5 / at : 1.0 / (at + std::sqrt(at * at + 1.0));
+        if (th < 0.0) t = -t;
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double mp = Mf[r * k + p], mq = Mf[r * k + q];
+          Mf[r * k + p] = c * mp - sn * mq;
+          Mf[r * k + q] = sn * mp + c * mq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double mp = Mf[p * k + r], mq = Mf[q * k + r];
+          Mf[p * k + r] = c * mp - sn * mq;
+          Mf[q * k + r] = sn * mp + c * mq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double qp = Qf[r * k + p], qq = Qf[r * k + q];
+          Qf[r * k + p] = c * qp - sn * qq;
+          Qf[r * k + q] = sn * qp + c * qq;
+        }
+      }
+  }
+  auto dd_matmul = [&](const std::vector<HD> &A_, bool transA, const std::vector<HD> &B_,
+                       std::vector<HD> &C_) {
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) {
+        HD acc = hd(0.0);
+        for (int c = 0; c < k; ++c)
+          acc = hd_add(acc, hd_mul(transA ? A_[c * k + a] : A_[a * k + c], B_[c * k + b]));
+        C_[a * k + b] = acc;
+      }
+  };
+  std::vector<HD> Q0(k * k), N(k * k), Q1(k * k), Mt(k * k);
+  for (int q = 0; q < k * k; ++q) Q0[q] = hd(Qf[q]);
+  dd_matmul(Q0, true, Q0, N);                          // N = Qf^T Qf
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) {
+      HD v = hd_neg(N[a * k + b]);
+      if (a == b) v = hd_add(v, hd(3.0));
+      N[a * k + b] = {0.5 * v.h, 0.5 * v.l};         // (3I - N) / 2
+    }
+  dd_matmul(Q0, false, N, Q1);                         // Q1 = Qf (3I - N) / 2
+  dd_matmul(M, false, Q1, Z);                          // Z = M Q1
+  dd_matmul(Q1, true, Z, Mt);                          // Mt = Q1^T M Q1
+  for (int a = 0; a < k; ++a)
+    for (int b = a + 1; b < k; ++b) {
+      HD m = hd_add(Mt[a * k + b], Mt[b * k + a]);
+      m = {0.5 * m.h, 0.5 * m.l};
+      Mt[a * k + b] = Mt[b * k + a] = m;
+    }
+  std::vector<HD> Qd(k * k);
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) Qd[a * k + b] = hd(a == b ? 1.0 : 0.0);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double dmax = 0.0, off = 0.0;
+    for (int a = 0; a < k; ++a) dmax = std::max(dmax, std::fabs(Mt[a * k + a].h));
+    for (int a = 0; a < k; ++a)
+      for (int b = a + 1; b < k; ++b) off = std::max(off, std::fabs(Mt[a * k + b].h));
     if (off == 0.0 || off <= 1e-32 * dmax) break;
     for (int p = 0; p < k; ++p)
       for (int q = p + 1; q < k; ++q) {
-        const HD apq = M[p * k + q];
+        const HD apq = Mt[p * k + q];
         if (apq.h == 0.0) continue;
-        const HD th = hd_div(hd_sub(M[q * k + q], M[p * k + p]), {2.0 * apq.h, 2.0 * apq.l});
+        const HD th = hd_div(hd_sub(Mt[q * k + q], Mt[p * k + p]), {2.0 * apq.h, 2.0 * apq.l});
         const HD at = th.h < 0.0 ? hd_neg(th) : th;
         HD t = at.h > 1e30 ? hd_div(hd(0.5), at)
                            : hd_div(hd(1.0), hd_add(at, hd_sqrt(hd_add(hd_mul(at, at), hd(1.0)))));
@@ -336,22 +405,24 @@ bool group_ritz(int k, const std::vector<HD> &G, const std::vector<double> &Wg,
         const HD c = hd_div(hd(1.0), hd_sqrt(hd_add(hd_mul(t, t), hd(1.0))));
         const HD sn = hd_mul(t, c);
         for (int r = 0; r < k; ++r) {
-          const HD mp = M[r * k + p], mq = M[r * k + q];
-          M[r * k + p] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
-          M[r * k + q] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
+          const HD mp = Mt[r * k + p], mq = Mt[r * k + q];
+          Mt[r * k + p] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
+          Mt[r * k + q] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
         }
         for (int r = 0; r < k; ++r) {
-          const HD mp = M[p * k + r], mq = M[q * k + r];
-          M[p * k + r] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
-          M[q * k + r] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
+          const HD mp = Mt[p * k + r], mq = Mt[q * k + r];
+          Mt[p * k + r] = hd_sub(hd_mul(c, mp), hd_mul(sn, mq));
+          Mt[q * k + r] = hd_add(hd_mul(sn, mp), hd_mul(c, mq));
         }
         for (int r = 0; r < k; ++r) {
-          const HD qp = Q[r * k + p], qq = Q[r * k + q];
-          Q[r * k + p] = hd_sub(hd_mul(c, qp), hd_mul(sn, qq));
-          Q[r * k + q] = hd_add(hd_mul(sn, qp), hd_mul(c, qq));
+          const HD qp = Qd[r * k + p], qq = Qd[r * k + q];
+          Qd[r * k + p] = hd_sub(hd_mul(c, qp), hd_mul(sn, qq));
+          Qd[r * k + q] = hd_add(hd_mul(sn, qp), hd_mul(c, qq));
         }
       }
   }
+  dd_matmul(Q1, false, Qd, Q);                         // Q = Q1 Qd
+  M = Mt;                                              // Ritz values on the diagonal
   // Ritz vectors V = L^-T Q (columns), by back substitution
   std::vector<HD> V(k * k);
   for (int b = 0; b < k; ++b)
@@ -770,8 +841,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   int status = REFEIG_OK;
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
   std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
-  std::vector<double> gaps_nat, eb_val(n);
-  std::vector<int> cmap(n), eb_idx(n);
+  std::vector<double> gaps_nat;
+  std::vector<int> cmap(n), cpl;
   int hflags = 0;
   hipEvent_t ev[8];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -899,31 +970,36 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int lw = (int)plan.groups.size();
     launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
     const bool grouping = o.group_tau > 0.0;
+    if (grouping) STEP(hipMemsetAsync(w.cpl, 0, sizeof(int), s));
     launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n, w.eE,
-                 w.emax, w.EP, kKeMax, w.flags, s, grouping ? w.eb_idx : nullptr,
-                 grouping ? w.eb_val : nullptr);
+                 w.emax, w.EP, kKeMax, w.flags, s, o.group_tau, grouping ? w.cpl : nullptr,
+                 w.cpl + 64, kCouplingsMax);
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (grouping) {
-      STEP(hipMemcpyAsync(eb_idx.data(), w.eb_idx, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-      STEP(hipMemcpyAsync(eb_val.data(), w.eb_val, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    }
+    int ncpl = 0;
+    if (grouping) STEP(hipMemcpyAsync(&ncpl, w.cpl, sizeof(int), hipMemcpyDeviceToHost, s));
     STEP(hipStreamSynchronize(s));
+    if (grouping && ncpl > 0 && ncpl <= kCouplingsMax) {
+      cpl.resize(2 * (size_t)ncpl);
+      STEP(hipMemcpyAsync(cpl.data(), w.cpl + 64, sizeof(int) * 2 * ncpl, hipMemcpyDeviceToHost,
+                          s));
+      STEP(hipStreamSynchronize(s));
+    }
     if (hflags & FLAG_TIE) return cleanup(REFEIG_E_GAP);
     if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
-    // ---- grouped correction (opt-in; not part of the paper's method): columns whose
-    // largest first-order correction exceeds group_tau are linked to that row; each linked
-    // group gets the Rayleigh-Ritz solution on its span instead of the first-order entries
+    // ---- grouped correction (opt-in; not part of the paper's method): every pair (i, j)
+    // whose first-order correction |e_ij| exceeds group_tau links columns i and j; each
+    // linked group gets the Rayleigh-Ritz solution on its span instead of the first-order
+    // entries. (More couplings than the list holds: no grouping in this iteration.)
     int ngroups = 0;
-    if (grouping) {
+    if (grouping && ncpl > 0 && ncpl <= kCouplingsMax) {
       std::vector<int> par(n);
       for (int j = 0; j < n; ++j) par[j] = j;
-      for (int j = 0; j < n; ++j)
-        if (eb_idx[j] >= 0 && eb_val[j] > o.group_tau) {
-          int a = uf_root(par, j), b = uf_root(par, eb_idx[j]);
-          if (a != b) par[std::max(a, b)] = std::min(a, b);
-        }
+      for (int q = 0; q < ncpl; ++q) {
+        int a = uf_root(par, cpl[2 * q]), b = uf_root(par, cpl[2 * q + 1]);
+        if (a != b) par[std::max(a, b)] = std::min(a, b);
+      }
       std::vector<std::vector<int>> comp(n);
       for (int j = 0; j < n; ++j) comp[uf_root(par, j)].push_back(j);
       std::vector<int> gcol, gfirst, gk, gpos, gbase, pa, pb;

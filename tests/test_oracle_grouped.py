@@ -47,6 +47,25 @@ def test_rotated_tight_pair_resolved_in_one_step(theta):
     assert _max_err_to_identity(Ph) > 0.1 * theta ** 2
 
 
+def test_chain_forms_one_group():
+    """Columns 0-1, 1-2 and 2-3 rotated in turn: the couplings chain the four columns into
+    one group, and one grouped step returns I."""
+    n = 14
+    d = np.concatenate([[1.0, 1.0 + 1e-10, 1.0 + 2e-10, 1.0 + 3e-10], np.arange(3.0, 3.0 + n - 4)])
+    A = np.asfortranarray(np.diag(d))
+    X0 = np.eye(n)
+    for a, t in ((0, 0.3), (1, 0.2), (2, 0.25)):
+        R = np.eye(n)
+        c, s_ = np.cos(t), np.sin(t)
+        R[a, a], R[a + 1, a], R[a, a + 1], R[a + 1, a + 1] = c, s_, -s_, c
+        X0 = X0 @ R
+    X0 = np.asfortranarray(X0)
+    Xh, Xl = X0.copy(order="F"), np.zeros((n, n), order="F")
+    st = oracle.refine_dd_step(A, Xh, Xl, tau=1e-3)
+    assert st.groups == 1
+    assert _max_err_to_identity(Xh) <= 1e-15
+
+
 def test_two_separate_groups():
     n = 16
     d = np.concatenate([[1.0, 1.0 + 1e-9, 5.0, 5.0 + 2e-9], np.arange(10.0, 10.0 + n - 4)])
