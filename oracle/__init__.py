@@ -136,7 +136,7 @@ class DDStep:
 
 def refine_dd_step(A, X_hi, X_lo, want_E=False, tau=0.0):
     """One iteration of Algorithm 1 in double-double. X_hi/X_lo updated in place.
-    tau > 0: columns whose largest first-order correction exceeds tau are grouped and
+    tau > 0: columns i, j whose first-order correction |e_ij| exceeds tau are grouped and
     corrected by the Rayleigh-Ritz problem on their span (or_refine_dd_step_grouped);
     the number of groups is returned in .groups."""
     n = A.shape[0]

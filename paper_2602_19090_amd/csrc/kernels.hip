@@ -18,7 +18,6 @@
 #include <hip/hip_ext.h>
 
 #include <float.h>
-#include <limits.h>
 #include <type_traits>
 
 namespace refeig {
@@ -160,20 +159,6 @@ __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
 #pragma unroll
   for (int q = 1; q < NT / 64; ++q) s = dd_add(s, ddv{scratch[2 * q], scratch[2 * q + 1]});
   return s;
-}
-
-template <int NT>
-__device__ __forceinline__ int block_min_int(int v, int *scratch) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) scratch[w] = v;
-  __syncthreads();
-  int m = scratch[0];
-#pragma unroll
-  for (int q = 1; q < NT / 64; ++q) m = min(m, scratch[q]);
-  return m;
 }
 
 // ---------------------------------------------------------------- column statistics

@@ -61,7 +61,7 @@ struct Work {
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
   int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
   int *colmap;   // working column p holds column colmap[p] of the caller's X
-  // grouped correction: per column argmax of |e_ij|, pair list, member table, Ritz data
+  // grouped correction: coupling list, pair list, member table, Ritz data
   int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
   double *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
   double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
