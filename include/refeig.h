@@ -73,7 +73,13 @@ typedef struct {
                             the beta rule of Sec. 4.1; 9 keeps X-hat at full FP64 precision,
                             the previous study's form without the X^(1) cut of Sec. 3.3
                             (an A/B for the paper's cost claim). 0: the beta rule.        */
-    int reserved_i[5];
+    int sparse_k;        /* > 0: the sparse-matrix rule of Sec. 4.3 with k = the largest
+                            number of nonzeros in a row of A (refeig_row_nonzeros gives it):
+                            xi = min(k^2, n) in beta (unless xi is set), and the error
+                            growth of the products of A's planes is taken as min(k, sqrt n)
+                            instead of sqrt n when the V product's diagonals are chosen.
+                            0: the dense rule.                                          */
+    int reserved_i[4];
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
                             every pair of columns whose first-order correction |e_ij|,
@@ -151,6 +157,10 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
                            size_t work_bytes, refeig_stream_t stream, refeig_report *reports);
 
 const char *refeig_strerror(int status);
+
+/* The largest number of nonzero entries in a row of A (device, n x n, ld lda),
+ * the k of the sparse rule (Sec. 4.3). Synchronous; *k is a host int. */
+int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream, int *k);
 
 /* ---- host-only entry points: the planning the library does on the host, exposed
  * for checks on a machine without a GPU (no device memory is touched) ----------- */

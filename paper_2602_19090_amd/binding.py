@@ -42,7 +42,8 @@ class Opts(ctypes.Structure):
                 ("stop_rule", ctypes.c_int), ("delta_safety", ctypes.c_double),
                 ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
                 ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("kx_force", ctypes.c_int), ("reserved_i", ctypes.c_int * 5),
+                ("kx_force", ctypes.c_int), ("sparse_k", ctypes.c_int),
+                ("reserved_i", ctypes.c_int * 4),
                 ("group_tau", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 3)]
 
@@ -91,6 +92,7 @@ _lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
 _lib.refine_eigvecs_batched.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.POINTER(Opts), _vp, _sz, _vp, _vp]
 
+_lib.refeig_row_nonzeros.argtypes = [_vp, _int, _int, _vp, ctypes.POINTER(_int)]
 _lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                                   ctypes.POINTER(_int), ctypes.POINTER(_int)]
 _lib.refeig_host_column_order.argtypes = [_int, _vp, _vp]
@@ -99,7 +101,7 @@ _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
             "refeig_split_cols", "refeig_slice_gemm", "refeig_batched_workspace_bytes",
             "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
-            "refeig_host_group_ritz"]
+            "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
 
 def _stream(stream=None):
@@ -191,6 +193,16 @@ def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=N
                                      ctypes.byref(opts) if opts is not None else None, _ptr(work),
                                      wb, _stream(stream), c(reps))
     return st, list(reps)
+
+
+def row_nonzeros(A, stream=None) -> int:
+    """refeig_row_nonzeros on a column-major device tensor A (n, n)."""
+    n = A.shape[0]
+    k = _int(0)
+    st = _lib.refeig_row_nonzeros(_ptr(A), n, n, _stream(stream), ctypes.byref(k))
+    if st != 0:
+        raise RuntimeError(strerror(st))
+    return k.value
 
 
 def _np_ptr(a):

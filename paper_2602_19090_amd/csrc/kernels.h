@@ -24,6 +24,10 @@ struct DiagOrder {
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
                      double *mx, int *flags, hipStream_t s, const int *colmap = nullptr);
 
+// The largest number of nonzeros in a column of the symmetric A (= in a row): atomicMax
+// into *kmax, which the caller zeroes.
+void launch_row_nonzeros(const double *A, int lda, int n, int *kmax, hipStream_t s);
+
 // 7-bit digit planes of M with column exponents e (see refeig_split_cols).
 //  planes: k planes, plane stride pstride, element (i, j) at j*rpad + i.
 //  trunc (optional, ld ldt): value of the k digits.

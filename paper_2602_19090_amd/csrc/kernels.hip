@@ -118,6 +118,11 @@ __device__ __forceinline__ int ceil_log2(double v) {
 }
 
 // ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -192,6 +197,27 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, 
     if (mx) mx[j] = m;
     if (m != 0.0 && (ee < -400 || ee > 400)) atomicOr(flags, FLAG_RANGE);
   }
+}
+
+// Nonzeros of column j of the symmetric A (= row j), block per column; the maximum goes
+// to *kmax (atomicMax on an int the caller zeroed).
+__global__ __launch_bounds__(256) void k_row_nnz(const double *__restrict__ A, int lda, int n,
+                                                 int *kmax) {
+  __shared__ double scratch[4];
+  const int j = blockIdx.x;
+  const double *col = A + (size_t)j * lda;
+  double cnt = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) cnt += (col[i] != 0.0) ? 1.0 : 0.0;
+  // counts are small integers: a maximum reduction over per-wave sums is exact
+  cnt = wave_sum(cnt);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(kmax, (int)(scratch[0] + scratch[1] + scratch[2] + scratch[3]));
+}
+
+void launch_row_nonzeros(const double *A, int lda, int n, int *kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_nnz, dim3(n), dim3(256), 0, s, A, lda, n, kmax);
 }
 
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,

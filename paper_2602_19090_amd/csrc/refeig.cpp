@@ -464,6 +464,20 @@ int uf_root(std::vector<int> &par, int a) {
   return a;
 }
 
+// xi of beta: the option, else min(k^2, n) under the sparse rule (Sec. 4.3), else n
+// (the dense rule of Sec. 4.1).
+double xi_of(const refeig_opts &o, int n) {
+  if (o.xi > 0.0) return o.xi;
+  if (o.sparse_k > 0) return std::min((double)o.sparse_k * o.sparse_k, (double)n);
+  return (double)n;
+}
+// log2 of the statistical error growth of a product with A: sqrt(n) for dense A,
+// min(k, sqrt(n)) under the sparse rule.
+double lgrowth_of(const refeig_opts &o, int n) {
+  const double sq = std::sqrt((double)n);
+  return std::log2(o.sparse_k > 0 ? std::min((double)o.sparse_k, sq) : sq);
+}
+
 // beta of Sec. 4.1 (floor form): beta = floor(log2((1/(0.75u)) sqrt(xi delta g / (L S)))),
 // evaluated as q = ((xi*delta)*g)/(L*S), t = sqrt(q)/(0.75*2^-53), beta = exponent(t) - 1.
 // kx = ceil((54 - beta + max_j(e_j - c_j)) / 7): the X^(1) grid 2^(c_j+beta-54) is the
@@ -545,8 +559,9 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
   const int npad = round_up(n, kTile);
   const size_t nn = (size_t)n * n;
   const double delta_int = target / o.delta_safety;
-  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  const double xi = xi_of(o, n);
   const double lsqn = 0.5 * std::log2((double)n);
+  const double lgrowth_a = lgrowth_of(o, n);   // error growth of products of A's planes
   const int alpha = (int)std::ceil((53.0 + std::log2((double)n)) / 2.0);
   const int b = 53 - alpha;  // bits per FP64 slice
   auto t_start = std::chrono::steady_clock::now();
@@ -630,7 +645,7 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
     int dv = 2;
     for (int j = 0; j < n; ++j) {
       if (mxX[j] == 0.0) continue;
-      double need_bits = eA_max + eX[j] + b + std::log2(1.5 * kx) + lsqn -
+      double need_bits = eA_max + eX[j] + b + std::log2(1.5 * kx) + lgrowth_a -
                          std::log2(o.theta * delta_int * gaps[j]);
       dv = std::max(dv, (int)std::ceil(need_bits / b));
     }
@@ -811,7 +826,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   if (rep) std::memset(rep, 0, sizeof(*rep));
   if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
-      !(o.group_tau >= 0.0) || o.kx_force < 0 || o.kx_force > kKxMax ||
+      !(o.group_tau >= 0.0) || o.kx_force < 0 || o.kx_force > kKxMax || o.sparse_k < 0 ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -833,9 +848,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   const int npad = w.npad;
   const size_t P = w.P;
   const double delta_int = target / o.delta_safety;
-  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  const double xi = xi_of(o, n);
   const double theta = o.theta;
   const double lsqn = 0.5 * std::log2((double)n);
+  const double lgrowth_a = lgrowth_of(o, n);   // error growth of products of A's planes
   auto t_start = std::chrono::steady_clock::now();
 
   int status = REFEIG_OK;
@@ -925,7 +941,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
     std::vector<int> dcol(npad, 2), dhost;
     {
-      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lsqn;
+      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lgrowth_a;
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
         double need = (c0 + eX[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
@@ -1163,6 +1179,22 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
 #undef STEP
 }
 
+int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream, int *k) {
+  if (!A || !k || n < 1 || lda < n) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int *d = nullptr;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMalloc((void **)&d, sizeof(int)));
+  HIPCHK(hipMemsetAsync(d, 0, sizeof(int), s));
+  launch_row_nonzeros(A, lda, n, d, s);
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFree(d));
+  *k = h;
+  return REFEIG_OK;
+}
+
 int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const double *mx,
                      double target, const refeig_opts *o_in, int *beta, int *kx) {
   if (n < 1 || !lam || !e || !c || !mx || !beta || !kx || !(target > 0.0)) return REFEIG_E_ARG;
@@ -1174,7 +1206,7 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
   double gmin, lmax;
   column_gaps(l, g, &gmin, &lmax);
   if (!(gmin > 0.0)) return REFEIG_E_GAP;
-  const double xi = o.xi > 0.0 ? o.xi : (double)n;
+  const double xi = xi_of(o, n);
   beta_rule(n, xi, target / o.delta_safety, gmin, lmax, ev, cv, m, beta, kx);
   return REFEIG_OK;
 }

@@ -368,3 +368,28 @@ def test_tile_boundaries(n):
     print(f"  n={n} status={st} iters={rep.iters} fwd={err:.2e}", flush=True)
     assert st == rb.REFEIG_OK, rb.strerror(st)
     assert err <= target
+
+
+def test_sparse_rule_band_matrix():
+    """The sparse rule on a band matrix (half-bandwidth 3, so k = 7 nonzeros per row):
+    refeig_row_nonzeros finds k; one step matches the oracle's step with xi = min(k^2, n);
+    the solve reaches the target against X_true."""
+    import torch
+    rb = _rb()
+    n, target = 600, 1e-13
+    p = workloads.banded_problem(n, 3)
+    A, X, D = _to_dev(p)
+    k = rb.row_nonzeros(A)
+    assert k == 7
+    opts = rb.default_opts(fixed_iters=1, sparse_k=k)
+    st, rep = rb.refine_eigvecs(A, X, D, target, opts)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    ref = oracle.method_step(p.A, p.X0, p.D0, target / opts.delta_safety, xi=float(min(k * k, n)))
+    assert rep.beta[0] == ref.beta and rep.kx[0] == ref.kx
+    assert float(np.max(np.abs(rb.from_colmajor(X) - ref.X_hi))) <= target / opts.delta_safety
+    Xt, _ = _xtrue(p)
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(sparse_k=k))
+    err = _fwd(rb.from_colmajor(X), Xt)
+    print(f"  sparse rule: iters={rep.iters} kx={list(rep.kx[:rep.iters])} fwd={err:.2e}", flush=True)
+    assert st == rb.REFEIG_OK and err <= target

@@ -109,3 +109,16 @@ def test_group_ritz_rejects_indefinite_gram():
     G = np.array([[1.0, 2.0], [2.0, 1.0]])
     st, *_ = rb.host_group_ritz(G, np.zeros((2, 2)), np.zeros((2, 2)), [1.0, 1.0], [0.0, 0.0])
     assert st == rb.REFEIG_E_GAP
+
+
+def test_sparse_rule_beta_matches_oracle():
+    """Under the sparse rule (Sec. 4.3) beta takes xi = min(k^2, n)."""
+    rb = _rb()
+    p = workloads.banded_problem(300, 3)
+    e, c, mx = _colstats(p.X0)
+    k = 7
+    st, beta, kx = rb.host_beta(p.D0, e, c, mx, 1e-12, rb.default_opts(sparse_k=k))
+    ref = oracle.beta_rule(p.D0, p.X0, 1e-12 / 8.0, xi=float(min(k * k, 300)))
+    dense = oracle.beta_rule(p.D0, p.X0, 1e-12 / 8.0)
+    assert st == 0 and (beta, kx) == (ref["beta"], ref["kx"])
+    assert ref["beta"] < dense["beta"]

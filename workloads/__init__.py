@@ -141,6 +141,27 @@ def spectrum_for_config(config_id: int, n: int, rng: np.random.Generator, cond_e
     return geometric_spectrum(n, float(cond_exp))
 
 
+def banded_problem(n: int, bw: int, index: int = 0, x0: str = "eigh") -> Problem:
+    """A sparse stand-in (Sec. 4.3 measures sparse matrices from ELSES and SuiteSparse, which
+    are not available): a symmetric band matrix of half-bandwidth bw (at most 2 bw + 1
+    nonzeros per row) with N(0, 1) entries plus a diagonal ramp 0..n-1, seeded by
+    (2602, 19090, 6, index). Start from an FP64 eigensolve (ascending)."""
+    rng = np.random.default_rng([SEED_BASE[0], SEED_BASE[1], 6, index])
+    A = np.zeros((n, n))
+    for d in range(1, bw + 1):
+        v = rng.standard_normal(n - d)
+        A[np.arange(n - d), np.arange(d, n)] = v
+    A = A + A.T
+    A[np.arange(n), np.arange(n)] = rng.standard_normal(n) + np.arange(n, dtype=np.float64)
+    A = np.asfortranarray(A)
+    X0 = D0 = None
+    if x0 == "eigh":
+        w, X = np.linalg.eigh(A)
+        X0, D0 = np.asfortranarray(X), w.copy()
+    meta = {"config": 6, "n": n, "index": index, "bw": bw, "digest": matrix_digest(A)}
+    return Problem(f"band{bw}_n{n}_i{index}", A, None, None, X0, D0, meta)
+
+
 def config4_sizes(count: int, batch: int = 0):
     """Orders and condition exponents of the many-small-matrices workload (config 4):
     n = round(exp(U(ln 32, ln 1024))), cond = 10^c with c ~ U(4, 12), seeded per batch.
