@@ -73,13 +73,24 @@ typedef struct {
                             the beta rule of Sec. 4.1; 9 keeps X-hat at full FP64 precision,
                             the previous study's form without the X^(1) cut of Sec. 3.3
                             (an A/B for the paper's cost claim). 0: the beta rule.        */
+    int schedule;        /* 1: adaptive accuracy, an extension beyond the paper (which aims
+                            every iteration's products at the final delta): from the second
+                            iteration on, with e the previous correction max|E~| (this
+                            iteration's output error is then about e^4, the next one's
+                            about e^8), the products aim at
+                              max(delta, min(e^4 / 100,
+                                  (0.1 / theta) sqrt(max(e^8, delta) gap / max|lambda|))):
+                            the second bound keeps the error the loose products leave in
+                            every entry of X, which the next iteration amplifies by about
+                            max|lambda| / gap, at a tenth of that iteration's own output
+                            error (gap: the smallest eigenvalue gap). 0: the paper's.      */
     int sparse_k;        /* > 0: the sparse-matrix rule of Sec. 4.3 with k = the largest
                             number of nonzeros in a row of A (refeig_row_nonzeros gives it):
                             xi = min(k^2, n) in beta (unless xi is set), and the error
                             growth of the products of A's planes is taken as min(k, sqrt n)
                             instead of sqrt n when the V product's diagonals are chosen.
                             0: the dense rule.                                          */
-    int reserved_i[4];
+    int reserved_i[3];
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
                             every pair of columns whose first-order correction |e_ij|,
@@ -111,6 +122,7 @@ typedef struct {
                                            last (events taken by the dispatches)          */
     int launches_p[REFEIG_MAX_ITERS][3];/* slice-GEMM kernel dispatches of each product    */
     int groups[REFEIG_MAX_ITERS];    /* groups corrected by Rayleigh-Ritz (group_tau > 0) */
+    double delta_it[REFEIG_MAX_ITERS];/* internal accuracy the iteration's products aimed at */
     double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
     double max_abs_lambda;           /* max |lambda| (last)                             */
     double ms_total;

@@ -42,8 +42,8 @@ class Opts(ctypes.Structure):
                 ("stop_rule", ctypes.c_int), ("delta_safety", ctypes.c_double),
                 ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
                 ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("kx_force", ctypes.c_int), ("sparse_k", ctypes.c_int),
-                ("reserved_i", ctypes.c_int * 4),
+                ("kx_force", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("sparse_k", ctypes.c_int), ("reserved_i", ctypes.c_int * 3),
                 ("group_tau", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 3)]
 
@@ -59,7 +59,8 @@ class Report(ctypes.Structure):
                 ("pairs_f", (ctypes.c_double * 3) * MAX_ITERS),
                 ("ms_p", (ctypes.c_double * 3) * MAX_ITERS),
                 ("launches_p", (ctypes.c_int * 3) * MAX_ITERS),
-                ("groups", ctypes.c_int * MAX_ITERS), ("min_gap", ctypes.c_double),
+                ("groups", ctypes.c_int * MAX_ITERS), ("delta_it", ctypes.c_double * MAX_ITERS),
+                ("min_gap", ctypes.c_double),
                 ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
     def as_dict(self):
@@ -72,7 +73,7 @@ class Report(ctypes.Structure):
                 "ms_p": [list(self.ms_p[i]) for i in range(k)],
                 "pairs_f": [list(self.pairs_f[i]) for i in range(k)],
                 "launches_p": [list(self.launches_p[i]) for i in range(k)],
-                "groups": list(self.groups[:k]),
+                "groups": list(self.groups[:k]), "delta_it": list(self.delta_it[:k]),
                 "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
                 "ms_total": self.ms_total}
 

@@ -827,6 +827,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
       !(o.group_tau >= 0.0) || o.kx_force < 0 || o.kx_force > kKxMax || o.sparse_k < 0 ||
+      o.schedule < 0 || o.schedule > 1 ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -931,7 +932,21 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     gaps.resize(n);
     for (int p = 0; p < n; ++p) gaps[p] = gaps_nat[cmap[p]];
     int beta, kx;
-    beta_rule(n, xi, delta_int, gmin, lmax, eX, cX, mxX, &beta, &kx);
+    // accuracy this iteration's products aim at: the internal delta, or, with the adaptive
+    // schedule (an extension beyond the paper), a looser level while the previous correction
+    // e was large. This iteration's output error is then about e^4 and the next one's about
+    // e^8 (quadratic convergence). Loose products leave an error nu = theta delta_k in every
+    // entry of X; the next iteration turns it into about nu^2 max|lambda| / gap (the same
+    // amplification that bounds the X^(1) cut of Sec. 4.1), kept at a tenth of that
+    // iteration's own output error, or of delta when that one is the last.
+    double delta_k = delta_int;
+    if (o.schedule == 1 && it > 0 && std::isfinite(eps_prev)) {
+      const double e4 = std::pow(eps_prev, 4.0);
+      const double direct = 0.01 * e4;
+      const double noise = (0.1 / theta) * std::sqrt(std::max(e4 * e4, delta_int) * gmin / lmax);
+      delta_k = std::max(delta_int, std::min(direct, noise));
+    }
+    beta_rule(n, xi, delta_k, gmin, lmax, eX, cX, mxX, &beta, &kx);
     if (o.kx_force > 0) kx = o.kx_force;
     // ---- X^(1) and its planes (both layouts)
     launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s,
@@ -944,7 +959,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lgrowth_a;
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
-        double need = (c0 + eX[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
+        double need = (c0 + eX[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
         dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
@@ -973,7 +988,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (resmax[j] == 0.0) continue;
-        double need = (c0 + eR[j] - std::log2(theta * delta_int * gaps[j])) / 7.0;
+        double need = (c0 + eR[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
         dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
@@ -1102,7 +1117,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
     // ---- X <- X^(1) + X^(1) E~
     {
-      const double c0 = 7 + std::log2(1.008 * kx) + lsqn - std::log2(theta * delta_int);
+      const double c0 = 7 + std::log2(1.008 * kx) + lsqn - std::log2(theta * delta_k);
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (emax[j] == 0.0) continue;
@@ -1150,6 +1165,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->launches_p[it][1] = lw;
       rep->launches_p[it][2] = lu;
       rep->groups[it] = ngroups;
+      rep->delta_it[it] = delta_k;
       rep->iters = it + 1;
       rep->min_gap = gmin;
       rep->max_abs_lambda = lmax;
@@ -1161,7 +1177,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
               it + 1, beta, kx, dv, dw, du, (int)std::lround(pv + pw + pu), eps, gmin, t_it,
               g1 + g2 + g3);
     for (int p = 0; p < n; ++p) lam_prev[cmap[p]] = lam[p];
-    if (o.fixed_iters > 0) continue;
+    if (o.fixed_iters > 0) {
+      eps_prev = eps;
+      continue;
+    }
     // The correction eps = max|E~| estimates the error of X^(1) (Sec. 3.2: X = X^(1)(I + E)),
     // which never falls below the truncation grid that beta sets. The forward error after
     // the update is modelled by eq. (assume2): eps^2 max|lambda| / (xi gap); stop once that

@@ -393,3 +393,36 @@ def test_sparse_rule_band_matrix():
     err = _fwd(rb.from_colmajor(X), Xt)
     print(f"  sparse rule: iters={rep.iters} kx={list(rep.kx[:rep.iters])} fwd={err:.2e}", flush=True)
     assert st == rb.REFEIG_OK and err <= target
+
+
+def test_adaptive_schedule():
+    """The adaptive accuracy schedule (an extension beyond the paper): from a start with
+    mixed pairs (errors up to 0.35) the second iteration's products aim at a looser level
+    than the final delta, never above eps^4 / 100 of the first correction, the last
+    iteration's products aim at the final delta, and the solve still meets the target
+    against X_true in no more iterations than the paper's schedule."""
+    import torch
+    rb = _rb()
+    target = 1e-14
+    p = workloads.make_problem(3, 700, x0="eigh")
+    Xt, lt = _xtrue(p)
+    X0 = _mixed_start(p, [(10, 11), (300, 301), (650, 651)], [0.35, 0.25, 0.15])
+    res = {}
+    for sched in (0, 1):
+        A, X = rb.colmajor(p.A), rb.colmajor(X0)
+        D = torch.from_numpy(np.array(p.D0)).cuda()
+        st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(schedule=sched, max_iter=12))
+        r = rep.as_dict()
+        err = _fwd(rb.from_colmajor(X), Xt)
+        res[sched] = (st, r, err)
+        print(f"  schedule={sched}: status={st} iters={r['iters']} "
+              f"delta={['%.1e' % d for d in r['delta_it']]} kx={r['kx']} "
+              f"eps={['%.1e' % e for e in r['eps']]} fwd={err:.2e}", flush=True)
+    st, r, err = res[1]
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert err <= target
+    delta = target / rb.default_opts().delta_safety
+    assert r["delta_it"][0] == delta and res[0][1]["delta_it"] == [delta] * res[0][1]["iters"]
+    assert delta < r["delta_it"][1] <= 0.01 * r["eps"][0] ** 4
+    assert r["delta_it"][-1] == delta
+    assert r["iters"] <= res[0][1]["iters"]
