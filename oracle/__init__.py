@@ -24,10 +24,10 @@ CFLAGS = ["-O3", "-mavx2", "-mfma", "-fopenmp", "-ffp-contract=off", "-fno-fast-
 
 
 def build(force: bool = True) -> str:
-    src = os.path.join(_HERE, "oracle.c")
+    srcs = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle_herm.c")]
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -63,6 +63,12 @@ def _load():
                                                   _c_double, _I]
         lib.or_secular_rank1.argtypes = [_c_int, _D, _D, _c_double, _D, _D, _D, _D, _D, _c_int,
                                          _c_int]
+        lib.or_herm_dd_step.argtypes = [_c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        lib.or_herm_beta_rule.argtypes = [_c_int, _D, _D, _D, _c_double, _c_double, _c_int, _I,
+                                          _I]
+        lib.or_herm_method_step.argtypes = [_c_int, _D, _D, _D, _D, _D, _c_double, _c_double,
+                                            _c_int, _c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                            _D, _I, _I]
         lib.or_two_sum.argtypes = [_c_double, _c_double, _D, _D]
         lib.or_two_prod.argtypes = [_c_double, _c_double, _D, _D]
         lib.or_dd_binop.argtypes = [_c_int, _c_double, _c_double, _c_double, _c_double, _D, _D]
@@ -296,3 +302,98 @@ def sign_align(X, Xref):
     s = np.sign(np.sum(X * Xref, axis=0))
     s[s == 0] = 1.0
     return Xref * s
+
+
+# ---------------------------------------------------------------- complex Hermitian case
+# Complex matrices are complex128 numpy arrays; the C side takes real and imaginary
+# parts (oracle_herm.c).
+
+def _parts(Z):
+    Z = np.asarray(Z, dtype=np.complex128)
+    return _f64(Z.real), _f64(Z.imag)
+
+
+def _cplx(re, im):
+    Z = np.empty(re.shape, dtype=np.complex128, order="F")
+    Z.real, Z.imag = re, im
+    return Z
+
+
+def herm_dd_step(A, X_hi, X_lo=None):
+    """One iteration of Algorithm 1 for Hermitian A in complex double-double.
+    Returns (X_hi, X_lo, lam_h, lam_l, r, emax) with X as complex128 pairs."""
+    Ar, Ai = _parts(A)
+    n = Ar.shape[0]
+    Xrh, Xih = _parts(X_hi)
+    Xrh, Xih = Xrh.copy(order="F"), Xih.copy(order="F")
+    if X_lo is None:
+        Xrl, Xil = np.zeros_like(Xrh, order="F"), np.zeros_like(Xih, order="F")
+    else:
+        Xrl, Xil = _parts(X_lo)
+        Xrl, Xil = Xrl.copy(order="F"), Xil.copy(order="F")
+    lh, ll, r, em = np.empty(n), np.empty(n), np.empty(n), np.zeros(1)
+    st = _load().or_herm_dd_step(n, _p(Ar), _p(Ai), _p(Xrh), _p(Xrl), _p(Xih), _p(Xil), _p(lh),
+                                 _p(ll), _p(r), _p(em))
+    if st != 0:
+        raise RuntimeError(f"or_herm_dd_step status {st}")
+    return _cplx(Xrh, Xih), _cplx(Xrl, Xil), lh, ll, r, float(em[0])
+
+
+def refine_dd_herm(A, X0, max_iter=12, tol=1e-28):
+    """Iterate the complex double-double step from X0 to its fixed point (stops as
+    refine_dd does). Returns (X_hi, X_lo, lam_h, history)."""
+    Xh, Xl = np.asarray(X0, dtype=np.complex128), None
+    hist, lh = [], None
+    for _ in range(max_iter):
+        Xh, Xl, lh, ll, r, em = herm_dd_step(A, Xh, Xl)
+        hist.append(em)
+        if em <= tol:
+            break
+        if len(hist) >= 3 and hist[-1] > 0.1 * hist[-2] and hist[-2] < 1e-10:
+            break
+    # Rayleigh quotients of the final iterate (one more step's lambda)
+    lam = herm_dd_step(A, Xh, Xl)[2]
+    return Xh, Xl, lam, hist
+
+
+def herm_beta_rule(lam, X, delta, xi=0.0, kx_max=9):
+    Xr, Xi = _parts(X)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    b = ctypes.c_int(); k = ctypes.c_int()
+    st = _load().or_herm_beta_rule(Xr.shape[0], _p(lam), _p(Xr), _p(Xi), float(delta), float(xi),
+                                   int(kx_max), ctypes.byref(b), ctypes.byref(k))
+    return {"status": st, "beta": b.value, "kx": k.value}
+
+
+def herm_method_step(A, X, lam_prev, delta, xi=0.0, kx_max=9, kx_force=0):
+    """One iteration of the proposed method for Hermitian A with exact (double-double)
+    products."""
+    Ar, Ai = _parts(A)
+    Xr, Xi = _parts(X)
+    n = Ar.shape[0]
+    lam_prev = np.ascontiguousarray(lam_prev, dtype=np.float64)
+    X1r, X1i = np.empty((n, n), order="F"), np.empty((n, n), order="F")
+    outs = [np.empty((n, n), order="F") for _ in range(4)]
+    lh, ll, r, em = np.empty(n), np.empty(n), np.empty(n), np.zeros(1)
+    b = ctypes.c_int(); k = ctypes.c_int()
+    st = _load().or_herm_method_step(n, _p(Ar), _p(Ai), _p(Xr), _p(Xi), _p(lam_prev),
+                                     float(delta), float(xi), int(kx_max), int(kx_force),
+                                     _p(X1r), _p(X1i), *[_p(o) for o in outs], _p(lh), _p(ll),
+                                     _p(r), _p(em), ctypes.byref(b), ctypes.byref(k))
+    if st != 0:
+        raise RuntimeError(f"or_herm_method_step status {st}")
+    out = MethodStep()
+    out.X1 = _cplx(X1r, X1i)
+    out.X_hi, out.X_lo = _cplx(outs[0], outs[2]), _cplx(outs[1], outs[3])
+    out.lam_h, out.lam_l, out.r, out.emax = lh, ll, r, float(em[0])
+    out.beta, out.kx = b.value, k.value
+    return out
+
+
+def phase_align(X, Xref):
+    """Multiply each column of Xref by the unit complex number that best aligns it with
+    the same column of X (the phase of xref_j^H x_j)."""
+    s = np.sum(np.conj(Xref) * X, axis=0)
+    a = np.abs(s)
+    ph = np.where(a > 0, s / np.where(a > 0, a, 1.0), 1.0)
+    return Xref * ph

@@ -624,7 +624,32 @@ static int cmp_double(const void *a, const void *b)
     return (x < y) ? -1 : (x > y) ? 1 : 0;
 }
 
+/* The rule itself, from the column maxima w_j of X (w_j = 0: an empty column). */
+int or_beta_core(int n, const double *lam, const double *w, double delta, double xi,
+                 int kx_max, int *beta_out, int *kx_out, double *gap_out, double *lmax_out,
+                 double *S_out);
+
 int or_beta_rule(int n, const double *lam, const double *X, int ldx, double delta, double xi,
+                 int kx_max, int *beta_out, int *kx_out, double *gap_out, double *lmax_out,
+                 double *S_out)
+{
+    double *w = (double *)malloc(sizeof(double) * n);
+    for (int j = 0; j < n; ++j) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double a = fabs(X[IX(i, j, ldx)]);
+            if (!isfinite(a)) { free(w); return -2; }
+            if (a > m) m = a;
+        }
+        w[j] = m;
+    }
+    int st = or_beta_core(n, lam, w, delta, xi, kx_max, beta_out, kx_out, gap_out, lmax_out,
+                          S_out);
+    free(w);
+    return st;
+}
+
+int or_beta_core(int n, const double *lam, const double *wmax, double delta, double xi,
                  int kx_max, int *beta_out, int *kx_out, double *gap_out, double *lmax_out,
                  double *S_out)
 {
@@ -645,12 +670,7 @@ int or_beta_rule(int n, const double *lam, const double *X, int ldx, double delt
     double S = 0.0;
     int extra = 0;
     for (int j = 0; j < n; ++j) {
-        double w = 0.0;
-        for (int i = 0; i < n; ++i) {
-            double a = fabs(X[IX(i, j, ldx)]);
-            if (!isfinite(a)) return -2;
-            if (a > w) w = a;
-        }
+        double w = wmax[j];
         if (w == 0.0) continue;
         int c = ceil_log2(w), e = exp_above(w);
         S += ldexp(1.0, 2 * c);

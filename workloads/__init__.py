@@ -51,6 +51,7 @@ def _load():
         lib.wl_householder_sym.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
         lib.wl_householder_q.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
         lib.wl_diag_rank1.argtypes = [ctypes.c_int, P, ctypes.c_double, P, P]
+        lib.wl_householder_herm.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -199,6 +200,42 @@ def make_problem(config_id: int, n: int, index: int = 0, x0: str = "eigh",
         raise ValueError(x0)
     meta = {"config": config_id, "n": n, "index": index, "x0": x0, "digest": matrix_digest(A)}
     return Problem(f"cfg{config_id}_n{n}_i{index}", A, lam, Q, X0, D0, meta)
+
+
+def hermitian_matrix(lam: np.ndarray, Vr: np.ndarray, Vi: np.ndarray) -> np.ndarray:
+    """A = Q diag(lam) Q^H with Q the product of the complex reflectors Vr + i Vi (columns);
+    exactly Hermitian, complex128, column-major."""
+    n, m = Vr.shape
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    Vr = np.asfortranarray(Vr, dtype=np.float64)
+    Vi = np.asfortranarray(Vi, dtype=np.float64)
+    Ar = np.empty((n, n), dtype=np.float64, order="F")
+    Ai = np.empty((n, n), dtype=np.float64, order="F")
+    if _load().wl_householder_herm(n, m, _ptr(Vr), _ptr(Vi), _ptr(lam), _ptr(Ar), _ptr(Ai)) != 0:
+        raise RuntimeError("wl_householder_herm failed")
+    A = np.empty((n, n), dtype=np.complex128, order="F")
+    A.real, A.imag = Ar, Ai
+    return A
+
+
+def hermitian_problem(config_id: int, n: int, index: int = 0, x0: str = "eigh") -> Problem:
+    """Complex Hermitian counterpart of make_problem: the spectrum of config 1, 2 or 3 and
+    four complex Householder reflectors with seeded N(0, 1) real and imaginary parts.
+    x0: "eigh" (LAPACK's complex Hermitian eigensolver in FP64) or "none"."""
+    rng = np.random.default_rng([SEED_BASE[0], SEED_BASE[1], 1000 + config_id, index])
+    Vr = np.asfortranarray(rng.standard_normal((n, 4)))
+    Vi = np.asfortranarray(rng.standard_normal((n, 4)))
+    lam = spectrum_for_config(config_id, n, rng)
+    A = hermitian_matrix(lam, Vr, Vi)
+    X0 = D0 = None
+    if x0 == "eigh":
+        w, X = np.linalg.eigh(A)
+        X0, D0 = np.asfortranarray(X), w.copy()
+    elif x0 != "none":
+        raise ValueError(x0)
+    meta = {"config": config_id, "n": n, "index": index, "x0": x0, "hermitian": True,
+            "digest": matrix_digest(A)}
+    return Problem(f"herm_cfg{config_id}_n{n}_i{index}", A, lam, None, X0, D0, meta)
 
 
 def jacobi_eig_fp32(A: np.ndarray, tol: float = 1e-7, max_sweeps: int = 60):

@@ -100,3 +100,65 @@ int wl_diag_rank1(int n, const double *dg, double rho, const double *u, double *
             A[i + (size_t)j * n] = (i == j) ? dg[i] + (rho * u[i]) * u[i] : (rho * u[i]) * u[j];
     return 0;
 }
+
+/* Complex Hermitian counterpart: M <- H M H with H = I - tau v v^H, tau = 2 / (v^H v),
+ * M Hermitian stored as real and imaginary parts (upper triangle authoritative).
+ * With p = tau M v, K = (tau/2) Re(v^H p) and q = p - K v: H M H = M - v q^H - q v^H. */
+static void reflect_two_sided_c(int n, double *Mr, double *Mi, const double *vr,
+                                const double *vi, double *pr, double *pi)
+{
+    double vv = 0.0;
+    for (int i = 0; i < n; ++i) vv += vr[i] * vr[i] + vi[i] * vi[i];
+    const double tau = 2.0 / vv;
+    /* p_j = sum_i M(j, i) v_i; M(j, i) = conj(M(i, j)) for i < j */
+    for (int j = 0; j < n; ++j) {
+        double ar = 0.0, ai = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double mr, mi;
+            if (i >= j) { mr = Mr[j + (size_t)i * n]; mi = Mi[j + (size_t)i * n]; }
+            else        { mr = Mr[i + (size_t)j * n]; mi = -Mi[i + (size_t)j * n]; }
+            ar += mr * vr[i] - mi * vi[i];
+            ai += mr * vi[i] + mi * vr[i];
+        }
+        pr[j] = tau * ar;
+        pi[j] = tau * ai;
+    }
+    double vp = 0.0;   /* Re(v^H p) */
+    for (int i = 0; i < n; ++i) vp += vr[i] * pr[i] + vi[i] * pi[i];
+    const double K = 0.5 * tau * vp;
+    for (int i = 0; i < n; ++i) { pr[i] -= K * vr[i]; pi[i] -= K * vi[i]; }   /* q */
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= j; ++i) {
+            /* v_i conj(q_j) + q_i conj(v_j) */
+            const double tr = (vr[i] * pr[j] + vi[i] * pi[j]) + (pr[i] * vr[j] + pi[i] * vi[j]);
+            const double ti = (vi[i] * pr[j] - vr[i] * pi[j]) + (pi[i] * vr[j] - pr[i] * vi[j]);
+            Mr[i + (size_t)j * n] -= tr;
+            Mi[i + (size_t)j * n] -= ti;
+        }
+}
+
+/* A = H_1 ... H_m diag(lam) H_m ... H_1 with complex reflectors (Vr + i Vi, column-major
+ * n x m). Output: real and imaginary parts, column-major, exactly Hermitian (the lower
+ * triangle mirrors the upper one, the diagonal is real). */
+int wl_householder_herm(int n, int m, const double *Vr, const double *Vi, const double *lam,
+                        double *Ar, double *Ai)
+{
+    if (n <= 0 || m < 0 || !Vr || !Vi || !lam || !Ar || !Ai) return -1;
+    double *pr = (double *)malloc(sizeof(double) * (size_t)n);
+    double *pi = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!pr || !pi) { free(pr); free(pi); return -2; }
+    memset(Ar, 0, sizeof(double) * (size_t)n * n);
+    memset(Ai, 0, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) Ar[i + (size_t)i * n] = lam[i];
+    for (int k = m - 1; k >= 0; --k)
+        reflect_two_sided_c(n, Ar, Ai, Vr + (size_t)k * n, Vi + (size_t)k * n, pr, pi);
+    for (int j = 0; j < n; ++j) {
+        Ai[j + (size_t)j * n] = 0.0;
+        for (int i = j + 1; i < n; ++i) {
+            Ar[i + (size_t)j * n] = Ar[j + (size_t)i * n];
+            Ai[i + (size_t)j * n] = -Ai[j + (size_t)i * n];
+        }
+    }
+    free(pr); free(pi);
+    return 0;
+}
