@@ -129,6 +129,87 @@ def solve_leg(rb, A, X0, D0, target, golden, args, ms_ref, **kw):
             "speedup_vs_paper_method": ms_ref / t, "status": rb.strerror(st)}
 
 
+def herm_leg(n, target, args):
+    """Complex Hermitian path: A_h = P A P^H with A the config-2 matrix of order n and P a
+    seeded diagonal of phases in {1, i, -1, -i} (exact), so X_true(A_h) = P X_true(A) column
+    by column up to a unit factor, and the stored X_true columns of A measure the error.
+    Start: the FP64 complex eigensolve of A_h (input preparation). Iterations to the target
+    from solves of k = 1, 2, ... iterations; then the K-iteration solve is timed."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2602_19090_amd import binding as rb
+    p = workloads.make_problem(2, n, x0="none")
+    golden = load_golden(2, n, p.meta["digest"])
+    rng = np.random.default_rng([2602, 19090, 77, n])
+    P = np.array([1.0, 1j, -1.0, -1j])[rng.integers(0, 4, n)]
+    Ah = (P[:, None] * p.A) * np.conj(P)[None, :]
+    del p
+    A = rb.colmajor_complex(Ah)
+    del Ah
+    log(f"hermitian n={n}: complex FP64 eigensolve for the start (untimed)")
+    try:
+        w, V = torch.linalg.eigh(A)          # A holds A_h^T = conj(A_h) row-major
+        X0 = V.conj().t().contiguous()       # rows: eigenvectors of A_h
+        del V
+    except RuntimeError as e:
+        log(f"torch complex eigh unavailable ({e}); LAPACK on the host")
+        w_np, V_np = np.linalg.eigh(rb.from_colmajor(A))
+        X0 = rb.colmajor_complex(V_np)
+        w = torch.from_numpy(w_np).cuda()
+    D0 = w.contiguous().to(torch.float64)
+
+    def err_of(X):
+        if golden is None:
+            return None
+        cols = golden["cols"]
+        Xs = X[torch.from_numpy(cols).to(X.device)].cpu().numpy().T
+        Xt = P[:, None] * golden["X"]
+        s_ = np.sum(np.conj(Xt) * Xs, axis=0)
+        ph = s_ / np.abs(s_)
+        return float(np.max(np.abs(Xs - Xt * ph)))
+
+    X, D = X0.clone(), D0.clone()
+    st, rep = rb.refine_eigvecs_herm(A, X, D, target)
+    stop_iters, stop_status = rep.iters, rb.strerror(st)
+    errs, K = [err_of(X0)], None
+    for k in range(1, 11):
+        X, D = X0.clone(), D0.clone()
+        st, rep = rb.refine_eigvecs_herm(A, X, D, target, rb.default_opts(fixed_iters=k))
+        errs.append(err_of(X))
+        log(f"  hermitian, {k} iterations: sampled error {errs[-1]}")
+        if errs[-1] is None or errs[-1] <= target:
+            K = k
+            break
+    if K is None:
+        return {"n": n, "ms_to_target": None, "fwd_err_per_iter": errs}
+    opts = rb.default_opts(fixed_iters=K)
+    ms, reps = [], []
+    for s_ in range(args.warmup + max(1, args.steps)):
+        X, D = X0.clone(), D0.clone()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st, rep = rb.refine_eigvecs_herm(A, X, D, target, opts)
+        e1.record()
+        torch.cuda.synchronize()
+        if s_ >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+            reps.append(rep.as_dict())
+    t = float(np.mean(ms))
+    r0 = reps[0]
+    return {"n": n, "workload": f"Hermitian, unitarily similar (phases 1, i, -1, -i) to the "
+                                f"config-2 matrix n={n} (cond 1e12), FP64-eigh start",
+            "target_fwd_err": target, "ms_to_target": t, "iters": K,
+            "value": 24.0 * n ** 3 * K / (t * 1e-3) / 1e12,
+            "unit": "TFLOP/s (FP64-equivalent: 3 complex products of 8 n^3 per iteration)",
+            "fwd_err_per_iter": errs, "stop_rule_iters": stop_iters,
+            "stop_rule_status": stop_status, "kx_per_iter": r0["kx"],
+            "pairs_per_iter": [round(sum(x), 2) for x in r0["pairs_f"]],
+            "ms_per_iter": r0["ms_iter"], "ms_gemm_per_iter": r0["ms_gemm"],
+            "status": rb.strerror(st)}
+
+
 def config4_leg(count):
     """Many small matrices (config 4): one batched call, exactly 3 iterations each, inputs
     resident on the device; matrices/s and FP64-equivalent TFLOP/s (6 n^3 per iteration)."""
@@ -281,6 +362,11 @@ def main():
     ap.add_argument("--group-tau", type=float, default=0.0, metavar="TAU",
                     help="also time the solve with the grouped correction (an extension beyond "
                          "the paper's method) at this threshold, e.g. 1e-3")
+    ap.add_argument("--herm", type=int, default=0, metavar="N",
+                    help="also time the complex Hermitian path (an extension the paper names as "
+                         "future work) at order N (4096: a matrix unitarily similar, by exact "
+                         "phases 1, i, -1, -i, to the config-2 matrix of order 4096, whose X_true "
+                         "columns are stored)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run one elementwise kernel of known traffic (for profiler byte counters)")
     args = ap.parse_args()
@@ -499,6 +585,10 @@ def main():
             grouped = {"group_tau": args.group_tau, "ms_to_target": None,
                        "fwd_err_per_iter": gerrs, "groups_per_iter": ggroups}
 
+    herm = None
+    if args.herm > 0:
+        herm = herm_leg(args.herm, target, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle double-double products on a column sample")
@@ -529,6 +619,8 @@ def main():
         out["ab_full_x_planes"] = ab
     if sched is not None:
         out["adaptive_schedule"] = sched
+    if herm is not None:
+        out["hermitian"] = herm
     print(json.dumps(out), flush=True)
 
 

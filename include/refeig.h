@@ -148,6 +148,29 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
                    double target_fwd_err, const refeig_opts *o, void *work, size_t work_bytes,
                    refeig_stream_t stream, refeig_report *report);
 
+/* Complex Hermitian extension (Sec. 5 names the Hermitian case as future
+ * work): the same iteration for A = A^H with complex X. A and X are complex
+ * matrices stored interleaved (real, imaginary) in column-major order, element
+ * (i, j) at A[2 (i + j lda)] (real part) and A[2 (i + j lda) + 1] (imaginary
+ * part), device pointers owned by the caller (e.g. torch complex128 tensors),
+ * 16-byte aligned; lda, ldx count complex elements. D holds n real eigenvalue
+ * estimates. r_i = 1 - x_i^H x_i, lambda_i = Re(x_i^H A x_i) / (1 - r_i),
+ * W = X^H (A X - X D), e_ij = w_ij / (lambda_j - lambda_i), e_ii = r_i / 2;
+ * X^(1) cuts both parts of a column on one grid, set by beta of Sec. 4.1 from
+ * the column maximum over both parts. Each complex product is two real slice
+ * products of reduction length 2n (real parts stacked above imaginary parts).
+ * The forward error is measured in the modulus, up to a unit complex factor
+ * per column. 1 <= n <= 4096. Options as refine_eigvecs, except that
+ * group_tau, schedule and sparse_k must be 0 and mode REFEIG_OZAKI_INT8
+ * (REFEIG_E_ARG otherwise). Workspace: refeig_herm_workspace_bytes, or NULL
+ * (the library allocates and frees it). Statuses and report as
+ * refine_eigvecs; pairs_f counts the slice products of both real GEMMs of a
+ * complex product, in units of one real n x n x 2n product. */
+int refeig_herm_workspace_bytes(int n, const refeig_opts *o, size_t *bytes);
+int refine_eigvecs_herm(const double *A, int lda, double *X, int ldx, double *D, int n,
+                        double target_fwd_err, const refeig_opts *o, void *work,
+                        size_t work_bytes, refeig_stream_t stream, refeig_report *report);
+
 /* Batched form of refine_eigvecs for `count` independent problems (the
  * serving and many-small-matrices workloads of Sec. 4's setting, one matrix
  * per request). Host arrays of length count hold each problem's order n[i],

@@ -84,6 +84,9 @@ _lib.refeig_workspace_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINT
 _lib.refine_eigvecs.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctypes.POINTER(Opts), _vp,
                                 _sz, _vp, ctypes.POINTER(Report)]
 _lib.refeig_strerror.restype = ctypes.c_char_p
+_lib.refeig_herm_workspace_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_lib.refine_eigvecs_herm.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctypes.POINTER(Opts),
+                                     _vp, _sz, _vp, ctypes.POINTER(Report)]
 _lib.refeig_strerror.argtypes = [_int]
 _lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
@@ -157,6 +160,39 @@ def refine_eigvecs(A, X, D, target: float, opts: Opts | None = None, work=None, 
     st = _lib.refine_eigvecs(_ptr(A), n, _ptr(X), n, _ptr(D), n, float(target),
                              ctypes.byref(opts) if opts is not None else None, _ptr(work), wb,
                              _stream(stream), ctypes.byref(rep))
+    return st, rep
+
+
+def colmajor_complex(M: np.ndarray, device="cuda"):
+    """numpy complex (n, m) matrix -> C-contiguous complex128 torch tensor holding it
+    column-major (interleaved real and imaginary parts)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(M, dtype=np.complex128).T)).to(device)
+
+
+def herm_workspace_bytes(n: int, opts: Opts | None = None) -> int:
+    out = _sz(0)
+    st = _lib.refeig_herm_workspace_bytes(int(n), ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(out))
+    if st != 0:
+        raise ValueError(strerror(st))
+    return out.value
+
+
+def refine_eigvecs_herm(A, X, D, target: float, opts: Opts | None = None, work=None, stream=None):
+    """Hermitian A: refine the complex X (complex128, column-major, see colmajor_complex) and
+    the real D in place. Returns (status, report)."""
+    import torch
+    n = D.numel()
+    assert A.dtype == X.dtype == torch.complex128 and D.dtype == torch.float64
+    assert A.is_cuda and X.is_cuda and D.is_cuda
+    assert A.is_contiguous() and X.is_contiguous() and D.is_contiguous()
+    assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+    rep = Report()
+    wb = work.numel() * work.element_size() if work is not None else 0
+    st = _lib.refine_eigvecs_herm(_ptr(A), n, _ptr(X), n, _ptr(D), n, float(target),
+                                  ctypes.byref(opts) if opts is not None else None, _ptr(work), wb,
+                                  _stream(stream), ctypes.byref(rep))
     return st, rep
 
 

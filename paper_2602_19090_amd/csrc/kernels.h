@@ -50,10 +50,12 @@ struct RowBlocks {
 // blocks when rb is null). The host issues one launch per group of row blocks
 // that need the same diagonals, so every block of a diagonal does real work.
 // ev_start / ev_stop (may be null) take the dispatch's own start / end times.
+// kdim: reduction length (a multiple of 128; 0 means npad). The complex products use
+// kdim = 2 npad: the imaginary parts are stacked after the real parts along K.
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
                        hipStream_t s, hipEvent_t ev_start = nullptr,
-                       hipEvent_t ev_stop = nullptr);
+                       hipEvent_t ev_stop = nullptr, int kdim = 0);
 // L rows per block tile of launch_slice_gemm for this npad.
 int gemm_tile_rows(int npad);
 
@@ -109,5 +111,44 @@ void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *d
 
 // out[colmap[p]] = v[p] for p < n (colmap may be null).
 void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s);
+
+
+// ---- complex Hermitian case. Complex matrices are interleaved (re, im), column-major,
+// element (i, j) at 2 (i + j ld). Complex operand rows are realified: a digit plane holds
+// K = 2 npad entries per row (real parts at k < npad, imaginary parts at npad + k) and has
+// stride 2 npad^2; the products run as real slice GEMMs with kdim = 2 npad.
+
+// Column statistics as launch_colstats over both parts (max_i max(|Re|, |Im|)).
+void launch_colstats_c(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
+                       double *mx, int *flags, hipStream_t s, const int *colmap = nullptr);
+
+// Realified digit planes with one exponent per column over both parts:
+//   planes: row j = (Re M_.j ; Im M_.j);  planes2 (optional): row j = (-Im M_.j ; Re M_.j);
+//   trunc (optional, complex, ld ldt): value of the k digits;
+//   planesT (optional, kT planes): row i = (Re M_i. ; -Im M_i.).
+void launch_split_c(const double *M, int ld, int rows, int cols, const int *e, int k,
+                    int8_t *planes, int8_t *planes2, size_t pstride, int rpad, int cpad,
+                    double *trunc, int ldt, int8_t *planesT, size_t pstrideT, int kT,
+                    hipStream_t s, const int *colmap = nullptr);
+
+// V epilogue + column pass (npad <= 4096): V = Vr + i Vi from the two products' slots,
+// r_j = 1 - x_j^H x_j, lambda_j = Re(x_j^H v_j) / (1 - r_j), Res = V - x_j lambda_j, eR_j
+// and resmax_j over both parts; planes of Res (Rpl) and of -i Res (Rpl2).
+void launch_epi_v_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eA, const int *eX, const double *X1, int n,
+                    double *lam, double *lam_lo, double *r, int *eR, double *resmax,
+                    int8_t *Rpl, int8_t *Rpl2, int kr, int *flags, hipStream_t s);
+
+// W epilogue: e_ij = w_ij / (lambda_j - lambda_i), e_jj = r_j / 2, E' = 2^eX_i e, emax_j =
+// max_i |e_ij| (modulus), eE_j; planes of E' (Epl) and of -i E' (Epl2).
+void launch_epi_w_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eX, const int *eR, const double *lam,
+                    const double *lam_lo, const double *r, int n, int *eE, double *emax,
+                    int8_t *Epl, int8_t *Epl2, int ke, int *flags, hipStream_t s);
+
+// Update: X_.colmap[j] = X1_.j + U_.j (both parts).
+void launch_epi_u_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eE, const double *X1, int n, double *X, int ldx,
+                    hipStream_t s, const int *colmap = nullptr);
 
 }  // namespace refeig

@@ -312,8 +312,8 @@ constexpr int GBM = 128, GBN = 128, GBK = 128, GLDS = GBK + 16;
 
 __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict__ Lp,
                                                        const int8_t *__restrict__ Rp,
-                                                       size_t pstride, int npad, int kl, int kr,
-                                                       int d_min, DiagOrder order,
+                                                       size_t pstride, int npad, int kdim,
+                                                       int kl, int kr, int d_min, DiagOrder order,
                                                        int32_t *__restrict__ C, RowBlocks rb) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
   const int d = d_min + slot;
   const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
   const int npairs = s_hi - s_lo + 1;
-  const int KT = npad / GBK;
+  const int KT = kdim / GBK;
   const int T = npairs * KT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -447,8 +447,9 @@ __device__ __forceinline__ void wait_vm_lds_barrier() {
 
 __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restrict__ Lp,
                                                            const int8_t *__restrict__ Rp,
-                                                           size_t pstride, int npad, int kl,
-                                                           int kr, int d_min, DiagOrder order,
+                                                           size_t pstride, int npad, int kdim,
+                                                           int kl, int kr, int d_min,
+                                                           DiagOrder order,
                                                            int32_t *__restrict__ C, RowBlocks rb) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   const int d = d_min + slot;
   const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
   const int npairs = s_hi - s_lo + 1;
-  const int KT = npad / DBK;
+  const int KT = kdim / DBK;
   const int T = npairs * KT;   // K-stages over all pairs of this diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -592,7 +593,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
 
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
-                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim) {
+  if (kdim <= 0) kdim = npad;
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
   int cnt[kMaxDiag];
@@ -621,10 +623,10 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   if (npad >= 1024)
     hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride,
-                       npad, kl, kr, d_min, o, C, rb);
+                       npad, kdim, kl, kr, d_min, o, C, rb);
   else
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
-                          Lp, Rp, pstride, npad,
+                          Lp, Rp, pstride, npad, kdim,
                        kl, kr, d_min, o, C, rb);
 }
 
@@ -1069,6 +1071,471 @@ __global__ void k_scatter(const double *__restrict__ v, const int *__restrict__ 
 
 void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, v, colmap, n, out);
+}
+
+
+// ================================================================ complex Hermitian case
+// Complex matrices are interleaved (real, imaginary) and column-major: element (i, j) at
+// 2 (i + j ld). A complex operand row is "realified": its digit plane holds K = 2 npad
+// entries, the real parts at k < npad and the imaginary parts at npad + k, so that one
+// real slice GEMM of reduction length 2 npad forms the real (or imaginary) part of a
+// complex product. Both parts of a column share one exponent (that of the larger part).
+
+__global__ __launch_bounds__(256) void k_colstats_c(const double *__restrict__ M, int ld,
+                                                    int rows, int cols, int *e, int *c,
+                                                    double *mx, int *flags,
+                                                    const int *__restrict__ colmap) {
+  __shared__ double scratch[4];
+  const int j = blockIdx.x;
+  if (j >= cols) {
+    if (threadIdx.x == 0) {
+      e[j] = 0;
+      c[j] = 0;
+      if (mx) mx[j] = 0.0;
+    }
+    return;
+  }
+  const double2 *col = (const double2 *)(M + 2 * (size_t)(colmap ? colmap[j] : j) * ld);
+  double m = 0.0;
+  int bad = 0;
+  for (int i = threadIdx.x; i < rows; i += 256) {
+    const double2 z = col[i];
+    const double a = fabs(z.x), b = fabs(z.y);
+    if (!(a <= DBL_MAX) || !(b <= DBL_MAX)) bad = 1;
+    else m = fmax(m, fmax(a, b));
+  }
+  if (bad) atomicOr(flags, FLAG_NONFINITE);
+  m = block_max<256>(m, scratch);
+  if (threadIdx.x == 0) {
+    int ee = exp_above(m);
+    e[j] = ee;
+    c[j] = ceil_log2(m);
+    if (mx) mx[j] = m;
+    if (m != 0.0 && (ee < -400 || ee > 400)) atomicOr(flags, FLAG_RANGE);
+  }
+}
+
+void launch_colstats_c(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
+                       double *mx, int *flags, hipStream_t s, const int *colmap) {
+  hipLaunchKernelGGL(k_colstats_c, dim3(cols_pad), dim3(256), 0, s, M, ld, rows, cols, e, c, mx,
+                     flags, colmap);
+}
+
+// Digits 1..kk of a (sign-magnitude, base 128 below 2^ej) into dig; returns the value of
+// the first k of them.
+__device__ __forceinline__ double digits_of(double a, int ej, int kk, int k,
+                                            int (&dig)[kMaxPlanesSplit]) {
+  double y = ldexp(fabs(a), -ej);
+  const int sg = (a < 0.0) ? -1 : 1;
+  double val = 0.0;
+#pragma unroll
+  for (int t = 0; t < kMaxPlanesSplit; ++t) {
+    dig[t] = 0;
+    if (t < kk) {
+      double t128 = y * 128.0;
+      double d = floor(t128);
+      y = t128 - d;
+      dig[t] = sg * (int)d;
+      if (t < k) val += ldexp(d, ej - 7 * (t + 1));
+    }
+  }
+  return (a < 0.0) ? -val : val;
+}
+
+// Digit planes of a complex matrix M (rows x cols, ld) with column exponents e, 64 x 64
+// tiles of the padded rpad x cpad area (zero digits outside):
+//   planes (k planes, stride pstride): row j = column j realified,
+//     (j, i) = digit of Re M_ij, (j, rpad + i) = digit of Im M_ij (K-blocked, cpad rows);
+//   planes2 (optional): the realified column of i M: (j, i) = -Im M_ij, (j, rpad + i) = Re M_ij;
+//   trunc (optional, complex, ld ldt): the value of the first k digits of both parts;
+//   planesT (optional, kT planes): row i = row i of M with its imaginary parts negated,
+//     (i, j) = Re M_ij, (i, cpad + j) = -Im M_ij (K-blocked, rpad rows).
+// colmap (may be null): column j is read from column colmap[j] of M.
+template <bool WITH_T>
+__global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ M, int ld, int rows,
+                                                 int cols, const int *__restrict__ e, int k,
+                                                 int8_t *__restrict__ planes,
+                                                 int8_t *__restrict__ planes2, size_t pstride,
+                                                 int rpad, int cpad, double *__restrict__ trunc,
+                                                 int ldt, int8_t *__restrict__ planesT,
+                                                 size_t pstrideT, int kT,
+                                                 const int *__restrict__ colmap) {
+  constexpr int TP = kMaxPlanesT * 64 * kTStride;   // one part's transpose tile
+  __shared__ __attribute__((aligned(16))) int8_t sT[WITH_T ? 2 * TP : 16];
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int ig = threadIdx.x & 15, jl = threadIdx.x >> 4;
+  const int kk = (WITH_T && kT > k) ? kT : k;
+  const double2 *Mz = (const double2 *)M;
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int jj = jl + 16 * q, j = j0 + jj;
+    const int ej = (j < cols) ? e[j] : 0;
+    const size_t mcol = (j < cols) ? (size_t)(colmap ? colmap[j] : j) * ld : 0;
+    unsigned pr[kMaxPlanesSplit], pi[kMaxPlanesSplit], pn[kMaxPlanesSplit];
+#pragma unroll
+    for (int t = 0; t < kMaxPlanesSplit; ++t) pr[t] = pi[t] = pn[t] = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ii = 4 * ig + u, i = i0 + ii;
+      double2 z = {0.0, 0.0};
+      if (i < rows && j < cols) z = Mz[mcol + i];
+      int dr[kMaxPlanesSplit], di[kMaxPlanesSplit];
+      const double vr = digits_of(z.x, ej, kk, k, dr);
+      const double vi = digits_of(z.y, ej, kk, k, di);
+#pragma unroll
+      for (int t = 0; t < kMaxPlanesSplit; ++t) {
+        if (t < k) {
+          pr[t] |= ((unsigned)(dr[t] & 0xff)) << (8 * u);
+          pi[t] |= ((unsigned)(di[t] & 0xff)) << (8 * u);
+          pn[t] |= ((unsigned)((-di[t]) & 0xff)) << (8 * u);
+        }
+        if (WITH_T && t < kT) {
+          sT[(t * 64 + ii) * kTStride + jj] = (int8_t)dr[t];
+          sT[TP + (t * 64 + ii) * kTStride + jj] = (int8_t)(-di[t]);
+        }
+      }
+      if (trunc && i < rows && j < cols) {
+        trunc[2 * ((size_t)j * ldt + i)] = vr;
+        trunc[2 * ((size_t)j * ldt + i) + 1] = vi;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxPlanesSplit; ++t)
+      if (t < k) {
+        int8_t *pl = planes + (size_t)t * pstride;
+        *(unsigned *)(pl + kb_off(j, i0 + 4 * ig, cpad)) = pr[t];
+        *(unsigned *)(pl + kb_off(j, rpad + i0 + 4 * ig, cpad)) = pi[t];
+        if (planes2) {
+          int8_t *p2 = planes2 + (size_t)t * pstride;
+          *(unsigned *)(p2 + kb_off(j, i0 + 4 * ig, cpad)) = pn[t];
+          *(unsigned *)(p2 + kb_off(j, rpad + i0 + 4 * ig, cpad)) = pr[t];
+        }
+      }
+  }
+  if (WITH_T) {
+    __syncthreads();
+    const int ii = threadIdx.x >> 2, jq = (threadIdx.x & 3) * 16;
+    for (int t = 0; t < kT; ++t) {
+      int8_t *pt = planesT + (size_t)t * pstrideT;
+      const v4i wr = *(const v4i *)(sT + (t * 64 + ii) * kTStride + jq);
+      const v4i wn = *(const v4i *)(sT + TP + (t * 64 + ii) * kTStride + jq);
+      *(v4i *)(pt + kb_off(i0 + ii, j0 + jq, rpad)) = wr;
+      *(v4i *)(pt + kb_off(i0 + ii, cpad + j0 + jq, rpad)) = wn;
+    }
+  }
+}
+
+void launch_split_c(const double *M, int ld, int rows, int cols, const int *e, int k,
+                    int8_t *planes, int8_t *planes2, size_t pstride, int rpad, int cpad,
+                    double *trunc, int ldt, int8_t *planesT, size_t pstrideT, int kT,
+                    hipStream_t s, const int *colmap) {
+  dim3 grid(rpad / 64, cpad / 64);
+  if (planesT && kT > 0)
+    hipLaunchKernelGGL(k_split_c<true>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
+                       planes2, pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT, colmap);
+  else
+    hipLaunchKernelGGL(k_split_c<false>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
+                       planes2, pstride, rpad, cpad, trunc, ldt, (int8_t *)nullptr, (size_t)0, 0,
+                       colmap);
+}
+
+// Realified digit planes of one complex operand row j (an output column of a column
+// epilogue) with exponent ee: planes gets (re; im), planes2 (im; -re), the realified
+// column of -i v. Plane stride 2 npad^2; rows i >= n hold zero digits.
+template <int EPT>
+__device__ __forceinline__ void write_col_planes_c(const double (&re)[EPT], const double (&im)[EPT],
+                                                   int ee, int j, int n, int npad,
+                                                   int8_t *__restrict__ planes,
+                                                   int8_t *__restrict__ planes2, int k) {
+  const size_t P2 = 2 * (size_t)npad * npad;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = threadIdx.x + kEpiThreads * q;
+    if (i < npad) {
+      const double ar = (i < n) ? re[q] : 0.0, ai = (i < n) ? im[q] : 0.0;
+      double yr = ldexp(fabs(ar), -ee), yi = ldexp(fabs(ai), -ee);
+      const int sr = (ar < 0.0) ? -1 : 1, si = (ai < 0.0) ? -1 : 1;
+      const size_t o1 = kb_off(j, i, npad), o2 = kb_off(j, npad + i, npad);
+      for (int t = 0; t < k; ++t) {
+        double t128 = yr * 128.0;
+        double d = floor(t128);
+        yr = t128 - d;
+        const int dr = sr * (int)d;
+        t128 = yi * 128.0;
+        d = floor(t128);
+        yi = t128 - d;
+        const int di = si * (int)d;
+        planes[t * P2 + o1] = (int8_t)dr;
+        planes[t * P2 + o2] = (int8_t)di;
+        planes2[t * P2 + o1] = (int8_t)di;
+        planes2[t * P2 + o2] = (int8_t)(-dr);
+      }
+    }
+  }
+}
+
+// V epilogue and column pass, complex: V = Vr + i Vi from the slots of the two products,
+// r_j = 1 - x_j^H x_j, lambda_j = Re(x_j^H v_j) / (1 - r_j) (double-word), the residual
+// V - x_j lambda_j of both parts (pair arithmetic), its exponent and maximum over both
+// parts, and the realified planes of Res (Rpl) and of -i Res (Rpl2).
+template <int EPT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_v_c(
+    const int32_t *__restrict__ Cr, const int32_t *__restrict__ Ci, int npad, int d_min,
+    int ndiag_all, const int *__restrict__ dcut, const int *__restrict__ eA,
+    const int *__restrict__ eX, const double *__restrict__ X1, int n, double *lam,
+    double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
+    int8_t *__restrict__ Rpl2, int kr, int *flags) {
+  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const size_t P = (size_t)npad * npad;
+  double rr[EPT], ri[EPT];
+  if (j >= n) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) rr[q] = ri[q] = 0.0;
+    write_col_planes_c<EPT>(rr, ri, 0, j, 0, npad, Rpl, Rpl2, kr);
+    return;
+  }
+  const int ej = eX[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
+  const size_t coff = (size_t)j * npad;
+  const double2 *xcol = (const double2 *)X1 + (size_t)j * n;
+  double vrh[EPT], vrl[EPT], vih[EPT], vil[EPT];
+  int eiq[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    vrh[q] = vrl[q] = vih[q] = vil[q] = 0.0;
+    eiq[q] = (i < n) ? eA[i] + ej : 0;
+  }
+#pragma unroll 1
+  for (int qq = ndiag - 1; qq >= 0; --qq) {
+    const int32_t *Cqr = Cr + coff + (size_t)qq * P, *Cqi = Ci + coff + (size_t)qq * P;
+    int32_t cr[EPT], ci[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int i = tid + kEpiThreads * q;
+      cr[q] = (i < n) ? Cqr[i] : 0;
+      ci[q] = (i < n) ? Cqi[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int sc = eiq[q] - 7 * (d_min + qq);
+      double s_, e_;
+      two_sum(vrh[q], ldexp((double)cr[q], sc), s_, e_);
+      vrh[q] = s_;
+      vrl[q] += e_;
+      two_sum(vih[q], ldexp((double)ci[q], sc), s_, e_);
+      vih[q] = s_;
+      vil[q] += e_;
+    }
+  }
+  ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    if (i < n) {
+      fast_two_sum(vrh[q], vrl[q], vrh[q], vrl[q]);
+      fast_two_sum(vih[q], vil[q], vih[q], vil[q]);
+      const double2 x = xcol[i];
+      double p, pe;
+      two_prod(x.x, x.x, p, pe);
+      sx = dd_add_prod(sx, p, pe);
+      two_prod(x.y, x.y, p, pe);
+      sx = dd_add_prod(sx, p, pe);
+      two_prod(x.x, vrh[q], p, pe);
+      sv = dd_add_prod(sv, p, pe + x.x * vrl[q]);
+      two_prod(x.y, vih[q], p, pe);
+      sv = dd_add_prod(sv, p, pe + x.y * vil[q]);
+    }
+  }
+  sx = block_dd_sum<kEpiThreads>(sx, scratch);
+  sv = block_dd_sum<kEpiThreads>(sv, scratch);
+  ddv rj = dd_add(ddv{1.0, 0.0}, ddv{-sx.h, -sx.l});
+  ddv den = dd_add(ddv{1.0, 0.0}, ddv{-rj.h, -rj.l});
+  const ddv ljd = dd_div_to_dd(sv, den);
+  const double lj = ljd.h;
+  double rmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    rr[q] = ri[q] = 0.0;
+    if (i < n) {
+      const double2 x = xcol[i];
+      double p, pe, s_, e_;
+      two_prod(x.x, lj, p, pe);
+      two_sum(vrh[q], -p, s_, e_);
+      rr[q] = s_ + (((e_ + vrl[q]) - pe) - x.x * ljd.l);
+      two_prod(x.y, lj, p, pe);
+      two_sum(vih[q], -p, s_, e_);
+      ri[q] = s_ + (((e_ + vil[q]) - pe) - x.y * ljd.l);
+      rmax = fmax(rmax, fmax(fabs(rr[q]), fabs(ri[q])));
+    }
+  }
+  rmax = block_max<kEpiThreads>(rmax, scratch);
+  const int er = exp_above(rmax);
+  write_col_planes_c<EPT>(rr, ri, er, j, n, npad, Rpl, Rpl2, kr);
+  if (tid == 0) {
+    lam[j] = lj;
+    lam_lo[j] = ljd.l;
+    r[j] = rj.h;
+    eR[j] = er;
+    resmax[j] = rmax;
+    if (!(fabs(lj) <= DBL_MAX)) atomicOr(flags, FLAG_NONFINITE);
+  }
+}
+
+void launch_epi_v_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eA, const int *eX, const double *X1, int n,
+                    double *lam, double *lam_lo, double *r, int *eR, double *resmax,
+                    int8_t *Rpl, int8_t *Rpl2, int kr, int *flags, hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+#define EPI_V_C(E)                                                                          \
+  hipLaunchKernelGGL(k_epi_v_c<E>, dim3(npad), dim3(kEpiThreads), 0, s, Cr, Ci, npad, d_min,  \
+                     ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, Rpl2, kr,   \
+                     flags)
+  if (ept <= 1) EPI_V_C(1);
+  else if (ept <= 2) EPI_V_C(2);
+  else EPI_V_C(4);
+#undef EPI_V_C
+}
+
+// W epilogue, complex: W = Wr + i Wi, e_ij = w_ij / (lambda_j - lambda_i) (both parts, the
+// difference of the double-word eigenvalues), e_jj = r_j / 2, E'_ij = 2^eX_i e_ij; emax_j =
+// max_i |e_ij| (modulus), eE_j the exponent of the larger part of column j of E', and the
+// realified planes of E' (Epl) and of -i E' (Epl2).
+template <int EPT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_w_c(
+    const int32_t *__restrict__ Cr, const int32_t *__restrict__ Ci, int npad, int d_min,
+    int ndiag_all, const int *__restrict__ dcut, const int *__restrict__ eX,
+    const int *__restrict__ eR, const double *__restrict__ lam,
+    const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
+    double *emax, int8_t *__restrict__ Epl, int8_t *__restrict__ Epl2, int ke, int *flags) {
+  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const size_t P = (size_t)npad * npad;
+  double er_[EPT], ei_[EPT];
+  if (j >= n) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) er_[q] = ei_[q] = 0.0;
+    write_col_planes_c<EPT>(er_, ei_, 0, j, 0, npad, Epl, Epl2, ke);
+    return;
+  }
+  const int ej = eR[j];
+  const double lj = lam[j], ljl = lam_lo[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
+  const size_t coff = (size_t)j * npad;
+  double wr[EPT], wi[EPT];
+  int eiq[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    wr[q] = wi[q] = 0.0;
+    eiq[q] = (i < n) ? eX[i] + ej : 0;
+  }
+#pragma unroll 1
+  for (int qq = ndiag - 1; qq >= 0; --qq) {
+    const int32_t *Cqr = Cr + coff + (size_t)qq * P, *Cqi = Ci + coff + (size_t)qq * P;
+    int32_t cr[EPT], ci[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int i = tid + kEpiThreads * q;
+      cr[q] = (i < n) ? Cqr[i] : 0;
+      ci[q] = (i < n) ? Cqi[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int sc = eiq[q] - 7 * (d_min + qq);
+      wr[q] += ldexp((double)cr[q], sc);
+      wi[q] += ldexp((double)ci[q], sc);
+    }
+  }
+  double ms = 0.0, mr = 0.0;
+  int tie = 0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    er_[q] = ei_[q] = 0.0;
+    if (i < n) {
+      double a, b;
+      if (i == j) {
+        a = 0.5 * r[j];
+        b = 0.0;
+      } else {
+        const double den = dd_diff(lj, ljl, lam[i], lam_lo[i]);
+        if (den == 0.0) {
+          tie = 1;
+          a = b = 0.0;
+        } else {
+          a = wr[q] / den;
+          b = wi[q] / den;
+        }
+      }
+      mr = fmax(mr, sqrt(a * a + b * b));
+      er_[q] = ldexp(a, eX[i]);
+      ei_[q] = ldexp(b, eX[i]);
+      ms = fmax(ms, fmax(fabs(er_[q]), fabs(ei_[q])));
+    }
+  }
+  if (tie) atomicOr(flags, FLAG_TIE);
+  ms = block_max<kEpiThreads>(ms, scratch);
+  mr = block_max<kEpiThreads>(mr, scratch);
+  const int ee = exp_above(ms);
+  write_col_planes_c<EPT>(er_, ei_, ee, j, n, npad, Epl, Epl2, ke);
+  if (tid == 0) {
+    eE[j] = ee;
+    emax[j] = mr;
+    if (!(mr <= DBL_MAX)) atomicOr(flags, FLAG_NONFINITE);
+  }
+}
+
+void launch_epi_w_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eX, const int *eR, const double *lam,
+                    const double *lam_lo, const double *r, int n, int *eE, double *emax,
+                    int8_t *Epl, int8_t *Epl2, int ke, int *flags, hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+#define EPI_W_C(E)                                                                          \
+  hipLaunchKernelGGL(k_epi_w_c<E>, dim3(npad), dim3(kEpiThreads), 0, s, Cr, Ci, npad, d_min,  \
+                     ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, Epl2, ke, flags)
+  if (ept <= 1) EPI_W_C(1);
+  else if (ept <= 2) EPI_W_C(2);
+  else EPI_W_C(4);
+#undef EPI_W_C
+}
+
+// Update, complex: X_ij = X1_ij + U_ij for both parts, U from the slots of the two products
+// scaled by 2^(eE_j - 7d); column j goes to column colmap[j] of X (colmap may be null).
+__global__ __launch_bounds__(256) void k_epi_u_c(const int32_t *__restrict__ Cr,
+                                                 const int32_t *__restrict__ Ci, int npad,
+                                                 int d_min, int ndiag_all,
+                                                 const int *__restrict__ dcut,
+                                                 const int *__restrict__ eE,
+                                                 const double *__restrict__ X1, int n,
+                                                 double *__restrict__ X, int ldx,
+                                                 const int *__restrict__ colmap) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i >= n) return;
+  const size_t P = (size_t)npad * npad;
+  const size_t coff = (size_t)j * npad + i;
+  const int ej = eE[j];
+  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
+  double ur = 0.0, ui = 0.0;
+  for (int qq = ndiag - 1; qq >= 0; --qq) {
+    const int sc = ej - 7 * (d_min + qq);
+    ur += ldexp((double)Cr[coff + (size_t)qq * P], sc);
+    ui += ldexp((double)Ci[coff + (size_t)qq * P], sc);
+  }
+  const double2 x1 = ((const double2 *)X1)[(size_t)j * n + i];
+  double2 out;
+  out.x = x1.x + ur;
+  out.y = x1.y + ui;
+  ((double2 *)X)[(size_t)(colmap ? colmap[j] : j) * ldx + i] = out;
+}
+
+void launch_epi_u_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, int ndiag,
+                    const int *dcut, const int *eE, const double *X1, int n, double *X, int ldx,
+                    hipStream_t s, const int *colmap) {
+  hipLaunchKernelGGL(k_epi_u_c, dim3((n + 255) / 256, n), dim3(256), 0, s, Cr, Ci, npad, d_min,
+                     ndiag, dcut, eE, X1, n, X, ldx, colmap);
 }
 
 }  // namespace refeig

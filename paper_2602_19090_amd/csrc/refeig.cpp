@@ -165,6 +165,62 @@ size_t carve_plain(int n, char *base, PlainWork *w) {
   return off;
 }
 
+// ---- complex Hermitian case: workspace. Digit planes are realified (K = 2 npad, plane
+// stride 2 npad^2); each complex product keeps the slots of its real and imaginary parts.
+constexpr int kMaxNHerm = 4096;   // the complex column epilogues hold 4 values per thread
+struct HermWork {
+  int npad = 0;
+  size_t P = 0;
+  int8_t *AP1, *AP2, *XP, *XT, *RP1, *RP2, *EP1, *EP2;
+  int32_t *Cr, *Ci;
+  double *X1;
+  int *eA, *cA, *eX, *cX, *eR, *eE, *flags, *colmap;
+  int *dcut[3];
+  double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
+};
+size_t carve_herm(int n, int ka, char *base, HermWork *w) {
+  HermWork t;
+  t.npad = round_up(n, kTile);
+  t.P = (size_t)t.npad * t.npad;
+  const size_t P2 = 2 * t.P;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  t.AP1 = (int8_t *)take(P2 * ka);
+  t.AP2 = (int8_t *)take(P2 * ka);
+  t.XP = (int8_t *)take(P2 * kKxMax);
+  t.XT = (int8_t *)take(P2 * kKxMax);
+  t.RP1 = (int8_t *)take(P2 * kKrMax);
+  t.RP2 = (int8_t *)take(P2 * kKrMax);
+  t.EP1 = (int8_t *)take(P2 * kKeMax);
+  t.EP2 = (int8_t *)take(P2 * kKeMax);
+  t.Cr = (int32_t *)take(t.P * 4 * (size_t)nslots(ka));
+  t.Ci = (int32_t *)take(t.P * 4 * (size_t)nslots(ka));
+  t.X1 = (double *)take(sizeof(double) * 2 * (size_t)n * n);
+  const size_t vi = sizeof(int) * t.npad, vd = sizeof(double) * t.npad;
+  t.eA = (int *)take(vi);
+  t.cA = (int *)take(vi);
+  t.eX = (int *)take(vi);
+  t.cX = (int *)take(vi);
+  t.eR = (int *)take(vi);
+  t.eE = (int *)take(vi);
+  t.flags = (int *)take(256);
+  t.colmap = (int *)take(vi);
+  for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
+  t.mxA = (double *)take(vd);
+  t.mxX = (double *)take(vd);
+  t.lam = (double *)take(vd);
+  t.lam_lo = (double *)take(vd);
+  t.r = (double *)take(vd);
+  t.resmax = (double *)take(vd);
+  t.emax = (double *)take(vd);
+  if (w) *w = t;
+  return off;
+}
+
 int ka_of(const refeig_opts *o) {
   int ka = (o && o->ka_max > 0) ? o->ka_max : kKaMaxLimit;
   return std::min(ka, kKaMaxLimit);
@@ -215,12 +271,12 @@ bool plan_cutoffs(const std::vector<int> &dcol, int n, int npad, int kl, int kr,
 // One launch per group; ev_start is taken by the first dispatch, ev_stop by the last.
 void launch_plan(const CutPlan &plan, const int8_t *Lp, const int8_t *Rp, size_t P, int npad,
                  int kl, int kr, int32_t *C, hipStream_t s, hipEvent_t ev_start,
-                 hipEvent_t ev_stop) {
+                 hipEvent_t ev_stop, int kdim = 0) {
   const size_t ng = plan.groups.size();
   for (size_t q = 0; q < ng; ++q)
     launch_slice_gemm(Lp, Rp, P, npad, kl, kr, 2, plan.groups[q].first - 1, C,
                       &plan.groups[q].second, s, q == 0 ? ev_start : nullptr,
-                      q + 1 == ng ? ev_stop : nullptr);
+                      q + 1 == ng ? ev_stop : nullptr, kdim);
 }
 
 // ---------------------------------------------------------------- grouped correction (host)
@@ -733,6 +789,246 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
 #undef BSTEP
 }
 
+// ---------------------------------------------------------------- complex Hermitian case
+// Algorithm 1 with the X^(1) cut for A = A^H (the extension Sec. 5 names as future work):
+// the same iteration as the real INT8 loop, with complex operands realified so that every
+// complex product is two real slice GEMMs of reduction length 2 npad:
+//   V = A X^(1):   Re V = (Re a_i ; Im a_i) . (Re x_j ; Im x_j),
+//                  Im V = (-Im a_i ; Re a_i) . (Re x_j ; Im x_j)      (a_i: column i of A)
+//   W = X^(1)H R:  Re W = (Re x_i ; Im x_i) . (Re r_j ; Im r_j),
+//                  Im W = (Re x_i ; Im x_i) . (Im r_j ; -Re r_j)
+//   U = X^(1) E':  Re U = (Re X_i. ; -Im X_i.) . (Re e'_j ; Im e'_j),
+//                  Im U = (Re X_i. ; -Im X_i.) . (Im e'_j ; -Re e'_j)
+// Options beyond the paper's method (grouping, schedule, sparse rule, FP64 form) are not
+// offered here.
+int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, double target,
+                const refeig_opts &o, void *work, size_t work_bytes, hipStream_t s,
+                refeig_report *rep) {
+  const int ka_max = ka_of(&o);
+  const size_t need = carve_herm(n, ka_max, nullptr, nullptr);
+  bool own = false;
+  if (!work) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMalloc(&work, need));
+    own = true;
+  } else if (work_bytes < need) {
+    return REFEIG_E_NOMEM;
+  }
+  HermWork w;
+  carve_herm(n, ka_max, (char *)work, &w);
+  const int npad = w.npad;
+  const size_t P = w.P, P2 = 2 * w.P;
+  const int K2 = 2 * npad;
+  const double delta = target / o.delta_safety;
+  const double xi = xi_of(o, n);
+  const double theta = o.theta;
+  const double lsq2n = 0.5 * std::log2(2.0 * n);   // statistical growth over 2n real terms
+  auto t_start = std::chrono::steady_clock::now();
+
+  int status = REFEIG_OK;
+  std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad);
+  std::vector<double> mxX(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps, gaps_nat;
+  std::vector<int> cmap(n), dhost;
+  int hflags = 0;
+  hipEvent_t ev[8];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  auto cleanup = [&](int st) {
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(work);
+    }
+    if (rep) {
+      rep->status = st;
+      rep->ms_total =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+              .count();
+    }
+    return st;
+  };
+#define STEP(x)                                   \
+  do {                                            \
+    hipError_t err__ = (x);                       \
+    if (err__ != hipSuccess) {                    \
+      fprintf(stderr, "refeig: %s failed: %s\n", #x, hipGetErrorString(err__)); \
+      return cleanup(REFEIG_E_HIP);               \
+    }                                             \
+  } while (0)
+
+  STEP(hipMemcpyAsync(lam_prev.data(), D, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  STEP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  // A: column exponents over both parts (column i realified = operand row i) and the planes
+  // of (Re a_i ; Im a_i) and (-Im a_i ; Re a_i), once
+  launch_colstats_c(A, lda, n, n, npad, w.eA, w.cA, w.mxA, w.flags, s);
+  STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  STEP(hipMemcpyAsync(eA.data(), w.eA, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+  STEP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(lam_prev[i])) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+  if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
+  int eA_max = -100000;
+  for (int i = 0; i < n; ++i) eA_max = std::max(eA_max, eA[i]);
+  launch_split_c(A, lda, n, n, w.eA, ka_max, w.AP1, w.AP2, P2, npad, npad, nullptr, 0, nullptr,
+                 0, 0, s);
+  STEP(hipGetLastError());
+
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  double eps_prev = INFINITY;
+  for (int it = 0; it < iters; ++it) {
+    STEP(hipEventRecord(ev[0], s));
+    double gmin, lmax;
+    column_gaps(lam_prev, gaps_nat, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    working_order(lam_prev, gaps_nat, cmap);
+    STEP(hipMemcpyAsync(w.colmap, cmap.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    launch_colstats_c(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap);
+    STEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    if (hflags & FLAG_RANGE) return cleanup(REFEIG_E_RANGE);
+    gaps.resize(n);
+    for (int p = 0; p < n; ++p) gaps[p] = gaps_nat[cmap[p]];
+    int beta, kx;
+    beta_rule(n, xi, delta, gmin, lmax, eX, cX, mxX, &beta, &kx);
+    if (o.kx_force > 0) kx = o.kx_force;
+    // X^(1): column planes (Re x_j ; Im x_j) and row planes (Re X_i. ; -Im X_i.)
+    launch_split_c(X, ldx, n, n, w.eX, kx, w.XP, nullptr, P2, npad, npad, w.X1, n, w.XT, P2, kx,
+                   s, w.colmap);
+    // ---- V = A X^(1)
+    int eXmax = -100000;
+    for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
+    std::vector<int> dcol(npad, 2);
+    {
+      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lsq2n;
+      for (int j = 0; j < n; ++j) {
+        if (mxX[j] == 0.0) continue;
+        double nd = (c0 + eX[j] - std::log2(theta * delta * gaps[j])) / 7.0;
+        dcol[j] = std::max(2, (int)std::ceil(nd) + o.d_extra);
+      }
+    }
+    CutPlan plan;
+    if (!plan_cutoffs(dcol, n, npad, kx, ka_max, std::min(ka_max + 1, kx + ka_max), w.dcut[0],
+                      dhost, s, plan))
+      return cleanup(REFEIG_E_HIP);
+    const int dv = plan.dmax;
+    const double pv = plan.pairs_eff;
+    launch_plan(plan, w.XP, w.AP1, P2, npad, kx, ka_max, w.Cr, s, ev[1], nullptr, K2);
+    launch_plan(plan, w.XP, w.AP2, P2, npad, kx, ka_max, w.Ci, s, nullptr, ev[2], K2);
+    launch_epi_v_c(w.Cr, w.Ci, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo,
+                   w.r, w.eR, w.resmax, w.RP1, w.RP2, kKrMax, w.flags, s);
+    STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    // ---- W = X^(1)H Res -> E~
+    column_gaps(lam, gaps, &gmin, &lmax);
+    if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
+    {
+      const double c0 = eXmax + 7 + std::log2(1.5 * kx) + lsq2n;
+      std::fill(dcol.begin(), dcol.end(), 2);
+      for (int j = 0; j < n; ++j) {
+        if (resmax[j] == 0.0) continue;
+        double nd = (c0 + eR[j] - std::log2(theta * delta * gaps[j])) / 7.0;
+        dcol[j] = std::max(2, (int)std::ceil(nd) + o.d_extra);
+      }
+    }
+    if (!plan_cutoffs(dcol, n, npad, kKrMax, kx, std::min(kKrMax + 1, kKrMax + kx), w.dcut[1],
+                      dhost, s, plan))
+      return cleanup(REFEIG_E_HIP);
+    const int dw = plan.dmax;
+    const double pw = plan.pairs_eff;
+    launch_plan(plan, w.RP1, w.XP, P2, npad, kKrMax, kx, w.Cr, s, ev[3], nullptr, K2);
+    launch_plan(plan, w.RP2, w.XP, P2, npad, kKrMax, kx, w.Ci, s, nullptr, ev[4], K2);
+    launch_epi_w_c(w.Cr, w.Ci, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n,
+                   w.eE, w.emax, w.EP1, w.EP2, kKeMax, w.flags, s);
+    STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    STEP(hipStreamSynchronize(s));
+    if (hflags & FLAG_TIE) return cleanup(REFEIG_E_GAP);
+    if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
+    double eps = 0.0;
+    for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
+    // ---- X <- X^(1) + X^(1) E~
+    {
+      const double c0 = 7 + std::log2(1.008 * kx) + lsq2n - std::log2(theta * delta);
+      std::fill(dcol.begin(), dcol.end(), 2);
+      for (int j = 0; j < n; ++j) {
+        if (emax[j] == 0.0) continue;
+        dcol[j] = std::max(2, (int)std::ceil((c0 + eE[j]) / 7.0) + o.d_extra);
+      }
+    }
+    if (!plan_cutoffs(dcol, n, npad, kKeMax, kx, std::min(kKeMax + 1, kKeMax + kx), w.dcut[2],
+                      dhost, s, plan))
+      return cleanup(REFEIG_E_HIP);
+    const int du = plan.dmax;
+    const double pu = plan.pairs_eff;
+    launch_plan(plan, w.EP1, w.XT, P2, npad, kKeMax, kx, w.Cr, s, ev[5], nullptr, K2);
+    launch_plan(plan, w.EP2, w.XT, P2, npad, kKeMax, kx, w.Ci, s, nullptr, ev[6], K2);
+    launch_epi_u_c(w.Cr, w.Ci, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s, w.colmap);
+    launch_scatter(w.lam, w.colmap, n, D, s);
+    STEP(hipEventRecord(ev[7], s));
+    STEP(hipGetLastError());
+    STEP(hipEventSynchronize(ev[7]));
+    float t_it = 0, g1 = 0, g2 = 0, g3 = 0;
+    (void)hipEventElapsedTime(&t_it, ev[0], ev[7]);
+    (void)hipEventElapsedTime(&g1, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&g2, ev[3], ev[4]);
+    (void)hipEventElapsedTime(&g3, ev[5], ev[6]);
+    if (rep && it < REFEIG_MAX_ITERS) {
+      // pair counts per real slice GEMM of reduction 2n; each product runs two of them
+      rep->beta[it] = beta;
+      rep->kx[it] = kx;
+      rep->dv[it] = dv;
+      rep->dw[it] = dw;
+      rep->du[it] = du;
+      rep->pairs[it] = (int)std::lround(2 * (pv + pw + pu));
+      rep->eps[it] = eps;
+      rep->ms_iter[it] = t_it;
+      rep->ms_gemm[it] = g1 + g2 + g3;
+      rep->pairs_f[it][0] = 2 * pv;
+      rep->pairs_f[it][1] = 2 * pw;
+      rep->pairs_f[it][2] = 2 * pu;
+      rep->pairs_p[it][0] = (int)std::lround(2 * pv);
+      rep->pairs_p[it][1] = (int)std::lround(2 * pw);
+      rep->pairs_p[it][2] = (int)std::lround(2 * pu);
+      rep->ms_p[it][0] = g1;
+      rep->ms_p[it][1] = g2;
+      rep->ms_p[it][2] = g3;
+      rep->delta_it[it] = delta;
+      rep->iters = it + 1;
+      rep->min_gap = gmin;
+      rep->max_abs_lambda = lmax;
+    }
+    if (o.verbose)
+      fprintf(stderr,
+              "refeig herm it %d: beta %d kx %d dv %d dw %d du %d eps %.3e gap %.3e ms %.2f "
+              "(gemm %.2f)\n",
+              it + 1, beta, kx, dv, dw, du, eps, gmin, t_it, g1 + g2 + g3);
+    for (int p = 0; p < n; ++p) lam_prev[cmap[p]] = lam[p];
+    if (o.fixed_iters > 0) {
+      eps_prev = eps;
+      continue;
+    }
+    const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
+    if (eps <= delta || eps * eps * lmax / (xi_stop * gmin) <= delta) break;
+    if (it >= 1 && eps > 0.5 * eps_prev) {
+      status = REFEIG_NOT_CONVERGED;
+      break;
+    }
+    eps_prev = eps;
+    if (it + 1 == iters) status = REFEIG_NOT_CONVERGED;
+  }
+  return cleanup(status);
+#undef STEP
+}
+
 }  // namespace
 
 extern "C" {
@@ -758,6 +1054,29 @@ int refeig_workspace_bytes(int n, const refeig_opts *o, size_t *bytes) {
   *bytes = (o && o->mode == REFEIG_FP64_PLAIN) ? carve_plain(n, nullptr, nullptr)
                                                : carve(n, ka_of(o), nullptr, nullptr);
   return REFEIG_OK;
+}
+
+int refeig_herm_workspace_bytes(int n, const refeig_opts *o, size_t *bytes) {
+  if (n < 1 || n > kMaxNHerm || !bytes) return REFEIG_E_ARG;
+  *bytes = carve_herm(n, ka_of(o), nullptr, nullptr);
+  return REFEIG_OK;
+}
+
+int refine_eigvecs_herm(const double *A, int lda, double *X, int ldx, double *D, int n,
+                        double target, const refeig_opts *opts, void *work, size_t work_bytes,
+                        refeig_stream_t stream, refeig_report *rep) {
+  refeig_opts o;
+  if (opts) o = *opts;
+  else refeig_default_opts(&o);
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  if (!A || !X || !D || n < 1 || n > kMaxNHerm || lda < n || ldx < n || !(target > 0.0) ||
+      !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
+      o.kx_force < 0 || o.kx_force > kKxMax || o.max_iter > REFEIG_MAX_ITERS ||
+      o.fixed_iters > REFEIG_MAX_ITERS || o.mode != REFEIG_OZAKI_INT8 || o.group_tau != 0.0 ||
+      o.schedule != 0 || o.sparse_k != 0)
+    return REFEIG_E_ARG;
+  return refine_herm(A, lda, X, ldx, D, n, target, o, work, work_bytes, (hipStream_t)stream,
+                     rep);
 }
 
 const char *refeig_strerror(int s) {

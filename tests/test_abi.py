@@ -30,7 +30,8 @@ def lib():
 def test_header_declares_expected_functions():
     names = _declared()
     for f in ("refine_eigvecs", "refeig_workspace_bytes", "refeig_default_opts", "refeig_strerror",
-              "refeig_split_cols", "refeig_slice_gemm"):
+              "refeig_split_cols", "refeig_slice_gemm", "refine_eigvecs_herm",
+              "refeig_herm_workspace_bytes"):
         assert f in names, names
 
 
@@ -49,6 +50,10 @@ def test_host_only_entry_points(lib):
     assert 8e9 < b < 16e9
     with pytest.raises(ValueError):
         rb.workspace_bytes(0)
+    hb = rb.herm_workspace_bytes(4096)
+    assert 4e9 < hb < 12e9
+    with pytest.raises(ValueError):
+        rb.herm_workspace_bytes(4097)
 
 
 def _c_layout(struct, fields):
