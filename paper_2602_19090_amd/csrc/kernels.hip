@@ -687,16 +687,23 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     vh[q] = vl[q] = 0.0;
     eiq[q] = (i < n) ? eA[i] + ej : 0;
   }
-  // slice sum, smallest scale first; diagonals outermost so each thread keeps EPT
-  // independent loads in flight
+  // slice sum, smallest scale first; diagonals outermost, and the next diagonal's values
+  // are loaded while this one is summed, so each thread keeps 2 EPT loads in flight
+  int32_t cv[EPT], cn[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
+  }
 #pragma unroll 1
   for (int qq = ndiag - 1; qq >= 0; --qq) {
-    const int32_t *Cq = Ccol + (size_t)qq * P;
-    int32_t cv[EPT];
+    if (qq > 0) {
+      const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + kEpiThreads * q;
-      cv[q] = (i < n) ? Cq[i] : 0;
+      for (int q = 0; q < EPT; ++q) {
+        const int i = tid + kEpiThreads * q;
+        cn[q] = (i < n) ? Cn[i] : 0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -706,6 +713,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
       vh[q] = s;
       vl[q] += e;
     }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
   }
   ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
 #pragma unroll
@@ -819,17 +828,27 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     wq[q] = 0.0;
     eiq[q] = (i < n) ? eX[i] + ej : 0;
   }
+  // as in the V epilogue: the next diagonal is loaded while this one is summed
+  int32_t cv[EPT], cn[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
+  }
 #pragma unroll 1
   for (int qq = ndiag - 1; qq >= 0; --qq) {
-    const int32_t *Cq = Ccol + (size_t)qq * P;
-    int32_t cv[EPT];
+    if (qq > 0) {
+      const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + kEpiThreads * q;
-      cv[q] = (i < n) ? Cq[i] : 0;
+      for (int q = 0; q < EPT; ++q) {
+        const int i = tid + kEpiThreads * q;
+        cn[q] = (i < n) ? Cn[i] : 0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
   }
   double ms = 0.0, mr = 0.0;
   int tie = 0;
