@@ -90,7 +90,17 @@ typedef struct {
                             growth of the products of A's planes is taken as min(k, sqrt n)
                             instead of sqrt n when the V product's diagonals are chosen.
                             0: the dense rule.                                          */
-    int reserved_i[3];
+    int vmode;           /* how V = A X^(1) is formed. 1 (default): by residues, a product
+                            algorithm other than the paper's slices: A cut to the digits
+                            the V cutoff asks for (one count for all columns) and X^(1)
+                            are integers, their product is formed exactly modulo N
+                            pairwise coprime odd moduli <= 255 (one INT8 GEMM each, N
+                            about 23 at n = 8192, target 1e-14; at most 28) and rebuilt
+                            by the Chinese remainder theorem; W and X^(1) E~ keep the
+                            slice products. 0: the slice products of Sec. 2.3 for V too
+                            (pair diagonals kept per column block). The Hermitian path
+                            always uses slices.                                          */
+    int reserved_i[2];
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
                             every pair of columns whose first-order correction |e_ij|,
@@ -162,7 +172,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
  * The forward error is measured in the modulus, up to a unit complex factor
  * per column. 1 <= n <= 4096. Options as refine_eigvecs, except that
  * group_tau, schedule and sparse_k must be 0 and mode REFEIG_OZAKI_INT8
- * (REFEIG_E_ARG otherwise). Workspace: refeig_herm_workspace_bytes, or NULL
+ * (REFEIG_E_ARG otherwise); vmode is not used (slice products). Workspace:
+ * refeig_herm_workspace_bytes, or NULL
  * (the library allocates and frees it). Statuses and report as
  * refine_eigvecs; pairs_f counts the slice products of both real GEMMs of a
  * complex product, in units of one real n x n x 2n product. */

@@ -43,7 +43,7 @@ class Opts(ctypes.Structure):
                 ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
                 ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("kx_force", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("sparse_k", ctypes.c_int), ("reserved_i", ctypes.c_int * 3),
+                ("sparse_k", ctypes.c_int), ("vmode", ctypes.c_int), ("reserved_i", ctypes.c_int * 2),
                 ("group_tau", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 3)]
 

@@ -52,10 +52,12 @@ struct RowBlocks {
 // ev_start / ev_stop (may be null) take the dispatch's own start / end times.
 // kdim: reduction length (a multiple of 128; 0 means npad). The complex products use
 // kdim = 2 npad: the imaginary parts are stacked after the real parts along K.
+// same_plane: slot q holds the single product of plane q + 1 of L with plane q + 1 of R
+// (the residue products, one modulus per slot) instead of diagonal d_min + q.
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
                        hipStream_t s, hipEvent_t ev_start = nullptr,
-                       hipEvent_t ev_stop = nullptr, int kdim = 0);
+                       hipEvent_t ev_stop = nullptr, int kdim = 0, bool same_plane = false);
 // L rows per block tile of launch_slice_gemm for this npad.
 int gemm_tile_rows(int npad);
 
@@ -65,6 +67,41 @@ int gemm_tile_rows(int npad);
 //   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots; lam gets
 //   the FP64 value, lam_lo its low word), Res_ij = V_ij - x_ij lambda_j (pair arithmetic),
 //   eR_j, resmax_j, and kr digit planes of Res (layout j*npad + i).
+// ---- V by residues (an alternative to the slice products of V, see CrtRec): the integer
+// product P = Ã X̃ of A's first ka digits and X^(1)'s kx digits is formed modulo N pairwise
+// coprime odd moduli m_q <= 255 by N INT8 GEMMs of residue planes and reconstructed by the
+// Chinese remainder theorem.
+constexpr int kCrtMax = 28;   // moduli at most (over 200 bits of product)
+constexpr int kCrtPlanes = 18;
+struct ResWeights {
+  int N, k;
+  int m[kCrtMax];
+  float rmf[kCrtMax];           // fl32(1 / m_q): a rmf_q rounds to the nearest integer of
+                                // a / m_q for |a| < 2^24 (a / m_q is never within 1 / (2 m_q)
+                                // of a half-integer for odd m_q)
+  int w[kCrtMax][kCrtPlanes];   // 128^(k-1-t) mod m_q in the symmetric range
+};
+// res plane q (stride pstride) = symmetric residue mod m_q of the integer sum_t d_t 128^(k-1-t)
+// that the k digit planes encode at the same offset; count bytes per plane (a multiple of 4).
+void launch_residues(const int8_t *planes, size_t pstride, size_t count, const ResWeights &w,
+                     int8_t *res, hipStream_t s);
+struct CrtRec {
+  int N;
+  int sh;                         // V = P 2^(eA_i + eX_j + sh)
+  int m[kCrtMax];
+  double rm[kCrtMax];             // fl(1 / m_q): c rm_q rounds to the nearest integer of
+                                  // c / m_q for |c| < 2^27 (never within 1 / (2 m_q) of a
+                                  // half-integer for odd m_q)
+  double u[kCrtMax][3];           // y_q / m_q in triple-double, y_q = (M / m_q)^-1 mod m_q
+  double M[3];                    // M = prod m_q in triple-double
+};
+// V epilogue as launch_epi_v, with V rebuilt from the residue products C_q (slot q) instead
+// of summed from slice diagonals.
+void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec &rec, const int *eA,
+                      const int *eX, const double *X1, int n, double *lam, double *lam_lo,
+                      double *r, int *eR, double *resmax, int8_t *Rpl, int kr, int *flags,
+                      hipStream_t s);
+
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eA, const int *eX, const double *X1, int n, double *lam,
                   double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rplanes, int kr,

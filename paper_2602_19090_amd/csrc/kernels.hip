@@ -314,7 +314,8 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
                                                        const int8_t *__restrict__ Rp,
                                                        size_t pstride, int npad, int kdim,
                                                        int kl, int kr, int d_min, DiagOrder order,
-                                                       int32_t *__restrict__ C, RowBlocks rb) {
+                                                       int32_t *__restrict__ C, RowBlocks rb,
+                                                       int same) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
   const int tiles_n = npad / GBN;
@@ -322,7 +323,10 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
   const int n0 = (blockIdx.x % tiles_n) * GBN;
   const int slot = order.q[blockIdx.y];
   const int d = d_min + slot;
-  const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
+  // same: slot q multiplies plane q + 1 of both operands (one pair); else the pairs of
+  // diagonal d, planes (s, d - s)
+  const int s_lo = same ? slot + 1 : max(1, d - kr), s_hi = same ? slot + 1 : min(kl, d - 1);
+  const int rsum = same ? 2 * (slot + 1) : d;   // R plane of pair s: rsum - s
   const int npairs = s_hi - s_lo + 1;
   const int KT = kdim / GBK;
   const int T = npairs * KT;
@@ -342,7 +346,7 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
     const int p = t / KT, k0 = (t - p * KT) * GBK;
     const int s = s_lo + p;
     const int8_t *Lb = Lp + (size_t)(s - 1) * pstride;
-    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride;
+    const int8_t *Rb = Rp + (size_t)(rsum - s - 1) * pstride;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
@@ -450,7 +454,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
                                                            size_t pstride, int npad, int kdim,
                                                            int kl, int kr, int d_min,
                                                            DiagOrder order,
-                                                           int32_t *__restrict__ C, RowBlocks rb) {
+                                                           int32_t *__restrict__ C, RowBlocks rb,
+                                                           int same) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
   const int tiles_n = npad / HBM_;
@@ -459,7 +464,10 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   const int m0 = rb.m[mi] * HBM_;
   const int slot = order.q[blockIdx.y];
   const int d = d_min + slot;
-  const int s_lo = max(1, d - kr), s_hi = min(kl, d - 1);
+  // same: slot q multiplies plane q + 1 of both operands (one pair); else the pairs of
+  // diagonal d, planes (s, d - s)
+  const int s_lo = same ? slot + 1 : max(1, d - kr), s_hi = same ? slot + 1 : min(kl, d - 1);
+  const int rsum = same ? 2 * (slot + 1) : d;   // R plane of pair s: rsum - s
   const int npairs = s_hi - s_lo + 1;
   const int KT = kdim / DBK;
   const int T = npairs * KT;   // K-stages over all pairs of this diagonal
@@ -481,7 +489,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
     const int p = tt / KT, k0 = (tt - p * KT) * DBK;
     const int s = s_lo + p;
     const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + kb_off(m0, k0, npad);
-    const int8_t *Rb = Rp + (size_t)(d - s - 1) * pstride + kb_off(n0, k0, npad);
+    const int8_t *Rb = Rp + (size_t)(rsum - s - 1) * pstride + kb_off(n0, k0, npad);
     int8_t *st = ring + (tt % S) * DSTAGE_BYTES;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -593,7 +601,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
 
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
-                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim) {
+                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
+                       bool same_plane) {
   if (kdim <= 0) kdim = npad;
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
@@ -601,7 +610,7 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   for (int q = 0; q < ndiag; ++q) {
     int d = d_min + q;
     int lo = d - kr > 1 ? d - kr : 1, hi = kl < d - 1 ? kl : d - 1;
-    cnt[q] = hi - lo + 1;
+    cnt[q] = same_plane ? 1 : hi - lo + 1;
     o.q[q] = q;
   }
   for (int a = 1; a < ndiag; ++a)
@@ -623,11 +632,11 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   if (npad >= 1024)
     hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride,
-                       npad, kdim, kl, kr, d_min, o, C, rb);
+                       npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane);
   else
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride, npad, kdim,
-                       kl, kr, d_min, o, C, rb);
+                       kl, kr, d_min, o, C, rb, (int)same_plane);
 }
 
 int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
@@ -658,12 +667,94 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
 }
 
 // ---------------------------------------------------------------- V epilogue + column pass
+// Triple-double reconstruction of P from its residues c_q = C_q mod m_q (symmetric), for
+// the EPT rows of a thread: P / M = frac(sum_q c_q u_q) in [-1/2, 1/2), kept as
+// s0 + s1 + s2 (absolute error about 2^-150: every product is split exactly, integer parts
+// leave s0 exactly), then V = (P / M) M 2^(scale) as a double-word (vh, vl). Moduli are the
+// outer loop, and the next modulus's slot is loaded while this one is added; s0 and s1 live
+// in vh and vl until the end.
 template <int EPT>
+__device__ __forceinline__ void crt_column(const int32_t *__restrict__ Ccol, size_t P, int n,
+                                           int tid, const CrtRec &rec, const int (&scale)[EPT],
+                                           double (&vh)[EPT], double (&vl)[EPT]) {
+  double s2[EPT];
+  int32_t cv[EPT], cn[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = tid + kEpiThreads * q;
+    vh[q] = vl[q] = s2[q] = 0.0;
+    cv[q] = (i < n) ? Ccol[i] : 0;
+  }
+#pragma unroll 1
+  for (int qm = 0; qm < rec.N; ++qm) {
+    if (qm + 1 < rec.N) {
+      const int32_t *Cn = Ccol + (size_t)(qm + 1) * P;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int i = tid + kEpiThreads * q;
+        cn[q] = (i < n) ? Cn[i] : 0;
+      }
+    }
+    const double m = (double)rec.m[qm], rm = rec.rm[qm];
+    const double u0 = rec.u[qm][0], u1 = rec.u[qm][1], u2 = rec.u[qm][2];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double c = (double)cv[q];
+      const double rq = c - m * rint(c * rm);   // exact: |c| < 2^27
+      double p0, e0, p1, e1, t, cc, u, c2;
+      two_prod(rq, u0, p0, e0);
+      two_prod(rq, u1, p1, e1);
+      const double p2 = rq * u2;
+      p0 -= rint(p0);
+      two_sum(vh[q], p0, t, cc);
+      vh[q] = t - rint(t);
+      two_sum(vl[q], cc, u, c2);
+      vl[q] = u;
+      s2[q] += c2;
+      two_sum(vl[q], e0, u, c2);
+      vl[q] = u;
+      s2[q] += c2;
+      two_sum(vl[q], p1, u, c2);
+      vl[q] = u;
+      s2[q] += c2;
+      s2[q] += e1 + p2;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    double s0 = vh[q];
+    const double s1 = vl[q];
+    double h, l;
+    two_sum(s0, s1, h, l);
+    if (h >= 0.5) s0 -= 1.0;
+    else if (h < -0.5) s0 += 1.0;
+    // (s0 + s1 + s2) (M0 + M1 + M2): the terms down to 2^-99 M are exact products and are
+    // summed as a double-word, so the absolute error stays near 2^-150 M
+    double ph, pl, q1, q1e, q2, q2e, L, Le, t, te;
+    two_prod(s0, rec.M[0], ph, pl);
+    two_prod(s0, rec.M[1], q1, q1e);
+    two_prod(s1, rec.M[0], q2, q2e);
+    two_sum(pl, q1, L, Le);
+    two_sum(L, q2, t, te);
+    L = t;
+    Le += te + (q1e + q2e) + (s1 * rec.M[1] + s2[q] * rec.M[0] + s0 * rec.M[2]);
+    double h2, l2;
+    two_sum(ph, L, h2, l2);
+    l2 += Le;
+    fast_two_sum(h2, l2, h2, l2);
+    vh[q] = ldexp(h2, scale[q]);
+    vl[q] = ldexp(l2, scale[q]);
+  }
+}
+
+template <int EPT, bool CRT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
-    int kr, int *flags) {
+    int kr, int *flags, const CrtRec rec) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -687,6 +778,12 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     vh[q] = vl[q] = 0.0;
     eiq[q] = (i < n) ? eA[i] + ej : 0;
   }
+  if constexpr (CRT) {
+    int sc[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
+    crt_column<EPT>(Ccol, P, n, tid, rec, sc, vh, vl);
+  } else {
   // slice sum, smallest scale first; diagonals outermost, and the next diagonal's values
   // are loaded while this one is summed, so each thread keeps 2 EPT loads in flight
   int32_t cv[EPT], cn[EPT];
@@ -715,6 +812,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+  }
   }
   ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
 #pragma unroll
@@ -783,8 +881,80 @@ template <int EPT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                     int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_v<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
-                     eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags);
+  CrtRec none;
+  none.N = 0;
+  none.sh = 0;
+  hipLaunchKernelGGL((k_epi_v<EPT, false>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min,
+                     ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, none);
+}
+
+void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec &rec, const int *eA,
+                      const int *eX, const double *X1, int n, double *lam, double *lam_lo,
+                      double *r, int *eR, double *resmax, int8_t *Rpl, int kr, int *flags,
+                      hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+#define EPI_V_CRT(E)                                                                          \
+  hipLaunchKernelGGL((k_epi_v<E, true>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, 2, 1,   \
+                     (const int *)nullptr, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr,  \
+                     flags, rec)
+  if (ept <= 1) EPI_V_CRT(1);
+  else if (ept <= 2) EPI_V_CRT(2);
+  else if (ept <= 4) EPI_V_CRT(4);
+  else EPI_V_CRT(8);
+#undef EPI_V_CRT
+}
+
+// Residue planes from digit planes: 4 bytes of every plane per thread, K planes (template,
+// so no predicated work for absent planes). The weights are taken in the symmetric range
+// (|w| <= 127), the digit sum (|sum| < 18 127 127 < 2^24) is reduced in FP32: its quotient
+// by m_q is off by less than 2^-10 and never within 1 / (2 m_q) >= 2^-9 of a half-integer.
+template <int K>
+__global__ __launch_bounds__(256) void k_residues(const int8_t *__restrict__ planes,
+                                                  size_t pstride, size_t count,
+                                                  const ResWeights w, int8_t *__restrict__ res) {
+  const size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (e >= count) return;
+  int d[K][4];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const unsigned v = *(const unsigned *)(planes + (size_t)t * pstride + e);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) d[t][b] = (int)(int8_t)((v >> (8 * b)) & 0xffu);
+  }
+  for (int q = 0; q < w.N; ++q) {
+    const float m = (float)w.m[q], rm = w.rmf[q];
+    unsigned packed = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int acc = 0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) acc += d[t][b] * w.w[q][t];
+      const float a = (float)acc;
+      const int rr = (int)(a - m * rintf(a * rm));   // |rr| <= (m - 1) / 2 <= 127
+      packed |= ((unsigned)(rr & 0xff)) << (8 * b);
+    }
+    *(unsigned *)(res + (size_t)q * pstride + e) = packed;
+  }
+}
+
+template <int K>
+static void residues_t(const int8_t *planes, size_t pstride, size_t count, const ResWeights &w,
+                       int8_t *res, hipStream_t s) {
+  const size_t threads = count / 4;
+  hipLaunchKernelGGL(k_residues<K>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     planes, pstride, count, w, res);
+}
+
+void launch_residues(const int8_t *planes, size_t pstride, size_t count, const ResWeights &w,
+                     int8_t *res, hipStream_t s) {
+  switch (w.k) {
+#define RES_K(K) \
+  case K: residues_t<K>(planes, pstride, count, w, res, s); break;
+    RES_K(1) RES_K(2) RES_K(3) RES_K(4) RES_K(5) RES_K(6) RES_K(7) RES_K(8) RES_K(9)
+    RES_K(10) RES_K(11) RES_K(12) RES_K(13) RES_K(14) RES_K(15) RES_K(16) RES_K(17) RES_K(18)
+#undef RES_K
+    default: break;
+  }
 }
 
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,

@@ -56,6 +56,7 @@ struct Work {
   int n = 0, npad = 0, ka = 0;
   size_t P = 0;
   int8_t *AP, *XP, *XPT, *RP, *EP;
+  int8_t *ARES = nullptr, *XRES = nullptr;   // residue planes of the V product by residues
   int32_t *Cs;
   double *X1;
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
@@ -67,13 +68,15 @@ struct Work {
   double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
 };
 
-int nslots(int ka) { return std::max(ka, kKrMax + kKxMax); }
+int nslots(int ka, bool crt = false) {
+  return std::max(std::max(ka, kKrMax + kKxMax), crt ? kCrtMax : 0);
+}
 
 constexpr int kGroupColsMax = 1024;   // group members corrected per iteration (at most)
 constexpr int kCouplingsMax = 1 << 16; // strong couplings listed per iteration (at most)
 
 // Carves the workspace; returns the bytes needed (base may be null).
-size_t carve(int n, int ka, char *base, Work *w) {
+size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   Work t;
   t.n = n;
   t.npad = round_up(n, kTile);
@@ -90,7 +93,11 @@ size_t carve(int n, int ka, char *base, Work *w) {
   t.XPT = (int8_t *)take(t.P * kKxMax);
   t.RP = (int8_t *)take(t.P * kKrMax);
   t.EP = (int8_t *)take(t.P * kKeMax);
-  t.Cs = (int32_t *)take(t.P * 4 * (size_t)nslots(ka));
+  t.Cs = (int32_t *)take(t.P * 4 * (size_t)nslots(ka, crt));
+  if (crt) {
+    t.ARES = (int8_t *)take(t.P * kCrtMax);
+    t.XRES = (int8_t *)take(t.P * kCrtMax);
+  }
   t.X1 = (double *)take(sizeof(double) * (size_t)n * n);
   const size_t vi = sizeof(int) * t.npad, vd = sizeof(double) * t.npad;
   t.eA = (int *)take(vi);
@@ -219,6 +226,101 @@ size_t carve_herm(int n, int ka, char *base, HermWork *w) {
   t.emax = (double *)take(vd);
   if (w) *w = t;
   return off;
+}
+
+// ---- V by residues: moduli and reconstruction constants.
+// Odd, pairwise coprime moduli <= 255, largest first (greedy over 255, 253, ...).
+const std::vector<int> &crt_moduli() {
+  static const std::vector<int> mods = [] {
+    std::vector<int> v;
+    for (int m = 255; m >= 3 && (int)v.size() < kCrtMax; m -= 2) {
+      bool ok = true;
+      for (int x : v) {
+        int a = m, b = x;
+        while (b) {
+          int t = a % b;
+          a = b;
+          b = t;
+        }
+        if (a != 1) ok = false;
+      }
+      if (ok) v.push_back(m);
+    }
+    return v;
+  }();
+  return mods;
+}
+
+int inv_mod(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1)
+  int t = 0, nt = 1, r = m, nr = ((a % m) + m) % m;
+  while (nr) {
+    const int q = r / nr, tt = t - q * nt, rr = r - q * nr;
+    t = nt;
+    nt = tt;
+    r = nr;
+    nr = rr;
+  }
+  return t < 0 ? t + m : t;
+}
+
+// Plans V = P 2^(eA_i + eX_j - 7 (ka1 + kx)) with P = Ã X̃ (ka1 digits of A, kx of X^(1),
+// reduction length npad): enough moduli that prod m_q > 4 npad 128^(ka1 + kx) (so
+// |P| < M / 4), the digit weights of both residue passes and the triple-double constants.
+// False when more than kCrtMax moduli would be needed.
+bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec &rec) {
+  const std::vector<int> &mods = crt_moduli();
+  const double need = 2.0 + std::log2((double)npad) + 7.0 * (ka1 + kx);
+  double bits = 0.0;
+  int N = 0;
+  while (N < (int)mods.size() && bits <= need) bits += std::log2((double)mods[N++]);
+  if (bits <= need || ka1 > kCrtPlanes || kx > kCrtPlanes) return false;
+  wA.N = wX.N = rec.N = N;
+  wA.k = ka1;
+  wX.k = kx;
+  rec.sh = -7 * (ka1 + kx);
+  for (int q = 0; q < N; ++q) {
+    const int m = mods[q];
+    wA.m[q] = wX.m[q] = rec.m[q] = m;
+    wA.rmf[q] = wX.rmf[q] = 1.0f / (float)m;
+    rec.rm[q] = 1.0 / (double)m;
+    for (int t = 0; t < kCrtPlanes; ++t) wA.w[q][t] = wX.w[q][t] = 0;
+    // 128^(k-1-t) mod m, from the least significant digit up, in the symmetric range
+    auto sym = [m](long long v) { return (int)(v > m / 2 ? v - m : v); };
+    long long pw = 1;
+    for (int t = ka1 - 1; t >= 0; --t) {
+      wA.w[q][t] = sym(pw);
+      pw = pw * 128 % m;
+    }
+    pw = 1;
+    for (int t = kx - 1; t >= 0; --t) {
+      wX.w[q][t] = sym(pw);
+      pw = pw * 128 % m;
+    }
+    long long Mq = 1;   // (M / m_q) mod m_q
+    for (int l = 0; l < N; ++l)
+      if (l != q) Mq = Mq * (mods[l] % m) % m;
+    const double y = (double)inv_mod((int)Mq, m), md = (double)m;
+    const double u0 = y / md, r0 = std::fma(-u0, md, y);
+    const double u1 = r0 / md, r1 = std::fma(-u1, md, r0);
+    rec.u[q][0] = u0;
+    rec.u[q][1] = u1;
+    rec.u[q][2] = r1 / md;
+  }
+  // M = prod m_q as a double-word (relative error about N 2^-105: it only scales P / M, so
+  // V keeps a double-word's relative accuracy)
+  double a0 = 1.0, a1 = 0.0;
+  for (int q = 0; q < N; ++q) {
+    const double md = (double)mods[q];
+    const double p0 = a0 * md, e0 = std::fma(a0, md, -p0);
+    const double sl = e0 + a1 * md;
+    a0 = p0 + sl;
+    a1 = sl - (a0 - p0);
+  }
+  const double a2 = 0.0;
+  rec.M[0] = a0;
+  rec.M[1] = a1;
+  rec.M[2] = a2;
+  return true;
 }
 
 int ka_of(const refeig_opts *o) {
@@ -1046,13 +1148,15 @@ int refeig_default_opts(refeig_opts *o) {
   o->ka_max = kKaMaxLimit;
   o->d_extra = 0;
   o->verbose = 0;
+  o->vmode = 1;
   return REFEIG_OK;
 }
 
 int refeig_workspace_bytes(int n, const refeig_opts *o, size_t *bytes) {
   if (n < 1 || n > kMaxN || !bytes) return REFEIG_E_ARG;
   *bytes = (o && o->mode == REFEIG_FP64_PLAIN) ? carve_plain(n, nullptr, nullptr)
-                                               : carve(n, ka_of(o), nullptr, nullptr);
+                                               : carve(n, ka_of(o), nullptr, nullptr,
+                                                       !o || o->vmode == 1);
   return REFEIG_OK;
 }
 
@@ -1073,7 +1177,7 @@ int refine_eigvecs_herm(const double *A, int lda, double *X, int ldx, double *D,
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
       o.kx_force < 0 || o.kx_force > kKxMax || o.max_iter > REFEIG_MAX_ITERS ||
       o.fixed_iters > REFEIG_MAX_ITERS || o.mode != REFEIG_OZAKI_INT8 || o.group_tau != 0.0 ||
-      o.schedule != 0 || o.sparse_k != 0)
+      o.schedule != 0 || o.sparse_k != 0 || o.vmode < 0 || o.vmode > 1)
     return REFEIG_E_ARG;
   return refine_herm(A, lda, X, ldx, D, n, target, o, work, work_bytes, (hipStream_t)stream,
                      rep);
@@ -1146,7 +1250,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   if (!A || !X || !D || n < 1 || n > kMaxN || lda < n || ldx < n || !(target > 0.0) ||
       !(o.delta_safety >= 1.0) || !(o.theta > 0.0 && o.theta <= 1.0) || o.max_iter < 1 ||
       !(o.group_tau >= 0.0) || o.kx_force < 0 || o.kx_force > kKxMax || o.sparse_k < 0 ||
-      o.schedule < 0 || o.schedule > 1 ||
+      o.schedule < 0 || o.schedule > 1 || o.vmode < 0 || o.vmode > 1 ||
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -1154,7 +1258,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     return refine_plain(A, lda, X, ldx, D, n, target, o, work, work_bytes, s, rep);
   if (o.mode != REFEIG_OZAKI_INT8) return REFEIG_E_ARG;
   const int ka_max = ka_of(&o);
-  const size_t need = carve(n, ka_max, nullptr, nullptr);
+  const bool crt = o.vmode == 1;
+  const size_t need = carve(n, ka_max, nullptr, nullptr, crt);
   bool own = false;
   if (!work) {
     HIPCHK(hipStreamSynchronize(s));
@@ -1164,7 +1269,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     return REFEIG_E_NOMEM;
   }
   Work w;
-  carve(n, ka_max, (char *)work, &w);
+  carve(n, ka_max, (char *)work, &w, crt);
   const int npad = w.npad;
   const size_t P = w.P;
   const double delta_int = target / o.delta_safety;
@@ -1226,6 +1331,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
 
   const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
   double eps_prev = INFINITY;
+  int ares_ka = -1, ares_n = -1;   // digit and modulus counts of the residues in w.ARES
   int it = 0;
   for (; it < iters; ++it) {
     STEP(hipEventRecord(ev[0], s));
@@ -1285,14 +1391,51 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int dv_allowed = std::min(ka_max + 1, kx + ka_max);
     const int ka = ka_max;
     CutPlan plan;
-    if (!plan_cutoffs(dcol, n, npad, kx, ka, dv_allowed, w.dcut[0], dhost, s, plan))
-      return cleanup(REFEIG_E_HIP);
-    const int dv = plan.dmax;
-    const double pv = plan.pairs_eff;
-    const int lv = (int)plan.groups.size();
-    launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
-    launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
-                 w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
+    int dv = 2, lv = 0;
+    double pv = 0.0;
+    bool by_res = false;
+    if (crt) {
+      // V by residues: one digit count ka1 of A for all columns, from the truncation bound
+      // sqrt(n) 2^(eA_max + eX_j - 7 ka1) <= theta delta gap_j (X^(1) enters exactly)
+      int ka1 = 1;
+      for (int j = 0; j < n; ++j) {
+        if (mxX[j] == 0.0) continue;
+        const double nd =
+            (eA_max + lgrowth_a + eX[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
+        ka1 = std::max(ka1, (int)std::ceil(nd) + o.d_extra);
+      }
+      ka1 = std::min(ka1, ka_max);
+      ResWeights wA, wX;
+      CrtRec rec;
+      if (crt_plan(npad, ka1, kx, wA, wX, rec)) {
+        by_res = true;
+        // A's residues depend only on ka1 and the moduli: reused while they repeat
+        if (ka1 != ares_ka || rec.N != ares_n) {
+          launch_residues(w.AP, P, P, wA, w.ARES, s);
+          ares_ka = ka1;
+          ares_n = rec.N;
+        }
+        launch_residues(w.XP, P, P, wX, w.XRES, s);
+        // one launch: slot q = residue planes q of X^(1) and A
+        launch_slice_gemm(w.XRES, w.ARES, P, npad, rec.N, rec.N, 2, rec.N, w.Cs, nullptr, s,
+                          ev[1], ev[2], 0, true);
+        launch_epi_v_crt(w.Cs, npad, rec, w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r, w.eR,
+                         w.resmax, w.RP, kKrMax, w.flags, s);
+        dv = ka1 + kx;
+        pv = rec.N;
+        lv = rec.N;
+      }
+    }
+    if (!by_res) {
+      if (!plan_cutoffs(dcol, n, npad, kx, ka, dv_allowed, w.dcut[0], dhost, s, plan))
+        return cleanup(REFEIG_E_HIP);
+      dv = plan.dmax;
+      pv = plan.pairs_eff;
+      lv = (int)plan.groups.size();
+      launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
+      launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
+                   w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
+    }
     STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));

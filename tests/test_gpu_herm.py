@@ -122,6 +122,6 @@ def test_herm_rejects_unsupported_options():
     rb = _rb()
     p = workloads.hermitian_problem(1, 64)
     A, X, D = _dev(p)
-    for kw in (dict(group_tau=1e-3), dict(schedule=1), dict(sparse_k=3)):
+    for kw in (dict(group_tau=1e-3), dict(schedule=1), dict(sparse_k=3), dict(vmode=2)):
         st, _ = rb.refine_eigvecs_herm(A, X, D, 1e-14, rb.default_opts(**kw))
         assert st == rb.REFEIG_E_ARG

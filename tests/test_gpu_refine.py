@@ -426,3 +426,42 @@ def test_adaptive_schedule():
     assert delta < r["delta_it"][1] <= 0.01 * r["eps"][0] ** 4
     assert r["delta_it"][-1] == delta
     assert r["iters"] <= res[0][1]["iters"]
+
+
+@pytest.mark.parametrize("cfg,n,target", [(1, 100, 1e-14), (2, 300, 1e-12), (3, 1100, 1e-14)])
+def test_one_step_v_by_residues_vs_oracle(cfg, n, target):
+    """vmode = 1 (V as the exact product of A's digits and X^(1) by residues and the Chinese
+    remainder theorem, an alternative to the slice products): one step against the oracle's
+    exact-product step, to the same bar as the slice form."""
+    print(f"step vmode=1 cfg={cfg} n={n} target={target}", flush=True)
+    rb = _rb()
+    p = workloads.make_problem(cfg, n, x0="eigh")
+    A, X, D = _to_dev(p)
+    opts = rb.default_opts(fixed_iters=1, vmode=1)
+    st, rep = rb.refine_eigvecs(A, X, D, target, opts)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    ref = oracle.method_step(p.A, p.X0, p.D0, target / opts.delta_safety)
+    assert rep.beta[0] == ref.beta and rep.kx[0] == ref.kx
+    Xg = rb.from_colmajor(X)
+    diff = float(np.max(np.abs(Xg - ref.X_hi)))
+    print(f"  moduli={rep.pairs_p[0][0]} dv={rep.dv[0]} |X_gpu - X_oracle|max={diff:.3e}",
+          flush=True)
+    assert 10 <= rep.pairs_p[0][0] <= 32
+    assert diff <= target / opts.delta_safety
+    lam = D.cpu().numpy()
+    assert float(np.max(np.abs(lam - ref.lam_h))) <= (target / opts.delta_safety) * float(
+        np.max(np.abs(ref.lam_h)))
+
+
+@pytest.mark.parametrize("cfg,n,target", [(3, 700, 1e-14), (2, 1025, 1e-13), (1, 257, 1e-12)])
+def test_refine_v_by_residues_to_target(cfg, n, target):
+    print(f"refine vmode=1 cfg={cfg} n={n} target={target}", flush=True)
+    rb = _rb()
+    p = workloads.make_problem(cfg, n, x0="eigh")
+    Xt, lt = _xtrue(p)
+    A, X, D = _to_dev(p)
+    st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(vmode=1))
+    err = _fwd(rb.from_colmajor(X), Xt)
+    print(f"  status={st} iters={rep.iters} fwd={err:.3e}", flush=True)
+    assert st == rb.REFEIG_OK, rb.strerror(st)
+    assert err <= target
