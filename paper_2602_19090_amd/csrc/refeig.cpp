@@ -1422,8 +1422,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         launch_epi_v_crt(w.Cs, npad, rec, w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r, w.eR,
                          w.resmax, w.RP, kKrMax, w.flags, s);
         dv = ka1 + kx;
-        pv = rec.N;
-        lv = rec.N;
+        pv = rec.N;   // N products of n x n x n
+        lv = 1;
       }
     }
     if (!by_res) {
