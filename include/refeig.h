@@ -219,6 +219,17 @@ int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream,
 int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const double *mx,
                      double target_fwd_err, const refeig_opts *o, int *beta, int *kx);
 
+/* Host-only (no GPU needed): the plan of the residue product of V (vmode 1)
+ * for ka1 digits of A, kx digits of X^(1) and reduction length npad, as the
+ * solver builds it: *N moduli (odd, pairwise coprime, <= 255, largest first)
+ * with prod m_q > 4 npad 128^(ka1 + kx); digit weights wA[q*18 + t] =
+ * 128^(ka1-1-t) mod m_q and wX[q*18 + t] = 128^(kx-1-t) mod m_q in the
+ * symmetric range; u[3q..3q+2] = y_q / m_q as a triple-double with
+ * y_q = (M / m_q)^-1 mod m_q; M[0..2] = prod m_q (double-word, M[2] = 0).
+ * Arrays hold 28 moduli (moduli, u: 28 and 84 entries; wA, wX: 28*18).
+ * Returns REFEIG_E_ARG when more than 28 moduli would be needed. */
+int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
+                         double *u, double *M);
 /* Working column order of an iteration: columns by the gap of their eigenvalue
  * estimate to its nearest neighbour, widest first, ties by eigenvalue.
  * order[p] = the column placed at working position p (host arrays of n). */

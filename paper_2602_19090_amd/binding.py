@@ -100,6 +100,8 @@ _lib.refeig_row_nonzeros.argtypes = [_vp, _int, _int, _vp, ctypes.POINTER(_int)]
 _lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                                   ctypes.POINTER(_int), ctypes.POINTER(_int)]
 _lib.refeig_host_column_order.argtypes = [_int, _vp, _vp]
+_lib.refeig_host_crt_plan.argtypes = [_int, _int, _int, ctypes.POINTER(_int), _vp, _vp, _vp, _vp,
+                                      _vp]
 _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
@@ -257,6 +259,24 @@ def host_beta(lam, e, c, mx, target, opts: Opts | None = None):
                                float(target), ctypes.byref(opts) if opts is not None else None,
                                ctypes.byref(b), ctypes.byref(k))
     return st, b.value, k.value
+
+
+def host_crt_plan(npad: int, ka1: int, kx: int):
+    """The residue-product plan of V (refeig_host_crt_plan): dict with moduli, wA, wX (N x 18),
+    u (N x 3) and M (3)."""
+    N = _int(0)
+    mods = np.zeros(28, dtype=np.int32)
+    wA = np.zeros(28 * 18, dtype=np.int32)
+    wX = np.zeros(28 * 18, dtype=np.int32)
+    u = np.zeros(84)
+    M = np.zeros(3)
+    st = _lib.refeig_host_crt_plan(int(npad), int(ka1), int(kx), ctypes.byref(N), _np_ptr(mods),
+                                   _np_ptr(wA), _np_ptr(wX), _np_ptr(u), _np_ptr(M))
+    if st != 0:
+        raise ValueError(strerror(st))
+    n = N.value
+    return {"moduli": mods[:n].tolist(), "wA": wA.reshape(28, 18)[:n], "wX": wX.reshape(28, 18)[:n],
+            "u": u.reshape(28, 3)[:n], "M": M}
 
 
 def host_column_order(lam):

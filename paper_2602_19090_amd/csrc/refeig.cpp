@@ -1692,6 +1692,26 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
   return REFEIG_OK;
 }
 
+int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
+                         double *u, double *M) {
+  if (npad < 1 || ka1 < 1 || kx < 1 || !N || !moduli || !wA || !wX || !u || !M)
+    return REFEIG_E_ARG;
+  ResWeights a, x;
+  CrtRec rec;
+  if (!crt_plan(npad, ka1, kx, a, x, rec)) return REFEIG_E_ARG;
+  *N = rec.N;
+  for (int q = 0; q < rec.N; ++q) {
+    moduli[q] = rec.m[q];
+    for (int t = 0; t < kCrtPlanes; ++t) {
+      wA[q * kCrtPlanes + t] = a.w[q][t];
+      wX[q * kCrtPlanes + t] = x.w[q][t];
+    }
+    for (int c = 0; c < 3; ++c) u[3 * q + c] = rec.u[q][c];
+  }
+  for (int c = 0; c < 3; ++c) M[c] = rec.M[c];
+  return REFEIG_OK;
+}
+
 int refeig_host_column_order(int n, const double *lam, int *order) {
   if (n < 1 || !lam || !order) return REFEIG_E_ARG;
   std::vector<double> l(lam, lam + n), g;
