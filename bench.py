@@ -36,6 +36,13 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
 
 
+WORK = None   # one caller-owned workspace for every solve (the library then allocates nothing)
+
+
+def refine(rb, A, X, D, target, opts=None):
+    return rb.refine_eigvecs(A, X, D, target, opts, work=WORK)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -98,7 +105,7 @@ def solve_leg(rb, A, X0, D0, target, golden, args, ms_ref, **kw):
     errs, K = [], None
     for k in range(1, 13):
         X, D = X0.clone(), D0.clone()
-        st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=k, **kw))
+        st, rep = refine(rb, A, X, D, target, rb.default_opts(fixed_iters=k, **kw))
         errs.append(sampled_error(X, golden))
         log(f"  {k} iterations: sampled error {errs[-1]:.3e}")
         if errs[-1] <= target:
@@ -113,7 +120,7 @@ def solve_leg(rb, A, X0, D0, target, golden, args, ms_ref, **kw):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        st, rep = rb.refine_eigvecs(A, X, D, target, opts)
+        st, rep = refine(rb, A, X, D, target, opts)
         e1.record()
         torch.cuda.synchronize()
         if s_ >= args.warmup:
@@ -395,6 +402,11 @@ def main():
     D0 = w.contiguous()
     del V
     golden = load_golden(args.config, n, p.meta["digest"])
+    global WORK
+    WORK = torch.empty(max(rb.workspace_bytes(n, rb.default_opts()),
+                           rb.workspace_bytes(n, rb.default_opts(vmode=0)),
+                           rb.workspace_bytes(n, rb.default_opts(mode=rb.REFEIG_FP64_PLAIN))),
+                       dtype=torch.uint8, device="cuda")
     if args.calibrate:
         # a plain elementwise kernel of known traffic (reads and writes n*n*8 bytes once),
         # used to scale the HBM byte counters of a profiler pass
@@ -405,7 +417,7 @@ def main():
 
     # ---- untimed: iterations to the target
     X, D = X0.clone(), D0.clone()
-    st, rep = rb.refine_eigvecs(A, X, D, target)
+    st, rep = refine(rb, A, X, D, target)
     stop_iters = rep.iters
     log(f"stop rule: status {rb.strerror(st)}, {stop_iters} iterations, eps {list(rep.as_dict()['eps'])}")
     errs = []
@@ -415,7 +427,7 @@ def main():
         errs.append(sampled_error(X, golden))
         K = None
         for k in range(1, 13):
-            st1, _ = rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=1))
+            st1, _ = refine(rb, A, X, D, target, rb.default_opts(fixed_iters=1))
             errs.append(sampled_error(X, golden))
             log(f"iteration {k}: sampled max-abs forward error {errs[-1]:.3e}")
             if errs[-1] <= target and K is None:
@@ -428,7 +440,7 @@ def main():
     # ---- warmup and timed steps
     for _ in range(args.warmup):
         X, D = X0.clone(), D0.clone()
-        rb.refine_eigvecs(A, X, D, target, opts)
+        refine(rb, A, X, D, target, opts)
     torch.cuda.synchronize()
     ms, reps = [], []
     Xw, Dw = torch.empty_like(X0), torch.empty_like(D0)
@@ -439,7 +451,7 @@ def main():
         Dw.copy_(D0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        st, rep = rb.refine_eigvecs(A, Xw, Dw, target, opts)
+        st, rep = refine(rb, A, Xw, Dw, target, opts)
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
@@ -468,14 +480,14 @@ def main():
         log("FP64 plain form: iterations to the target")
         popts = rb.default_opts(mode=rb.REFEIG_FP64_PLAIN)
         X, D = X0.clone(), D0.clone()
-        pst, prep = rb.refine_eigvecs(A, X, D, target, popts)
+        pst, prep = refine(rb, A, X, D, target, popts)
         Kp = prep.iters
         perrs = []
         if golden is not None:
             X, D = X0.clone(), D0.clone()
             Kp = None
             for k in range(1, 13):
-                rb.refine_eigvecs(A, X, D, target, rb.default_opts(mode=rb.REFEIG_FP64_PLAIN,
+                refine(rb, A, X, D, target, rb.default_opts(mode=rb.REFEIG_FP64_PLAIN,
                                                                     fixed_iters=1))
                 perrs.append(sampled_error(X, golden))
                 log(f"plain iteration {k}: sampled max-abs forward error {perrs[-1]:.3e}")
@@ -490,7 +502,7 @@ def main():
                 Dw.copy_(D0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                pst, prep = rb.refine_eigvecs(A, Xw, Dw, target, popts)
+                pst, prep = refine(rb, A, Xw, Dw, target, popts)
                 e1.record()
                 torch.cuda.synchronize()
                 pms.append(e0.elapsed_time(e1))
@@ -518,7 +530,7 @@ def main():
         X, D = X0.clone(), D0.clone()
         aerrs, aK = [sampled_error(X, golden)], None
         for k in range(1, 13):
-            rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=1, kx_force=args.ab_kx))
+            refine(rb, A, X, D, target, rb.default_opts(fixed_iters=1, kx_force=args.ab_kx))
             aerrs.append(sampled_error(X, golden))
             if aerrs[-1] <= target:
                 aK = k
@@ -531,7 +543,7 @@ def main():
                 Dw.copy_(D0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                ast_, arep = rb.refine_eigvecs(A, Xw, Dw, target, aopts)
+                ast_, arep = refine(rb, A, Xw, Dw, target, aopts)
                 e1.record()
                 torch.cuda.synchronize()
                 if s_ >= args.warmup:
@@ -561,7 +573,7 @@ def main():
         X, D = X0.clone(), D0.clone()
         gerrs, gK, ggroups = [sampled_error(X, golden)], None, []
         for k in range(1, 13):
-            _, grep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(
+            _, grep = refine(rb, A, X, D, target, rb.default_opts(
                 fixed_iters=1, group_tau=args.group_tau))
             ggroups.append(grep.groups[0])
             gerrs.append(sampled_error(X, golden))
@@ -577,7 +589,7 @@ def main():
                 Dw.copy_(D0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                gst, _ = rb.refine_eigvecs(A, Xw, Dw, target, gopts)
+                gst, _ = refine(rb, A, Xw, Dw, target, gopts)
                 e1.record()
                 torch.cuda.synchronize()
                 if s_ >= args.warmup:
