@@ -263,12 +263,12 @@ def host_beta(lam, e, c, mx, target, opts: Opts | None = None):
 
 def host_crt_plan(npad: int, ka1: int, kx: int):
     """The residue-product plan of V (refeig_host_crt_plan): dict with moduli, wA, wX (N x 18),
-    u (N x 3) and M (3)."""
+    U ((N + 1) / 2 x 3, per reconstruction term) and M (3)."""
     N = _int(0)
     mods = np.zeros(28, dtype=np.int32)
     wA = np.zeros(28 * 18, dtype=np.int32)
     wX = np.zeros(28 * 18, dtype=np.int32)
-    u = np.zeros(84)
+    u = np.zeros(42)
     M = np.zeros(3)
     st = _lib.refeig_host_crt_plan(int(npad), int(ka1), int(kx), ctypes.byref(N), _np_ptr(mods),
                                    _np_ptr(wA), _np_ptr(wX), _np_ptr(u), _np_ptr(M))
@@ -276,7 +276,7 @@ def host_crt_plan(npad: int, ka1: int, kx: int):
         raise ValueError(strerror(st))
     n = N.value
     return {"moduli": mods[:n].tolist(), "wA": wA.reshape(28, 18)[:n], "wX": wX.reshape(28, 18)[:n],
-            "u": u.reshape(28, 3)[:n], "M": M}
+            "U": u.reshape(14, 3)[:(n + 1) // 2], "M": M}
 
 
 def host_column_order(lam):

@@ -53,15 +53,35 @@ struct RowBlocks {
 // kdim: reduction length (a multiple of 128; 0 means npad). The complex products use
 // kdim = 2 npad: the imaginary parts are stacked after the real parts along K.
 // same_plane: slot q holds the single product of plane q + 1 of L with plane q + 1 of R
-// (the residue products, one modulus per slot) instead of diagonal d_min + q.
+// (the residue products, one modulus per slot) instead of diagonal d_min + q. mods (device,
+// with same_plane): slot q is stored reduced mod mods[q] (symmetric, INT8, slot stride npad^2
+// bytes) instead of as INT32.
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
                        hipStream_t s, hipEvent_t ev_start = nullptr,
-                       hipEvent_t ev_stop = nullptr, int kdim = 0, bool same_plane = false);
+                       hipEvent_t ev_stop = nullptr, int kdim = 0, bool same_plane = false,
+                       const int *tcut = nullptr, const int *mods = nullptr);
+// The same products for npad >= 1024 in one launch of nblocks 256 x 256 blocks, block b
+// computing the tile and diagonal slot of tab[b] (device memory; L row block | R row block
+// << 8 | slot << 16, slot = d - d_min); the host orders the table. tcut as above.
+void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad,
+                             int kl, int kr, int d_min, const int *tab, int nblocks, int32_t *C,
+                             hipStream_t s, hipEvent_t ev_start = nullptr,
+                             hipEvent_t ev_stop = nullptr, int kdim = 0,
+                             const int *tcut = nullptr);
 // L rows per block tile of launch_slice_gemm for this npad.
 int gemm_tile_rows(int npad);
 
 // Epilogues sum, for output column j, the diagonals d_min .. min(d_min+ndiag-1, dcut[j]).
+// Per-tile cutoffs of W (256 x 256 tiles, T a side): tcut[J T + I] = the last pair diagonal
+// that keeps the W error of tile (column block J, row block I) within theta delta times the
+// distance from each column's eigenvalue estimate to the nearest one of row block I;
+// cx = 7 + log2(1.5 kx) + log2(sqrt n) - log2(theta delta). T <= kMaxTileSide.
+constexpr int kMaxTileSide = 32;
+void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
+                         int n, int T, double cx, int dmax, int dextra, int *tcut,
+                         hipStream_t s);
+
 // V epilogue fused with the column pass of Algorithm 1 (column j per block):
 //   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),
 //   r_j = 1 - x_j^T x_j, lambda_j = x_j^T v_j / (1 - r_j) (double-word dots; lam gets
@@ -89,14 +109,20 @@ struct CrtRec {
   int N;
   int sh;                         // V = P 2^(eA_i + eX_j + sh)
   int m[kCrtMax];
-  double rm[kCrtMax];             // fl(1 / m_q): c rm_q rounds to the nearest integer of
-                                  // c / m_q for |c| < 2^27 (never within 1 / (2 m_q) of a
-                                  // half-integer for odd m_q)
+  double rm[kCrtMax];             // fl(1 / m_q)
   double u[kCrtMax][3];           // y_q / m_q in triple-double, y_q = (M / m_q)^-1 mod m_q
   double M[3];                    // M = prod m_q in triple-double
+  // The epilogue combines slots 2t and 2t + 1 into one residue modulo m_2t m_2t+1 (exactly,
+  // in FP32: (r_b - r_a) inv_t stays below 2^24) and sums T terms c_t U_t, U_t = Y_t / M_t,
+  // Y_t = (M / M_t)^-1 mod M_t; an odd last slot is a term of its own.
+  int T;
+  float pinv[kCrtMax / 2];        // m_2t^-1 mod m_2t+1
+  float pmb[kCrtMax / 2], prmb[kCrtMax / 2];   // m_2t+1 and fl32(1 / m_2t+1)
+  float pma[kCrtMax / 2];         // m_2t
+  double U[kCrtMax / 2 + 1][3];   // triple-double
 };
-// V epilogue as launch_epi_v, with V rebuilt from the residue products C_q (slot q) instead
-// of summed from slice diagonals.
+// V epilogue as launch_epi_v, with V rebuilt from the residues of the products (INT8 slot q
+// of stride npad^2 bytes, reduced mod m_q by the GEMM) instead of summed from slice diagonals.
 void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec &rec, const int *eA,
                       const int *eX, const double *X1, int n, double *lam, double *lam_lo,
                       double *r, int *eR, double *resmax, int8_t *Rpl, int kr, int *flags,
@@ -119,7 +145,8 @@ void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *d
                   const double *r, int n, int *eE, double *emax, int8_t *Eplanes, int ke,
                   int *flags, hipStream_t s,
                   double tau = 0.0, int *cpl_count = nullptr, int *cpl_pairs = nullptr,
-                  int cpl_cap = 0);
+                  int cpl_cap = 0,
+                  const int *tcut = nullptr);
 
 // Grouped correction (Rayleigh-Ritz on strongly coupled columns). Groups hold at most
 // kGroupMax members.
@@ -129,7 +156,7 @@ constexpr int kGroupMax = 128;
 void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                        const int *eX, const int *eR, const double *X1, int n, const int *pa,
                        const int *pb, int npairs, double *gh, double *gl, double *wab,
-                       hipStream_t s);
+                       hipStream_t s, const int *tcut = nullptr);
 // For each of nmem member slots m: column gcol[m], the group's slots start at gfirst[m],
 // it has gk[m] members, this member is number gpos[m]; Ritz vectors row-major at
 // Y + gbase[m], Ritz value mu[m] + mu_lo[m]. Rewrites that column's E' planes, eE and emax.
@@ -138,7 +165,7 @@ void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const in
                       int n, const int *gcol, const int *gfirst, const int *gk, const int *gpos,
                       const int *gbase, const double *Y, const double *mu, const double *mu_lo,
                       int nmem, int *eE, double *emax, int8_t *Eplanes, int ke, int *flags,
-                      hipStream_t s);
+                      hipStream_t s, const int *tcut = nullptr);
 
 // Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j); column j
 // is written to column colmap[j] of X (colmap may be null).

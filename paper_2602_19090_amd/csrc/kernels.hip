@@ -18,6 +18,7 @@
 #include <hip/hip_ext.h>
 
 #include <float.h>
+#include <limits.h>
 #include <type_traits>
 
 namespace refeig {
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
                                                        size_t pstride, int npad, int kdim,
                                                        int kl, int kr, int d_min, DiagOrder order,
                                                        int32_t *__restrict__ C, RowBlocks rb,
-                                                       int same) {
+                                                       int same, const int *__restrict__ mods) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
   const int tiles_n = npad / GBN;
@@ -379,6 +380,22 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[x], b[y], acc[x][y], 0, 0, 0);
     }
+  }
+  if (mods) {   // residue products: the slot's value mod m_slot as INT8 (as the 256 kernel)
+    int8_t *Cq8 = (int8_t *)C + (size_t)slot * npad * npad;
+    const double m = (double)mods[slot], rm = 1.0 / m;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm * 64 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const int col = n0 + wn * 64 + y * 32 + (lane & 31);
+          const double c = (double)acc[x][y][v];
+          Cq8[(size_t)row * npad + col] = (int8_t)(int)(c - m * rint(c * rm));
+        }
+    return;
   }
   int32_t *Cq = C + (size_t)slot * npad * npad;
 #pragma unroll
@@ -455,15 +472,27 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
                                                            int kl, int kr, int d_min,
                                                            DiagOrder order,
                                                            int32_t *__restrict__ C, RowBlocks rb,
-                                                           int same) {
+                                                           int same, const int *__restrict__ tcut,
+                                                           const int *__restrict__ tab,
+                                                           const int *__restrict__ mods) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
-  const int tiles_n = npad / HBM_;
-  int mi, n0;
-  tile_of_block(blockIdx.x, rb.count, tiles_n, mi, n0);
-  const int m0 = rb.m[mi] * HBM_;
-  const int slot = order.q[blockIdx.y];
+  int m0, n0, slot;
+  if (tab) {   // block table: row block | column block << 8 | slot << 16
+    const int ent = tab[blockIdx.x];
+    m0 = (ent & 0xff) * HBM_;
+    n0 = ((ent >> 8) & 0xff) * HBM_;
+    slot = ent >> 16;
+  } else {
+    int mi;
+    tile_of_block(blockIdx.x, rb.count, npad / HBM_, mi, n0);
+    m0 = rb.m[mi] * HBM_;
+    slot = order.q[blockIdx.y];
+  }
   const int d = d_min + slot;
+  // per-tile diagonal limit (tile = output column block m0 / 256, output row block n0 / 256):
+  // the block's diagonal is not needed there, and nothing reads its slot
+  if (tcut && d > tcut[(m0 / HBM_) * (npad / HBM_) + n0 / HBM_]) return;
   // same: slot q multiplies plane q + 1 of both operands (one pair); else the pairs of
   // diagonal d, planes (s, d - s)
   const int s_lo = same ? slot + 1 : max(1, d - kr), s_hi = same ? slot + 1 : min(kl, d - 1);
@@ -586,6 +615,22 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
     stage(Tail(), tt, fA[0], fB[0], fA[1], fB[1]);
     if (tt + 1 < T) stage(Tail(), tt + 1, fA[1], fB[1], fA[0], fB[0]);
   }
+  if (mods) {   // residue products: store the slot's value mod m_slot (|r| <= 127) as INT8
+    int8_t *Cq8 = (int8_t *)C + (size_t)slot * npad * npad;
+    const double m = (double)mods[slot], rm = 1.0 / m;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm * 128 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const int col = n0 + wn * 128 + y * 32 + (lane & 31);
+          const double c = (double)acc[x][y][v];
+          Cq8[(size_t)row * npad + col] = (int8_t)(int)(c - m * rint(c * rm));
+        }
+    return;
+  }
   int32_t *Cq = C + (size_t)slot * npad * npad;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -602,7 +647,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
                        hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
-                       bool same_plane) {
+                       bool same_plane, const int *tcut, const int *mods) {
   if (kdim <= 0) kdim = npad;
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
@@ -632,14 +677,30 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   if (npad >= 1024)
     hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride,
-                       npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane);
+                       npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane, tcut,
+                       (const int *)nullptr, mods);
   else
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride, npad, kdim,
-                       kl, kr, d_min, o, C, rb, (int)same_plane);
+                       kl, kr, d_min, o, C, rb, (int)same_plane, mods);
 }
 
 int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
+
+void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad,
+                             int kl, int kr, int d_min, const int *tab, int nblocks, int32_t *C,
+                             hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
+                             const int *tcut) {
+  if (kdim <= 0) kdim = npad;
+  if (nblocks <= 0) return;
+  DiagOrder o;
+  RowBlocks rb;
+  rb.count = 0;
+  for (int q = 0; q < kMaxDiag; ++q) o.q[q] = q;
+  hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
+                        Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0, tcut, tab,
+                        (const int *)nullptr);
+}
 
 // Digit planes of one operand row j (an output column of a column epilogue): the values
 // v (EPT per thread, row i = tid + kEpiThreads q; zero beyond n) with column maximum ms,
@@ -674,40 +735,51 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
 // outer loop, and the next modulus's slot is loaded while this one is added; s0 and s1 live
 // in vh and vl until the end.
 template <int EPT>
-__device__ __forceinline__ void crt_column(const int32_t *__restrict__ Ccol, size_t P, int n,
+__device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size_t P, int n,
                                            int tid, const CrtRec &rec, const int (&scale)[EPT],
                                            double (&vh)[EPT], double (&vl)[EPT]) {
   double s2[EPT];
-  int32_t cv[EPT], cn[EPT];
+  int ca[EPT], cb[EPT], na[EPT], nb[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
     vh[q] = vl[q] = s2[q] = 0.0;
-    cv[q] = (i < n) ? Ccol[i] : 0;
+    ca[q] = (i < n) ? Ccol[i] : 0;
+    cb[q] = (i < n && rec.N > 1) ? Ccol[P + i] : 0;
   }
 #pragma unroll 1
-  for (int qm = 0; qm < rec.N; ++qm) {
-    if (qm + 1 < rec.N) {
-      const int32_t *Cn = Ccol + (size_t)(qm + 1) * P;
+  for (int t = 0; t < rec.T; ++t) {
+    const int qa = 2 * t, qb = 2 * t + 1;   // qb == N: a single last slot
+    const bool pair = qb < rec.N;
+    if (t + 1 < rec.T) {   // next term's slots
+      const int8_t *Ca = Ccol + (size_t)(qa + 2) * P;
+      const bool pn = qa + 3 < rec.N;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int i = tid + kEpiThreads * q;
-        cn[q] = (i < n) ? Cn[i] : 0;
+        na[q] = (i < n) ? Ca[i] : 0;
+        nb[q] = (i < n && pn) ? Ca[P + i] : 0;
       }
     }
-    const double m = (double)rec.m[qm], rm = rec.rm[qm];
-    const double u0 = rec.u[qm][0], u1 = rec.u[qm][1], u2 = rec.u[qm][2];
+    const double u0 = rec.U[t][0], u1 = rec.U[t][1], u2 = rec.U[t][2];
+    const float ma = pair ? rec.pma[t] : 0.0f, mb = pair ? rec.pmb[t] : 1.0f;
+    const float inv = pair ? rec.pinv[t] : 0.0f, rmb = pair ? rec.prmb[t] : 0.0f;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const double c = (double)cv[q];
-      const double rq = c - m * rint(c * rm);   // exact: |c| < 2^27
-      double p0, e0, p1, e1, t, cc, u, c2;
+      // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15
+      double rq = (double)ca[q];
+      if (pair) {
+        const float d = (float)(cb[q] - ca[q]) * inv;   // |d| < 2^16, exact
+        const float tt = d - mb * rintf(d * rmb);
+        rq = (double)ca[q] + (double)ma * (double)tt;
+      }
+      double p0, e0, p1, e1, tsum, cc, u, c2;
       two_prod(rq, u0, p0, e0);
       two_prod(rq, u1, p1, e1);
       const double p2 = rq * u2;
       p0 -= rint(p0);
-      two_sum(vh[q], p0, t, cc);
-      vh[q] = t - rint(t);
+      two_sum(vh[q], p0, tsum, cc);
+      vh[q] = tsum - rint(tsum);
       two_sum(vl[q], cc, u, c2);
       vl[q] = u;
       s2[q] += c2;
@@ -720,7 +792,10 @@ __device__ __forceinline__ void crt_column(const int32_t *__restrict__ Ccol, siz
       s2[q] += e1 + p2;
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+    for (int q = 0; q < EPT; ++q) {
+      ca[q] = na[q];
+      cb[q] = nb[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
@@ -782,7 +857,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     int sc[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
-    crt_column<EPT>(Ccol, P, n, tid, rec, sc, vh, vl);
+    crt_column<EPT>((const int8_t *)C + (size_t)j * npad, P, n, tid, rec, sc, vh, vl);
   } else {
   // slice sum, smallest scale first; diagonals outermost, and the next diagonal's values
   // are loaded while this one is summed, so each thread keeps 2 EPT loads in flight
@@ -967,6 +1042,90 @@ void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *d
   else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
 }
 
+// Slots of W entry (i, j) that hold diagonals to sum: up to the column's cutoff dcut[j] or,
+// with a per-tile table (T = npad / 256 tiles a side), the cutoff of tile (j / 256, i / 256).
+__device__ __forceinline__ int w_ndiag(const int *__restrict__ dcut, const int *__restrict__ tcut,
+                                       int T, int ndiag_all, int d_min, int i, int j) {
+  int dc = dcut ? dcut[j] : d_min + ndiag_all - 1;
+  if (tcut) dc = min(dc, tcut[(j >> 8) * T + (i >> 8)]);
+  return min(ndiag_all, dc - d_min + 1);
+}
+
+// Per-tile W cutoffs, one block per row block I (256 rows): sorts the eigenvalue estimates
+// of its rows in LDS, then for every column j takes g = the distance from lambda_j to the
+// nearest of them (other than lambda_j itself when j is in I) and the tile maximum over the
+// column block J of eR_j - floor(log2 g); tcut[J T + I] = the last diagonal that keeps the
+// tile's W error within theta delta g: ceil((max_{i in I} eX_i + cx + that) / 7), in
+// [2, dmax] (+ dextra). Columns with a zero residual (mask[j] == 0) need nothing.
+__global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__ lam,
+                                                      const int *__restrict__ eX,
+                                                      const int *__restrict__ eR,
+                                                      const double *__restrict__ resmax, int n,
+                                                      int T, double cx, int dmax, int dextra,
+                                                      int *__restrict__ tcut) {
+  __shared__ double v[256];
+  __shared__ int tm[kMaxTileSide];
+  __shared__ int exb;
+  const int I = blockIdx.x, tid = threadIdx.x;
+  const int i0 = I * 256, cnt = min(256, n - i0);
+  v[tid] = (tid < cnt) ? lam[i0 + tid] : INFINITY;
+  if (tid < T) tm[tid] = INT_MIN;
+  if (tid == 0) exb = -100000;
+  __syncthreads();
+  if (tid < cnt) atomicMax(&exb, eX[i0 + tid]);
+  // bitonic sort of the 256 values (padding +inf at the end)
+  for (int k = 2; k <= 256; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+      const int p = tid ^ j;
+      if (p > tid) {
+        const double a = v[tid], b = v[p];
+        const bool up = (tid & k) == 0;
+        if ((a > b) == up) {
+          v[tid] = b;
+          v[p] = a;
+        }
+      }
+    }
+  __syncthreads();
+  for (int j = tid; j < n; j += 256) {
+    if (resmax[j] == 0.0) continue;
+    const double x = lam[j];
+    // first index with v[idx] >= x
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (v[mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    // nearest entry at or above x, passing over column j's own value once when j is in I
+    // (a second equal value is a tie: g = 0); the entry below, v[lo - 1] < x, is another
+    int q = lo;
+    if ((j / 256) == I && q < cnt && v[q] == x) ++q;
+    double g = (q < cnt) ? v[q] - x : INFINITY;
+    if (lo > 0) g = fmin(g, x - v[lo - 1]);
+    const int val = (g > 0.0 && g <= DBL_MAX) ? eR[j] - ilogb(g) : (1 << 20);
+    atomicMax(&tm[j / 256], val);
+  }
+  __syncthreads();
+  if (tid < T) {
+    const int val = tm[tid];
+    int d = 2;
+    if (val != INT_MIN && cnt > 0) {
+      const double need = (exb + cx + (double)val) / 7.0;
+      d = min(dmax, max(2, (int)ceil(need) + dextra));
+    }
+    tcut[tid * T + I] = d;
+  }
+}
+
+void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
+                         int n, int T, double cx, int dmax, int dextra, int *tcut,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_cutoffs, dim3(T), dim3(256), 0, s, lam, eX, eR, resmax, n, T, cx,
+                     dmax, dextra, tcut);
+}
+
 // ---------------------------------------------------------------- W epilogue -> E~
 template <int EPT>
 __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
@@ -974,7 +1133,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
     double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
-    int *cpl_pairs, int cpl_cap) {
+    int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -990,13 +1149,15 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
   const double lj = lam[j], ljl = lam_lo[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad;
+  const int T = npad >> 8;
   double ev[EPT], wq[EPT];
-  int eiq[EPT];
+  int eiq[EPT], ndq[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
     wq[q] = 0.0;
     eiq[q] = (i < n) ? eX[i] + ej : 0;
+    ndq[q] = w_ndiag(dcut, tcut, T, ndiag_all, d_min, i, j);
   }
   // as in the V epilogue: the next diagonal is loaded while this one is summed
   int32_t cv[EPT], cn[EPT];
@@ -1016,7 +1177,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
       }
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+    for (int q = 0; q < EPT; ++q)
+      if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
 #pragma unroll
     for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
   }
@@ -1069,21 +1231,22 @@ template <int EPT>
 static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n,
                     int *eE, double *emax, int8_t *Epl, int ke, int *flags, double tau,
-                    int *cpl_count, int *cpl_pairs, int cpl_cap, hipStream_t s) {
+                    int *cpl_count, int *cpl_pairs, int cpl_cap, const int *tcut,
+                    hipStream_t s) {
   hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
                      eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs,
-                     cpl_cap);
+                     cpl_cap, tcut);
 }
 
 void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n, int *eE,
                   double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, double tau,
-                  int *cpl_count, int *cpl_pairs, int cpl_cap) {
+                  int *cpl_count, int *cpl_pairs, int cpl_cap, const int *tcut) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, s);
+  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
+  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
+  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
+  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
 }
 
 // ---------------------------------------------------------------- grouped correction
@@ -1103,7 +1266,8 @@ __device__ __forceinline__ double w_entry(const int32_t *__restrict__ C, size_t 
 __global__ __launch_bounds__(256) void k_group_gram(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ X1, int n,
-    const int *__restrict__ pa, const int *__restrict__ pb, double *gh, double *gl, double *wab) {
+    const int *__restrict__ pa, const int *__restrict__ pb, double *gh, double *gl, double *wab,
+    const int *__restrict__ tcut) {
   __shared__ double scratch[2 * 4];
   const int q = blockIdx.x, a = pa[q], b = pb[q];
   const double *xa = X1 + (size_t)a * n, *xb = X1 + (size_t)b * n;
@@ -1117,7 +1281,7 @@ __global__ __launch_bounds__(256) void k_group_gram(
   if (threadIdx.x == 0) {
     gh[q] = acc.h;
     gl[q] = acc.l;
-    const int nd = dcut ? min(ndiag_all, dcut[b] - d_min + 1) : ndiag_all;
+    const int nd = w_ndiag(dcut, tcut, npad >> 8, ndiag_all, d_min, a, b);
     wab[q] = w_entry(C, (size_t)npad * npad, npad, d_min, nd, eX[a] + eR[b], a, b);
   }
 }
@@ -1125,9 +1289,9 @@ __global__ __launch_bounds__(256) void k_group_gram(
 void launch_group_gram(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                        const int *eX, const int *eR, const double *X1, int n, const int *pa,
                        const int *pb, int npairs, double *gh, double *gl, double *wab,
-                       hipStream_t s) {
+                       hipStream_t s, const int *tcut) {
   hipLaunchKernelGGL(k_group_gram, dim3(npairs), dim3(256), 0, s, C, npad, d_min, ndiag, dcut, eX,
-                     eR, X1, n, pa, pb, gh, gl, wab);
+                     eR, X1, n, pa, pb, gh, gl, wab, tcut);
 }
 
 // One block per group member: its new correction column, from the group's Ritz vectors
@@ -1143,7 +1307,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
     const int *__restrict__ gfirst, const int *__restrict__ gk, const int *__restrict__ gpos,
     const int *__restrict__ gbase, const double *__restrict__ Y, const double *__restrict__ mu,
     const double *__restrict__ mu_lo, int *eE, double *emax, int8_t *__restrict__ Epl, int ke,
-    int *flags) {
+    int *flags, const int *__restrict__ tcut) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   __shared__ int smem[kGroupMax], snd[kGroupMax], ser[kGroupMax];
   __shared__ double sy[kGroupMax];
@@ -1176,8 +1340,11 @@ __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
       } else {
         double num = 0.0;
         const int ei = eX[i];
-        for (int a = 0; a < k; ++a)
-          num += w_entry(C, P, npad, d_min, snd[a], ei + ser[a], i, smem[a]) * sy[a];
+        for (int a = 0; a < k; ++a) {
+          const int nd = tcut ? w_ndiag(dcut, tcut, npad >> 8, ndiag_all, d_min, i, smem[a])
+                              : snd[a];
+          num += w_entry(C, P, npad, d_min, nd, ei + ser[a], i, smem[a]) * sy[a];
+        }
         const double den = dd_diff(muj, mujl, lam[i], lam_lo[i]);
         if (den == 0.0) {
           tie = 1;
@@ -1208,22 +1375,22 @@ static void group_fix_t(const int32_t *C, int npad, int d_min, int ndiag, const 
                         const int *eX, const int *eR, const double *lam, const double *lam_lo, int n, const int *gcol,
                         const int *gfirst, const int *gk, const int *gpos, const int *gbase,
                         const double *Y, const double *mu, const double *mu_lo, int nmem, int *eE, double *emax,
-                        int8_t *Epl, int ke, int *flags, hipStream_t s) {
+                        int8_t *Epl, int ke, int *flags, const int *tcut, hipStream_t s) {
   hipLaunchKernelGGL(k_group_fix<EPT>, dim3(nmem), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag,
                      dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, eE, emax, Epl, ke,
-                     flags);
+                     flags, tcut);
 }
 
 void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                       const int *eX, const int *eR, const double *lam, const double *lam_lo, int n, const int *gcol,
                       const int *gfirst, const int *gk, const int *gpos, const int *gbase,
                       const double *Y, const double *mu, const double *mu_lo, int nmem, int *eE, double *emax,
-                      int8_t *Epl, int ke, int *flags, hipStream_t s) {
+                      int8_t *Epl, int ke, int *flags, hipStream_t s, const int *tcut) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) group_fix_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 2) group_fix_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
-  else if (ept <= 4) group_fix_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
-  else group_fix_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, s);
+  if (ept <= 1) group_fix_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, tcut, s);
+  else if (ept <= 2) group_fix_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, tcut, s);
+  else if (ept <= 4) group_fix_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, tcut, s);
+  else group_fix_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, n, gcol, gfirst, gk, gpos, gbase, Y, mu, mu_lo, nmem, eE, emax, Epl, ke, flags, tcut, s);
 }
 
 // ---------------------------------------------------------------- update X <- X1 + X1 E~

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -62,6 +63,9 @@ struct Work {
   int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
   int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
   int *colmap;   // working column p holds column colmap[p] of the caller's X
+  int *tcut;     // per-tile last diagonal of W (256 x 256 tiles)
+  int *mods;     // moduli of the residue product of V
+  int *tab[3];   // block tables of the V, W and X^(1) E~ products
   // grouped correction: coupling list, pair list, member table, Ritz data
   int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
   double *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
@@ -109,6 +113,10 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.flags = (int *)take(256);
   for (int q = 0; q < 3; ++q) t.dcut[q] = (int *)take(vi);
   t.colmap = (int *)take(vi);
+  t.tcut = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256));
+  t.mods = (int *)take(sizeof(int) * kCrtMax);
+  for (int q = 0; q < 3; ++q)
+    t.tab[q] = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256) * kMaxDiag);
   t.cpl = (int *)take(sizeof(int) * (2 * (size_t)kCouplingsMax + 64));
   const size_t npr = (size_t)kGroupColsMax * kGroupMax;
   t.g_pa = (int *)take(sizeof(int) * npr);
@@ -317,6 +325,37 @@ bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec 
     a1 = sl - (a0 - p0);
   }
   const double a2 = 0.0;
+  // pairs of slots (2t, 2t + 1) and their triple-double constants U_t = Y_t / M_t
+  rec.T = (N + 1) / 2;
+  for (int t = 0; t < rec.T; ++t) {
+    const int qa = 2 * t, qb = 2 * t + 1;
+    long long Mt = mods[qa];
+    if (qb < N) {
+      Mt *= mods[qb];
+      rec.pma[t] = (float)mods[qa];
+      rec.pmb[t] = (float)mods[qb];
+      rec.prmb[t] = 1.0f / (float)mods[qb];
+      rec.pinv[t] = (float)inv_mod(mods[qa] % mods[qb], mods[qb]);
+    }
+    long long rest = 1;   // (M / M_t) mod M_t
+    for (int l = 0; l < N; ++l)
+      if (l != qa && l != qb) rest = rest * (mods[l] % Mt) % Mt;
+    // Y_t = rest^-1 mod M_t (extended Euclid in 64-bit)
+    long long r0 = Mt, r1 = rest % Mt, t0 = 0, t1 = 1;
+    while (r1) {
+      const long long qq = r0 / r1, r2 = r0 - qq * r1, t2 = t0 - qq * t1;
+      r0 = r1;
+      r1 = r2;
+      t0 = t1;
+      t1 = t2;
+    }
+    const double Y = (double)(t0 < 0 ? t0 + Mt : t0), Md = (double)Mt;
+    const double v0 = Y / Md, q0 = std::fma(-v0, Md, Y);
+    const double v1 = q0 / Md, q1 = std::fma(-v1, Md, q0);
+    rec.U[t][0] = v0;
+    rec.U[t][1] = v1;
+    rec.U[t][2] = q1 / Md;
+  }
   rec.M[0] = a0;
   rec.M[1] = a1;
   rec.M[2] = a2;
@@ -371,14 +410,76 @@ bool plan_cutoffs(const std::vector<int> &dcol, int n, int npad, int kl, int kr,
 }
 
 // One launch per group; ev_start is taken by the first dispatch, ev_stop by the last.
+// Block order of the 256 x 256 kernel within one (group, diagonal): a launch-local block
+// id -> (index into the group's row blocks, column block). Blocks go round-robin to the 8
+// XCDs (id mod 8), each with its own L2; with tiles_n a multiple of 8 each XCD owns a band
+// of column blocks and walks it in groups of up to 8 row blocks (the kernel's own order
+// without a table).
+void xcd_tile_order(int bid, int tiles_m, int tiles_n, int &mi, int &nb) {
+  if (tiles_n % 8 == 0) {
+    const int xcd = bid & 7, local = bid >> 3, cb = tiles_n >> 3;
+    const int rg = local / (8 * cb), rem = local - rg * 8 * cb;
+    const int gs = std::min(8, tiles_m - rg * 8);
+    mi = rg * 8 + rem % gs;
+    nb = xcd * cb + rem / gs;
+  } else if (tiles_m % 8 == 0) {
+    const int xcd = bid & 7, local = bid >> 3, rows = tiles_m >> 3;
+    mi = xcd + 8 * (local % rows);
+    nb = local / rows;
+  } else {
+    const int group = bid / (4 * tiles_n), first_m = group * 4;
+    const int gsz = std::min(tiles_m - first_m, 4), inb = bid - group * 4 * tiles_n;
+    mi = first_m + inb % gsz;
+    nb = inb / gsz;
+  }
+}
+
+// One launch per product (npad >= 1024): the blocks of every group and diagonal in one table,
+// the diagonals with the most pairs first, so blocks of all groups share the chip and the
+// launch ends on light blocks (with per-tile cutoffs many blocks exit at once, and one launch
+// per group would end on its few heavy blocks). Uploaded to dev; returns the block count (0:
+// npad < 1024, one launch per group).
+int prepare_table(const CutPlan &plan, int npad, int kl, int kr, std::vector<int> &tab, int *dev,
+                  hipStream_t s) {
+  if (npad < 1024 || !dev) return 0;
+  const int tiles_n = npad / 256;
+  std::vector<std::pair<int, std::pair<int, int>>> combos;   // (-pairs, (group, slot))
+  for (int g = 0; g < (int)plan.groups.size(); ++g)
+    for (int q = 0; q + 2 <= plan.groups[g].first; ++q)
+      combos.push_back({-npairs_of(2 + q, kl, kr), {g, q}});
+  std::stable_sort(combos.begin(), combos.end(),
+                   [](const auto &a, const auto &b) { return a.first < b.first; });
+  tab.clear();
+  for (const auto &c : combos) {
+    const RowBlocks &rb = plan.groups[c.second.first].second;
+    const int q = c.second.second;
+    for (int b = 0; b < rb.count * tiles_n; ++b) {
+      int mi, nb;
+      xcd_tile_order(b, rb.count, tiles_n, mi, nb);
+      tab.push_back(rb.m[mi] | (nb << 8) | (q << 16));
+    }
+  }
+  if (tab.empty()) return 0;
+  if (hipMemcpyAsync(dev, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return -1;
+  return (int)tab.size();
+}
+
 void launch_plan(const CutPlan &plan, const int8_t *Lp, const int8_t *Rp, size_t P, int npad,
                  int kl, int kr, int32_t *C, hipStream_t s, hipEvent_t ev_start,
-                 hipEvent_t ev_stop, int kdim = 0) {
+                 hipEvent_t ev_stop, int kdim = 0, const int *tcut = nullptr,
+                 const int *tab = nullptr, int nblocks = 0) {
+  if (tab && nblocks > 0) {
+    launch_slice_gemm_table(Lp, Rp, P, npad, kl, kr, 2, tab, nblocks, C, s, ev_start, ev_stop,
+                            kdim, tcut);
+    return;
+  }
   const size_t ng = plan.groups.size();
   for (size_t q = 0; q < ng; ++q)
     launch_slice_gemm(Lp, Rp, P, npad, kl, kr, 2, plan.groups[q].first - 1, C,
                       &plan.groups[q].second, s, q == 0 ? ev_start : nullptr,
-                      q + 1 == ng ? ev_stop : nullptr, kdim);
+                      q + 1 == ng ? ev_stop : nullptr, kdim, false, tcut);
 }
 
 // ---------------------------------------------------------------- grouped correction (host)
@@ -1283,7 +1384,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
   std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
   std::vector<double> gaps_nat;
-  std::vector<int> cmap(n), cpl;
+  std::vector<int> cmap(n), cpl, tcut, htab[3];
   int hflags = 0;
   hipEvent_t ev[8];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -1416,9 +1517,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
           ares_n = rec.N;
         }
         launch_residues(w.XP, P, P, wX, w.XRES, s);
-        // one launch: slot q = residue planes q of X^(1) and A
+        // one launch: slot q = residue planes q of X^(1) and A, stored mod m_q as INT8
+        STEP(hipMemcpyAsync(w.mods, rec.m, sizeof(int) * rec.N, hipMemcpyHostToDevice, s));
         launch_slice_gemm(w.XRES, w.ARES, P, npad, rec.N, rec.N, 2, rec.N, w.Cs, nullptr, s,
-                          ev[1], ev[2], 0, true);
+                          ev[1], ev[2], 0, true, nullptr, w.mods);
         launch_epi_v_crt(w.Cs, npad, rec, w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r, w.eR,
                          w.resmax, w.RP, kKrMax, w.flags, s);
         dv = ka1 + kx;
@@ -1432,7 +1534,11 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       dv = plan.dmax;
       pv = plan.pairs_eff;
       lv = (int)plan.groups.size();
-      launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2]);
+      const int nbv = prepare_table(plan, npad, kx, ka, htab[0], w.tab[0], s);
+      if (nbv < 0) return cleanup(REFEIG_E_HIP);
+      if (nbv > 0) lv = 1;
+      launch_plan(plan, w.XP, w.AP, P, npad, kx, ka, w.Cs, s, ev[1], ev[2], 0, nullptr, w.tab[0],
+                  nbv);
       launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
                    w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
     }
@@ -1455,18 +1561,40 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       }
     }
     const int kR = kKrMax, kxw = kx;
-    if (!plan_cutoffs(dcol, n, npad, kR, kxw, std::min(kKrMax + 1, kR + kxw), w.dcut[1], dhost, s,
-                      plan))
+    const int dw_allowed = std::min(kKrMax + 1, kR + kxw);
+    // Per-tile cutoffs (256 x 256 tiles, npad >= 1024): entry (i, j) needs its error within
+    // theta delta |lambda_j - lambda_i|, so tile (column block J, row block I) keeps the
+    // diagonals its columns need against the nearest eigenvalue in row block I (the column's
+    // own gap in its own block). Never more than the column cutoff above.
+    const int *tcut_dev = nullptr;
+    double pw_tiles = -1.0;
+    const int T = npad / 256;
+    if (npad >= 1024) {
+      // on the device (nothing for the host to wait for); the pair count of the report is
+      // read back after the iteration
+      const double cx = 7 + std::log2(1.5 * kx) + lsqn - std::log2(theta * delta_k);
+      launch_tile_cutoffs(w.lam, w.eX, w.eR, w.resmax, n, T, cx, dw_allowed, o.d_extra, w.tcut,
+                          s);
+      STEP(hipGetLastError());
+      tcut_dev = w.tcut;
+      pw_tiles = 0.0;
+    }
+    if (!plan_cutoffs(dcol, n, npad, kR, kxw, dw_allowed, w.dcut[1], dhost, s, plan))
       return cleanup(REFEIG_E_HIP);
     const int dw = plan.dmax;
-    const double pw = plan.pairs_eff;
-    const int lw = (int)plan.groups.size();
-    launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4]);
+    const double pw = pw_tiles >= 0.0 ? pw_tiles : plan.pairs_eff;
+    const std::vector<int> whost = dhost;   // per-column last diagonal of the W launches
+    int lw = (int)plan.groups.size();
+    const int nbw = prepare_table(plan, npad, kR, kxw, htab[1], w.tab[1], s);
+    if (nbw < 0) return cleanup(REFEIG_E_HIP);
+    if (nbw > 0) lw = 1;
+    launch_plan(plan, w.RP, w.XP, P, npad, kR, kxw, w.Cs, s, ev[3], ev[4], 0, tcut_dev, w.tab[1],
+                nbw);
     const bool grouping = o.group_tau > 0.0;
     if (grouping) STEP(hipMemsetAsync(w.cpl, 0, sizeof(int), s));
     launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n, w.eE,
                  w.emax, w.EP, kKeMax, w.flags, s, o.group_tau, grouping ? w.cpl : nullptr,
-                 w.cpl + 64, kCouplingsMax);
+                 w.cpl + 64, kCouplingsMax, tcut_dev);
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1535,7 +1663,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         STEP(hipMemcpyAsync(w.g_pa, pa.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(w.g_pb, pb.data(), sizeof(int) * npr, hipMemcpyHostToDevice, s));
         launch_group_gram(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.X1, n, w.g_pa, w.g_pb,
-                          npr, w.g_gh, w.g_gl, w.g_w, s);
+                          npr, w.g_gh, w.g_gl, w.g_w, s, tcut_dev);
         std::vector<double> gh(npr), gl(npr), gw(npr), Yh(npr), muh(nmem), mul(nmem), laml(n);
         STEP(hipMemcpyAsync(laml.data(), w.lam_lo, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(gh.data(), w.g_gh, sizeof(double) * npr, hipMemcpyDeviceToHost, s));
@@ -1566,7 +1694,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         STEP(hipMemcpyAsync(w.g_base, gbase.data(), sizeof(int) * nmem, hipMemcpyHostToDevice, s));
         launch_group_fix(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, n,
                          w.g_col, w.g_first, w.g_k, w.g_pos, w.g_base, w.g_Y, w.g_mu, w.g_mul,
-                         nmem, w.eE, w.emax, w.EP, kKeMax, w.flags, s);
+                         nmem, w.eE, w.emax, w.EP, kKeMax, w.flags, s, tcut_dev);
         STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
         STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1592,13 +1720,28 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       return cleanup(REFEIG_E_HIP);
     const int du = plan.dmax;
     const double pu = plan.pairs_eff;
-    const int lu = (int)plan.groups.size();
-    launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6]);
+    int lu = (int)plan.groups.size();
+    const int nbu = prepare_table(plan, npad, kE, kxu, htab[2], w.tab[2], s);
+    if (nbu < 0) return cleanup(REFEIG_E_HIP);
+    if (nbu > 0) lu = 1;
+    launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6], 0, nullptr, w.tab[2],
+                nbu);
     launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s, w.colmap);
     launch_scatter(w.lam, w.colmap, n, D, s);
     STEP(hipEventRecord(ev[7], s));
     STEP(hipGetLastError());
     STEP(hipEventSynchronize(ev[7]));
+    double pw_it = pw;
+    if (tcut_dev) {   // W pairs actually computed under the per-tile cutoffs
+      tcut.resize((size_t)T * T);
+      STEP(hipMemcpy(tcut.data(), w.tcut, sizeof(int) * T * T, hipMemcpyDeviceToHost));
+      pw_it = 0.0;
+      for (int q = 0; q < T * T; ++q) {
+        const int dl = std::min(tcut[q], whost[(size_t)(q / T) * 256]);   // the block's launch
+        for (int d = 2; d <= dl; ++d) pw_it += npairs_of(d, kR, kxw);
+      }
+      pw_it /= (double)T * T;
+    }
     float t_it = 0, g1 = 0, g2 = 0, g3 = 0;
     (void)hipEventElapsedTime(&t_it, ev[0], ev[7]);
     (void)hipEventElapsedTime(&g1, ev[1], ev[2]);
@@ -1610,15 +1753,15 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->dv[it] = dv;
       rep->dw[it] = dw;
       rep->du[it] = du;
-      rep->pairs[it] = (int)std::lround(pv + pw + pu);
+      rep->pairs[it] = (int)std::lround(pv + pw_it + pu);
       rep->eps[it] = eps;
       rep->ms_iter[it] = t_it;
       rep->ms_gemm[it] = g1 + g2 + g3;
       rep->pairs_p[it][0] = (int)std::lround(pv);
-      rep->pairs_p[it][1] = (int)std::lround(pw);
+      rep->pairs_p[it][1] = (int)std::lround(pw_it);
       rep->pairs_p[it][2] = (int)std::lround(pu);
       rep->pairs_f[it][0] = pv;
-      rep->pairs_f[it][1] = pw;
+      rep->pairs_f[it][1] = pw_it;
       rep->pairs_f[it][2] = pu;
       rep->ms_p[it][0] = g1;
       rep->ms_p[it][1] = g2;
@@ -1636,7 +1779,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       fprintf(stderr,
               "refeig it %d: beta %d kx %d dv %d dw %d du %d pairs %d eps %.3e gap %.3e "
               "ms %.2f (gemm %.2f)\n",
-              it + 1, beta, kx, dv, dw, du, (int)std::lround(pv + pw + pu), eps, gmin, t_it,
+              it + 1, beta, kx, dv, dw, du, (int)std::lround(pv + pw_it + pu), eps, gmin, t_it,
               g1 + g2 + g3);
     for (int p = 0; p < n; ++p) lam_prev[cmap[p]] = lam[p];
     if (o.fixed_iters > 0) {
@@ -1693,8 +1836,8 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
 }
 
 int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
-                         double *u, double *M) {
-  if (npad < 1 || ka1 < 1 || kx < 1 || !N || !moduli || !wA || !wX || !u || !M)
+                         double *U, double *M) {
+  if (npad < 1 || ka1 < 1 || kx < 1 || !N || !moduli || !wA || !wX || !U || !M)
     return REFEIG_E_ARG;
   ResWeights a, x;
   CrtRec rec;
@@ -1706,8 +1849,9 @@ int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA
       wA[q * kCrtPlanes + t] = a.w[q][t];
       wX[q * kCrtPlanes + t] = x.w[q][t];
     }
-    for (int c = 0; c < 3; ++c) u[3 * q + c] = rec.u[q][c];
   }
+  for (int t = 0; t < rec.T; ++t)
+    for (int c = 0; c < 3; ++c) U[3 * t + c] = rec.U[t][c];
   for (int c = 0; c < 3; ++c) M[c] = rec.M[c];
   return REFEIG_OK;
 }

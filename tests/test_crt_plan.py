@@ -3,10 +3,11 @@
 * the plan of refeig_host_crt_plan against exact integer arithmetic: odd, pairwise coprime
   moduli <= 255 whose product exceeds 4 npad 128^(ka1 + kx); digit weights congruent to the
   powers of 128 and in the symmetric INT8 range; y_q u_q-constants that invert M / m_q; M;
-* the reconstruction the V epilogue performs, ported operation for operation (Dekker products
-  stand in for fma, both exact), on random integer products P = sum_k a_k x_k of the planned
-  size (|P| from 2^60 to the bound): the rebuilt value is within 2^-115 M of P, far inside the
-  2^-108 M that the tightest column of the n = 8192 workload needs.
+* the reconstruction that the GEMM's store (each slot mod m_q) and the V epilogue (pairs of
+  slots combined in FP32, triple-double sum) perform, ported operation for operation (Dekker
+  products stand in for fma, both exact), on random integer products P = sum_k a_k x_k of the
+  planned size (|P| from 2^60 to the bound): the rebuilt value is within 2^-115 M of P, far
+  inside the 2^-108 M that the tightest column of the n = 8192 workload needs.
 """
 import math
 import random
@@ -34,9 +35,12 @@ def test_plan_constants_exact(npad, ka1, kx):
         for t in range(kx):
             w = int(p["wX"][q][t])
             assert -127 <= w <= 127 and (w - pow(128, kx - 1 - t, m)) % m == 0
-        y = pow(M // m, -1, m)
-        uq = sum(Fraction(float(v)) for v in p["u"][q])
-        assert abs(uq - Fraction(y, m)) < Fraction(1, 2 ** 150)
+    for t, U in enumerate(p["U"]):
+        qs = [q for q in (2 * t, 2 * t + 1) if q < len(ms)]
+        Mt = math.prod(ms[q] for q in qs)
+        Y = pow(M // Mt, -1, Mt)
+        Ut = sum(Fraction(float(v)) for v in U)
+        assert abs(Ut - Fraction(Y, Mt)) < Fraction(1, 2 ** 150)
     Mdd = Fraction(float(p["M"][0])) + Fraction(float(p["M"][1]))
     assert abs(Mdd - M) / M < Fraction(1, 2 ** 100)
 
@@ -65,12 +69,25 @@ def _two_sum(a, b):
     return s, (a - (s - z)) + (b - z)
 
 
+def _f32(x):
+    return float(np.float32(x))
+
+
 def _rebuild(cs, ms, U, M):
-    """The V epilogue's reconstruction for one element (scale 2^0)."""
+    """The reconstruction for one element (scale 2^0): the GEMM stores each slot mod m_q
+    (symmetric); the V epilogue combines slots 2t, 2t + 1 into a residue mod m_2t m_2t+1 in
+    FP32 and sums the terms in triple-double."""
+    r = [c - m * round(c * (1.0 / m)) for c, m in zip(cs, ms)]
     s0 = s1 = s2 = 0.0
-    for c, m, u in zip(cs, ms, U):
-        c = float(c)
-        rq = c - m * round(c * (1.0 / m))
+    for t, u in enumerate(U):
+        qa, qb = 2 * t, 2 * t + 1
+        rq = float(r[qa])
+        if qb < len(ms):
+            inv = _f32(pow(ms[qa] % ms[qb], -1, ms[qb]))
+            mb, rmb = _f32(ms[qb]), _f32(np.float32(1.0) / np.float32(ms[qb]))
+            d = _f32(np.float32(r[qb] - r[qa]) * np.float32(inv))
+            tt = _f32(np.float32(d) - np.float32(mb) * np.float32(np.rint(np.float32(d) * np.float32(rmb))))
+            rq = float(r[qa]) + float(ms[qa]) * tt
         p0, e0 = _two_prod(rq, float(u[0]))
         p1, e1 = _two_prod(rq, float(u[1]))
         p2 = rq * float(u[2])
@@ -103,10 +120,11 @@ def _rebuild(cs, ms, U, M):
     return s, l2 - (s - h2)
 
 
-def test_reconstruction_error_bound():
-    npad, ka1, kx, K = 8192, 15, 8, 48
+@pytest.mark.parametrize("npad,ka1,kx", [(8192, 15, 8), (1024, 10, 6)])
+def test_reconstruction_error_bound(npad, ka1, kx):
+    K = 48
     p = rb.host_crt_plan(npad, ka1, kx)
-    ms, U, M = p["moduli"], p["u"], p["M"]
+    ms, U, M = p["moduli"], p["U"], p["M"]
     Mx = math.prod(ms)
     rng = random.Random(7)
 
