@@ -21,8 +21,10 @@ struct DiagOrder {
 //   c[j] = ceil(log2 max_i |M_ij|)      (0 for a zero column),
 //   mx[j] = max_i |M_ij|.  Columns cols..cols_pad-1 get zeros.
 // colmap (device, may be null): column j of the result is column colmap[j] of M.
+// ss (optional): sum of squares of each column (plain FP64).
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
-                     double *mx, int *flags, hipStream_t s, const int *colmap = nullptr);
+                     double *mx, int *flags, hipStream_t s, const int *colmap = nullptr,
+                     double *ss = nullptr);
 
 // The largest number of nonzeros in a column of the symmetric A (= in a row): atomicMax
 // into *kmax, which the caller zeroes.

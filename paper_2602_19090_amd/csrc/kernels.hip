@@ -170,7 +170,8 @@ __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
 // ---------------------------------------------------------------- column statistics
 __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, int ld, int rows,
                                                   int cols, int *e, int *c, double *mx,
-                                                  int *flags, const int *__restrict__ colmap) {
+                                                  int *flags, const int *__restrict__ colmap,
+                                                  double *ss) {
   __shared__ double scratch[4];
   const int j = blockIdx.x;
   if (j >= cols) {
@@ -178,18 +179,30 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, 
       e[j] = 0;
       c[j] = 0;
       if (mx) mx[j] = 0.0;
+      if (ss) ss[j] = 0.0;
     }
     return;
   }
   const double *col = M + (size_t)(colmap ? colmap[j] : j) * ld;
-  double m = 0.0;
+  double m = 0.0, q = 0.0;
   int bad = 0;
   for (int i = threadIdx.x; i < rows; i += 256) {
     double a = fabs(col[i]);
     if (!(a <= DBL_MAX)) bad = 1;
-    else m = fmax(m, a);
+    else {
+      m = fmax(m, a);
+      q += a * a;
+    }
   }
   if (bad) atomicOr(flags, FLAG_NONFINITE);
+  if (ss) {   // sum of squares (for a product bound; plain FP64 is enough)
+    q = wave_sum(q);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) ss[j] = (scratch[0] + scratch[1]) + (scratch[2] + scratch[3]);
+    __syncthreads();
+  }
   m = block_max<256>(m, scratch);
   if (threadIdx.x == 0) {
     int ee = exp_above(m);
@@ -222,9 +235,9 @@ void launch_row_nonzeros(const double *A, int lda, int n, int *kmax, hipStream_t
 }
 
 void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, int *e, int *c,
-                     double *mx, int *flags, hipStream_t s, const int *colmap) {
+                     double *mx, int *flags, hipStream_t s, const int *colmap, double *ss) {
   hipLaunchKernelGGL(k_colstats, dim3(cols_pad), dim3(256), 0, s, M, ld, rows, cols, e, c, mx,
-                     flags, colmap);
+                     flags, colmap, ss);
 }
 
 // ---------------------------------------------------------------- digit planes

@@ -65,6 +65,7 @@ struct Work {
   int *colmap;   // working column p holds column colmap[p] of the caller's X
   int *tcut;     // per-tile last diagonal of W (256 x 256 tiles)
   int *mods;     // moduli of the residue product of V
+  double *ssA, *ssX;   // column sums of squares of A and X (the residue product's bound)
   int *tab[3];   // block tables of the V, W and X^(1) E~ products
   // grouped correction: coupling list, pair list, member table, Ritz data
   int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
@@ -115,6 +116,8 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.colmap = (int *)take(vi);
   t.tcut = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256));
   t.mods = (int *)take(sizeof(int) * kCrtMax);
+  t.ssA = (double *)take(vd);
+  t.ssX = (double *)take(vd);
   for (int q = 0; q < 3; ++q)
     t.tab[q] = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256) * kMaxDiag);
   t.cpl = (int *)take(sizeof(int) * (2 * (size_t)kCouplingsMax + 64));
@@ -272,12 +275,18 @@ int inv_mod(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1)
 }
 
 // Plans V = P 2^(eA_i + eX_j - 7 (ka1 + kx)) with P = Ã X̃ (ka1 digits of A, kx of X^(1),
-// reduction length npad): enough moduli that prod m_q > 4 npad 128^(ka1 + kx) (so
+// reduction length npad): enough moduli that prod m_q > 4 2^hbits 128^(ka1 + kx) (so
 // |P| < M / 4), the digit weights of both residue passes and the triple-double constants.
 // False when more than kCrtMax moduli would be needed.
-bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec &rec) {
+// hbits (optional): log2 of a bound on ||a_i|| 2^-eA_i times ||x_j|| 2^-eX_j over all rows
+// and columns (Cauchy-Schwarz: |P_ij| <= ||Ã_i|| ||X̃_j|| <= 2^(hbits + 7 (ka1 + kx)));
+// log2(npad) (the bound for any input) when absent or larger.
+bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec &rec,
+              double hbits = -1.0) {
   const std::vector<int> &mods = crt_moduli();
-  const double need = 2.0 + std::log2((double)npad) + 7.0 * (ka1 + kx);
+  const double hb = (hbits >= 0.0 && hbits < std::log2((double)npad)) ? hbits
+                                                                      : std::log2((double)npad);
+  const double need = 2.0 + hb + 7.0 * (ka1 + kx);
   double bits = 0.0;
   int N = 0;
   while (N < (int)mods.size() && bits <= need) bits += std::log2((double)mods[N++]);
@@ -1416,10 +1425,19 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   STEP(hipMemcpyAsync(lam_prev.data(), D, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   STEP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
   // A: column exponents (= row exponents, A is symmetric) and its digit planes, once
-  launch_colstats(A, lda, n, n, npad, w.eA, w.cA, w.mxA, w.flags, s);
+  launch_colstats(A, lda, n, n, npad, w.eA, w.cA, w.mxA, w.flags, s, nullptr, crt ? w.ssA : nullptr);
   STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
   STEP(hipMemcpyAsync(eA.data(), w.eA, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
+  std::vector<double> ssA(crt ? npad : 0), mxAh(crt ? npad : 0), ssX(crt ? npad : 0);
+  if (crt) {
+    STEP(hipMemcpyAsync(ssA.data(), w.ssA, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    STEP(hipMemcpyAsync(mxAh.data(), w.mxA, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+  }
   STEP(hipStreamSynchronize(s));
+  // max_i ||a_i|| 2^-eA_i (A symmetric: rows = columns) for the residue product's bound
+  double hA = 0.0;
+  for (int i = 0; crt && i < n; ++i)
+    if (mxAh[i] != 0.0) hA = std::max(hA, std::ldexp(std::sqrt(ssA[i]), -eA[i]));
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(lam_prev[i])) return cleanup(REFEIG_E_NONFINITE);
   if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
@@ -1447,10 +1465,12 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     working_order(lam_prev, gaps_nat, cmap);
     STEP(hipMemcpyAsync(w.colmap, cmap.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     // ---- beta and kx from the previous eigenvalue estimates and column maxima of X
-    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap);
+    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap,
+                    crt ? w.ssX : nullptr);
     STEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
+    if (crt) STEP(hipMemcpyAsync(ssX.data(), w.ssX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     STEP(hipStreamSynchronize(s));
     if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
@@ -1508,7 +1528,13 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       ka1 = std::min(ka1, ka_max);
       ResWeights wA, wX;
       CrtRec rec;
-      if (crt_plan(npad, ka1, kx, wA, wX, rec)) {
+      // Cauchy-Schwarz headroom: max ||x_j|| 2^-eX_j (X^(1) is X truncated, never larger)
+      double hX = 0.0;
+      for (int j = 0; j < n; ++j)
+        if (mxX[j] != 0.0) hX = std::max(hX, std::ldexp(std::sqrt(ssX[j]), -eX[j]));
+      const double hbits =
+          (hA > 0.0 && hX > 0.0) ? std::log2(hA * hX * (1.0 + 1e-6)) : -1.0;
+      if (crt_plan(npad, ka1, kx, wA, wX, rec, hbits)) {
         by_res = true;
         // A's residues depend only on ka1 and the moduli: reused while they repeat
         if (ka1 != ares_ka || rec.N != ares_n) {
