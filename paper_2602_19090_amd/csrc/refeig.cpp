@@ -535,7 +535,6 @@ inline HD hd_sqrt(HD a) {
   HD r = hd_sub(a, hd_mul(hd(x), hd(x)));
   return hd_norm(x, r.h / (2.0 * x));
 }
-inline bool hd_less(HD a, HD b) { return a.h < b.h || (a.h == b.h && a.l < b.l); }
 
 // Ritz pairs of one group: G (k x k, double-word Gram matrix of the members' columns),
 // Wg (k x k, w_ab), lamg (current double-word eigenvalue estimates). T = W + G diag(lambda),
@@ -828,7 +827,6 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
   const size_t nn = (size_t)n * n;
   const double delta_int = target / o.delta_safety;
   const double xi = xi_of(o, n);
-  const double lsqn = 0.5 * std::log2((double)n);
   const double lgrowth_a = lgrowth_of(o, n);   // error growth of products of A's planes
   const int alpha = (int)std::ceil((53.0 + std::log2((double)n)) / 2.0);
   const int b = 53 - alpha;  // bits per FP64 slice
@@ -1029,7 +1027,7 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
   HermWork w;
   carve_herm(n, ka_max, (char *)work, &w);
   const int npad = w.npad;
-  const size_t P = w.P, P2 = 2 * w.P;
+  const size_t P2 = 2 * w.P;
   const int K2 = 2 * npad;
   const double delta = target / o.delta_safety;
   const double xi = xi_of(o, n);
