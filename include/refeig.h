@@ -60,7 +60,9 @@ typedef struct {
     int stop_rule;       /* stop after an iteration whose correction eps = max|E~|
                             satisfies eps^2 max|lambda| / (xi gap) <= target/delta_safety,
                             the post-update error that eq. (assume2) of Sec. 3.2
-                            predicts, or eps <= target/delta_safety.
+                            predicts, or eps <= target/delta_safety. An eps that
+                            no longer halves is the products' noise floor: status
+                            OK when eps <= target, else REFEIG_NOT_CONVERGED.
                             0: xi as below (default); 1: strict, xi = 1              */
     double delta_safety; /* internal delta = target / delta_safety (default 8)          */
     double xi;           /* xi of eq. (assume2); <= 0 means n, the Sec. 4.1 choice        */

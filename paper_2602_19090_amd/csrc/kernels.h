@@ -81,8 +81,8 @@ int gemm_tile_rows(int npad);
 // cx = 7 + log2(1.5 kx) + log2(sqrt n) - log2(theta delta). T <= kMaxTileSide.
 constexpr int kMaxTileSide = 32;
 void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
-                         int n, int T, double cx, int dmax, int dextra, int *tcut,
-                         hipStream_t s);
+                         int n, int T, double cx, int dmax, int dextra, const double *tcol,
+                         const double *gcol, int *tcut, hipStream_t s);
 
 // V epilogue fused with the column pass of Algorithm 1 (column j per block):
 //   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),

@@ -1070,11 +1070,16 @@ __device__ __forceinline__ int w_ndiag(const int *__restrict__ dcut, const int *
 // column block J of eR_j - floor(log2 g); tcut[J T + I] = the last diagonal that keeps the
 // tile's W error within theta delta g: ceil((max_{i in I} eX_i + cx + that) / 7), in
 // [2, dmax] (+ dextra). Columns with a zero residual (mask[j] == 0) need nothing.
+// With tcol and gcol (per column, optional), g is replaced by max(gcol_j, tcol_j g): a column
+// whose own gap gcol_j is small takes its far tiles tcol_j <= 1 times tighter, never tighter
+// than its own gap (the column-wide rule).
 __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__ lam,
                                                       const int *__restrict__ eX,
                                                       const int *__restrict__ eR,
                                                       const double *__restrict__ resmax, int n,
                                                       int T, double cx, int dmax, int dextra,
+                                                      const double *__restrict__ tcol,
+                                                      const double *__restrict__ gcol,
                                                       int *__restrict__ tcut) {
   __shared__ double v[256];
   __shared__ int tm[kMaxTileSide];
@@ -1117,6 +1122,7 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
     if ((j / 256) == I && q < cnt && v[q] == x) ++q;
     double g = (q < cnt) ? v[q] - x : INFINITY;
     if (lo > 0) g = fmin(g, x - v[lo - 1]);
+    if (tcol && g > 0.0 && g <= DBL_MAX) g = fmax(gcol[j], tcol[j] * g);
     const int val = (g > 0.0 && g <= DBL_MAX) ? eR[j] - ilogb(g) : (1 << 20);
     atomicMax(&tm[j / 256], val);
   }
@@ -1133,10 +1139,10 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
 }
 
 void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
-                         int n, int T, double cx, int dmax, int dextra, int *tcut,
-                         hipStream_t s) {
+                         int n, int T, double cx, int dmax, int dextra, const double *tcol,
+                         const double *gcol, int *tcut, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_cutoffs, dim3(T), dim3(256), 0, s, lam, eX, eR, resmax, n, T, cx,
-                     dmax, dextra, tcut);
+                     dmax, dextra, tcol, gcol, tcut);
 }
 
 // ---------------------------------------------------------------- W epilogue -> E~

@@ -66,6 +66,7 @@ struct Work {
   int *tcut;     // per-tile last diagonal of W (256 x 256 tiles)
   int *mods;     // moduli of the residue product of V
   double *ssA, *ssX;   // column sums of squares of A and X (the residue product's bound)
+  double *wtol;        // per column: W tile tightening t_j, then the column's own gap g_j
   int *tab[3];   // block tables of the V, W and X^(1) E~ products
   // grouped correction: coupling list, pair list, member table, Ritz data
   int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
@@ -118,6 +119,7 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.mods = (int *)take(sizeof(int) * kCrtMax);
   t.ssA = (double *)take(vd);
   t.ssX = (double *)take(vd);
+  t.wtol = (double *)take(2 * vd);
   for (int q = 0; q < 3; ++q)
     t.tab[q] = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256) * kMaxDiag);
   t.cpl = (int *)take(sizeof(int) * (2 * (size_t)kCouplingsMax + 64));
@@ -988,7 +990,9 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
     const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
     if (eps <= delta_int || eps * eps * lmax / (xi_stop * gmin) <= delta_int) break;
     if (it >= 1 && eps > 0.5 * eps_prev) {
-      status = REFEIG_NOT_CONVERGED;
+      // no quadratic decrease: the floor that the products' truncation leaves. When that
+      // floor is within the target the iterate has converged to it, else it has stagnated.
+      if (eps > target) status = REFEIG_NOT_CONVERGED;
       break;
     }
     eps_prev = eps;
@@ -1229,7 +1233,9 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
     const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
     if (eps <= delta || eps * eps * lmax / (xi_stop * gmin) <= delta) break;
     if (it >= 1 && eps > 0.5 * eps_prev) {
-      status = REFEIG_NOT_CONVERGED;
+      // no quadratic decrease: the floor that the products' truncation leaves. When that
+      // floor is within the target the iterate has converged to it, else it has stagnated.
+      if (eps > target) status = REFEIG_NOT_CONVERGED;
       break;
     }
     eps_prev = eps;
@@ -1389,7 +1395,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
 
   int status = REFEIG_OK;
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
-  std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps;
+  std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps,
+      wtolh(2 * (size_t)npad, 0.0);
   std::vector<double> gaps_nat;
   std::vector<int> cmap(n), cpl, tcut, htab[3];
   int hflags = 0;
@@ -1584,6 +1591,18 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
+    // Noise stability: the W tiles far from column j's eigenvalue, and the product X^(1) E~,
+    // leave an error of about nu_j = theta delta t_j along every eigenvector in column j of
+    // the new X; the next iteration turns it into about nu_j^2 max|lambda| / g_j (the
+    // amplification that bounds the X^(1) cut of Sec. 4.1), kept at a quarter of the
+    // internal delta. t_j = 1 unless g_j is tiny next to max|lambda| and delta is loose.
+    bool tight = false;
+    for (int j = 0; j < n; ++j) {
+      const double t = std::sqrt(delta_int * gaps[j] / (4.0 * lmax)) / (theta * delta_k);
+      wtolh[j] = std::min(1.0, t);
+      wtolh[npad + j] = gaps[j];
+      tight = tight || t < 1.0;
+    }
     const int kR = kKrMax, kxw = kx;
     const int dw_allowed = std::min(kKrMax + 1, kR + kxw);
     // Per-tile cutoffs (256 x 256 tiles, npad >= 1024): entry (i, j) needs its error within
@@ -1597,8 +1616,11 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       // on the device (nothing for the host to wait for); the pair count of the report is
       // read back after the iteration
       const double cx = 7 + std::log2(1.5 * kx) + lsqn - std::log2(theta * delta_k);
-      launch_tile_cutoffs(w.lam, w.eX, w.eR, w.resmax, n, T, cx, dw_allowed, o.d_extra, w.tcut,
-                          s);
+      if (tight)
+        STEP(hipMemcpyAsync(w.wtol, wtolh.data(), sizeof(double) * 2 * npad,
+                            hipMemcpyHostToDevice, s));
+      launch_tile_cutoffs(w.lam, w.eX, w.eR, w.resmax, n, T, cx, dw_allowed, o.d_extra,
+                          tight ? w.wtol : nullptr, tight ? w.wtol + npad : nullptr, w.tcut, s);
       STEP(hipGetLastError());
       tcut_dev = w.tcut;
       pw_tiles = 0.0;
@@ -1735,7 +1757,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (emax[j] == 0.0) continue;
-        dcol[j] = std::max(2, (int)std::ceil((c0 + eE[j]) / 7.0) + o.d_extra);
+        const double need = (c0 + eE[j] - std::log2(wtolh[j])) / 7.0;
+        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
     const int kE = kKeMax, kxu = kx;
@@ -1817,7 +1840,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const double xi_stop = (o.stop_rule == 1) ? 1.0 : xi;
     if (eps <= delta_int || eps * eps * lmax / (xi_stop * gmin) <= delta_int) break;
     if (it >= 1 && eps > 0.5 * eps_prev) {
-      status = REFEIG_NOT_CONVERGED;
+      // no quadratic decrease: the floor that the products' truncation leaves. When that
+      // floor is within the target the iterate has converged to it, else it has stagnated.
+      if (eps > target) status = REFEIG_NOT_CONVERGED;
       break;
     }
     eps_prev = eps;
