@@ -18,7 +18,11 @@ Output: one JSON line. value = FP64-equivalent TFLOP/s = 6 n^3 K / time
 (three n x n x n products per iteration, the algorithmic work of Algorithm 1);
 ms_per_step = time to target. roofline: the INT8 slice GEMM kernel against the
 dense INT8 MFMA peak (5.0 POP/s); cpu_baseline: the double-double oracle on a
-bounded sample of the same workload.
+bounded sample of the same workload. Further legs in the same line: the FP64
+plain form (the comparison the metric names), V by the paper's slice products
+(A/B against residues), and the precision sweep (targets 1e-8 and 1e-11 on the
+same matrix, each form timed like the main leg), and the FP8 ablation (4-bit
+digits in FP8 E4M3 operands against 7-bit INT8 digits).
 """
 from __future__ import annotations
 
@@ -217,6 +221,67 @@ def herm_leg(n, target, args):
             "status": rb.strerror(st)}
 
 
+def _pairs_upto(D, kl, kr):
+    """Digit pairs (s, t), 1 <= s <= kl, 1 <= t <= kr, with s + t <= D."""
+    return sum(max(0, min(kl, d - 1) - max(1, d - kr) + 1) for d in range(2, D + 1))
+
+
+def fp8_leg(rb, A, X0, D0):
+    """FP8 ablation: 4-bit digits in FP8 E4M3 operands against 7-bit INT8 digits. Measured: the
+    time per n x n x n pair product of both slice GEMMs at n = 8192 (diagonals 2..10 of 9 x 9
+    random digit planes, 45 pairs, one launch each). Projected: the V product of the slice
+    form at the 1e-8 target (last iteration of a 4-iteration solve) with every INT8 digit
+    count scaled to 4-bit digits of the same bits (A, X^(1) and the kept diagonals), priced
+    at the measured FP8 pair time."""
+    import math
+    import torch
+    n, k = A.shape[0], 9
+    g = torch.Generator(device="cuda").manual_seed(19090)
+    L = torch.randint(-127, 128, (k, n, n), dtype=torch.int8, device="cuda", generator=g)
+    R = torch.randint(-127, 128, (k, n, n), dtype=torch.int8, device="cuda", generator=g)
+    L4 = torch.randint(-15, 16, (k, n, n), dtype=torch.int8, device="cuda", generator=g)
+    st1, L8 = rb.digits_to_e4m3(L4)
+    R4 = torch.randint(-15, 16, (k, n, n), dtype=torch.int8, device="cuda", generator=g)
+    st2, R8 = rb.digits_to_e4m3(R4)
+    del L4, R4
+    assert st1 == st2 == rb.REFEIG_OK
+    npair = _pairs_upto(k + 1, k, k)
+
+    def timed(fn):
+        ms = []
+        for rep in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            st, C = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            assert st == rb.REFEIG_OK, rb.strerror(st)
+            del C
+            if rep:
+                ms.append(e0.elapsed_time(e1))
+        return sum(ms) / len(ms)
+    t8 = timed(lambda: rb.slice_gemm(L, R, n, k, k, 2, k)) / npair
+    tf = timed(lambda: rb.slice_gemm_fp8(L8, R8, n, k, k, 2, k)) / npair
+    del L, R, L8, R8
+    torch.cuda.empty_cache()
+    X, D = X0.clone(), D0.clone()
+    st, rep = refine(rb, A, X, D, 1e-8, rb.default_opts(fixed_iters=4, vmode=0))
+    r = rep.as_dict()
+    it = r["iters"] - 1
+    dv, kx, ka = r["dv"][it], r["kx"][it], rb.default_opts().ka_max
+    p7 = _pairs_upto(dv, ka, kx)
+    p4 = _pairs_upto(math.ceil(7 * dv / 4), math.ceil(7 * ka / 4), math.ceil(7 * kx / 4))
+    v_ms = r["ms_p"][it][0]
+    tops = lambda t: 2.0 * n ** 3 / (t * 1e-3) / 1e12
+    return {"pair_ms_int8": t8, "pair_ms_fp8_e4m3": tf, "int8_tops": tops(t8),
+            "fp8_tflops": tops(tf), "digit_bits": {"int8": 7, "fp8_e4m3": 4},
+            "v_product_1e-8": {"dv": dv, "kx": kx, "ka": ka, "int8_pairs_full_diagonals": p7,
+                               "fp8_pairs_full_diagonals": p4, "int8_pairs_kept": r["pairs_f"][it][0],
+                               "int8_ms_measured": v_ms,
+                               "fp8_ms_projected": v_ms * (p4 / p7) * (tf / t8)},
+            "status": rb.strerror(st)}
+
+
 def config4_leg(count):
     """Many small matrices (config 4): one batched call, exactly 3 iterations each, inputs
     resident on the device; matrices/s and FP64-equivalent TFLOP/s (6 n^3 per iteration)."""
@@ -366,6 +431,12 @@ def main():
     ap.add_argument("--schedule", action="store_true",
                     help="also time the solve with the adaptive accuracy schedule (an extension "
                          "beyond the paper's method)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the precision sweep: targets 1e-8 and 1e-11 besides the main "
+                         "leg's, V by residues and by slices, each timed like the main leg")
+    ap.add_argument("--no-fp8", action="store_true",
+                    help="skip the FP8 ablation: E4M3 4-bit digit products against INT8 7-bit "
+                         "ones (measured pair-product times, projected V product at 1e-8)")
     ap.add_argument("--no-vslices", action="store_true",
                     help="skip the A/B leg that forms V = A X^(1) by the paper's slice products "
                          "(vmode 0) instead of by residues (the default, vmode 1)")
@@ -521,6 +592,10 @@ def main():
             plain = {"ms_to_target": None, "iters": None, "status": "did not reach the target",
                      "fwd_err_per_iter": perrs or None}
 
+    fp8 = None
+    if not args.no_fp8 and n >= 1024:
+        log("FP8 ablation: pair products of E4M3 and INT8 digits")
+        fp8 = fp8_leg(rb, A, X0, D0)
     batch = config4_leg(args.config4) if args.config4 > 0 else None
     serve = serve_leg([float(r) for r in args.serve.split(",")], args.serve_requests) \
         if args.serve else None
@@ -563,6 +638,15 @@ def main():
         if args.group_tau > 0.0:
             sched["with_group_tau"] = solve_leg(rb, A, X0, D0, target, golden, args, ms_step,
                                                 schedule=1, group_tau=args.group_tau)
+    sweep = None
+    if not args.no_sweep and golden is not None:
+        sweep = []
+        for tgt in (t for t in (1e-8, 1e-11) if t != target):
+            for vm in (1, 0):
+                log(f"sweep: target {tgt:g}, vmode {vm}")
+                leg = solve_leg(rb, A, X0, D0, tgt, golden, args, ms_step, vmode=vm)
+                leg["target_fwd_err"] = tgt
+                sweep.append(leg)
     vslices = None
     if not args.no_vslices and golden is not None:
         log("A/B: V by the slice products (vmode 0)")
@@ -643,6 +727,10 @@ def main():
         out["hermitian"] = herm
     if vslices is not None:
         out["ab_v_by_slices"] = vslices
+    if sweep is not None:
+        out["precision_sweep"] = sweep
+    if fp8 is not None:
+        out["fp8_ablation"] = fp8
     print(json.dumps(out), flush=True)
 
 

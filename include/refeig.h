@@ -277,6 +277,26 @@ int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *e
 int refeig_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, int npad, int kl,
                       int kr, int d_min, int ndiag, int32_t *C, refeig_stream_t stream);
 
+/* FP8 ablation of the slice products (the error-free products of Sec. 2.3, eq. mat_mul, with
+ * 4-bit digits in FP8 E4M3 operands instead of 7-bit digits in INT8). refine_eigvecs does
+ * not use it: at equal dense MFMA peaks (FP8 and INT8), a 4-bit digit carries 4 bits where
+ * an INT8 digit carries 7, so the same accuracy needs about (7/4)^2 times the pairs.
+ *
+ * refeig_digits_to_e4m3: codes[i] = the E4M3 code (sign bit, 4 exponent bits with bias 7,
+ * 3 mantissa bits) of the integer digits[i]; count entries, device pointers, the caller
+ * owns both. Every integer in [-15, 15] is exact in E4M3. Returns REFEIG_E_ARG if a digit is
+ * outside [-15, 15] (those codes are NaN) or a pointer is NULL with count > 0. Synchronous.
+ *
+ * refeig_slice_gemm_fp8: the products of refeig_slice_gemm, same plane layout, same C,
+ * with Lp8 and Rp8 holding E4M3 codes of digits in [-15, 15]. The MFMA sums in FP32, which is
+ * exact while pairs * npad * 15^2 < 2^24 for every diagonal (checked: REFEIG_E_ARG).
+ * npad >= 1024, a multiple of 256. Synchronous. */
+int refeig_digits_to_e4m3(const int8_t *digits, uint8_t *codes, size_t count,
+                          refeig_stream_t stream);
+int refeig_slice_gemm_fp8(const uint8_t *Lp8, const uint8_t *Rp8, size_t plane_stride, int npad,
+                          int kl, int kr, int d_min, int ndiag, int32_t *C,
+                          refeig_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,8 @@ _lib.refine_eigvecs_herm.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctyp
 _lib.refeig_strerror.argtypes = [_int]
 _lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
+_lib.refeig_slice_gemm_fp8.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
+_lib.refeig_digits_to_e4m3.argtypes = [_vp, _vp, _sz, _vp]
 
 _lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
                                                 ctypes.POINTER(_sz)]
@@ -105,7 +107,8 @@ _lib.refeig_host_crt_plan.argtypes = [_int, _int, _int, ctypes.POINTER(_int), _v
 _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
-            "refeig_split_cols", "refeig_slice_gemm", "refeig_batched_workspace_bytes",
+            "refeig_split_cols", "refeig_slice_gemm", "refeig_slice_gemm_fp8",
+            "refeig_digits_to_e4m3", "refeig_batched_workspace_bytes",
             "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
             "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
@@ -321,6 +324,26 @@ def split_cols(M, rows: int, cols: int, k: int, want_trunc=True, stream=None):
     st = _lib.refeig_split_cols(_ptr(M), rows, rows, cols, k, _ptr(exps), _ptr(planes), _ptr(trunc),
                                 _stream(stream))
     return st, exps, planes, trunc
+
+
+def digits_to_e4m3(D, stream=None):
+    """refeig_digits_to_e4m3: FP8 E4M3 codes (uint8 tensor, same shape) of the int8 digits D,
+    each in [-15, 15]."""
+    import torch
+    assert D.dtype == torch.int8 and D.is_contiguous()
+    codes = torch.empty(D.shape, dtype=torch.uint8, device=D.device)
+    st = _lib.refeig_digits_to_e4m3(_ptr(D), _ptr(codes), D.numel(), _stream(stream))
+    return st, codes
+
+
+def slice_gemm_fp8(Lp8, Rp8, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stream=None):
+    """refeig_slice_gemm_fp8 (the FP8 ablation): as slice_gemm, with planes of E4M3 codes."""
+    import torch
+    assert Lp8.stride(0) == Rp8.stride(0) == npad * npad
+    C = torch.empty((ndiag, npad, npad), dtype=torch.int32, device=Lp8.device)
+    st = _lib.refeig_slice_gemm_fp8(_ptr(Lp8), _ptr(Rp8), npad * npad, npad, kl, kr, d_min, ndiag,
+                                    _ptr(C), _stream(stream))
+    return st, C
 
 
 def slice_gemm(Lp, Rp, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stream=None):

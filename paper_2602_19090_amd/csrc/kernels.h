@@ -62,7 +62,10 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
                        hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr, int kdim = 0, bool same_plane = false,
-                       const int *tcut = nullptr, const int *mods = nullptr);
+                       const int *tcut = nullptr, const int *mods = nullptr, bool f8 = false);
+// f8 (npad >= 1024 only): the planes hold FP8 E4M3 codes of digits in [-15, 15].
+// Digits (|d| <= 15) to FP8 E4M3 codes; a digit outside [-15, 15] sets *bad to 1.
+void launch_digits_e4m3(const int8_t *in, uint8_t *out, size_t count, int *bad, hipStream_t s);
 // The same products for npad >= 1024 in one launch of nblocks 256 x 256 blocks, block b
 // computing the tile and diagonal slot of tab[b] (device memory; L row block | R row block
 // << 8 | slot << 16, slot = d - d_min); the host orders the table. tcut as above.

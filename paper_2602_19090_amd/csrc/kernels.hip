@@ -19,12 +19,15 @@
 
 #include <float.h>
 #include <limits.h>
+#include <algorithm>
 #include <type_traits>
 
 namespace refeig {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 // Offset of element (row m, reduction index k) in a K-blocked plane of `rows` rows.
 __device__ __forceinline__ size_t kb_off(int m, int k, int rows) {
@@ -479,6 +482,12 @@ __device__ __forceinline__ void wait_vm_lds_barrier() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
+// F8: the planes hold FP8 E4M3 bytes of small integer digits (|digit| <= 15) instead of
+// INT8 digits; one v_mfma_f32_32x32x64_f8f6f4 takes the two 32-deep halves of a stage that
+// the INT8 form feeds to two v_mfma_i32_32x32x32_i8 (both operands see the same lane and byte
+// order of k, so the sum over k is unchanged). The FP32 sums are integers below 2^24 (exact)
+// and are stored as INT32 like the INT8 form's.
+template <bool F8>
 __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restrict__ Lp,
                                                            const int8_t *__restrict__ Rp,
                                                            size_t pstride, int npad, int kdim,
@@ -516,7 +525,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  v16i acc[4][4];
+  using Acc = std::conditional_t<F8, v16f, v16i>;
+  Acc acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -597,21 +607,47 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
       if (tt + S - 1 < T) issue(tt + S - 1);
       load_frags(tt + 1, na, nb);
     }
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    if constexpr (F8) {
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[ks][x], cb[ks][y], acc[x][y], 0, 0, 0);
-    if constexpr (decltype(steady)::value) {
-      // per 4 MFMAs: one DMA instruction and two fragment reads
+        for (int y = 0; y < 4; ++y) {
+          const v8i a8 = {ca[0][x][0], ca[0][x][1], ca[0][x][2], ca[0][x][3],
+                          ca[1][x][0], ca[1][x][1], ca[1][x][2], ca[1][x][3]};
+          const v8i b8 = {cb[0][y][0], cb[0][y][1], cb[0][y][2], cb[0][y][3],
+                          cb[1][y][0], cb[1][y][1], cb[1][y][2], cb[1][y][3]};
+          // formats 0, 0: E4M3 for both operands; zero scale operands select the unscaled form
+          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[x][y], 0, 0, 0,
+                                                                      0, 0, 0);
+        }
+      if constexpr (decltype(steady)::value) {
+        // per 2 MFMAs: one DMA instruction and two fragment reads
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        for (int g = 0; g < 8; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+            acc[x][y] =
+                __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[ks][x], cb[ks][y], acc[x][y], 0, 0, 0);
+      if constexpr (decltype(steady)::value) {
+        // per 4 MFMAs: one DMA instruction and two fragment reads
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -628,7 +664,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
     stage(Tail(), tt, fA[0], fB[0], fA[1], fB[1]);
     if (tt + 1 < T) stage(Tail(), tt + 1, fA[1], fB[1], fA[0], fB[0]);
   }
-  if (mods) {   // residue products: store the slot's value mod m_slot (|r| <= 127) as INT8
+  if (!F8 && mods) {   // residue products: store the slot's value mod m_slot (|r| <= 127) as INT8
     int8_t *Cq8 = (int8_t *)C + (size_t)slot * npad * npad;
     const double m = (double)mods[slot], rm = 1.0 / m;
 #pragma unroll
@@ -653,14 +689,14 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
       for (int v = 0; v < 16; ++v) {
         const int row = m0 + wm * 128 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int col = n0 + wn * 128 + y * 32 + (lane & 31);
-        Cq[(size_t)row * npad + col] = acc[x][y][v];
+        Cq[(size_t)row * npad + col] = (int32_t)acc[x][y][v];
       }
 }
 
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
                        hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
-                       bool same_plane, const int *tcut, const int *mods) {
+                       bool same_plane, const int *tcut, const int *mods, bool f8) {
   if (kdim <= 0) kdim = npad;
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
@@ -687,8 +723,12 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   }
   if (rb.count <= 0) return;
   const int tiles = rb.count * (npad / tr);
-  if (npad >= 1024)
-    hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
+  if (f8)
+    hipExtLaunchKernelGGL(k_slice_gemm256d<true>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start,
+                          ev_stop, 0, Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb,
+                          (int)same_plane, tcut, (const int *)nullptr, (const int *)nullptr);
+  else if (npad >= 1024)
+    hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride,
                        npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane, tcut,
                        (const int *)nullptr, mods);
@@ -696,6 +736,33 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride, npad, kdim,
                        kl, kr, d_min, o, C, rb, (int)same_plane, mods);
+}
+
+// FP8 E4M3 (sign, 4 exponent bits with bias 7, 3 mantissa bits): a nonzero |d| <= 15 is
+// 2^e (1 + m/8) with e = floor(log2 |d|) and m = 8 |d| / 2^e - 8, an integer since e <= 3.
+__global__ void k_digits_e4m3(const int8_t *__restrict__ in, uint8_t *__restrict__ out,
+                              size_t count, int *__restrict__ bad) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int d = in[i], a = d < 0 ? -d : d;
+    if (a > 15) {
+      atomicOr(bad, 1);
+      out[i] = 0x7f;   // NaN
+      continue;
+    }
+    int code = 0;
+    if (a) {
+      const int e = 31 - __clz(a);
+      code = ((e + 7) << 3) | (((a << 3) >> e) - 8);
+    }
+    out[i] = (uint8_t)((d < 0 ? 0x80 : 0) | code);
+  }
+}
+
+void launch_digits_e4m3(const int8_t *in, uint8_t *out, size_t count, int *bad, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 65536);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_digits_e4m3, dim3((unsigned)blocks), dim3(256), 0, s, in, out, count, bad);
 }
 
 int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
@@ -710,7 +777,7 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
   RowBlocks rb;
   rb.count = 0;
   for (int q = 0; q < kMaxDiag; ++q) o.q[q] = q;
-  hipExtLaunchKernelGGL(k_slice_gemm256d, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
+  hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
                         Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0, tcut, tab,
                         (const int *)nullptr);
 }

@@ -1353,6 +1353,43 @@ int refeig_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, i
   return REFEIG_OK;
 }
 
+int refeig_digits_to_e4m3(const int8_t *digits, uint8_t *codes, size_t count,
+                          refeig_stream_t stream) {
+  if (count == 0) return REFEIG_OK;
+  if (!digits || !codes) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int *bad = nullptr, hbad = 0;
+  HIPCHK(hipMalloc((void **)&bad, sizeof(int)));
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    launch_digits_e4m3(digits, codes, count, bad, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(bad);
+  if (e != hipSuccess) return REFEIG_E_HIP;
+  return hbad ? REFEIG_E_ARG : REFEIG_OK;
+}
+
+int refeig_slice_gemm_fp8(const uint8_t *Lp8, const uint8_t *Rp8, size_t plane_stride, int npad,
+                          int kl, int kr, int d_min, int ndiag, int32_t *C,
+                          refeig_stream_t stream) {
+  if (!Lp8 || !Rp8 || !C || npad < 1024 || npad % kTile || kl < 1 || kr < 1 || d_min < 2 ||
+      ndiag < 1 || ndiag > kMaxDiag || d_min + ndiag - 1 > kl + kr)
+    return REFEIG_E_ARG;
+  for (int q = 0; q < ndiag; ++q)
+    if ((double)npairs_of(d_min + q, kl, kr) * npad * 15.0 * 15.0 >= 16777216.0)
+      return REFEIG_E_ARG;
+  if (plane_stride < (size_t)npad * npad) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  launch_slice_gemm((const int8_t *)Lp8, (const int8_t *)Rp8, plane_stride, npad, kl, kr, d_min,
+                    ndiag, C, nullptr, s, nullptr, nullptr, 0, false, nullptr, nullptr, true);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return REFEIG_OK;
+}
+
 int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int n,
                    double target, const refeig_opts *o_in, void *work, size_t work_bytes,
                    refeig_stream_t stream, refeig_report *rep) {
