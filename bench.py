@@ -541,7 +541,8 @@ def main():
     launches = sum(c for r in reps for it in r["launches_p"] for c in it)
     achieved = ops / (gemm_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "k_slice_gemm256d", "achieved": achieved,
-                "peak": INT8_PEAK_TOPS, "unit": "TOP/s (INT8)", "frac": achieved / INT8_PEAK_TOPS,
+                "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s", "op_type": "int8 (dense MFMA peak 5.0 POP/s)",
+                "frac": achieved / INT8_PEAK_TOPS,
                 "traffic": measured_traffic(), "avg_launch_ms": gemm_ms / launches,
                 "ops_per_launch": ops / launches}
 
