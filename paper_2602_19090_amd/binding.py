@@ -103,7 +103,7 @@ _lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER
                                   ctypes.POINTER(_int), ctypes.POINTER(_int)]
 _lib.refeig_host_column_order.argtypes = [_int, _vp, _vp]
 _lib.refeig_host_crt_plan.argtypes = [_int, _int, _int, ctypes.POINTER(_int), _vp, _vp, _vp, _vp,
-                                      _vp]
+                                      _vp, _vp]
 _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
@@ -266,20 +266,22 @@ def host_beta(lam, e, c, mx, target, opts: Opts | None = None):
 
 def host_crt_plan(npad: int, ka1: int, kx: int):
     """The residue-product plan of V (refeig_host_crt_plan): dict with moduli, wA, wX (N x 18),
-    U ((N + 1) / 2 x 3, per reconstruction term) and M (3)."""
+    U ((N + 1) / 2 x 3, per reconstruction term), L ((N + 1) / 2 x 4, the 34-bit limbs of the
+    same terms) and M (3)."""
     N = _int(0)
     mods = np.zeros(28, dtype=np.int32)
     wA = np.zeros(28 * 18, dtype=np.int32)
     wX = np.zeros(28 * 18, dtype=np.int32)
     u = np.zeros(42)
+    lim = np.zeros(56)
     M = np.zeros(3)
     st = _lib.refeig_host_crt_plan(int(npad), int(ka1), int(kx), ctypes.byref(N), _np_ptr(mods),
-                                   _np_ptr(wA), _np_ptr(wX), _np_ptr(u), _np_ptr(M))
+                                   _np_ptr(wA), _np_ptr(wX), _np_ptr(u), _np_ptr(lim), _np_ptr(M))
     if st != 0:
         raise ValueError(strerror(st))
     n = N.value
     return {"moduli": mods[:n].tolist(), "wA": wA.reshape(28, 18)[:n], "wX": wX.reshape(28, 18)[:n],
-            "U": u.reshape(14, 3)[:(n + 1) // 2], "M": M}
+            "U": u.reshape(14, 3)[:(n + 1) // 2], "L": lim.reshape(14, 4)[:(n + 1) // 2], "M": M}
 
 
 def host_column_order(lam):

@@ -97,6 +97,7 @@ void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const 
 // coprime odd moduli m_q <= 255 by N INT8 GEMMs of residue planes and reconstructed by the
 // Chinese remainder theorem.
 constexpr int kCrtMax = 28;   // moduli at most (over 200 bits of product)
+constexpr int kCrtLimbs = 4, kCrtLimbBits = 34;   // limbs of the CRT fractions U_t
 constexpr int kCrtPlanes = 18;
 struct ResWeights {
   int N, k;
@@ -125,6 +126,9 @@ struct CrtRec {
   float pmb[kCrtMax / 2], prmb[kCrtMax / 2];   // m_2t+1 and fl32(1 / m_2t+1)
   float pma[kCrtMax / 2];         // m_2t
   double U[kCrtMax / 2 + 1][3];   // triple-double
+  // U_t truncated to kCrtLimbs limbs of kCrtLimbBits bits: U_t ~ sum_k L[t][k] 2^(-34 (k + 1)),
+  // each L an integer below 2^34 held exactly in a double (what the epilogue sums)
+  double L[kCrtMax / 2 + 1][kCrtLimbs];
 };
 // V epilogue as launch_epi_v, with V rebuilt from the residues of the products (INT8 slot q
 // of stride npad^2 bytes, reduced mod m_q by the GEMM) instead of summed from slice diagonals.

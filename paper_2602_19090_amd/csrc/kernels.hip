@@ -818,12 +818,16 @@ template <int EPT>
 __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size_t P, int n,
                                            int tid, const CrtRec &rec, const int (&scale)[EPT],
                                            double (&vh)[EPT], double (&vl)[EPT]) {
-  double s2[EPT];
+  // F = sum_t c_t U_t mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |c_t| < 2^15, so
+  // c_t L[t][k] is an integer below 2^49 and at most 14 of them sum below 2^52.9: every limb
+  // sum is exact. Truncating U_t to 136 bits moves F by at most 14 2^15 2^-136 = 2^-117.2.
+  double a[EPT][kCrtLimbs];
   int ca[EPT], cb[EPT], na[EPT], nb[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + kEpiThreads * q;
-    vh[q] = vl[q] = s2[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
     ca[q] = (i < n) ? Ccol[i] : 0;
     cb[q] = (i < n && rec.N > 1) ? Ccol[P + i] : 0;
   }
@@ -841,7 +845,9 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
         nb[q] = (i < n && pn) ? Ca[P + i] : 0;
       }
     }
-    const double u0 = rec.U[t][0], u1 = rec.U[t][1], u2 = rec.U[t][2];
+    double L[kCrtLimbs];
+#pragma unroll
+    for (int k = 0; k < kCrtLimbs; ++k) L[k] = rec.L[t][k];
     const float ma = pair ? rec.pma[t] : 0.0f, mb = pair ? rec.pmb[t] : 1.0f;
     const float inv = pair ? rec.pinv[t] : 0.0f, rmb = pair ? rec.prmb[t] : 0.0f;
 #pragma unroll
@@ -853,23 +859,8 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
         const float tt = d - mb * rintf(d * rmb);
         rq = (double)ca[q] + (double)ma * (double)tt;
       }
-      double p0, e0, p1, e1, tsum, cc, u, c2;
-      two_prod(rq, u0, p0, e0);
-      two_prod(rq, u1, p1, e1);
-      const double p2 = rq * u2;
-      p0 -= rint(p0);
-      two_sum(vh[q], p0, tsum, cc);
-      vh[q] = tsum - rint(tsum);
-      two_sum(vl[q], cc, u, c2);
-      vl[q] = u;
-      s2[q] += c2;
-      two_sum(vl[q], e0, u, c2);
-      vl[q] = u;
-      s2[q] += c2;
-      two_sum(vl[q], p1, u, c2);
-      vl[q] = u;
-      s2[q] += c2;
-      s2[q] += e1 + p2;
+#pragma unroll
+      for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
     }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -877,26 +868,37 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
       cb[q] = nb[q];
     }
   }
+  static_assert(kCrtLimbs == 4 && kCrtLimbBits == 34, "limb scales below are written for 4 x 34");
+  const double base = 0x1p34, rbase = 0x1p-34;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    double s0 = vh[q];
-    const double s1 = vl[q];
-    double h, l;
-    two_sum(s0, s1, h, l);
-    if (h >= 0.5) s0 -= 1.0;
-    else if (h < -0.5) s0 += 1.0;
+    // carries from the last limb up (exact: all values are integers below 2^53), then the
+    // first limb mod 2^34: F in [0, 1) as limbs in [0, 2^34)
+#pragma unroll
+    for (int k = kCrtLimbs - 1; k > 0; --k) {
+      const double cr = floor(a[q][k] * rbase);
+      a[q][k] = fma(-cr, base, a[q][k]);
+      a[q][k - 1] += cr;
+    }
+    a[q][0] = fma(-floor(a[q][0] * rbase), base, a[q][0]);
+    // F = s0 + s1 + s2: s0 exact (34 bits), s1 + e the exact sum of the next two limbs
+    double s0 = a[q][0] * 0x1p-34, s1, e;
+    two_sum(a[q][1] * 0x1p-68, a[q][2] * 0x1p-102, s1, e);
+    const double s2 = e + a[q][3] * 0x1p-136;
+    // the symmetric representative: F in [-1/2, 1/2)
+    if (s0 + s1 >= 0.5) s0 -= 1.0;
     // (s0 + s1 + s2) (M0 + M1 + M2): the terms down to 2^-99 M are exact products and are
-    // summed as a double-word, so the absolute error stays near 2^-150 M
-    double ph, pl, q1, q1e, q2, q2e, L, Le, t, te;
+    // summed as a double-word, so the absolute error stays near 2^-130 M
+    double ph, pl, q1, q1e, q2, q2e, Lw, Le, tw, te;
     two_prod(s0, rec.M[0], ph, pl);
     two_prod(s0, rec.M[1], q1, q1e);
     two_prod(s1, rec.M[0], q2, q2e);
-    two_sum(pl, q1, L, Le);
-    two_sum(L, q2, t, te);
-    L = t;
-    Le += te + (q1e + q2e) + (s1 * rec.M[1] + s2[q] * rec.M[0] + s0 * rec.M[2]);
+    two_sum(pl, q1, Lw, Le);
+    two_sum(Lw, q2, tw, te);
+    Lw = tw;
+    Le += te + (q1e + q2e) + (s1 * rec.M[1] + s2 * rec.M[0] + s0 * rec.M[2]);
     double h2, l2;
-    two_sum(ph, L, h2, l2);
+    two_sum(ph, Lw, h2, l2);
     l2 += Le;
     fast_two_sum(h2, l2, h2, l2);
     vh[q] = ldexp(h2, scale[q]);

@@ -366,6 +366,13 @@ bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec 
     rec.U[t][0] = v0;
     rec.U[t][1] = v1;
     rec.U[t][2] = q1 / Md;
+    // limbs of Y_t / M_t by long division (every quotient and remainder exact: num < 2^50)
+    long long rem = (long long)Y;
+    for (int k = 0; k < kCrtLimbs; ++k) {
+      const long long num = rem << kCrtLimbBits;
+      rec.L[t][k] = (double)(num / Mt);
+      rem = num % Mt;
+    }
   }
   rec.M[0] = a0;
   rec.M[1] = a1;
@@ -1922,8 +1929,8 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
 }
 
 int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
-                         double *U, double *M) {
-  if (npad < 1 || ka1 < 1 || kx < 1 || !N || !moduli || !wA || !wX || !U || !M)
+                         double *U, double *L, double *M) {
+  if (npad < 1 || ka1 < 1 || kx < 1 || !N || !moduli || !wA || !wX || !U || !L || !M)
     return REFEIG_E_ARG;
   ResWeights a, x;
   CrtRec rec;
@@ -1938,6 +1945,8 @@ int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA
   }
   for (int t = 0; t < rec.T; ++t)
     for (int c = 0; c < 3; ++c) U[3 * t + c] = rec.U[t][c];
+  for (int t = 0; t < rec.T; ++t)
+    for (int k = 0; k < kCrtLimbs; ++k) L[kCrtLimbs * t + k] = rec.L[t][k];
   for (int c = 0; c < 3; ++c) M[c] = rec.M[c];
   return REFEIG_OK;
 }

@@ -3,11 +3,13 @@
 * the plan of refeig_host_crt_plan against exact integer arithmetic: odd, pairwise coprime
   moduli <= 255 whose product exceeds 4 npad 128^(ka1 + kx); digit weights congruent to the
   powers of 128 and in the symmetric INT8 range; y_q u_q-constants that invert M / m_q; M;
+* the 34-bit limbs of each term's fraction Y_t / M_t, exactly (integers from long division);
 * the reconstruction that the GEMM's store (each slot mod m_q) and the V epilogue (pairs of
-  slots combined in FP32, triple-double sum) perform, ported operation for operation (Dekker
-  products stand in for fma, both exact), on random integer products P = sum_k a_k x_k of the
-  planned size (|P| from 2^60 to the bound): the rebuilt value is within 2^-115 M of P, far
-  inside the 2^-108 M that the tightest column of the n = 8192 workload needs.
+  slots combined in FP32, the terms summed exactly in four 34-bit limbs, then scaled by M in
+  double-word) perform, ported operation for operation (Dekker products stand in for fma, both
+  exact), on random integer products P = sum_k a_k x_k of the planned size (|P| from 2^60 to
+  the bound): the rebuilt value is within 2^-115 M of P, far inside the 2^-108 M that the
+  tightest column of the n = 8192 workload needs.
 """
 import math
 import random
@@ -41,6 +43,9 @@ def test_plan_constants_exact(npad, ka1, kx):
         Y = pow(M // Mt, -1, Mt)
         Ut = sum(Fraction(float(v)) for v in U)
         assert abs(Ut - Fraction(Y, Mt)) < Fraction(1, 2 ** 150)
+        for k in range(4):
+            want = (Y * 2 ** (34 * (k + 1)) // Mt) % 2 ** 34
+            assert float(p["L"][t][k]) == float(want)
     Mdd = Fraction(float(p["M"][0])) + Fraction(float(p["M"][1]))
     assert abs(Mdd - M) / M < Fraction(1, 2 ** 100)
 
@@ -73,13 +78,14 @@ def _f32(x):
     return float(np.float32(x))
 
 
-def _rebuild(cs, ms, U, M):
+def _rebuild(cs, ms, L, M):
     """The reconstruction for one element (scale 2^0): the GEMM stores each slot mod m_q
     (symmetric); the V epilogue combines slots 2t, 2t + 1 into a residue mod m_2t m_2t+1 in
-    FP32 and sums the terms in triple-double."""
+    FP32 and sums c_t L[t][k] in four limbs (every product and sum an integer below 2^53,
+    so float arithmetic is exact here as on the GPU)."""
     r = [c - m * round(c * (1.0 / m)) for c, m in zip(cs, ms)]
-    s0 = s1 = s2 = 0.0
-    for t, u in enumerate(U):
+    a = [0.0, 0.0, 0.0, 0.0]
+    for t, lt in enumerate(L):
         qa, qb = 2 * t, 2 * t + 1
         rq = float(r[qa])
         if qb < len(ms):
@@ -88,24 +94,21 @@ def _rebuild(cs, ms, U, M):
             d = _f32(np.float32(r[qb] - r[qa]) * np.float32(inv))
             tt = _f32(np.float32(d) - np.float32(mb) * np.float32(np.rint(np.float32(d) * np.float32(rmb))))
             rq = float(r[qa]) + float(ms[qa]) * tt
-        p0, e0 = _two_prod(rq, float(u[0]))
-        p1, e1 = _two_prod(rq, float(u[1]))
-        p2 = rq * float(u[2])
-        p0 -= round(p0)
-        t, cc = _two_sum(s0, p0)
-        s0 = t - round(t)
-        s1, c2 = _two_sum(s1, cc)
-        s2 += c2
-        s1, c2 = _two_sum(s1, e0)
-        s2 += c2
-        s1, c2 = _two_sum(s1, p1)
-        s2 += c2
-        s2 += e1 + p2
-    h, _ = _two_sum(s0, s1)
-    if h >= 0.5:
+        for k in range(4):
+            prod = rq * float(lt[k])
+            assert abs(prod) < 2.0 ** 53 and prod == Fraction(rq) * Fraction(float(lt[k]))
+            a[k] = a[k] + prod
+            assert abs(a[k]) < 2.0 ** 53
+    for k in (3, 2, 1):
+        cr = math.floor(a[k] * 2.0 ** -34)
+        a[k] = a[k] - cr * 2.0 ** 34
+        a[k - 1] = a[k - 1] + cr
+    a[0] = a[0] - math.floor(a[0] * 2.0 ** -34) * 2.0 ** 34
+    s0 = a[0] * 2.0 ** -34
+    s1, e = _two_sum(a[1] * 2.0 ** -68, a[2] * 2.0 ** -102)
+    s2 = e + a[3] * 2.0 ** -136
+    if s0 + s1 >= 0.5:
         s0 -= 1.0
-    elif h < -0.5:
-        s0 += 1.0
     M0, M1, M2 = (float(v) for v in M)
     ph, pl = _two_prod(s0, M0)
     q1, q1e = _two_prod(s0, M1)
@@ -124,7 +127,7 @@ def _rebuild(cs, ms, U, M):
 def test_reconstruction_error_bound(npad, ka1, kx):
     K = 48
     p = rb.host_crt_plan(npad, ka1, kx)
-    ms, U, M = p["moduli"], p["U"], p["M"]
+    ms, L, M = p["moduli"], p["L"], p["M"]
     Mx = math.prod(ms)
     rng = random.Random(7)
 
@@ -140,6 +143,6 @@ def test_reconstruction_error_bound(npad, ka1, kx):
         P = sum(ai * xi for ai, xi in zip(a, x))
         cs = [sum(sym(ai, m) * sym(xi, m) for ai, xi in zip(a, x)) for m in ms]
         assert all(abs(c) < 2 ** 27 for c in cs)
-        h, l = _rebuild(cs, ms, U, M)
+        h, l = _rebuild(cs, ms, L, M)
         worst = max(worst, abs(Fraction(h) + Fraction(l) - P) / Mx)
     assert worst < Fraction(1, 2 ** 115), float(worst)
