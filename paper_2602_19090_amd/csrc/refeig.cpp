@@ -1176,13 +1176,16 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
     if (hflags & FLAG_NONFINITE) return cleanup(REFEIG_E_NONFINITE);
     double eps = 0.0;
     for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
-    // ---- X <- X^(1) + X^(1) E~
+    // ---- X <- X^(1) + X^(1) E~ (each column t_j times tighter for noise stability, as in
+    // the real path; W here already keeps each column within theta delta g_j)
     {
       const double c0 = 7 + std::log2(1.008 * kx) + lsq2n - std::log2(theta * delta);
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (emax[j] == 0.0) continue;
-        dcol[j] = std::max(2, (int)std::ceil((c0 + eE[j]) / 7.0) + o.d_extra);
+        const double t = std::sqrt(delta * gaps[j] / (4.0 * lmax)) / (theta * delta);
+        const double need = (c0 + eE[j] - std::log2(std::min(1.0, t))) / 7.0;
+        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
     if (!plan_cutoffs(dcol, n, npad, kKeMax, kx, std::min(kKeMax + 1, kKeMax + kx), w.dcut[2],

@@ -79,6 +79,24 @@ def test_herm_refine_to_target(cfg, n, target):
     assert float(np.max(np.abs(D.cpu().numpy() - lt))) <= target * float(np.max(np.abs(lt)))
 
 
+def test_herm_loose_target_is_a_stable_fixed_point():
+    """Config 3 at n = 1024 (smallest gap about 3e-14 of max|lambda|) at a loose target: the
+    solve with the stop rule and one of 8 fixed iterations both stay within the target, so the
+    products' own noise does not return amplified by max|lambda| / g_j."""
+    print("herm loose target cfg=3 n=1024 target=1e-8", flush=True)
+    rb = _rb()
+    p = workloads.hermitian_problem(3, 1024)
+    Xt, _ = _xtrue_herm(p)
+    for fixed in (0, 8):
+        A, X, D = _dev(p)
+        st, rep = rb.refine_eigvecs_herm(A, X, D, 1e-8, rb.default_opts(fixed_iters=fixed))
+        err = _fwd(rb.from_colmajor(X), Xt)
+        print(f"  fixed_iters={fixed} status={st} iters={rep.iters} "
+              f"eps={['%.1e' % e for e in rep.eps[:rep.iters]]} fwd={err:.3e}", flush=True)
+        assert st == rb.REFEIG_OK, rb.strerror(st)
+        assert err <= 1e-8
+
+
 def test_herm_phase_equivariance():
     """A' = P A P^H, X' = P X with phases in {1, i, -1, -i} (exact): every integer product
     is the same up to the exchange of parts, so two iterations give X' = P X to rounding."""
