@@ -488,3 +488,35 @@ def test_loose_target_is_a_stable_fixed_point(cfg, n, target, vmode):
               f"eps={['%.1e' % e for e in rep.eps[:rep.iters]]} fwd={err:.3e}", flush=True)
         assert st == rb.REFEIG_OK, rb.strerror(st)
         assert err <= target
+
+
+def test_config1_slice_counts():
+    """Config 1 (n = 100, cond 1e8) read as "4 INT8 slices": k_X = 4 is what the beta rule of
+    Sec. 4.1 gives at target 1e-6 (internal delta 1.25e-7; the oracle's rule agrees), but 4
+    digit planes of A (28 bits) cannot resolve the bottom gaps (about 2e-9 of max|lambda|).
+    3 fixed iterations from the FP64 eigensolve start: the automatic plane counts meet 1e-6,
+    k_A = 4 does not, and the k_A x k_X grid is printed (rows k_A = 2..14, columns k_X = 2..8)."""
+    rb = _rb()
+    p = workloads.make_problem(1, 100, x0="eigh")
+    Xt, _ = _xtrue(p)
+    target = 1e-6
+
+    def run(**kw):
+        A, X, D = _to_dev(p)
+        st, rep = rb.refine_eigvecs(A, X, D, target, rb.default_opts(fixed_iters=3, **kw))
+        err = _fwd(rb.from_colmajor(X), Xt) if st >= 0 else float("nan")
+        return st, rep, err
+
+    st, rep, err = run()
+    print(f"  automatic: kx {list(rep.kx[:3])} dv {list(rep.dv[:3])} fwd {err:.2e}", flush=True)
+    assert st == rb.REFEIG_OK and err <= target
+    assert rep.kx[0] == oracle.beta_rule(p.D0, p.X0, target / 8)["kx"] == 4
+    st, rep, err4 = run(ka_max=4, kx_force=4)
+    print(f"  k_A = 4, k_X = 4: status {st} fwd {err4:.2e}", flush=True)
+    assert not (st == rb.REFEIG_OK and err4 <= target)
+    for ka in range(2, 15, 2):
+        row = []
+        for kx in range(2, 9):
+            st, rep, e = run(ka_max=ka, kx_force=kx)
+            row.append(f"{e:8.1e}" if st >= 0 else f"{'st' + str(st):>8}")
+        print(f"  k_A={ka:2d}: " + " ".join(row), flush=True)
