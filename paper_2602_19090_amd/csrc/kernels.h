@@ -62,7 +62,11 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rb,
                        hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr, int kdim = 0, bool same_plane = false,
-                       const int *tcut = nullptr, const int *mods = nullptr, bool f8 = false);
+                       const int *tcut = nullptr, const int *mods = nullptr, bool f8 = false,
+                       const int *vblk = nullptr);
+// vblk (device, with same_plane and npad >= 1024): per 256-row block of Lp (the output rows),
+// {slot count N_J, level}: slots q >= N_J are skipped and the R operand of level l is the
+// planes Rp + (l kCrtMax + q) pstride.
 // f8 (npad >= 1024 only): the planes hold FP8 E4M3 codes of digits in [-15, 15].
 // Digits (|d| <= 15) to FP8 E4M3 codes; a digit outside [-15, 15] sets *bad to 1.
 void launch_digits_e4m3(const int8_t *in, uint8_t *out, size_t count, int *bad, hipStream_t s);
@@ -97,6 +101,7 @@ void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const 
 // coprime odd moduli m_q <= 255 by N INT8 GEMMs of residue planes and reconstructed by the
 // Chinese remainder theorem.
 constexpr int kCrtMax = 28;   // moduli at most (over 200 bits of product)
+constexpr int kVLevels = 4;   // digit counts of A (levels) in one residue product of V
 constexpr int kCrtLimbs = 4, kCrtLimbBits = 34;   // limbs of the CRT fractions U_t
 constexpr int kCrtPlanes = 18;
 struct ResWeights {
@@ -132,10 +137,12 @@ struct CrtRec {
 };
 // V epilogue as launch_epi_v, with V rebuilt from the residues of the products (INT8 slot q
 // of stride npad^2 bytes, reduced mod m_q by the GEMM) instead of summed from slice diagonals.
-void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec &rec, const int *eA,
-                      const int *eX, const double *X1, int n, double *lam, double *lam_lo,
-                      double *r, int *eR, double *resmax, int8_t *Rpl, int kr, int *flags,
-                      hipStream_t s);
+// recs (device): one record per level; vblk (device, may be null: level 0 for all): per
+// 256-column block, its slot count and level.
+void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec *recs, const int *vblk,
+                      const int *eA, const int *eX, const double *X1, int n, double *lam,
+                      double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rpl, int kr,
+                      int *flags, hipStream_t s);
 
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eA, const int *eX, const double *X1, int n, double *lam,

@@ -496,7 +496,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
                                                            int32_t *__restrict__ C, RowBlocks rb,
                                                            int same, const int *__restrict__ tcut,
                                                            const int *__restrict__ tab,
-                                                           const int *__restrict__ mods) {
+                                                           const int *__restrict__ mods,
+                                                           const int *__restrict__ vblk) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
   int m0, n0, slot;
@@ -515,6 +516,14 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
   // per-tile diagonal limit (tile = output column block m0 / 256, output row block n0 / 256):
   // the block's diagonal is not needed there, and nothing reads its slot
   if (tcut && d > tcut[(m0 / HBM_) * (npad / HBM_) + n0 / HBM_]) return;
+  // vblk (same-plane products, per 256-row block of L: slot count, level): the block's
+  // slots beyond its count are not needed; its R planes start at level * kCrtMax
+  int roff = 0;
+  if (vblk) {
+    const int mb = m0 / HBM_;
+    if (slot >= vblk[2 * mb]) return;
+    roff = vblk[2 * mb + 1] * kCrtMax;
+  }
   // same: slot q multiplies plane q + 1 of both operands (one pair); else the pairs of
   // diagonal d, planes (s, d - s)
   const int s_lo = same ? slot + 1 : max(1, d - kr), s_hi = same ? slot + 1 : min(kl, d - 1);
@@ -541,7 +550,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
     const int p = tt / KT, k0 = (tt - p * KT) * DBK;
     const int s = s_lo + p;
     const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + kb_off(m0, k0, npad);
-    const int8_t *Rb = Rp + (size_t)(rsum - s - 1) * pstride + kb_off(n0, k0, npad);
+    const int8_t *Rb = Rp + (size_t)(roff + rsum - s - 1) * pstride + kb_off(n0, k0, npad);
     int8_t *st = ring + (tt % S) * DSTAGE_BYTES;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -696,7 +705,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
                        int kr, int d_min, int ndiag, int32_t *C, const RowBlocks *rbp,
                        hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
-                       bool same_plane, const int *tcut, const int *mods, bool f8) {
+                       bool same_plane, const int *tcut, const int *mods, bool f8,
+                       const int *vblk) {
   if (kdim <= 0) kdim = npad;
   // heaviest diagonals (most pairs) first, so the tail of the launch is light
   DiagOrder o;
@@ -726,12 +736,13 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
   if (f8)
     hipExtLaunchKernelGGL(k_slice_gemm256d<true>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start,
                           ev_stop, 0, Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb,
-                          (int)same_plane, tcut, (const int *)nullptr, (const int *)nullptr);
+                          (int)same_plane, tcut, (const int *)nullptr, (const int *)nullptr,
+                          (const int *)nullptr);
   else if (npad >= 1024)
     hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride,
                        npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane, tcut,
-                       (const int *)nullptr, mods);
+                       (const int *)nullptr, mods, vblk);
   else
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
                           Lp, Rp, pstride, npad, kdim,
@@ -779,7 +790,7 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
   for (int q = 0; q < kMaxDiag; ++q) o.q[q] = q;
   hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
                         Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0, tcut, tab,
-                        (const int *)nullptr);
+                        (const int *)nullptr, (const int *)nullptr);
 }
 
 // Digit planes of one operand row j (an output column of a column epilogue): the values
@@ -911,7 +922,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
-    int kr, int *flags, const CrtRec rec) {
+    int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -936,6 +947,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     eiq[q] = (i < n) ? eA[i] + ej : 0;
   }
   if constexpr (CRT) {
+    // the record of this column's level (per 256-column block: slot count, level)
+    const CrtRec &rec = recs[vblk ? vblk[2 * (j >> 8) + 1] : 0];
     int sc[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
@@ -1038,22 +1051,20 @@ template <int EPT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                     int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
-  CrtRec none;
-  none.N = 0;
-  none.sh = 0;
   hipLaunchKernelGGL((k_epi_v<EPT, false>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min,
-                     ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, none);
+                     ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags,
+                     (const CrtRec *)nullptr, (const int *)nullptr);
 }
 
-void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec &rec, const int *eA,
-                      const int *eX, const double *X1, int n, double *lam, double *lam_lo,
-                      double *r, int *eR, double *resmax, int8_t *Rpl, int kr, int *flags,
-                      hipStream_t s) {
+void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec *recs, const int *vblk,
+                      const int *eA, const int *eX, const double *X1, int n, double *lam,
+                      double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rpl, int kr,
+                      int *flags, hipStream_t s) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
 #define EPI_V_CRT(E)                                                                          \
   hipLaunchKernelGGL((k_epi_v<E, true>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, 2, 1,   \
                      (const int *)nullptr, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr,  \
-                     flags, rec)
+                     flags, recs, vblk)
   if (ept <= 1) EPI_V_CRT(1);
   else if (ept <= 2) EPI_V_CRT(2);
   else if (ept <= 4) EPI_V_CRT(4);

@@ -65,6 +65,8 @@ struct Work {
   int *colmap;   // working column p holds column colmap[p] of the caller's X
   int *tcut;     // per-tile last diagonal of W (256 x 256 tiles)
   int *mods;     // moduli of the residue product of V
+  CrtRec *recs;  // its reconstruction records, one per level (digit count of A)
+  int *vblk;     // per 256-column block of V: slot count, level
   double *ssA, *ssX;   // column sums of squares of A and X (the residue product's bound)
   double *wtol;        // per column: W tile tightening t_j, then the column's own gap g_j
   int *tab[3];   // block tables of the V, W and X^(1) E~ products
@@ -101,7 +103,7 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.EP = (int8_t *)take(t.P * kKeMax);
   t.Cs = (int32_t *)take(t.P * 4 * (size_t)nslots(ka, crt));
   if (crt) {
-    t.ARES = (int8_t *)take(t.P * kCrtMax);
+    t.ARES = (int8_t *)take(t.P * kCrtMax * kVLevels);   // level l at planes l kCrtMax
     t.XRES = (int8_t *)take(t.P * kCrtMax);
   }
   t.X1 = (double *)take(sizeof(double) * (size_t)n * n);
@@ -117,6 +119,8 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.colmap = (int *)take(vi);
   t.tcut = (int *)take(sizeof(int) * (kMaxN / 256) * (kMaxN / 256));
   t.mods = (int *)take(sizeof(int) * kCrtMax);
+  t.recs = (CrtRec *)take(sizeof(CrtRec) * kVLevels);
+  t.vblk = (int *)take(sizeof(int) * 2 * (kMaxN / 256));
   t.ssA = (double *)take(vd);
   t.ssX = (double *)take(vd);
   t.wtol = (double *)take(2 * vd);
@@ -1502,7 +1506,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
 
   const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
   double eps_prev = INFINITY;
-  int ares_ka = -1, ares_n = -1;   // digit and modulus counts of the residues in w.ARES
+  int ares_ka[kVLevels], ares_n[kVLevels];   // digit and modulus counts of A's residues per level
+  for (int l = 0; l < kVLevels; ++l) ares_ka[l] = ares_n[l] = -1;
   int it = 0;
   for (; it < iters; ++it) {
     STEP(hipEventRecord(ev[0], s));
@@ -1568,41 +1573,70 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     double pv = 0.0;
     bool by_res = false;
     if (crt) {
-      // V by residues: one digit count ka1 of A for all columns, from the truncation bound
-      // sqrt(n) 2^(eA_max + eX_j - 7 ka1) <= theta delta gap_j (X^(1) enters exactly)
-      int ka1 = 1;
+      // V by residues. The digits of A that column j needs follow from the truncation bound
+      // sqrt(n) 2^(eA_max + eX_j - 7 ka1) <= theta delta gap_j (X^(1) enters exactly). Each
+      // 256-column block takes the count of its neediest column, rounded up to one of at most
+      // kVLevels levels spaced two digits apart below the largest; a level's product needs
+      // fewer moduli (its P is smaller), so its blocks skip the GEMM slots beyond its count.
+      const int nb = npad / 256;
+      std::vector<int> kab(nb, 1);
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
         const double nd =
             (eA_max + lgrowth_a + eX[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
-        ka1 = std::max(ka1, (int)std::ceil(nd) + o.d_extra);
+        kab[j / 256] = std::max(kab[j / 256], (int)std::ceil(nd) + o.d_extra);
       }
-      ka1 = std::min(ka1, ka_max);
-      ResWeights wA, wX;
-      CrtRec rec;
+      int ka_top = 1;
+      for (int b = 0; b < nb; ++b) ka_top = std::max(ka_top, kab[b] = std::min(kab[b], ka_max));
+      const bool levels = npad >= 1024;   // the 256-tile GEMM reads the block table
+      std::vector<int> lvb(nb, 0);
+      int ka_l[kVLevels] = {0};
+      for (int b = 0; b < nb; ++b) {
+        lvb[b] = levels ? std::min(kVLevels - 1, (ka_top - kab[b]) / 2) : 0;
+        ka_l[lvb[b]] = std::max(ka_l[lvb[b]], kab[b]);
+      }
       // Cauchy-Schwarz headroom: max ||x_j|| 2^-eX_j (X^(1) is X truncated, never larger)
       double hX = 0.0;
       for (int j = 0; j < n; ++j)
         if (mxX[j] != 0.0) hX = std::max(hX, std::ldexp(std::sqrt(ssX[j]), -eX[j]));
       const double hbits =
           (hA > 0.0 && hX > 0.0) ? std::log2(hA * hX * (1.0 + 1e-6)) : -1.0;
-      if (crt_plan(npad, ka1, kx, wA, wX, rec, hbits)) {
+      ResWeights wA[kVLevels], wX, wXl;   // X's weights: level 0's (the most moduli)
+      CrtRec rec[kVLevels];
+      bool ok = true;
+      for (int l = 0; l < kVLevels && ok; ++l)
+        if (ka_l[l] > 0) ok = crt_plan(npad, ka_l[l], kx, wA[l], l == 0 ? wX : wXl, rec[l],
+                                       hbits);
+      if (ok) {
         by_res = true;
-        // A's residues depend only on ka1 and the moduli: reused while they repeat
-        if (ka1 != ares_ka || rec.N != ares_n) {
-          launch_residues(w.AP, P, P, wA, w.ARES, s);
-          ares_ka = ka1;
-          ares_n = rec.N;
+        // A's residues depend only on the digit count and the moduli: reused while they repeat
+        for (int l = 0; l < kVLevels; ++l) {
+          if (ka_l[l] == 0 || (ka_l[l] == ares_ka[l] && rec[l].N == ares_n[l])) continue;
+          launch_residues(w.AP, P, P, wA[l], w.ARES + (size_t)l * kCrtMax * P, s);
+          ares_ka[l] = ka_l[l];
+          ares_n[l] = rec[l].N;
         }
+        // level 0 has the most moduli; the other levels use a prefix of them
         launch_residues(w.XP, P, P, wX, w.XRES, s);
-        // one launch: slot q = residue planes q of X^(1) and A, stored mod m_q as INT8
-        STEP(hipMemcpyAsync(w.mods, rec.m, sizeof(int) * rec.N, hipMemcpyHostToDevice, s));
-        launch_slice_gemm(w.XRES, w.ARES, P, npad, rec.N, rec.N, 2, rec.N, w.Cs, nullptr, s,
-                          ev[1], ev[2], 0, true, nullptr, w.mods);
-        launch_epi_v_crt(w.Cs, npad, rec, w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r, w.eR,
-                         w.resmax, w.RP, kKrMax, w.flags, s);
-        dv = ka1 + kx;
-        pv = rec.N;   // N products of n x n x n
+        std::vector<int> vb(2 * nb);
+        double nsum = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          vb[2 * b] = rec[lvb[b]].N;
+          vb[2 * b + 1] = lvb[b];
+          nsum += rec[lvb[b]].N;
+        }
+        STEP(hipMemcpyAsync(w.mods, rec[0].m, sizeof(int) * rec[0].N, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.recs, rec, sizeof(CrtRec) * kVLevels, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.vblk, vb.data(), sizeof(int) * 2 * nb, hipMemcpyHostToDevice, s));
+        // one launch: slot q = residue planes q of X^(1) and of A at the block's level,
+        // stored mod m_q as INT8
+        launch_slice_gemm(w.XRES, w.ARES, P, npad, rec[0].N, rec[0].N, 2, rec[0].N, w.Cs,
+                          nullptr, s, ev[1], ev[2], 0, true, nullptr, w.mods, false,
+                          levels ? w.vblk : nullptr);
+        launch_epi_v_crt(w.Cs, npad, w.recs, levels ? w.vblk : nullptr, w.eA, w.eX, w.X1, n,
+                         w.lam, w.lam_lo, w.r, w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
+        dv = ka_top + kx;
+        pv = nsum / nb;   // products of n x n x n
         lv = 1;
       }
     }
