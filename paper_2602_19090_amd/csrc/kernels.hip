@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_residues(const int8_t *__restrict__ pla
     for (int b = 0; b < 4; ++b) {
       int acc = 0;
 #pragma unroll
-      for (int t = 0; t < K; ++t) acc += d[t][b] * w.w[q][t];
+      for (int t = 0; t < K; ++t) acc += __mul24(d[t][b], w.w[q][t]);   // |d|, |w| <= 127
       const float a = (float)acc;
       const int rr = (int)(a - m * rintf(a * rm));   // |rr| <= (m - 1) / 2 <= 127
       packed |= ((unsigned)(rr & 0xff)) << (8 * b);
