@@ -111,6 +111,9 @@ struct ResWeights {
                                 // a / m_q for |a| < 2^24 (a / m_q is never within 1 / (2 m_q)
                                 // of a half-integer for odd m_q)
   int w[kCrtMax][kCrtPlanes];   // 128^(k-1-t) mod m_q in the symmetric range
+  // the same weights as INT8, four planes to a dword: byte i of wp[q][g] is w[q][4g + i]
+  // (zero beyond the planes), for the dot4 products of the residue kernel
+  int wp[kCrtMax][(kCrtPlanes + 3) / 4];
 };
 // res plane q (stride pstride) = symmetric residue mod m_q of the integer sum_t d_t 128^(k-1-t)
 // that the k digit planes encode at the same offset; count bytes per plane (a multiple of 4).

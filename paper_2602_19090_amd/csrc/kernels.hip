@@ -1080,23 +1080,32 @@ template <int K>
 __global__ __launch_bounds__(256) void k_residues(const int8_t *__restrict__ planes,
                                                   size_t pstride, size_t count,
                                                   const ResWeights w, int8_t *__restrict__ res) {
+  constexpr int G = (K + 3) / 4;   // groups of four planes
   const size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (e >= count) return;
-  int d[K][4];
+  unsigned v[4 * G];
 #pragma unroll
-  for (int t = 0; t < K; ++t) {
-    const unsigned v = *(const unsigned *)(planes + (size_t)t * pstride + e);
+  for (int t = 0; t < 4 * G; ++t)
+    v[t] = (t < K) ? *(const unsigned *)(planes + (size_t)t * pstride + e) : 0u;
+  // per element b and group g: the digits of planes 4g .. 4g + 3 as the bytes of one dword
+  int dg[G][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) d[t][b] = (int)(int8_t)((v >> (8 * b)) & 0xffu);
-  }
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      dg[g][b] = (int)(((v[4 * g] >> (8 * b)) & 0xffu) |
+                       (((v[4 * g + 1] >> (8 * b)) & 0xffu) << 8) |
+                       (((v[4 * g + 2] >> (8 * b)) & 0xffu) << 16) |
+                       (((v[4 * g + 3] >> (8 * b)) & 0xffu) << 24));
   for (int q = 0; q < w.N; ++q) {
     const float m = (float)w.m[q], rm = w.rmf[q];
     unsigned packed = 0u;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
+      // sum_t d_t w_qt as signed byte dot products: |sum| <= 18 127^2 < 2^19
       int acc = 0;
 #pragma unroll
-      for (int t = 0; t < K; ++t) acc += __mul24(d[t][b], w.w[q][t]);   // |d|, |w| <= 127
+      for (int g = 0; g < G; ++g) acc = __builtin_amdgcn_sdot4(dg[g][b], w.wp[q][g], acc, false);
       const float a = (float)acc;
       const int rr = (int)(a - m * rintf(a * rm));   // |rr| <= (m - 1) / 2 <= 127
       packed |= ((unsigned)(rr & 0xff)) << (8 * b);

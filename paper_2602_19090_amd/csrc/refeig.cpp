@@ -319,6 +319,13 @@ bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec 
       wX.w[q][t] = sym(pw);
       pw = pw * 128 % m;
     }
+    for (ResWeights *rw : {&wA, &wX})
+      for (int g = 0; g < (kCrtPlanes + 3) / 4; ++g) {
+        unsigned v = 0u;
+        for (int i = 0; i < 4 && 4 * g + i < kCrtPlanes; ++i)
+          v |= ((unsigned)rw->w[q][4 * g + i] & 0xffu) << (8 * i);
+        rw->wp[q][g] = (int)v;
+      }
     long long Mq = 1;   // (M / m_q) mod m_q
     for (int l = 0; l < N; ++l)
       if (l != q) Mq = Mq * (mods[l] % m) % m;
