@@ -1455,6 +1455,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   std::vector<int> eX(npad), cX(npad), eR(npad), eE(npad), eA(npad), cA(npad);
   std::vector<double> mxX(npad), mxA(npad), lam(n), lam_prev(n), resmax(npad), emax(npad), gaps,
       wtolh(2 * (size_t)npad, 0.0);
+  // host sources of the residue product's uploads, alive until the function returns
+  std::vector<CrtRec> rec(kVLevels);
+  std::vector<int> vb(2 * (size_t)(npad / 256));
   std::vector<double> gaps_nat;
   std::vector<int> cmap(n), cpl, tcut, htab[3];
   int hflags = 0;
@@ -1609,7 +1612,6 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       const double hbits =
           (hA > 0.0 && hX > 0.0) ? std::log2(hA * hX * (1.0 + 1e-6)) : -1.0;
       ResWeights wA[kVLevels], wX, wXl;   // X's weights: level 0's (the most moduli)
-      CrtRec rec[kVLevels];
       bool ok = true;
       for (int l = 0; l < kVLevels && ok; ++l)
         if (ka_l[l] > 0) ok = crt_plan(npad, ka_l[l], kx, wA[l], l == 0 ? wX : wXl, rec[l],
@@ -1625,7 +1627,6 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         }
         // level 0 has the most moduli; the other levels use a prefix of them
         launch_residues(w.XP, P, P, wX, w.XRES, s);
-        std::vector<int> vb(2 * nb);
         double nsum = 0.0;
         for (int b = 0; b < nb; ++b) {
           vb[2 * b] = rec[lvb[b]].N;
@@ -1633,7 +1634,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
           nsum += rec[lvb[b]].N;
         }
         STEP(hipMemcpyAsync(w.mods, rec[0].m, sizeof(int) * rec[0].N, hipMemcpyHostToDevice, s));
-        STEP(hipMemcpyAsync(w.recs, rec, sizeof(CrtRec) * kVLevels, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(w.recs, rec.data(), sizeof(CrtRec) * kVLevels, hipMemcpyHostToDevice,
+                            s));
         STEP(hipMemcpyAsync(w.vblk, vb.data(), sizeof(int) * 2 * nb, hipMemcpyHostToDevice, s));
         // one launch: slot q = residue planes q of X^(1) and of A at the block's level,
         // stored mod m_q as INT8
