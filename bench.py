@@ -317,12 +317,13 @@ def config4_leg(count):
             "lanes": 8}
 
 
-def serve_leg(rates, nreq, pool_size=16):
+def serve_leg(rates, nreq, pool_size=16, lanes=8):
     """Serving (config 5): requests arrive as a Poisson process and draw a problem from a
     pool (n = round(exp(U(ln 128, ln 8192))), cond 10^U(4,12), target from {1e-8, 1e-11,
-    1e-14}, FP64-eigh start), all resident on the device. One server loop takes every
-    request that has arrived (up to 8) and refines them in one batched call; latency =
-    completion - arrival. Reports p50/p99 latency and completed matrices/s per rate."""
+    1e-14}, FP64-eigh start), all resident on the device. Each request is submitted to the
+    continuous-batching server at its arrival time and starts as soon as one of its lanes is
+    free; latency = completion - arrival. Reports p50/p99 latency and completed matrices/s
+    per rate."""
     import numpy as np
     import torch
     import workloads
@@ -331,7 +332,7 @@ def serve_leg(rates, nreq, pool_size=16):
     ns = np.rint(np.exp(rng.uniform(np.log(128.0), np.log(8192.0), pool_size))).astype(int)
     cs = rng.uniform(4.0, 12.0, pool_size)
     ts = rng.choice([1e-8, 1e-11, 1e-14], pool_size)
-    log(f"serving pool: {pool_size} problems, n {ns.min()}..{ns.max()}")
+    log(f"serving pool: {pool_size} problems, n {ns.min()}..{ns.max()}, {lanes} lanes")
     pool = []
     for i, (n, c, t) in enumerate(zip(ns, cs, ts)):
         q = workloads.make_problem(5, int(n), index=i, x0="none", cond_exp=float(c))
@@ -340,49 +341,46 @@ def serve_leg(rates, nreq, pool_size=16):
         pool.append((A, V.t().contiguous(), w.contiguous(), float(t)))
         del V
     torch.cuda.synchronize()
-    work = torch.empty(rb.batched_workspace_bytes([int(n) for n in ns]), dtype=torch.uint8,
-                       device="cuda")
-    # warm the path once per pool entry
-    st, _ = rb.refine_eigvecs_batched([e[0] for e in pool], [e[1].clone() for e in pool],
-                                      [e[2].clone() for e in pool], [e[3] for e in pool],
-                                      work=work)
+    srv = rb.Server(lanes, int(ns.max()))
     out = []
-    for rate in rates:
-        arr_rng = np.random.default_rng([2602, 19090, 5, int(rate * 1000)])
-        arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, nreq))
-        picks = arr_rng.integers(0, pool_size, nreq)
-        done = np.zeros(nreq)
-        batches = []
-        t0 = time.perf_counter()
-        nxt = 0
-        while nxt < nreq:
-            now = time.perf_counter() - t0
-            if arrivals[nxt] > now:
-                time.sleep(arrivals[nxt] - now)
-                continue
-            take = []
-            while nxt < nreq and arrivals[nxt] <= time.perf_counter() - t0 and len(take) < 8:
-                take.append(nxt)
-                nxt += 1
-            Xs = [pool[picks[i]][1].clone() for i in take]
-            Ds = [pool[picks[i]][2].clone() for i in take]
-            st, _ = rb.refine_eigvecs_batched([pool[picks[i]][0] for i in take], Xs, Ds,
-                                              [pool[picks[i]][3] for i in take], work=work)
-            torch.cuda.synchronize()
-            tdone = time.perf_counter() - t0
-            for i in take:
-                done[i] = tdone
-            batches.append(len(take))
-            assert st in (rb.REFEIG_OK, rb.REFEIG_NOT_CONVERGED), rb.strerror(st)
-        lat = (done - arrivals) * 1e3
-        span = done.max() - arrivals[0]
-        out.append({"rate_req_s": rate, "requests": nreq, "p50_ms": float(np.percentile(lat, 50)),
-                    "p99_ms": float(np.percentile(lat, 99)), "matrices_per_s": nreq / span,
-                    "mean_batch": float(np.mean(batches))})
-        log(f"serving at {rate:g} req/s: p50 {out[-1]['p50_ms']:.0f} ms, p99 "
-            f"{out[-1]['p99_ms']:.0f} ms, {out[-1]['matrices_per_s']:.1f} matrices/s, "
-            f"mean batch {out[-1]['mean_batch']:.2f}")
-    return {"pool": {"size": pool_size, "n": [int(n) for n in ns]}, "rates": out}
+    try:
+        # warm the path once per pool entry
+        warm = [(e[1].clone(), e[2].clone()) for e in pool]
+        torch.cuda.synchronize()
+        for k in [srv.submit(e[0], X, D, e[3]) for e, (X, D) in zip(pool, warm)]:
+            srv.wait(k)
+        for rate in rates:
+            arr_rng = np.random.default_rng([2602, 19090, 5, int(rate * 1000)])
+            arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, nreq))
+            picks = arr_rng.integers(0, pool_size, nreq)
+            reqs = [(pool[k][1].clone(), pool[k][2].clone()) for k in picks]
+            torch.cuda.synchronize()   # the copies are done before any lane reads them
+            tickets = []
+            t0 = time.monotonic()
+            for i in range(nreq):
+                wait_s = arrivals[i] - (time.monotonic() - t0)
+                if wait_s > 0:
+                    time.sleep(wait_s)
+                e = pool[picks[i]]
+                tickets.append(srv.submit(e[0], reqs[i][0], reqs[i][1], e[3]))
+            done = np.zeros(nreq)
+            for i, k in enumerate(tickets):
+                st, _, td = srv.wait(k)
+                assert st in (rb.REFEIG_OK, rb.REFEIG_NOT_CONVERGED), rb.strerror(st)
+                done[i] = td - t0
+            del reqs
+            lat = (done - arrivals) * 1e3
+            span = done.max() - arrivals[0]
+            out.append({"rate_req_s": rate, "requests": nreq,
+                        "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)), "matrices_per_s": nreq / span,
+                        "lanes": lanes})
+            log(f"serving at {rate:g} req/s: p50 {out[-1]['p50_ms']:.0f} ms, p99 "
+                f"{out[-1]['p99_ms']:.0f} ms, {out[-1]['matrices_per_s']:.1f} matrices/s")
+    finally:
+        srv.close()
+    return {"pool": {"size": pool_size, "n": [int(n) for n in ns]}, "lanes": lanes,
+            "engine": "continuous batching (refeig_server)", "rates": out}
 
 
 def cpu_baseline(A, X0cm, n, cols):

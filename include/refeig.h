@@ -206,6 +206,31 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
 
 const char *refeig_strerror(int status);
 
+/* Continuous-batching server for Algorithm 1 per request (the serving
+ * workload: requests of uneven n that arrive while others run). refeig_server_create starts `lanes` host threads,
+ * each with its own stream (default priority) and a workspace for orders up to
+ * max_n, all allocated here (about lanes * refeig_workspace_bytes(max_n)); the
+ * device is the one current in the calling thread. refeig_server_submit queues
+ * one refine_eigvecs problem (device pointers as there; the caller keeps A, X
+ * and D alive and untouched until the request is waited for) and returns at
+ * once with a ticket; a lane starts it as soon as the lane is free, so requests
+ * overlap on the device and a short one does not wait for a long one admitted
+ * before it. Each result is bit for bit what refine_eigvecs returns for that
+ * problem alone. refeig_server_wait blocks until the ticket's request is done
+ * and returns its status, report (may be NULL) and completion time t_done (may
+ * be NULL; seconds on the monotonic clock, CLOCK_MONOTONIC). Requests are
+ * served in submission order as lanes free up. REFEIG_E_ARG for n > max_n, a
+ * NULL pointer or an unknown ticket; REFEIG_E_NOMEM / REFEIG_E_HIP from create
+ * when the workspaces or streams cannot be made. refeig_server_destroy waits
+ * for every submitted request, then frees everything. */
+typedef struct refeig_server refeig_server;
+int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_server **server);
+int refeig_server_submit(refeig_server *server, const double *A, int lda, double *X, int ldx,
+                         double *D, int n, double target_fwd_err, int *ticket);
+int refeig_server_wait(refeig_server *server, int ticket, int *status, refeig_report *report,
+                       double *t_done);
+int refeig_server_destroy(refeig_server *server);
+
 /* The largest number of nonzero entries in a row of A (device, n x n, ld lda),
  * the k of the sparse rule (Sec. 4.3). Synchronous; *k is a host int. */
 int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream, int *k);

@@ -92,6 +92,12 @@ _lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _
 _lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 _lib.refeig_slice_gemm_fp8.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 _lib.refeig_digits_to_e4m3.argtypes = [_vp, _vp, _sz, _vp]
+_lib.refeig_server_create.argtypes = [_int, _int, ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
+_lib.refeig_server_submit.argtypes = [_vp, _vp, _int, _vp, _int, _vp, _int, _dbl,
+                                      ctypes.POINTER(_int)]
+_lib.refeig_server_wait.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(Report),
+                                    ctypes.POINTER(_dbl)]
+_lib.refeig_server_destroy.argtypes = [_vp]
 
 _lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
                                                 ctypes.POINTER(_sz)]
@@ -109,6 +115,8 @@ _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
             "refeig_split_cols", "refeig_slice_gemm", "refeig_slice_gemm_fp8",
             "refeig_digits_to_e4m3", "refeig_batched_workspace_bytes",
+            "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
+            "refeig_server_destroy",
             "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
             "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
@@ -235,6 +243,48 @@ def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=N
                                      ctypes.byref(opts) if opts is not None else None, _ptr(work),
                                      wb, _stream(stream), c(reps))
     return st, list(reps)
+
+
+class Server:
+    """The continuous-batching server (refeig_server_*): submit() returns a ticket at once;
+    wait(ticket) returns (status, report, t_done) with t_done on time.monotonic()'s clock.
+    The tensors of a request must stay alive until it is waited for (kept here until then)."""
+
+    def __init__(self, lanes: int, max_n: int, opts: Opts | None = None):
+        self._h = _vp()
+        st = _lib.refeig_server_create(int(lanes), int(max_n),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(self._h))
+        if st != 0:
+            raise RuntimeError(strerror(st))
+        self._keep = {}
+
+    def submit(self, A, X, D, target: float) -> int:
+        n = D.numel()
+        assert A.is_cuda and X.is_cuda and D.is_cuda and A.is_contiguous() and X.is_contiguous()
+        assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+        t = _int(0)
+        st = _lib.refeig_server_submit(self._h, _ptr(A), n, _ptr(X), n, _ptr(D), n,
+                                       float(target), ctypes.byref(t))
+        if st != 0:
+            raise ValueError(strerror(st))
+        self._keep[t.value] = (A, X, D)
+        return t.value
+
+    def wait(self, ticket: int):
+        st, rep, td = _int(0), Report(), _dbl(0.0)
+        r = _lib.refeig_server_wait(self._h, int(ticket), ctypes.byref(st), ctypes.byref(rep),
+                                    ctypes.byref(td))
+        if r != 0:
+            raise ValueError(strerror(r))
+        self._keep.pop(int(ticket), None)
+        return st.value, rep, td.value
+
+    def close(self):
+        if self._h:
+            _lib.refeig_server_destroy(self._h)
+            self._h = _vp()
+            self._keep.clear()
 
 
 def row_nonzeros(A, stream=None) -> int:

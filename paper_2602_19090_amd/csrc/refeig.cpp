@@ -23,7 +23,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <thread>
+#include <time.h>
 #include <vector>
 
 #include <rocblas/rocblas.h>
@@ -2098,6 +2102,147 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
     if (status[i] != REFEIG_OK) worst = status[i];
   }
   return worst;
+}
+
+struct refeig_server {
+  struct Req {
+    const double *A;
+    double *X, *D;
+    int lda, ldx, n;
+    double target;
+  };
+  struct Done {
+    bool done = false;
+    int status = REFEIG_E_HIP;
+    refeig_report rep;
+    double t_done = 0.0;
+  };
+  int device = 0, lanes = 0, max_n = 0;
+  refeig_opts opts;
+  size_t slice = 0;
+  void *work = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<std::thread> threads;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::pair<int, Req>> queue;   // (ticket, request)
+  std::deque<Done> results;                // by ticket (stable references)
+  bool stop = false;
+
+  static double now() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+  }
+  void lane(int l) {
+    (void)hipSetDevice(device);
+    char *wl = (char *)work + (size_t)l * slice;
+    for (;;) {
+      std::pair<int, Req> job;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        if (queue.empty()) return;   // stop requested and nothing left
+        job = queue.front();
+        queue.pop_front();
+      }
+      refeig_report rep;
+      const Req &r = job.second;
+      // refine_eigvecs returns after its last kernel has finished (it waits for it)
+      const int st = refine_eigvecs(r.A, r.lda, r.X, r.ldx, r.D, r.n, r.target, &opts, wl, slice,
+                                    (refeig_stream_t)streams[l], &rep);
+      const double t = now();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        Done &d = results[job.first];
+        d.status = st;
+        d.rep = rep;
+        d.t_done = t;
+        d.done = true;
+      }
+      cv_done.notify_all();
+    }
+  }
+};
+
+int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_server **server) {
+  if (!server || lanes < 1 || lanes > 64 || max_n < 1 || max_n > kMaxN) return REFEIG_E_ARG;
+  *server = nullptr;
+  refeig_server *sv = new refeig_server();
+  if (o) sv->opts = *o;
+  else refeig_default_opts(&sv->opts);
+  sv->lanes = lanes;
+  sv->max_n = max_n;
+  size_t one = 0;
+  int st = refeig_workspace_bytes(max_n, &sv->opts, &one);
+  if (st != REFEIG_OK) {
+    delete sv;
+    return st;
+  }
+  sv->slice = (one + 255) / 256 * 256;
+  if (hipGetDevice(&sv->device) != hipSuccess ||
+      hipMalloc(&sv->work, sv->slice * (size_t)lanes) != hipSuccess) {
+    delete sv;
+    return REFEIG_E_NOMEM;
+  }
+  sv->streams.assign(lanes, nullptr);
+  for (int l = 0; l < lanes; ++l)
+    if (hipStreamCreateWithFlags(&sv->streams[l], hipStreamNonBlocking) != hipSuccess) {
+      for (int k = 0; k < l; ++k) (void)hipStreamDestroy(sv->streams[k]);
+      (void)hipFree(sv->work);
+      delete sv;
+      return REFEIG_E_HIP;
+    }
+  for (int l = 0; l < lanes; ++l) sv->threads.emplace_back(&refeig_server::lane, sv, l);
+  *server = sv;
+  return REFEIG_OK;
+}
+
+int refeig_server_submit(refeig_server *sv, const double *A, int lda, double *X, int ldx,
+                         double *D, int n, double target_fwd_err, int *ticket) {
+  if (!sv || !A || !X || !D || !ticket || n < 1 || n > sv->max_n || lda < n || ldx < n ||
+      !(target_fwd_err > 0.0))
+    return REFEIG_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return REFEIG_E_ARG;
+    *ticket = (int)sv->results.size();
+    sv->results.emplace_back();
+    sv->queue.push_back({*ticket, {A, X, D, lda, ldx, n, target_fwd_err}});
+  }
+  sv->cv_work.notify_one();
+  return REFEIG_OK;
+}
+
+int refeig_server_wait(refeig_server *sv, int ticket, int *status, refeig_report *report,
+                       double *t_done) {
+  if (!sv || !status) return REFEIG_E_ARG;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (ticket < 0 || ticket >= (int)sv->results.size()) return REFEIG_E_ARG;
+  sv->cv_done.wait(lk, [&] { return sv->results[ticket].done; });
+  const refeig_server::Done &d = sv->results[ticket];
+  *status = d.status;
+  if (report) *report = d.rep;
+  if (t_done) *t_done = d.t_done;
+  return REFEIG_OK;
+}
+
+int refeig_server_destroy(refeig_server *sv) {
+  if (!sv) return REFEIG_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  for (auto &t : sv->threads) t.join();
+  for (auto st : sv->streams)
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  (void)hipFree(sv->work);
+  delete sv;
+  return REFEIG_OK;
 }
 
 }  // extern "C"

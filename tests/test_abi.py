@@ -31,7 +31,9 @@ def test_header_declares_expected_functions():
     names = _declared()
     for f in ("refine_eigvecs", "refeig_workspace_bytes", "refeig_default_opts", "refeig_strerror",
               "refeig_split_cols", "refeig_slice_gemm", "refine_eigvecs_herm",
-              "refeig_herm_workspace_bytes", "refeig_slice_gemm_fp8", "refeig_digits_to_e4m3"):
+              "refeig_herm_workspace_bytes", "refeig_slice_gemm_fp8", "refeig_digits_to_e4m3",
+              "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
+              "refeig_server_destroy"):
         assert f in names, names
 
 

@@ -520,3 +520,42 @@ def test_config1_slice_counts():
             st, rep, e = run(ka_max=ka, kx_force=kx)
             row.append(f"{e:8.1e}" if st >= 0 else f"{'st' + str(st):>8}")
         print(f"  k_A={ka:2d}: " + " ".join(row), flush=True)
+
+
+def test_server_results_match_single_calls():
+    """The continuous-batching server: config-4 style requests of uneven n and mixed targets
+    (1e-8, 1e-11, 1e-14, the serving mix), submitted while earlier ones run on 4 lanes, each
+    come back bit for bit as a single call alone gives them (stop rule on, so the iteration
+    counts differ between requests). Requests beyond max_n and unknown tickets are refused."""
+    import time
+    import torch
+    rb = _rb()
+    ns, cs = workloads.config4_sizes(24)
+    probs = [workloads.make_problem(4, int(n), index=100 + i, cond_exp=float(c))
+             for i, (n, c) in enumerate(zip(ns, cs))]
+    targets = [(1e-8, 1e-11, 1e-14)[i % 3] for i in range(len(probs))]
+    singles = []
+    for p, t in zip(probs, targets):
+        A, X, D = _to_dev(p)
+        st, rep = rb.refine_eigvecs(A, X, D, t)
+        singles.append((st, rep.iters, X.cpu().numpy(), D.cpu().numpy()))
+    srv = rb.Server(4, 1024)
+    try:
+        dev = [_to_dev(p) for p in probs]
+        t0 = time.monotonic()
+        tickets = [srv.submit(A, X, D, t) for (A, X, D), t in zip(dev, targets)]
+        done = [srv.wait(k) for k in tickets]
+        for (A, X, D), (st1, it1, Xs, Ds), (st, rep, td), p in zip(dev, singles, done, probs):
+            assert st == st1 and rep.iters == it1, (p.n, st, st1, rep.iters, it1)
+            assert td >= t0
+            assert np.array_equal(X.cpu().numpy(), Xs) and np.array_equal(D.cpu().numpy(), Ds)
+        print("server: n", [p.n for p in probs], "iters", [r.iters for _, r, _ in done],
+              flush=True)
+        big = workloads.make_problem(4, 1100, index=999, cond_exp=6.0)
+        A, X, D = _to_dev(big)
+        with pytest.raises(ValueError):
+            srv.submit(A, X, D, 1e-14)
+        with pytest.raises(ValueError):
+            srv.wait(10 ** 6)
+    finally:
+        srv.close()
