@@ -94,12 +94,16 @@ typedef struct {
                             0: the dense rule.                                          */
     int vmode;           /* how V = A X^(1) is formed. 1 (default): by residues, a product
                             algorithm other than the paper's slices: A cut to the digits
-                            the V cutoff asks for (one count for all columns) and X^(1)
-                            are integers, their product is formed exactly modulo N
-                            pairwise coprime odd moduli <= 255 (one INT8 GEMM each, N
-                            about 23 at n = 8192, target 1e-14; at most 28) and rebuilt
-                            by the Chinese remainder theorem; W and X^(1) E~ keep the
-                            slice products. 0: the slice products of Sec. 2.3 for V too
+                            the V cutoff asks for and X^(1) are integers (the digit count
+                            of A is chosen per 256-column block of V, in up to 4 levels
+                            two digits apart), their product is formed exactly modulo N
+                            pairwise coprime odd moduli <= 255 (one INT8 GEMM each; N is
+                            sized per level from a Cauchy-Schwarz bound on the product,
+                            22 for the top level at n = 8192, target 1e-14; at most 28) and
+                            rebuilt by the Chinese remainder theorem; W and X^(1) E~ keep
+                            the slice products. When a column's V tolerance lies below
+                            what the reconstruction resolves, that iteration forms V by
+                            slices instead. 0: the slice products of Sec. 2.3 for V too
                             (pair diagonals kept per column block). The Hermitian path
                             always uses slices.                                          */
     int reserved_i[2];
@@ -138,6 +142,12 @@ typedef struct {
     double min_gap;                  /* min_{i != j} |lambda_i - lambda_j| (last)       */
     double max_abs_lambda;           /* max |lambda| (last)                             */
     double ms_total;
+    int vres[REFEIG_MAX_ITERS];      /* 1: V formed by residues (vmode 1), 0: by slices  */
+    double ms_phase[REFEIG_MAX_ITERS][5];/* device time of the iteration's phases (HIP
+                                           events around each): column statistics of X,
+                                           split of X^(1), V and the column pass, W and E~,
+                                           the update; ms_iter minus their sum is the host
+                                           planning and the copies it waits for           */
 } refeig_report;
 
 /* Defaults as documented in refeig_opts. Returns REFEIG_OK or REFEIG_E_ARG (o NULL). */
@@ -293,6 +303,43 @@ int refeig_host_group_ritz(int k, const double *G_hi, const double *G_lo, const 
  * This is the integer form of the error-free splitting of Sec. 2.3 (eq. a/x). */
 int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *exps,
                       int8_t *planes, double *trunc, refeig_stream_t stream);
+
+/* refeig_split_cols with two more outputs of the splitter as the refinement runs it:
+ * colmap (host, cols ints, may be NULL): column j of the result is column colmap[j] of M
+ * (the working column order the solver folds into its reads of X; a permutation of 0..cols-1,
+ * else REFEIG_E_ARG); exps and planes as refeig_split_cols for that column order.
+ * planesT (device, kT * rows_pad * cols_pad bytes, may be NULL with kT = 0; 1 <= kT <= 9 when
+ * given): the first kT digit planes in the transposed operand form, row i of the operand
+ * holding the digits of row i of M (K index j): digit r of M_i,colmap[j] at
+ * planesT[(r-1) * rows_pad * cols_pad + ((j / 64) * rows_pad + i) * 64 + j % 64] (the right
+ * operand of the X^(1) E~ product, Algorithm 1 line 6 with the split of Sec. 2.3); zero
+ * outside rows x cols. Errors as refeig_split_cols. */
+int refeig_split_cols_ex(const double *M, int ld, int rows, int cols, int k, const int *colmap,
+                         int *exps, int8_t *planes, double *trunc, int kT, int8_t *planesT,
+                         refeig_stream_t stream);
+
+/* Residue planes of the V product by residues (vmode 1; the Chinese-remainder form of the
+ * error-free product of Sec. 2.3): the k digit planes at planes + t * plane_stride
+ * (t = 0..k-1, digit t the most significant first, as refeig_split_cols writes them) encode
+ * at each byte offset e < count the integer z = sum_t d_t 128^(k-1-t). For q = 0..nmod-1,
+ * res[q * plane_stride + e] = z mod moduli[q] in the symmetric range
+ * [-(m_q - 1) / 2, (m_q - 1) / 2] (int8). moduli (host): odd integers in [3, 255].
+ * count a multiple of 4 (device pointers; every plane holds count bytes). Synchronous.
+ * REFEIG_E_ARG: k outside 1..18, nmod outside 1..28, a bad modulus or count. */
+int refeig_residue_planes(const int8_t *planes, size_t plane_stride, size_t count, int k,
+                          int nmod, const int *moduli, int8_t *res, refeig_stream_t stream);
+
+/* Residue products of the V product by residues: for q = 0..nmod-1,
+ *   C[q][m][p] = (sum_k L_q[m][k] * R_{l q}[p][k]) mod moduli[q], symmetric range, int8,
+ * at C + q*npad*npad + m*npad + p, with L_q and R_q residue planes in the K-blocked layout of
+ * refeig_slice_gemm (plane stride plane_stride, npad a multiple of 256). vblk (host, may be
+ * NULL; npad >= 1024 when given): per 256-row block b of L, {slot count c_b, level l_b}:
+ * slots q >= c_b of that block's rows are not computed (C left as it was) and R_{l q} is
+ * plane l_b * 28 + q of Rp (one residue set per digit count of A); NULL: c_b = nmod,
+ * l_b = 0. Every slot sums npad terms below 127^2 exactly in INT32. Synchronous. */
+int refeig_residue_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, int npad,
+                        int nmod, const int *moduli, const int *vblk, int8_t *C,
+                        refeig_stream_t stream);
 
 /* Exact per-diagonal slice products: for q = 0..ndiag-1 and d = d_min + q,
  *   C[q][m][p] = sum_{s + t = d, 1<=s<=kl, 1<=t<=kr} sum_k L_s[m][k] * R_t[p][k]

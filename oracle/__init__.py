@@ -217,6 +217,52 @@ def slice_gemm_i64(Ap, Bp):
     return C
 
 
+def coprime_moduli(count):
+    """The first `count` odd moduli <= 255 taken greedily from 255 down, each coprime to
+    all taken before it (the modulus set of a Chinese-remainder form of the exact
+    product of Sec. 2.3)."""
+    from math import gcd
+    out = []
+    for m in range(255, 2, -2):
+        if all(gcd(m, x) == 1 for x in out):
+            out.append(m)
+        if len(out) == count:
+            break
+    return out
+
+
+def _sym(r, m):
+    """Residues r in [0, m) to the symmetric range [-(m - 1) / 2, (m - 1) / 2] (m odd)."""
+    return np.where(r > m // 2, r - m, r)
+
+
+def digit_residues(planes, moduli):
+    """Residues of the integers that digit planes encode: planes (k, ...) int8 holds digits
+    d_0 .. d_{k-1} (most significant first) of z = sum_t d_t 128^(k-1-t); returns (N, ...)
+    int8 with z mod m_q in the symmetric range. Horner's rule in int64 (every partial value
+    stays below 2^16 in magnitude)."""
+    P = np.asarray(planes, dtype=np.int64)
+    out = []
+    for m in moduli:
+        z = np.zeros(P.shape[1:], dtype=np.int64)
+        for t in range(P.shape[0]):
+            z = np.mod(z * 128 + P[t], m)
+        out.append(_sym(z, m))
+    return np.asarray(out, dtype=np.int8)
+
+
+def residue_product(Lres, Rres, moduli):
+    """C[q][i, j] = (sum_k Lres[q][i, k] Rres[q][j, k]) mod m_q, symmetric range, int8.
+    The FP64 matrix product is exact: every term is below 127^2 and the sums stay far
+    below 2^53 for K < 2^38."""
+    out = []
+    for q, m in enumerate(moduli):
+        c = np.asarray(Lres[q], dtype=np.float64) @ np.asarray(Rres[q], dtype=np.float64).T
+        assert Lres.shape[-1] < (1 << 38)
+        out.append(_sym(np.mod(c.astype(np.int64), m), m))
+    return np.asarray(out, dtype=np.int8)
+
+
 def sigma_split(M, alpha, ns, by_rows=True):
     """FP64 splitting of eq. (a)/(x). Returns (slices (ns, m, n), remainder)."""
     M = _f64(M)

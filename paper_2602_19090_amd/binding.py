@@ -61,7 +61,9 @@ class Report(ctypes.Structure):
                 ("launches_p", (ctypes.c_int * 3) * MAX_ITERS),
                 ("groups", ctypes.c_int * MAX_ITERS), ("delta_it", ctypes.c_double * MAX_ITERS),
                 ("min_gap", ctypes.c_double),
-                ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("max_abs_lambda", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("vres", ctypes.c_int * MAX_ITERS),
+                ("ms_phase", (ctypes.c_double * 5) * MAX_ITERS)]
 
     def as_dict(self):
         k = self.iters
@@ -75,7 +77,8 @@ class Report(ctypes.Structure):
                 "launches_p": [list(self.launches_p[i]) for i in range(k)],
                 "groups": list(self.groups[:k]), "delta_it": list(self.delta_it[:k]),
                 "min_gap": self.min_gap, "max_abs_lambda": self.max_abs_lambda,
-                "ms_total": self.ms_total}
+                "ms_total": self.ms_total, "vres": list(self.vres[:k]),
+                "ms_phase": [list(self.ms_phase[i]) for i in range(k)]}
 
 
 _vp, _int, _dbl, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
@@ -90,6 +93,10 @@ _lib.refine_eigvecs_herm.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctyp
 _lib.refeig_strerror.argtypes = [_int]
 _lib.refeig_split_cols.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
+_lib.refeig_split_cols_ex.argtypes = [_vp, _int, _int, _int, _int, _vp, _vp, _vp, _vp, _int, _vp,
+                                      _vp]
+_lib.refeig_residue_planes.argtypes = [_vp, _sz, _sz, _int, _int, _vp, _vp, _vp]
+_lib.refeig_residue_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm_fp8.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 _lib.refeig_digits_to_e4m3.argtypes = [_vp, _vp, _sz, _vp]
 _lib.refeig_server_create.argtypes = [_int, _int, ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
@@ -113,12 +120,14 @@ _lib.refeig_host_crt_plan.argtypes = [_int, _int, _int, ctypes.POINTER(_int), _v
 _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
-            "refeig_split_cols", "refeig_slice_gemm", "refeig_slice_gemm_fp8",
+            "refeig_herm_workspace_bytes", "refine_eigvecs_herm",
+            "refeig_split_cols", "refeig_split_cols_ex", "refeig_slice_gemm",
+            "refeig_residue_planes", "refeig_residue_gemm", "refeig_slice_gemm_fp8",
             "refeig_digits_to_e4m3", "refeig_batched_workspace_bytes",
             "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
             "refeig_server_destroy",
             "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
-            "refeig_host_group_ritz", "refeig_row_nonzeros"]
+            "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
 
 def _stream(stream=None):
@@ -406,4 +415,52 @@ def slice_gemm(Lp, Rp, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stre
     C = torch.empty((ndiag, npad, npad), dtype=torch.int32, device=Lp.device)
     st = _lib.refeig_slice_gemm(_ptr(Lp), _ptr(Rp), npad * npad, npad, kl, kr, d_min, ndiag,
                                 _ptr(C), _stream(stream))
+    return st, C
+
+
+def split_cols_ex(M, rows: int, cols: int, k: int, colmap=None, kT: int = 0, stream=None):
+    """Debug entry point refeig_split_cols_ex on a column-major tensor M (cols, rows): the
+    planes of columns colmap[j] (host int array, or None), and kT planes in the transposed
+    operand form. Returns (status, exps, planes (k, cols_pad, rows_pad), trunc,
+    planesT (kT, rows_pad, cols_pad) or None), all K-blocked."""
+    import torch
+    rpad, cpad = -(-rows // 256) * 256, -(-cols // 256) * 256
+    exps = torch.empty(cols, dtype=torch.int32, device=M.device)
+    planes = torch.empty((k, cpad, rpad), dtype=torch.int8, device=M.device)
+    trunc = torch.empty((cols, rows), dtype=torch.float64, device=M.device)
+    planesT = torch.empty((kT, rpad, cpad), dtype=torch.int8, device=M.device) if kT > 0 else None
+    cm = None if colmap is None else np.ascontiguousarray(colmap, dtype=np.int32)
+    st = _lib.refeig_split_cols_ex(_ptr(M), rows, rows, cols, k,
+                                   _np_ptr(cm) if cm is not None else None, _ptr(exps),
+                                   _ptr(planes), _ptr(trunc), int(kT), _ptr(planesT),
+                                   _stream(stream))
+    return st, exps, planes, trunc, planesT
+
+
+def residue_planes(planes, k: int, moduli, stream=None):
+    """refeig_residue_planes: planes (>= k, ...) int8 tensor (plane stride = one plane);
+    returns (status, res) with res (len(moduli), ...) int8, same plane shape."""
+    import torch
+    assert planes.dtype == torch.int8 and planes.is_contiguous()
+    stride = planes[0].numel()
+    m = np.ascontiguousarray(moduli, dtype=np.int32)
+    res = torch.empty((len(m),) + tuple(planes.shape[1:]), dtype=torch.int8, device=planes.device)
+    st = _lib.refeig_residue_planes(_ptr(planes), stride, stride, int(k), len(m), _np_ptr(m),
+                                    _ptr(res), _stream(stream))
+    return st, res
+
+
+def residue_gemm(Lp, Rp, npad: int, moduli, vblk=None, out=None, stream=None):
+    """refeig_residue_gemm: residue planes Lp (>= N, npad, npad) and Rp (K-blocked), N =
+    len(moduli); vblk: host (npad / 256, 2) ints (slot count, level) or None. Returns (status,
+    C) with C (N, npad, npad) int8 (out, when given, is written in place)."""
+    import torch
+    assert Lp.stride(0) == Rp.stride(0) == npad * npad
+    m = np.ascontiguousarray(moduli, dtype=np.int32)
+    C = out if out is not None else torch.empty((len(m), npad, npad), dtype=torch.int8,
+                                                device=Lp.device)
+    vb = None if vblk is None else np.ascontiguousarray(vblk, dtype=np.int32).reshape(-1)
+    st = _lib.refeig_residue_gemm(_ptr(Lp), _ptr(Rp), npad * npad, npad, len(m), _np_ptr(m),
+                                  _np_ptr(vb) if vb is not None else None, _ptr(C),
+                                  _stream(stream))
     return st, C

@@ -284,6 +284,33 @@ int inv_mod(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1)
   return t < 0 ? t + m : t;
 }
 
+// Residue weights of k digit planes for N odd moduli m_q <= 255: w_qt = 128^(k-1-t) mod m_q
+// in the symmetric range (|w| <= 127), also packed four planes to a dword for the dot4
+// products of the residue kernel.
+void res_weights(int k, int N, const int *mods, ResWeights &rw) {
+  rw.N = N;
+  rw.k = k;
+  for (int q = 0; q < N; ++q) {
+    const int m = mods[q];
+    rw.m[q] = m;
+    rw.rmf[q] = 1.0f / (float)m;
+    for (int t = 0; t < kCrtPlanes; ++t) rw.w[q][t] = 0;
+    // 128^(k-1-t) mod m, from the least significant digit up, in the symmetric range
+    auto sym = [m](long long v) { return (int)(v > m / 2 ? v - m : v); };
+    long long pw = 1;
+    for (int t = k - 1; t >= 0; --t) {
+      rw.w[q][t] = sym(pw);
+      pw = pw * 128 % m;
+    }
+    for (int g = 0; g < (kCrtPlanes + 3) / 4; ++g) {
+      unsigned v = 0u;
+      for (int i = 0; i < 4 && 4 * g + i < kCrtPlanes; ++i)
+        v |= ((unsigned)rw.w[q][4 * g + i] & 0xffu) << (8 * i);
+      rw.wp[q][g] = (int)v;
+    }
+  }
+}
+
 // Plans V = P 2^(eA_i + eX_j - 7 (ka1 + kx)) with P = Ã X̃ (ka1 digits of A, kx of X^(1),
 // reduction length npad): enough moduli that prod m_q > 4 2^hbits 128^(ka1 + kx) (so
 // |P| < M / 4), the digit weights of both residue passes and the triple-double constants.
@@ -301,35 +328,14 @@ bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec 
   int N = 0;
   while (N < (int)mods.size() && bits <= need) bits += std::log2((double)mods[N++]);
   if (bits <= need || ka1 > kCrtPlanes || kx > kCrtPlanes) return false;
-  wA.N = wX.N = rec.N = N;
-  wA.k = ka1;
-  wX.k = kx;
+  rec.N = N;
   rec.sh = -7 * (ka1 + kx);
+  res_weights(ka1, N, mods.data(), wA);
+  res_weights(kx, N, mods.data(), wX);
   for (int q = 0; q < N; ++q) {
     const int m = mods[q];
-    wA.m[q] = wX.m[q] = rec.m[q] = m;
-    wA.rmf[q] = wX.rmf[q] = 1.0f / (float)m;
+    rec.m[q] = m;
     rec.rm[q] = 1.0 / (double)m;
-    for (int t = 0; t < kCrtPlanes; ++t) wA.w[q][t] = wX.w[q][t] = 0;
-    // 128^(k-1-t) mod m, from the least significant digit up, in the symmetric range
-    auto sym = [m](long long v) { return (int)(v > m / 2 ? v - m : v); };
-    long long pw = 1;
-    for (int t = ka1 - 1; t >= 0; --t) {
-      wA.w[q][t] = sym(pw);
-      pw = pw * 128 % m;
-    }
-    pw = 1;
-    for (int t = kx - 1; t >= 0; --t) {
-      wX.w[q][t] = sym(pw);
-      pw = pw * 128 % m;
-    }
-    for (ResWeights *rw : {&wA, &wX})
-      for (int g = 0; g < (kCrtPlanes + 3) / 4; ++g) {
-        unsigned v = 0u;
-        for (int i = 0; i < 4 && 4 * g + i < kCrtPlanes; ++i)
-          v |= ((unsigned)rw->w[q][4 * g + i] & 0xffu) << (8 * i);
-        rw->wp[q][g] = (int)v;
-      }
     long long Mq = 1;   // (M / m_q) mod m_q
     for (int l = 0; l < N; ++l)
       if (l != q) Mq = Mq * (mods[l] % m) % m;
@@ -1338,27 +1344,101 @@ const char *refeig_strerror(int s) {
 
 int refeig_split_cols(const double *M, int ld, int rows, int cols, int k, int *exps,
                       int8_t *planes, double *trunc, refeig_stream_t stream) {
-  if (!M || !exps || !planes || rows < 1 || cols < 1 || ld < rows || k < 1 || k > 18)
+  return refeig_split_cols_ex(M, ld, rows, cols, k, nullptr, exps, planes, trunc, 0, nullptr,
+                              stream);
+}
+
+int refeig_split_cols_ex(const double *M, int ld, int rows, int cols, int k, const int *colmap,
+                         int *exps, int8_t *planes, double *trunc, int kT, int8_t *planesT,
+                         refeig_stream_t stream) {
+  if (!M || !exps || !planes || rows < 1 || cols < 1 || ld < rows || k < 1 || k > 18 ||
+      kT < 0 || kT > kKxMax || (kT > 0) != (planesT != nullptr))
     return REFEIG_E_ARG;
+  if (colmap)
+    for (int j = 0; j < cols; ++j)
+      if (colmap[j] < 0 || colmap[j] >= cols) return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   const int rpad = round_up(rows, kTile), cpad = round_up(cols, kTile);
   // exponents are produced for the padded column range; copy the first cols out
   int *cbuf = nullptr;
   HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipMalloc((void **)&cbuf, sizeof(int) * (2 * (size_t)cpad + 64)));
-  int *e_int = cbuf, *c_int = cbuf + cpad, *flags = cbuf + 2 * cpad;
-  HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), s));
-  launch_colstats(M, ld, rows, cols, cpad, e_int, c_int, nullptr, flags, s);
-  launch_split_cols(M, ld, rows, cols, e_int, k, planes, (size_t)rpad * cpad, rpad, cpad, trunc,
-                    rows, nullptr, 0, 0, s);
-  HIPCHK(hipMemcpyAsync(exps, e_int, sizeof(int) * cols, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMalloc((void **)&cbuf, sizeof(int) * (3 * (size_t)cpad + 64)));
+  int *e_int = cbuf, *c_int = cbuf + cpad, *dmap = cbuf + 2 * cpad, *flags = cbuf + 3 * cpad;
+  hipError_t err = hipSuccess;
+  if (colmap)
+    err = hipMemcpyAsync(dmap, colmap, sizeof(int) * cols, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) err = hipMemsetAsync(flags, 0, sizeof(int), s);
   int hf = 0;
-  HIPCHK(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipFree(cbuf));
-  HIPCHK(hipGetLastError());
+  if (err == hipSuccess) {
+    launch_colstats(M, ld, rows, cols, cpad, e_int, c_int, nullptr, flags, s,
+                    colmap ? dmap : nullptr);
+    launch_split_cols(M, ld, rows, cols, e_int, k, planes, (size_t)rpad * cpad, rpad, cpad,
+                      trunc, rows, planesT, (size_t)rpad * cpad, kT, s, colmap ? dmap : nullptr);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(exps, e_int, sizeof(int) * cols, hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess) err = hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  (void)hipFree(cbuf);
+  if (err != hipSuccess) {
+    fprintf(stderr, "refeig: refeig_split_cols_ex: %s\n", hipGetErrorString(err));
+    return REFEIG_E_HIP;
+  }
   if (hf & FLAG_NONFINITE) return REFEIG_E_NONFINITE;
   if (hf & FLAG_RANGE) return REFEIG_E_RANGE;
+  return REFEIG_OK;
+}
+
+int refeig_residue_planes(const int8_t *planes, size_t plane_stride, size_t count, int k,
+                          int nmod, const int *moduli, int8_t *res, refeig_stream_t stream) {
+  if (!planes || !res || !moduli || k < 1 || k > kCrtPlanes || nmod < 1 || nmod > kCrtMax ||
+      count == 0 || count % 4 != 0 || plane_stride < count || plane_stride % 4 != 0)
+    return REFEIG_E_ARG;
+  for (int q = 0; q < nmod; ++q)
+    if (moduli[q] < 3 || moduli[q] > 255 || moduli[q] % 2 == 0) return REFEIG_E_ARG;
+  ResWeights w;
+  res_weights(k, nmod, moduli, w);
+  hipStream_t s = (hipStream_t)stream;
+  launch_residues(planes, plane_stride, count, w, res, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return REFEIG_OK;
+}
+
+int refeig_residue_gemm(const int8_t *Lp, const int8_t *Rp, size_t plane_stride, int npad,
+                        int nmod, const int *moduli, const int *vblk, int8_t *C,
+                        refeig_stream_t stream) {
+  if (!Lp || !Rp || !C || !moduli || npad < kTile || npad % kTile || nmod < 1 ||
+      nmod > kCrtMax || plane_stride < (size_t)npad * npad || (vblk && npad < 1024))
+    return REFEIG_E_ARG;
+  for (int q = 0; q < nmod; ++q)
+    if (moduli[q] < 3 || moduli[q] > 255 || moduli[q] % 2 == 0) return REFEIG_E_ARG;
+  const int nb = npad / kTile;
+  if (vblk)
+    for (int b = 0; b < nb; ++b)
+      if (vblk[2 * b] < 0 || vblk[2 * b] > nmod || vblk[2 * b + 1] < 0 ||
+          vblk[2 * b + 1] >= kVLevels)
+        return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int *buf = nullptr;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMalloc((void **)&buf, sizeof(int) * (kCrtMax + 2 * (size_t)nb)));
+  hipError_t err = hipMemcpyAsync(buf, moduli, sizeof(int) * nmod, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess && vblk)
+    err = hipMemcpyAsync(buf + kCrtMax, vblk, sizeof(int) * 2 * nb, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) {
+    launch_slice_gemm(Lp, Rp, plane_stride, npad, nmod, nmod, 2, nmod, (int32_t *)C, nullptr, s,
+                      nullptr, nullptr, 0, true, nullptr, buf, false,
+                      vblk ? buf + kCrtMax : nullptr);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (err != hipSuccess) {
+    fprintf(stderr, "refeig: refeig_residue_gemm: %s\n", hipGetErrorString(err));
+    return REFEIG_E_HIP;
+  }
   return REFEIG_OK;
 }
 
@@ -1465,7 +1545,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   std::vector<double> gaps_nat;
   std::vector<int> cmap(n), cpl, tcut, htab[3];
   int hflags = 0;
-  hipEvent_t ev[8];
+  // ev[0] / ev[7]: iteration start / end; ev[1..6]: the three slice products; ev[8..17]:
+  // the phases (column statistics, split, V, W, update) for the report
+  hipEvent_t ev[18];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
 
   auto cleanup = [&](int st) {
@@ -1536,8 +1618,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     working_order(lam_prev, gaps_nat, cmap);
     STEP(hipMemcpyAsync(w.colmap, cmap.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     // ---- beta and kx from the previous eigenvalue estimates and column maxima of X
+    STEP(hipEventRecord(ev[8], s));
     launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap,
                     crt ? w.ssX : nullptr);
+    STEP(hipEventRecord(ev[9], s));
     STEP(hipMemcpyAsync(eX.data(), w.eX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(cX.data(), w.cX, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(mxX.data(), w.mxX, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -1566,8 +1650,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     beta_rule(n, xi, delta_k, gmin, lmax, eX, cX, mxX, &beta, &kx);
     if (o.kx_force > 0) kx = o.kx_force;
     // ---- X^(1) and its planes (both layouts)
+    STEP(hipEventRecord(ev[10], s));
     launch_split_cols(X, ldx, n, n, w.eX, kx, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kx, s,
                       w.colmap);
+    STEP(hipEventRecord(ev[11], s));
     // ---- V = A X^(1): per column j keep pair diagonals d <= dv(j)
     int eXmax = -100000;
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
@@ -1583,6 +1669,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int dv_allowed = std::min(ka_max + 1, kx + ka_max);
     const int ka = ka_max;
     CutPlan plan;
+    STEP(hipEventRecord(ev[12], s));
     int dv = 2, lv = 0;
     double pv = 0.0;
     bool by_res = false;
@@ -1620,6 +1707,15 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       for (int l = 0; l < kVLevels && ok; ++l)
         if (ka_l[l] > 0) ok = crt_plan(npad, ka_l[l], kx, wA[l], l == 0 ? wX : wXl, rec[l],
                                        hbits);
+      // The reconstruction resolves P to within 2^-115 M (four 34-bit limbs of at most 14
+      // terms), so V_ij carries up to 2^(eA_max + eX_j + sh - 115) M of it. Where that is not
+      // well inside column j's share theta delta gap_j, this iteration forms V by slices.
+      for (int j = 0; ok && j < n; ++j) {
+        if (mxX[j] == 0.0) continue;
+        const CrtRec &rl = rec[lvb[j / 256]];
+        const double fl = std::ldexp(rl.M[0], eA_max + eX[j] + rl.sh - 115);
+        if (!(fl <= 0.25 * theta * delta_k * gaps[j])) ok = false;
+      }
       if (ok) {
         by_res = true;
         // A's residues depend only on the digit count and the moduli: reused while they repeat
@@ -1667,6 +1763,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       launch_epi_v(w.Cs, npad, 2, dv - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
                    w.eR, w.resmax, w.RP, kKrMax, w.flags, s);
     }
+    STEP(hipEventRecord(ev[13], s));
     STEP(hipMemcpyAsync(lam.data(), w.lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(eR.data(), w.eR, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(resmax.data(), w.resmax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
@@ -1706,6 +1803,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int *tcut_dev = nullptr;
     double pw_tiles = -1.0;
     const int T = npad / 256;
+    STEP(hipEventRecord(ev[14], s));
     if (npad >= 1024) {
       // on the device (nothing for the host to wait for); the pair count of the report is
       // read back after the iteration
@@ -1735,6 +1833,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     launch_epi_w(w.Cs, npad, 2, dw - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n, w.eE,
                  w.emax, w.EP, kKeMax, w.flags, s, o.group_tau, grouping ? w.cpl : nullptr,
                  w.cpl + 64, kCouplingsMax, tcut_dev);
+    STEP(hipEventRecord(ev[15], s));
     STEP(hipMemcpyAsync(eE.data(), w.eE, sizeof(int) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(emax.data(), w.emax, sizeof(double) * npad, hipMemcpyDeviceToHost, s));
     STEP(hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1865,10 +1964,12 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     const int nbu = prepare_table(plan, npad, kE, kxu, htab[2], w.tab[2], s);
     if (nbu < 0) return cleanup(REFEIG_E_HIP);
     if (nbu > 0) lu = 1;
+    STEP(hipEventRecord(ev[16], s));
     launch_plan(plan, w.EP, w.XPT, P, npad, kE, kxu, w.Cs, s, ev[5], ev[6], 0, nullptr, w.tab[2],
                 nbu);
     launch_epi_u(w.Cs, npad, 2, du - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s, w.colmap);
     launch_scatter(w.lam, w.colmap, n, D, s);
+    STEP(hipEventRecord(ev[17], s));
     STEP(hipEventRecord(ev[7], s));
     STEP(hipGetLastError());
     STEP(hipEventSynchronize(ev[7]));
@@ -1888,6 +1989,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     (void)hipEventElapsedTime(&g1, ev[1], ev[2]);
     (void)hipEventElapsedTime(&g2, ev[3], ev[4]);
     (void)hipEventElapsedTime(&g3, ev[5], ev[6]);
+    float ph[5] = {0, 0, 0, 0, 0};
+    for (int q = 0; q < 5; ++q) (void)hipEventElapsedTime(&ph[q], ev[8 + 2 * q], ev[9 + 2 * q]);
     if (rep && it < REFEIG_MAX_ITERS) {
       rep->beta[it] = beta;
       rep->kx[it] = kx;
@@ -1912,6 +2015,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       rep->launches_p[it][2] = lu;
       rep->groups[it] = ngroups;
       rep->delta_it[it] = delta_k;
+      rep->vres[it] = by_res ? 1 : 0;
+      for (int q = 0; q < 5; ++q) rep->ms_phase[it][q] = ph[q];
       rep->iters = it + 1;
       rep->min_gap = gmin;
       rep->max_abs_lambda = lmax;

@@ -85,3 +85,9 @@ def test_binding_struct_layout_matches_header(lib, cname, pyname):
     assert ctypes.sizeof(py) == size
     for f, off in zip(fields, offs):
         assert getattr(py, f).offset == off, f
+
+
+def test_binding_lists_every_declared_symbol():
+    """binding.EXPORTED names exactly the functions the header declares."""
+    from paper_2602_19090_amd import binding as rb
+    assert sorted(rb.EXPORTED) == _declared()
