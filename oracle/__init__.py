@@ -24,7 +24,8 @@ CFLAGS = ["-O3", "-mavx2", "-mfma", "-fopenmp", "-ffp-contract=off", "-fno-fast-
 
 
 def build(force: bool = True) -> str:
-    srcs = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle_herm.c")]
+    srcs = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle_herm.c"),
+            os.path.join(_HERE, "allcols.c")]
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"])
@@ -69,6 +70,10 @@ def _load():
         lib.or_herm_method_step.argtypes = [_c_int, _D, _D, _D, _D, _D, _c_double, _c_double,
                                             _c_int, _c_int, _D, _D, _D, _D, _D, _D, _D, _D, _D,
                                             _D, _I, _I]
+        lib.or_dd_acc.argtypes = [ctypes.c_size_t, _D, _D, _D]
+        lib.or_dd_norm.argtypes = [ctypes.c_size_t, _D, _D]
+        lib.or_colpass.argtypes = [_c_int, _c_int, _D, _D, _D, _D, _D, _D, _D]
+        lib.or_form_e.argtypes = [_c_int, _D, _D, _D, _D, _D, _D, _D, _D]
         lib.or_two_sum.argtypes = [_c_double, _c_double, _D, _D]
         lib.or_two_prod.argtypes = [_c_double, _c_double, _D, _D]
         lib.or_dd_binop.argtypes = [_c_int, _c_double, _c_double, _c_double, _c_double, _D, _D]

@@ -580,27 +580,54 @@ int or_sigma_split(int by_rows, int m, int ncols, const double *M, int ld, int a
 {
     size_t sz = (size_t)m * ncols;
     double *rem = slices + (size_t)ns * sz;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ncols; ++j)
         for (int i = 0; i < m; ++i) rem[IX(i, j, m)] = M[IX(i, j, ld)];
-    int nvec = by_rows ? m : ncols, len = by_rows ? ncols : m;
+    int nvec = by_rows ? m : ncols;
+    double *sig = (double *)malloc(sizeof(double) * (size_t)(nvec > 0 ? nvec : 1));
+    if (!sig) return -5;
     for (int r = 0; r < ns; ++r) {
         double *out = slices + (size_t)r * sz;
-        for (int v = 0; v < nvec; ++v) {
-            double mx = 0.0;
-            for (int t = 0; t < len; ++t) {
-                double a = by_rows ? rem[IX(v, t, m)] : rem[IX(t, v, m)];
-                if (fabs(a) > mx) mx = fabs(a);
+        /* sigma of each row / column from the maximum of its current remainder (the
+         * traversal order does not change a maximum) */
+        if (by_rows) {
+#pragma omp parallel for schedule(static)
+            for (int ib = 0; ib < m; ib += 64) {
+                int ie = ib + 64 < m ? ib + 64 : m;
+                double mx[64];
+                for (int i = ib; i < ie; ++i) mx[i - ib] = 0.0;
+                for (int j = 0; j < ncols; ++j)
+                    for (int i = ib; i < ie; ++i) {
+                        double a = fabs(rem[IX(i, j, m)]);
+                        if (a > mx[i - ib]) mx[i - ib] = a;
+                    }
+                for (int i = ib; i < ie; ++i)
+                    sig[i] = (mx[i - ib] == 0.0) ? 0.0 : ldexp(0.75, ceil_log2(mx[i - ib]) + alpha);
             }
-            double sigma = (mx == 0.0) ? 0.0 : ldexp(0.75, ceil_log2(mx) + alpha);
-            for (int t = 0; t < len; ++t) {
-                size_t q = by_rows ? IX(v, t, m) : IX(t, v, m);
+        } else {
+#pragma omp parallel for schedule(static)
+            for (int j = 0; j < ncols; ++j) {
+                double mx = 0.0;
+                for (int i = 0; i < m; ++i) {
+                    double a = fabs(rem[IX(i, j, m)]);
+                    if (a > mx) mx = a;
+                }
+                sig[j] = (mx == 0.0) ? 0.0 : ldexp(0.75, ceil_log2(mx) + alpha);
+            }
+        }
+        /* slice = fl((sigma + a) - sigma), a <- fl(a - slice) */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < ncols; ++j)
+            for (int i = 0; i < m; ++i) {
+                size_t q = IX(i, j, m);
+                double sigma = by_rows ? sig[i] : sig[j];
                 volatile double s1 = sigma + rem[q];
                 double sl = s1 - sigma;
                 out[q] = sl;
                 rem[q] = rem[q] - sl;
             }
-        }
     }
+    free(sig);
     return 0;
 }
 

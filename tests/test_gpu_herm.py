@@ -6,6 +6,7 @@ phases, a real symmetric input against the real path's X_true)."""
 import numpy as np
 import pytest
 
+import lambda_bounds
 import oracle
 import workloads
 
@@ -57,8 +58,12 @@ def test_herm_one_step_vs_oracle(cfg, n, target):
           f"|X_gpu - X_oracle|max={diff:.3e}", flush=True)
     assert diff <= target / opts.delta_safety
     lam = D.cpu().numpy()
-    assert float(np.max(np.abs(lam - ref.lam_h))) <= (target / opts.delta_safety) * float(
-        np.max(np.abs(ref.lam_h)))
+    tol = lambda_bounds.one_step_tol(ref.X1, ref.lam_h, lambda_bounds.entry_gaps(p.D0),
+                                     target / opts.delta_safety,
+                                     float(np.max(np.abs(ref.lam_h))), opts.theta, cplx=True)
+    ratio = np.abs(lam - ref.lam_h) / tol
+    print(f"  eigenvalues: max |err| / bound = {float(np.max(ratio)):.3e}", flush=True)
+    assert np.all(ratio <= 1.0)
 
 
 @pytest.mark.parametrize("cfg,n,target", [(1, 100, 1e-14), (2, 300, 1e-12), (3, 700, 1e-14),
@@ -76,7 +81,20 @@ def test_herm_refine_to_target(cfg, n, target):
           f"fwd={err:.3e}", flush=True)
     assert st == rb.REFEIG_OK, rb.strerror(st)
     assert err <= target
-    assert float(np.max(np.abs(D.cpu().numpy() - lt))) <= target * float(np.max(np.abs(lt)))
+    # eigenvalues within their derived bound (lambda_bounds); the last iteration's input is
+    # the solve of one iteration fewer
+    K = rep.iters
+    _, Xin, Din = _dev(p)
+    if K > 1:
+        st1, _ = rb.refine_eigvecs_herm(A, Xin, Din, target, rb.default_opts(fixed_iters=K - 1))
+        assert st1 == rb.REFEIG_OK
+    Xi = rb.from_colmajor(Xin)
+    tol = lambda_bounds.solve_tol(Xi, oracle.phase_align(Xi, Xt), rep.kx[K - 1], lt,
+                                  lambda_bounds.entry_gaps(Din.cpu().numpy()), target / 8.0,
+                                  float(np.max(np.abs(lt))), cplx=True)
+    ratio = np.abs(D.cpu().numpy() - lt) / tol
+    print(f"  eigenvalues: max |err| / bound = {float(np.max(ratio)):.3e}", flush=True)
+    assert np.all(ratio <= 1.0)
 
 
 def test_herm_loose_target_is_a_stable_fixed_point():
