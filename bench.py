@@ -317,13 +317,13 @@ def config4_leg(count):
             "lanes": 8}
 
 
-def serve_leg(rates, nreq, pool_size=16, lanes=8):
+def serve_leg(rates, nreq, pool_size=256, lanes=4, budget_gib=64.0):
     """Serving (config 5): requests arrive as a Poisson process and draw a problem from a
     pool (n = round(exp(U(ln 128, ln 8192))), cond 10^U(4,12), target from {1e-8, 1e-11,
     1e-14}, FP64-eigh start), all resident on the device. Each request is submitted to the
-    continuous-batching server at its arrival time and starts as soon as one of its lanes is
-    free; latency = completion - arrival. Reports p50/p99 latency and completed matrices/s
-    per rate."""
+    continuous-batching server at its arrival time; it starts when one of the lanes is free
+    and its workspace fits in the server's arena (admission by HBM footprint). Latency =
+    completion - arrival. Reports p50/p99 latency and completed matrices/s per rate."""
     import numpy as np
     import torch
     import workloads
@@ -332,7 +332,10 @@ def serve_leg(rates, nreq, pool_size=16, lanes=8):
     ns = np.rint(np.exp(rng.uniform(np.log(128.0), np.log(8192.0), pool_size))).astype(int)
     cs = rng.uniform(4.0, 12.0, pool_size)
     ts = rng.choice([1e-8, 1e-11, 1e-14], pool_size)
-    log(f"serving pool: {pool_size} problems, n {ns.min()}..{ns.max()}, {lanes} lanes")
+    budget = int(budget_gib * 2 ** 30)
+    log(f"serving pool: {pool_size} problems, n {ns.min()}..{ns.max()}, {lanes} lanes, "
+        f"arena {budget_gib:g} GiB")
+    t_pool = time.perf_counter()
     pool = []
     for i, (n, c, t) in enumerate(zip(ns, cs, ts)):
         q = workloads.make_problem(5, int(n), index=i, x0="none", cond_exp=float(c))
@@ -341,20 +344,21 @@ def serve_leg(rates, nreq, pool_size=16, lanes=8):
         pool.append((A, V.t().contiguous(), w.contiguous(), float(t)))
         del V
     torch.cuda.synchronize()
-    srv = rb.Server(lanes, int(ns.max()))
+    log(f"serving pool ready ({time.perf_counter() - t_pool:.0f} s)")
+    foot = [rb.server_request_bytes(int(n)) for n in ns]
+    srv = rb.Server(lanes, budget)
     out = []
     try:
-        # warm the path once per pool entry
+        # warm the path once per distinct pool entry (one pass, all submitted at once)
         warm = [(e[1].clone(), e[2].clone()) for e in pool]
-        torch.cuda.synchronize()
         for k in [srv.submit(e[0], X, D, e[3]) for e, (X, D) in zip(pool, warm)]:
             srv.wait(k)
+        del warm
         for rate in rates:
             arr_rng = np.random.default_rng([2602, 19090, 5, int(rate * 1000)])
             arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, nreq))
             picks = arr_rng.integers(0, pool_size, nreq)
             reqs = [(pool[k][1].clone(), pool[k][2].clone()) for k in picks]
-            torch.cuda.synchronize()   # the copies are done before any lane reads them
             tickets = []
             t0 = time.monotonic()
             for i in range(nreq):
@@ -362,6 +366,7 @@ def serve_leg(rates, nreq, pool_size=16, lanes=8):
                 if wait_s > 0:
                     time.sleep(wait_s)
                 e = pool[picks[i]]
+                # the copies were enqueued on this stream: the server waits for them
                 tickets.append(srv.submit(e[0], reqs[i][0], reqs[i][1], e[3]))
             done = np.zeros(nreq)
             for i, k in enumerate(tickets):
@@ -373,36 +378,61 @@ def serve_leg(rates, nreq, pool_size=16, lanes=8):
             span = done.max() - arrivals[0]
             out.append({"rate_req_s": rate, "requests": nreq,
                         "p50_ms": float(np.percentile(lat, 50)),
-                        "p99_ms": float(np.percentile(lat, 99)), "matrices_per_s": nreq / span,
-                        "lanes": lanes})
+                        "p99_ms": float(np.percentile(lat, 99)), "matrices_per_s": nreq / span})
             log(f"serving at {rate:g} req/s: p50 {out[-1]['p50_ms']:.0f} ms, p99 "
                 f"{out[-1]['p99_ms']:.0f} ms, {out[-1]['matrices_per_s']:.1f} matrices/s")
     finally:
         srv.close()
-    return {"pool": {"size": pool_size, "n": [int(n) for n in ns]}, "lanes": lanes,
-            "engine": "continuous batching (refeig_server)", "rates": out}
+    return {"pool": {"size": pool_size, "n_min": int(ns.min()), "n_max": int(ns.max()),
+                     "n_median": float(np.median(ns)),
+                     "footprint_gib_max": max(foot) / 2 ** 30},
+            "lanes": lanes, "arena_gib": budget_gib,
+            "engine": "continuous batching, admission by HBM footprint (refeig_server)",
+            "rates": out}
 
 
-def cpu_baseline(A, X0cm, n, cols):
-    """Time the oracle's double-double products on `cols` columns and scale to one
-    iteration (three n x n x n double-double products)."""
+def cpu_baseline(A, X0cm, Xcm, lam, n, cols):
+    """The oracle on the host's cores. (1) Its double-double product (oracle.dd_gemm, plain C
+    with OpenMP) timed on one full V-type product A X at order n, plus a W-type product
+    X^T X on `cols` columns; one iteration = that V product and two double-double products of
+    n x n x n (the W-type time scaled by (n / cols)^2). (2) The all-column check of the timed
+    solve's result: one double-double step of Algorithm 1 from it (oracle/dd_numpy.py, exact
+    FP64 slice products on the host BLAS) estimates every column's forward error."""
     import numpy as np
     import oracle
-    X = np.asfortranarray(X0cm[:cols].cpu().numpy().T)       # n x cols
-    Xl = np.zeros_like(X, order="F")
+    from oracle import dd_numpy as dn
+    X = np.asfortranarray(X0cm.cpu().numpy().T)                     # n x n, the FP64 start
     t0 = time.perf_counter()
-    oracle.dd_gemm(A, X, None, Xl)                          # V-type: FP64 x double-double
+    oracle.dd_gemm(A, X, None, np.zeros_like(X, order="F"))        # V-type: FP64 x double-double
     t1 = time.perf_counter()
-    oracle.dd_gemm(X, X, Xl, Xl, transA=True)                # W-type: double-double x double-double
+    Xc = np.asfortranarray(X[:, :cols])
+    Xl = np.zeros_like(Xc, order="F")
+    oracle.dd_gemm(Xc, Xc, Xl, Xl, transA=True)                      # W-type on a column sample
     t2 = time.perf_counter()
-    # per iteration: one V-type product and two double-double products of n x n x n
-    t_iter = ((t1 - t0) + 2 * (t2 - t1) * (n / cols)) * (n / cols)
+    t_w = (t2 - t1) * (n / cols) ** 2
+    t_iter = (t1 - t0) + 2 * t_w
     tflops = 6.0 * n ** 3 / t_iter / 1e12
+    Xf = np.asfortranarray(Xcm.cpu().numpy().T)
+    res = dn.allcols_forward_error(A, Xf, lam)
+    import subprocess
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(
+            ["lscpu"], capture_output=True, text=True).stdout.splitlines()
+            if l.startswith("Model name")][0]
+    except Exception:
+        model = "unknown"
     return {"value": tflops, "unit": "TFLOP/s (FP64-equivalent)", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"double-double products A*X[:, :{cols}] and X[:, :{cols}]^T X[:, :{cols}] "
-                      f"at n={n} ({t2 - t0:.1f} s), scaled to one iteration "
-                      f"(3 products of n x n x n): {t_iter:.0f} s per iteration"}
+            "cpu_model": model, "kind": "oracle",
+            "sample": f"double-double product A*X at n={n}, all columns ({t1 - t0:.1f} s), and "
+                      f"X^T X on {cols} columns ({t2 - t1:.1f} s, scaled by (n/{cols})^2 to "
+                      f"{t_w:.0f} s for the two products of W and X E~ type): "
+                      f"{t_iter:.0f} s per iteration (3 products of n x n x n)",
+            "all_columns": {"fwd_err_max": float(res["est"].max()),
+                            "second_order_max": float(res["second"].max()),
+                            "columns": int(n), "seconds": res["seconds"],
+                            "method": "one double-double step of Algorithm 1 from the solve's "
+                                      "X (exact FP64 slice products on the host BLAS); "
+                                      "estimate max_i |(X E~)_ij| per column"}}
 
 
 def main():
@@ -413,16 +443,17 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--target", type=float, default=1e-14)
-    ap.add_argument("--cpu-cols", type=int, default=2048)
+    ap.add_argument("--cpu-cols", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain-form leg")
-    ap.add_argument("--config4", type=int, default=0, metavar="COUNT",
-                    help="also time a batch of COUNT config-4 matrices (n log-uniform in "
-                         "[32, 1024], cond 10^U(4,12), 3 iterations) through the batched entry point")
-    ap.add_argument("--serve", type=str, default="", metavar="RATES",
-                    help="also run the serving workload (config 5) at these Poisson arrival "
-                         "rates, comma-separated requests/s, e.g. 2,5,10,20")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--config4", type=int, default=512, metavar="COUNT",
+                    help="the batch of COUNT config-4 matrices (n log-uniform in [32, 1024], "
+                         "cond 10^U(4,12), 3 iterations) through the batched entry point; 0 skips")
+    ap.add_argument("--serve", type=str, default="50,100,200,500,1000,2000", metavar="RATES",
+                    help="the serving workload (config 5) at these Poisson arrival rates, "
+                         "comma-separated requests/s; empty skips")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--ab-kx", type=int, default=0, metavar="K",
                     help="also time the solve with X-hat's digit planes fixed at K (9 = the "
                          "previous study's untruncated X-hat) for the paper's A/B")
@@ -530,6 +561,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall0
     final_err = sampled_error(Xw, golden) if golden is not None else None
+    X_main = Xw.clone()   # the timed solve's result (later legs reuse Xw)
     ms_step = float(np.mean(ms))
     value = 6.0 * n ** 3 * K / (ms_step * 1e-3) / 1e12
 
@@ -596,8 +628,8 @@ def main():
         log("FP8 ablation: pair products of E4M3 and INT8 digits")
         fp8 = fp8_leg(rb, A, X0, D0)
     batch = config4_leg(args.config4) if args.config4 > 0 else None
-    serve = serve_leg([float(r) for r in args.serve.split(",")], args.serve_requests) \
-        if args.serve else None
+    serve = serve_leg([float(r) for r in args.serve.split(",")], args.serve_requests,
+                      pool_size=args.serve_pool) if args.serve else None
     ab = None
     if args.ab_kx > 0 and golden is not None:
         log(f"A/B: X-hat planes fixed at {args.ab_kx}: iterations to the target")
@@ -694,7 +726,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle double-double products on a column sample")
-        cpu = cpu_baseline(p.A, X0, n, args.cpu_cols)
+        cpu = cpu_baseline(p.A, X0, X_main,
+                           golden["lam"] if golden is not None else Dw.cpu().numpy(), n,
+                           args.cpu_cols)
 
     r0 = reps[0]
     out = {

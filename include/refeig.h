@@ -216,30 +216,40 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
 
 const char *refeig_strerror(int status);
 
-/* Continuous-batching server for Algorithm 1 per request (the serving
- * workload: requests of uneven n that arrive while others run). refeig_server_create starts `lanes` host threads,
- * each with its own stream (default priority) and a workspace for orders up to
- * max_n, all allocated here (about lanes * refeig_workspace_bytes(max_n)); the
- * device is the one current in the calling thread. refeig_server_submit queues
- * one refine_eigvecs problem (device pointers as there; the caller keeps A, X
- * and D alive and untouched until the request is waited for) and returns at
- * once with a ticket; a lane starts it as soon as the lane is free, so requests
- * overlap on the device and a short one does not wait for a long one admitted
- * before it. Each result is bit for bit what refine_eigvecs returns for that
- * problem alone. refeig_server_wait blocks until the ticket's request is done
- * and returns its status, report (may be NULL) and completion time t_done (may
- * be NULL; seconds on the monotonic clock, CLOCK_MONOTONIC). Requests are
- * served in submission order as lanes free up. REFEIG_E_ARG for n > max_n, a
- * NULL pointer or an unknown ticket; REFEIG_E_NOMEM / REFEIG_E_HIP from create
- * when the workspaces or streams cannot be made. refeig_server_destroy waits
- * for every submitted request, then frees everything. */
+/* Continuous-batching server for Algorithm 1 per request (the serving workload: requests
+ * of uneven n that arrive while others run), with admission by HBM footprint.
+ * refeig_server_create allocates one device arena of budget_bytes on the device current in
+ * the calling thread and starts `lanes` host threads, each with its own stream (default
+ * priority). A request's footprint is its workspace, refeig_server_request_bytes(n); it holds
+ * that much of the arena from its start until it completes. A request starts when a lane is
+ * free and its footprint fits in the arena's free space: the oldest pending one that fits
+ * starts; one that does not fit yet may be passed by later ones at most 4 times, after which
+ * nothing starts before it. Requests overlap on the device, and a short one does not wait
+ * for a long one admitted before it. The machine's GPU runs 4 hardware queues per process by
+ * default: with more than 4 lanes, lanes share queues.
+ * refeig_server_submit queues one refine_eigvecs problem (device pointers as there; the caller
+ * keeps A, X and D alive and untouched until the request is waited for) and returns at once
+ * with a ticket. An event is recorded on `stream` (the caller's, NULL = default) at
+ * submission; the lane waits for it before reading, so async writes of A, X or D that the
+ * caller enqueued on that stream come first. REFEIG_E_NOMEM when the footprint exceeds the
+ * budget (the request could never start), REFEIG_E_ARG for bad arguments.
+ * refeig_server_wait blocks until the ticket's request is done and returns its status,
+ * report (may be NULL) and completion time t_done (may be NULL; seconds on the monotonic
+ * clock, CLOCK_MONOTONIC); a ticket is waited for once (REFEIG_E_ARG for an unknown or
+ * already waited ticket). Each result is bit for bit what refine_eigvecs returns for that
+ * problem alone. refeig_server_destroy waits for every submitted request, then frees
+ * everything. */
 typedef struct refeig_server refeig_server;
-int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_server **server);
+int refeig_server_create(int lanes, size_t budget_bytes, const refeig_opts *o,
+                         refeig_server **server);
 int refeig_server_submit(refeig_server *server, const double *A, int lda, double *X, int ldx,
-                         double *D, int n, double target_fwd_err, int *ticket);
+                         double *D, int n, double target_fwd_err, refeig_stream_t stream,
+                         int *ticket);
 int refeig_server_wait(refeig_server *server, int ticket, int *status, refeig_report *report,
                        double *t_done);
 int refeig_server_destroy(refeig_server *server);
+/* Footprint of one request of order n in the server's arena (host out-pointer). */
+int refeig_server_request_bytes(int n, const refeig_opts *o, size_t *bytes);
 
 /* The largest number of nonzero entries in a row of A (device, n x n, ld lda),
  * the k of the sparse rule (Sec. 4.3). Synchronous; *k is a host int. */
@@ -271,6 +281,15 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
  * Returns REFEIG_E_ARG when more than 28 moduli would be needed. */
 int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
                          double *U, double *L, double *M);
+/* Host-only: the server's admission rule on a fake executor. count requests arrive at
+ * t_arr[i] (seconds, ascending), each holding bytes[i] of an arena of budget bytes (both
+ * rounded up to 256) for dur[i] seconds once started, served by `lanes` lanes; completions
+ * are handled before arrivals at equal times. t_start[i] receives each request's start time
+ * (-1 for a request larger than the budget, which never starts) and offset[i] (may be NULL)
+ * its arena offset. */
+int refeig_host_admission_sim(int count, const double *t_arr, const size_t *bytes,
+                              const double *dur, int lanes, size_t budget, double *t_start,
+                              size_t *offset);
 /* Working column order of an iteration: columns by the gap of their eigenvalue
  * estimate to its nearest neighbour, widest first, ties by eigenvalue.
  * order[p] = the column placed at working position p (host arrays of n). */

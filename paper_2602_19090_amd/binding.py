@@ -99,9 +99,11 @@ _lib.refeig_residue_planes.argtypes = [_vp, _sz, _sz, _int, _int, _vp, _vp, _vp]
 _lib.refeig_residue_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm_fp8.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 _lib.refeig_digits_to_e4m3.argtypes = [_vp, _vp, _sz, _vp]
-_lib.refeig_server_create.argtypes = [_int, _int, ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
-_lib.refeig_server_submit.argtypes = [_vp, _vp, _int, _vp, _int, _vp, _int, _dbl,
+_lib.refeig_server_create.argtypes = [_int, _sz, ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
+_lib.refeig_server_submit.argtypes = [_vp, _vp, _int, _vp, _int, _vp, _int, _dbl, _vp,
                                       ctypes.POINTER(_int)]
+_lib.refeig_server_request_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_lib.refeig_host_admission_sim.argtypes = [_int, _vp, _vp, _vp, _int, _sz, _vp, _vp]
 _lib.refeig_server_wait.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(Report),
                                     ctypes.POINTER(_dbl)]
 _lib.refeig_server_destroy.argtypes = [_vp]
@@ -125,7 +127,7 @@ EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "
             "refeig_residue_planes", "refeig_residue_gemm", "refeig_slice_gemm_fp8",
             "refeig_digits_to_e4m3", "refeig_batched_workspace_bytes",
             "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
-            "refeig_server_destroy",
+            "refeig_server_destroy", "refeig_server_request_bytes", "refeig_host_admission_sim",
             "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
             "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
@@ -255,26 +257,28 @@ def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=N
 
 
 class Server:
-    """The continuous-batching server (refeig_server_*): submit() returns a ticket at once;
-    wait(ticket) returns (status, report, t_done) with t_done on time.monotonic()'s clock.
-    The tensors of a request must stay alive until it is waited for (kept here until then)."""
+    """The continuous-batching server (refeig_server_*) with admission by HBM footprint:
+    a device arena of budget_bytes, `lanes` concurrent requests at most. submit() returns a
+    ticket at once (the request waits for the work already enqueued on torch's current
+    stream); wait(ticket) returns (status, report, t_done) with t_done on time.monotonic()'s
+    clock. The tensors of a request are kept alive here until it is waited for."""
 
-    def __init__(self, lanes: int, max_n: int, opts: Opts | None = None):
+    def __init__(self, lanes: int, budget_bytes: int, opts: Opts | None = None):
         self._h = _vp()
-        st = _lib.refeig_server_create(int(lanes), int(max_n),
+        st = _lib.refeig_server_create(int(lanes), int(budget_bytes),
                                        ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(self._h))
         if st != 0:
             raise RuntimeError(strerror(st))
         self._keep = {}
 
-    def submit(self, A, X, D, target: float) -> int:
+    def submit(self, A, X, D, target: float, stream=None) -> int:
         n = D.numel()
         assert A.is_cuda and X.is_cuda and D.is_cuda and A.is_contiguous() and X.is_contiguous()
         assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
         t = _int(0)
         st = _lib.refeig_server_submit(self._h, _ptr(A), n, _ptr(X), n, _ptr(D), n,
-                                       float(target), ctypes.byref(t))
+                                       float(target), _stream(stream), ctypes.byref(t))
         if st != 0:
             raise ValueError(strerror(st))
         self._keep[t.value] = (A, X, D)
@@ -294,6 +298,26 @@ class Server:
             _lib.refeig_server_destroy(self._h)
             self._h = _vp()
             self._keep.clear()
+
+
+def server_request_bytes(n: int, opts: Opts | None = None) -> int:
+    b = _sz()
+    st = _lib.refeig_server_request_bytes(int(n), ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(b))
+    if st != 0:
+        raise ValueError(strerror(st))
+    return b.value
+
+
+def host_admission_sim(t_arr, nbytes, dur, lanes: int, budget: int):
+    """refeig_host_admission_sim: (status, t_start, offsets)."""
+    t = np.ascontiguousarray(t_arr, dtype=np.float64)
+    b = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    d = np.ascontiguousarray(dur, dtype=np.float64)
+    ts = np.empty(len(t)); off = np.empty(len(t), dtype=np.uint64)
+    st = _lib.refeig_host_admission_sim(len(t), _np_ptr(t), _np_ptr(b), _np_ptr(d), int(lanes),
+                                        int(budget), _np_ptr(ts), _np_ptr(off))
+    return st, ts, off
 
 
 def row_nonzeros(A, stream=None) -> int:

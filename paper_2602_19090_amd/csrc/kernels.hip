@@ -246,8 +246,16 @@ void launch_colstats(const double *M, int ld, int rows, int cols, int cols_pad, 
 // ---------------------------------------------------------------- digit planes
 constexpr int kMaxPlanesSplit = 18;
 constexpr int kMaxPlanesT = 9;
-constexpr int kTStride = 80;  // LDS row stride of the transpose tile (16-byte aligned)
+constexpr int kSplitRow = 80;  // LDS row stride of a staged 64 x 64 digit tile (16-byte aligned)
+constexpr int kTStride = 80;   // LDS row stride of the complex splitter's transpose tile
 
+// One block splits a 64 x 64 tile (rows i0.., columns j0..) of M; thread (ig, jg) holds the
+// 4 x 4 micro-tile of rows i0 + 4 ig .. + 3 and columns j0 + 4 jg .. + 3. Per plane, each
+// thread packs its 16 digits into four column words (4 rows of one column) and, for the
+// transposed layout, four row words (4 columns of one row), stages them in LDS, and the
+// block writes each layout's tile as one contiguous 4 KiB run (in the K-blocked layout a
+// 64 x 64 tile is contiguous), 16 bytes per thread. Reads and the X^(1) writes take 32
+// contiguous bytes per thread and column.
 template <bool WITH_T>
 __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M, int ld, int rows,
                                                     int cols, const int *__restrict__ e, int k,
@@ -256,52 +264,88 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
                                                     int ldt, int8_t *__restrict__ planesT,
                                                     size_t pstrideT, int kT,
                                                     const int *__restrict__ colmap) {
-  __shared__ __attribute__((aligned(16))) int8_t sT[WITH_T ? kMaxPlanesT * 64 * kTStride : 16];
+  __shared__ __attribute__((aligned(16))) int8_t sC[64 * kSplitRow];
+  __shared__ __attribute__((aligned(16))) int8_t sR[WITH_T ? 64 * kSplitRow : 16];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  const int ig = threadIdx.x & 15, jl = threadIdx.x >> 4;
+  const int tid = threadIdx.x, ig = tid & 15, jg = tid >> 4;
   const int kk = (WITH_T && kT > k) ? kT : k;
-#pragma unroll 1
-  for (int q = 0; q < 4; ++q) {
-    const int jj = jl + 16 * q, j = j0 + jj;
-    const int ej = (j < cols) ? e[j] : 0;
-    const size_t mcol = (j < cols) ? (size_t)(colmap ? colmap[j] : j) * ld : 0;
-    unsigned packed[kMaxPlanesSplit];
+  const int ib = i0 + 4 * ig;
+  // 16-byte aligned runs of 4 rows
+  const bool vec = (ld % 2 == 0) && ((uintptr_t)M % 16 == 0) && ib + 3 < rows;
+  double y[4][4], val[4][4];
+  bool neg[4][4];
+  int ej[4];
+  const double *colp[4];
 #pragma unroll
-    for (int t = 0; t < kMaxPlanesSplit; ++t) packed[t] = 0u;
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + 4 * jg + c;
+    ej[c] = (j < cols) ? e[j] : 0;
+    colp[c] = (j < cols) ? M + (size_t)(colmap ? colmap[j] : j) * ld : nullptr;
+    double a[4];
+    if (colp[c] && vec) {
+      const double2 lo = *(const double2 *)(colp[c] + ib);
+      const double2 hi = *(const double2 *)(colp[c] + ib + 2);
+      a[0] = lo.x; a[1] = lo.y; a[2] = hi.x; a[3] = hi.y;
+    } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ii = 4 * ig + u, i = i0 + ii;
-      const double a = (i < rows && j < cols) ? M[mcol + i] : 0.0;
-      double y = ldexp(fabs(a), -ej);
-      const int sg = (a < 0.0) ? -1 : 1;
-      double val = 0.0;
-#pragma unroll
-      for (int t = 0; t < kMaxPlanesSplit; ++t) {
-        if (t < kk) {
-          double t128 = y * 128.0;
-          double d = floor(t128);
-          y = t128 - d;
-          int dig = sg * (int)d;
-          if (t < k) {
-            packed[t] |= ((unsigned)(dig & 0xff)) << (8 * u);
-            val += ldexp(d, ej - 7 * (t + 1));
-          }
-          if (WITH_T && t < kT) sT[(t * 64 + ii) * kTStride + jj] = (int8_t)dig;
-        }
-      }
-      if (trunc && i < rows && j < cols) trunc[(size_t)j * ldt + i] = (a < 0.0) ? -val : val;
+      for (int u = 0; u < 4; ++u) a[u] = (colp[c] && ib + u < rows) ? colp[c][ib + u] : 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < kMaxPlanesSplit; ++t)
-      if (t < k)
-        *(unsigned *)(planes + (size_t)t * pstride + kb_off(j, i0 + 4 * ig, cpad)) = packed[t];
+    for (int u = 0; u < 4; ++u) {
+      y[u][c] = ldexp(fabs(a[u]), -ej[c]);
+      neg[u][c] = a[u] < 0.0;
+      val[u][c] = 0.0;
+    }
   }
-  if (WITH_T) {
+  const int rr = tid >> 2, q16 = (tid & 3) * 16;   // this thread's 16 bytes of a staged tile
+#pragma unroll 1
+  for (int t = 0; t < kk; ++t) {
+    unsigned cw[4] = {0u, 0u, 0u, 0u}, rw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double t128 = y[u][c] * 128.0;
+        const double d = floor(t128);
+        y[u][c] = t128 - d;
+        if (t < k) val[u][c] += ldexp(d, ej[c] - 7 * (t + 1));
+        const unsigned b = (unsigned)((neg[u][c] ? -(int)d : (int)d) & 0xff);
+        cw[c] |= b << (8 * u);
+        rw[u] |= b << (8 * c);
+      }
+    if (t < k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) *(unsigned *)(sC + (4 * jg + c) * kSplitRow + 4 * ig) = cw[c];
+    if (WITH_T && t < kT)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) *(unsigned *)(sR + (4 * ig + u) * kSplitRow + 4 * jg) = rw[u];
     __syncthreads();
-    const int ii = threadIdx.x >> 2, jq = (threadIdx.x & 3) * 16;
-    for (int t = 0; t < kT; ++t) {
-      v4i w = *(const v4i *)(sT + (t * 64 + ii) * kTStride + jq);
-      *(v4i *)(planesT + (size_t)t * pstrideT + kb_off(i0 + ii, j0 + jq, rpad)) = w;
+    // tile rows j0 + rr of the column layout, i0 + rr of the transposed one
+    if (t < k)
+      *(v4i *)(planes + (size_t)t * pstride + kb_off(j0 + rr, i0 + q16, cpad)) =
+          *(const v4i *)(sC + rr * kSplitRow + q16);
+    if (WITH_T && t < kT)
+      *(v4i *)(planesT + (size_t)t * pstrideT + kb_off(i0 + rr, j0 + q16, rpad)) =
+          *(const v4i *)(sR + rr * kSplitRow + q16);
+    __syncthreads();
+  }
+  if (trunc) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + 4 * jg + c;
+      if (j >= cols) continue;
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = neg[u][c] ? -val[u][c] : val[u][c];
+      double *out = trunc + (size_t)j * ldt + ib;
+      if (ib + 3 < rows && ldt % 2 == 0 && (uintptr_t)trunc % 16 == 0) {
+        *(double2 *)out = double2{v[0], v[1]};
+        *(double2 *)(out + 2) = double2{v[2], v[3]};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ib + u < rows) out[u] = v[u];
+      }
     }
   }
 }

@@ -26,6 +26,10 @@
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <unordered_set>
+#include <unordered_map>
+#include <queue>
+#include <map>
 #include <thread>
 #include <time.h>
 #include <vector>
@@ -1983,6 +1987,24 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
         for (int d = 2; d <= dl; ++d) pw_it += npairs_of(d, kR, kxw);
       }
       pw_it /= (double)T * T;
+      if (verbose && nbw > 0) {   // blocks of the W table that ran (not above their tile cutoff)
+        int live = 0;
+        std::vector<int> by_pairs(kKrMax + 2, 0), by_pairs_all(kKrMax + 2, 0);
+        for (int e : htab[1]) {
+          const int J = e & 0xff, I = (e >> 8) & 0xff, d = 2 + (e >> 16);
+          const int np = npairs_of(d, kR, kxw);
+          ++by_pairs_all[np];
+          if (d <= tcut[(size_t)J * T + I]) {
+            ++live;
+            ++by_pairs[np];
+          }
+        }
+        fprintf(stderr, "refeig it %d: W table %d blocks, %d live; live blocks by pairs:", it + 1,
+                nbw, live);
+        for (int q = 1; q <= kKrMax; ++q)
+          if (by_pairs_all[q]) fprintf(stderr, " %d:%d/%d", q, by_pairs[q], by_pairs_all[q]);
+        fprintf(stderr, "\n");
+      }
     }
     float t_it = 0, g1 = 0, g2 = 0, g3 = 0;
     (void)hipEventElapsedTime(&t_it, ev[0], ev[7]);
@@ -2209,29 +2231,104 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
   return worst;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- HBM-footprint admission of the serving loop (the server below and its host-only
+// simulation share it). A request holds its workspace, refeig_workspace_bytes(n) rounded to
+// 256 bytes, in the server's arena from its start until it completes.
+struct Arena {
+  std::map<size_t, size_t> free_;   // offset -> length of each free run
+  explicit Arena(size_t size) {
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t *off) {   // first fit
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        const size_t o = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[o + bytes] = rest;
+        *off = o;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Pending {
+  int ticket;
+  size_t bytes;
+  int passed;   // later requests that started before this one
+};
+
+// When a lane is free: the oldest pending request whose workspace fits in the arena starts.
+// A request that does not fit may be passed by later ones that do, at most kBypassMax
+// times; after that nothing starts before it (no starvation of large requests). Returns the
+// queue index (and the arena offset) or -1.
+constexpr int kBypassMax = 4;
+int admit(std::deque<Pending> &q, Arena &ar, size_t *off) {
+  for (size_t i = 0; i < q.size(); ++i) {
+    if (ar.alloc(q[i].bytes, off)) {
+      for (size_t k = 0; k < i; ++k) ++q[k].passed;
+      return (int)i;
+    }
+    if (q[i].passed >= kBypassMax) return -1;
+  }
+  return -1;
+}
+
+size_t request_bytes(int n, const refeig_opts *o) {
+  size_t b = 0;
+  if (refeig_workspace_bytes(n, o, &b) != REFEIG_OK) return 0;
+  return (b + 255) / 256 * 256;
+}
+
+}  // namespace
+
 struct refeig_server {
   struct Req {
     const double *A;
     double *X, *D;
     int lda, ldx, n;
     double target;
+    size_t bytes;
+    hipEvent_t ready;   // recorded on the caller's stream at submission
   };
   struct Done {
-    bool done = false;
     int status = REFEIG_E_HIP;
     refeig_report rep;
     double t_done = 0.0;
   };
-  int device = 0, lanes = 0, max_n = 0;
+  int device = 0, lanes = 0;
+  size_t budget = 0;
   refeig_opts opts;
-  size_t slice = 0;
-  void *work = nullptr;
+  void *base = nullptr;
+  Arena arena{0};
   std::vector<hipStream_t> streams;
   std::vector<std::thread> threads;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::pair<int, Req>> queue;   // (ticket, request)
-  std::deque<Done> results;                // by ticket (stable references)
+  std::deque<Pending> queue;
+  std::unordered_map<int, Req> reqs;      // submitted, not yet started
+  std::unordered_map<int, Done> results;  // finished, not yet waited for
+  std::unordered_set<int> live;           // submitted, not yet waited for
+  int next_ticket = 0;
   bool stop = false;
 
   static double now() {
@@ -2241,52 +2338,64 @@ struct refeig_server {
   }
   void lane(int l) {
     (void)hipSetDevice(device);
-    char *wl = (char *)work + (size_t)l * slice;
     for (;;) {
-      std::pair<int, Req> job;
+      int t = -1;
+      size_t off = 0;
+      Req r;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-        if (queue.empty()) return;   // stop requested and nothing left
-        job = queue.front();
-        queue.pop_front();
+        for (;;) {
+          if (!queue.empty()) {
+            const int i = admit(queue, arena, &off);
+            if (i >= 0) {
+              t = queue[i].ticket;
+              queue.erase(queue.begin() + i);
+              r = reqs[t];
+              reqs.erase(t);
+              break;
+            }
+          } else if (stop) {
+            return;
+          }
+          cv_work.wait(lk);
+        }
       }
+      // the caller's writes of A, X and D (on its stream) come first
       refeig_report rep;
-      const Req &r = job.second;
+      int st = REFEIG_E_HIP;
+      if (hipStreamWaitEvent(streams[l], r.ready, 0) == hipSuccess)
+        st = refine_eigvecs(r.A, r.lda, r.X, r.ldx, r.D, r.n, r.target, &opts,
+                            (char *)base + off, r.bytes, (refeig_stream_t)streams[l], &rep);
       // refine_eigvecs returns after its last kernel has finished (it waits for it)
-      const int st = refine_eigvecs(r.A, r.lda, r.X, r.ldx, r.D, r.n, r.target, &opts, wl, slice,
-                                    (refeig_stream_t)streams[l], &rep);
-      const double t = now();
+      (void)hipEventDestroy(r.ready);
+      const double td = now();
       {
         std::lock_guard<std::mutex> lk(mu);
-        Done &d = results[job.first];
+        arena.release(off, r.bytes);
+        Done &d = results[t];
         d.status = st;
         d.rep = rep;
-        d.t_done = t;
-        d.done = true;
+        d.t_done = td;
       }
       cv_done.notify_all();
+      cv_work.notify_all();   // freed memory may admit waiting requests
     }
   }
 };
 
-int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_server **server) {
-  if (!server || lanes < 1 || lanes > 64 || max_n < 1 || max_n > kMaxN) return REFEIG_E_ARG;
+extern "C" {
+
+int refeig_server_create(int lanes, size_t budget_bytes, const refeig_opts *o,
+                         refeig_server **server) {
+  if (!server || lanes < 1 || lanes > 64 || budget_bytes < 256) return REFEIG_E_ARG;
   *server = nullptr;
   refeig_server *sv = new refeig_server();
   if (o) sv->opts = *o;
   else refeig_default_opts(&sv->opts);
   sv->lanes = lanes;
-  sv->max_n = max_n;
-  size_t one = 0;
-  int st = refeig_workspace_bytes(max_n, &sv->opts, &one);
-  if (st != REFEIG_OK) {
-    delete sv;
-    return st;
-  }
-  sv->slice = (one + 255) / 256 * 256;
-  if (hipGetDevice(&sv->device) != hipSuccess ||
-      hipMalloc(&sv->work, sv->slice * (size_t)lanes) != hipSuccess) {
+  sv->budget = budget_bytes / 256 * 256;
+  sv->arena = Arena(sv->budget);
+  if (hipGetDevice(&sv->device) != hipSuccess || hipMalloc(&sv->base, sv->budget) != hipSuccess) {
     delete sv;
     return REFEIG_E_NOMEM;
   }
@@ -2294,7 +2403,7 @@ int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_serv
   for (int l = 0; l < lanes; ++l)
     if (hipStreamCreateWithFlags(&sv->streams[l], hipStreamNonBlocking) != hipSuccess) {
       for (int k = 0; k < l; ++k) (void)hipStreamDestroy(sv->streams[k]);
-      (void)hipFree(sv->work);
+      (void)hipFree(sv->base);
       delete sv;
       return REFEIG_E_HIP;
     }
@@ -2304,16 +2413,30 @@ int refeig_server_create(int lanes, int max_n, const refeig_opts *o, refeig_serv
 }
 
 int refeig_server_submit(refeig_server *sv, const double *A, int lda, double *X, int ldx,
-                         double *D, int n, double target_fwd_err, int *ticket) {
-  if (!sv || !A || !X || !D || !ticket || n < 1 || n > sv->max_n || lda < n || ldx < n ||
+                         double *D, int n, double target_fwd_err, refeig_stream_t stream,
+                         int *ticket) {
+  if (!sv || !A || !X || !D || !ticket || n < 1 || n > kMaxN || lda < n || ldx < n ||
       !(target_fwd_err > 0.0))
     return REFEIG_E_ARG;
+  const size_t bytes = request_bytes(n, &sv->opts);
+  if (bytes == 0) return REFEIG_E_ARG;
+  if (bytes > sv->budget) return REFEIG_E_NOMEM;   // would never fit
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return REFEIG_E_HIP;
+  if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    return REFEIG_E_HIP;
+  }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) return REFEIG_E_ARG;
-    *ticket = (int)sv->results.size();
-    sv->results.emplace_back();
-    sv->queue.push_back({*ticket, {A, X, D, lda, ldx, n, target_fwd_err}});
+    if (sv->stop) {
+      (void)hipEventDestroy(ev);
+      return REFEIG_E_ARG;
+    }
+    *ticket = sv->next_ticket++;
+    sv->reqs[*ticket] = {A, X, D, lda, ldx, n, target_fwd_err, bytes, ev};
+    sv->queue.push_back({*ticket, bytes, 0});
+    sv->live.insert(*ticket);
   }
   sv->cv_work.notify_one();
   return REFEIG_OK;
@@ -2323,12 +2446,14 @@ int refeig_server_wait(refeig_server *sv, int ticket, int *status, refeig_report
                        double *t_done) {
   if (!sv || !status) return REFEIG_E_ARG;
   std::unique_lock<std::mutex> lk(sv->mu);
-  if (ticket < 0 || ticket >= (int)sv->results.size()) return REFEIG_E_ARG;
-  sv->cv_done.wait(lk, [&] { return sv->results[ticket].done; });
+  if (!sv->live.count(ticket)) return REFEIG_E_ARG;
+  sv->cv_done.wait(lk, [&] { return sv->results.count(ticket) > 0; });
   const refeig_server::Done &d = sv->results[ticket];
   *status = d.status;
   if (report) *report = d.rep;
   if (t_done) *t_done = d.t_done;
+  sv->results.erase(ticket);
+  sv->live.erase(ticket);
   return REFEIG_OK;
 }
 
@@ -2345,8 +2470,72 @@ int refeig_server_destroy(refeig_server *sv) {
       (void)hipStreamSynchronize(st);
       (void)hipStreamDestroy(st);
     }
-  (void)hipFree(sv->work);
+  (void)hipFree(sv->base);
   delete sv;
+  return REFEIG_OK;
+}
+
+int refeig_server_request_bytes(int n, const refeig_opts *o, size_t *bytes) {
+  if (!bytes || n < 1 || n > kMaxN) return REFEIG_E_ARG;
+  refeig_opts d;
+  if (!o) {
+    refeig_default_opts(&d);
+    o = &d;
+  }
+  *bytes = request_bytes(n, o);
+  return *bytes ? REFEIG_OK : REFEIG_E_ARG;
+}
+
+int refeig_host_admission_sim(int count, const double *t_arr, const size_t *bytes,
+                              const double *dur, int lanes, size_t budget, double *t_start,
+                              size_t *offset) {
+  if (count < 0 || lanes < 1 || (count > 0 && (!t_arr || !bytes || !dur || !t_start)))
+    return REFEIG_E_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!(dur[i] >= 0.0) || (i > 0 && t_arr[i] < t_arr[i - 1])) return REFEIG_E_ARG;
+  budget = budget / 256 * 256;
+  Arena ar(budget);
+  std::deque<Pending> q;
+  struct Run {
+    double t_end;
+    int req;
+    size_t off;
+    bool operator>(const Run &o) const { return t_end > o.t_end || (t_end == o.t_end && req > o.req); }
+  };
+  std::priority_queue<Run, std::vector<Run>, std::greater<Run>> running;
+  std::vector<size_t> rb(count);
+  int next = 0, busy = 0;
+  double now = 0.0;
+  for (int i = 0; i < count; ++i) {
+    t_start[i] = -1.0;
+    if (offset) offset[i] = 0;
+    rb[i] = (bytes[i] + 255) / 256 * 256;
+  }
+  while (next < count || !running.empty()) {
+    // next event: a completion first when it is not later than the next arrival
+    if (!running.empty() && (next >= count || running.top().t_end <= t_arr[next])) {
+      const Run r = running.top();
+      running.pop();
+      now = r.t_end;
+      ar.release(r.off, rb[r.req]);
+      --busy;
+    } else {
+      now = t_arr[next];
+      if (rb[next] <= budget) q.push_back({next, rb[next], 0});
+      ++next;
+    }
+    size_t off = 0;
+    while (busy < lanes && !q.empty()) {
+      const int i = admit(q, ar, &off);
+      if (i < 0) break;
+      const int rq = q[i].ticket;
+      q.erase(q.begin() + i);
+      t_start[rq] = now;
+      if (offset) offset[rq] = off;
+      running.push({now + dur[rq], rq, off});
+      ++busy;
+    }
+  }
   return REFEIG_OK;
 }
 

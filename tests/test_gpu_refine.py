@@ -595,10 +595,12 @@ def test_config1_slice_counts():
 
 
 def test_server_results_match_single_calls():
-    """The continuous-batching server: config-4 style requests of uneven n and mixed targets
-    (1e-8, 1e-11, 1e-14, the serving mix), submitted while earlier ones run on 4 lanes, each
-    come back bit for bit as a single call alone gives them (stop rule on, so the iteration
-    counts differ between requests). Requests beyond max_n and unknown tickets are refused."""
+    """The continuous-batching server with admission by HBM footprint: config-4 style
+    requests of uneven n and mixed targets (1e-8, 1e-11, 1e-14, the serving mix), submitted
+    while earlier ones run on 4 lanes from an arena that holds about three of the largest
+    footprints, each come back bit for bit as a single call alone gives them (stop rule on,
+    so the iteration counts differ between requests). A request whose footprint exceeds the
+    arena, unknown tickets and a second wait are refused."""
     import time
     import torch
     rb = _rb()
@@ -611,9 +613,11 @@ def test_server_results_match_single_calls():
         A, X, D = _to_dev(p)
         st, rep = rb.refine_eigvecs(A, X, D, t)
         singles.append((st, rep.iters, X.cpu().numpy(), D.cpu().numpy()))
-    srv = rb.Server(4, 1024)
+    budget = 3 * rb.server_request_bytes(max(p.n for p in probs))
+    srv = rb.Server(4, budget)
     try:
         dev = [_to_dev(p) for p in probs]
+        torch.cuda.synchronize()
         t0 = time.monotonic()
         tickets = [srv.submit(A, X, D, t) for (A, X, D), t in zip(dev, targets)]
         done = [srv.wait(k) for k in tickets]
@@ -623,11 +627,45 @@ def test_server_results_match_single_calls():
             assert np.array_equal(X.cpu().numpy(), Xs) and np.array_equal(D.cpu().numpy(), Ds)
         print("server: n", [p.n for p in probs], "iters", [r.iters for _, r, _ in done],
               flush=True)
-        big = workloads.make_problem(4, 1100, index=999, cond_exp=6.0)
-        A, X, D = _to_dev(big)
         with pytest.raises(ValueError):
-            srv.submit(A, X, D, 1e-14)
+            srv.wait(tickets[0])                      # already waited for
         with pytest.raises(ValueError):
             srv.wait(10 ** 6)
+    finally:
+        srv.close()
+    # a footprint above the arena can never start: refused at submission
+    small = rb.Server(2, rb.server_request_bytes(256))
+    try:
+        big = workloads.make_problem(4, 700, index=999, cond_exp=6.0)
+        A, X, D = _to_dev(big)
+        with pytest.raises(ValueError):
+            small.submit(A, X, D, 1e-14)
+    finally:
+        small.close()
+
+
+def test_server_waits_for_the_callers_stream():
+    """A request submitted right after asynchronous copies of its inputs on the caller's
+    stream (no synchronisation in between) reads the copied values: the lane waits for an
+    event recorded on that stream."""
+    import torch
+    rb = _rb()
+    p = workloads.make_problem(2, 1024, x0="eigh")
+    A, X0, D0 = _to_dev(p)
+    X1, D1 = X0.clone(), D0.clone()
+    st1, _ = rb.refine_eigvecs(A, X1, D1, 1e-13)
+    assert st1 == rb.REFEIG_OK
+    srv = rb.Server(2, 2 * rb.server_request_bytes(1024))
+    try:
+        for rep_i in range(3):
+            X = torch.zeros_like(X0)
+            D = torch.zeros_like(D0)
+            torch.cuda.synchronize()
+            X.copy_(X0)            # asynchronous on the current stream
+            D.copy_(D0)
+            k = srv.submit(A, X, D, 1e-13)
+            st, _, _ = srv.wait(k)
+            assert st == rb.REFEIG_OK, rb.strerror(st)
+            assert torch.equal(X, X1) and torch.equal(D, D1), rep_i
     finally:
         srv.close()
