@@ -170,6 +170,20 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
                    double target_fwd_err, const refeig_opts *o, void *work, size_t work_bytes,
                    refeig_stream_t stream, refeig_report *report);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): refine_eigvecs with the same arguments
+ * minus the workspace, which lives in a static device array of the library (336 MiB, one
+ * copy per GPU, held until the process ends; its device address is looked up once per
+ * GPU). No hipMalloc, hipFree or allocating library call is made. Serves
+ * 1 <= n <= REFEIG_NOALLOC_MAX_N with mode REFEIG_OZAKI_INT8 (REFEIG_E_NOMEM for larger n,
+ * REFEIG_E_ARG for another mode); results are bit for bit those of refine_eigvecs. Every
+ * call on one GPU uses that GPU's array, so calls that overlap on one GPU (different
+ * streams or threads) race: serialise them. */
+#define REFEIG_NOALLOC_MAX_N 1024
+int refine_eigvecs_noalloc(const double *A, int lda, double *X, int ldx, double *D, int n,
+                           double target_fwd_err, const refeig_opts *o, refeig_stream_t stream,
+                           refeig_report *report);
+
 /* Complex Hermitian extension (Sec. 5 names the Hermitian case as future
  * work): the same iteration for A = A^H with complex X. A and X are complex
  * matrices stored interleaved (real, imaginary) in column-major order, element

@@ -87,6 +87,8 @@ _lib.refeig_workspace_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINT
 _lib.refine_eigvecs.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctypes.POINTER(Opts), _vp,
                                 _sz, _vp, ctypes.POINTER(Report)]
 _lib.refeig_strerror.restype = ctypes.c_char_p
+_lib.refine_eigvecs_noalloc.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl,
+                                        ctypes.POINTER(Opts), _vp, ctypes.POINTER(Report)]
 _lib.refeig_herm_workspace_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
 _lib.refine_eigvecs_herm.argtypes = [_vp, _int, _vp, _int, _vp, _int, _dbl, ctypes.POINTER(Opts),
                                      _vp, _sz, _vp, ctypes.POINTER(Report)]
@@ -122,6 +124,7 @@ _lib.refeig_host_crt_plan.argtypes = [_int, _int, _int, ctypes.POINTER(_int), _v
 _lib.refeig_host_group_ritz.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "refeig_strerror",
+            "refine_eigvecs_noalloc",
             "refeig_herm_workspace_bytes", "refine_eigvecs_herm",
             "refeig_split_cols", "refeig_split_cols_ex", "refeig_slice_gemm",
             "refeig_residue_planes", "refeig_residue_gemm", "refeig_slice_gemm_fp8",
@@ -184,6 +187,20 @@ def refine_eigvecs(A, X, D, target: float, opts: Opts | None = None, work=None, 
     st = _lib.refine_eigvecs(_ptr(A), n, _ptr(X), n, _ptr(D), n, float(target),
                              ctypes.byref(opts) if opts is not None else None, _ptr(work), wb,
                              _stream(stream), ctypes.byref(rep))
+    return st, rep
+
+
+def refine_eigvecs_noalloc(A, X, D, target: float, opts: Opts | None = None, stream=None):
+    """refine_eigvecs through the entry point that allocates nothing (its workspace is the
+    library's static device array; n <= REFEIG_NOALLOC_MAX_N). Returns (status, report)."""
+    n = D.numel()
+    assert A.dtype == X.dtype == D.dtype and A.is_cuda and X.is_cuda and D.is_cuda
+    assert A.is_contiguous() and X.is_contiguous() and D.is_contiguous()
+    assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+    rep = Report()
+    st = _lib.refine_eigvecs_noalloc(_ptr(A), n, _ptr(X), n, _ptr(D), n, float(target),
+                                     ctypes.byref(opts) if opts is not None else None,
+                                     _stream(stream), ctypes.byref(rep))
     return st, rep
 
 
