@@ -282,6 +282,33 @@ def fp8_leg(rb, A, X0, D0):
             "status": rb.strerror(st)}
 
 
+def planning_leg(rb, A, X0, D0, K, steps):
+    """Device against host planning of the same K-iteration solve (same plan, same result):
+    the time the host's three waits per iteration, and its planning between them, cost."""
+    import numpy as np
+    import torch
+    out = {}
+    for name, plan in (("device", 0), ("host", 1)):
+        opts = rb.default_opts(fixed_iters=K, plan=plan)
+        ms = []
+        for s_ in range(1 + max(1, steps)):
+            X, D = X0.clone(), D0.clone()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            refine(rb, A, X, D, 1e-14, opts)
+            e1.record()
+            torch.cuda.synchronize()
+            if s_ > 0:
+                ms.append(e0.elapsed_time(e1))
+        out[name + "_ms"] = float(np.mean(ms))
+        out[name + "_X"] = X
+    same = bool(torch.equal(out.pop("device_X"), out.pop("host_X")))
+    out.update({"iters": K, "saved_ms_per_iter": (out["host_ms"] - out["device_ms"]) / K,
+                "bit_identical": same})
+    return out
+
+
 def config4_leg(count):
     """Many small matrices (config 4): one batched call, exactly 3 iterations each, inputs
     resident on the device; matrices/s and FP64-equivalent TFLOP/s (6 n^3 per iteration)."""
@@ -623,6 +650,9 @@ def main():
             plain = {"ms_to_target": None, "iters": None, "status": "did not reach the target",
                      "fwd_err_per_iter": perrs or None}
 
+    log("planning on the device against planning on the host")
+    planning = planning_leg(rb, A, X0, D0, K, args.steps)
+    log(f"planning: device {planning['device_ms']:.1f} ms, host {planning['host_ms']:.1f} ms")
     fp8 = None
     if not args.no_fp8 and n >= 1024:
         log("FP8 ablation: pair products of E4M3 and INT8 digits")
@@ -745,6 +775,7 @@ def main():
         "eps_per_iter": r0["eps"], "pairs_per_iter": [round(sum(x), 2) for x in r0["pairs_f"]], "ms_per_iter": r0["ms_iter"],
         "ms_gemm_per_iter": r0["ms_gemm"], "timed_wall_s": wall,
         "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": plain,
+        "planning": planning,
     }
     if batch is not None:
         out["config4_batched"] = batch

@@ -106,7 +106,18 @@ typedef struct {
                             slices instead. 0: the slice products of Sec. 2.3 for V too
                             (pair diagonals kept per column block). The Hermitian path
                             always uses slices.                                          */
-    int reserved_i[2];
+    int plan;            /* where each iteration is planned (beta, k_X, cutoffs, modulus counts,
+                            block tables): 0 (default) on the device, by small kernels between
+                            the products, so the host enqueues the whole solve without waiting
+                            (one wait per iteration for the stop test; none with fixed_iters);
+                            1 on the host, which reads the device's column statistics three
+                            times per iteration. group_tau > 0 and schedule = 1 always plan on
+                            the host. Both give the same plan and bit-identical results.       */
+    int enqueue_only;    /* 1: with fixed_iters > 0 and a caller workspace, device planning:
+                            only enqueue the solve on the stream (no wait, no allocation, no
+                            event; the stream may be under HIP graph capture). The return value
+                            reports argument errors only; the status and report are read after
+                            the stream has finished with refeig_read_report(work, ...).       */
     double group_tau;    /* > 0: grouped correction, an extension beyond the paper's
                             method (which assumes well-separated eigenvalues, Sec. 3.2):
                             every pair of columns whose first-order correction |e_ij|,
@@ -183,6 +194,12 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
 int refine_eigvecs_noalloc(const double *A, int lda, double *X, int ldx, double *D, int n,
                            double target_fwd_err, const refeig_opts *o, refeig_stream_t stream,
                            refeig_report *report);
+
+/* The status and report of a solve enqueued with opts.enqueue_only, from its workspace
+ * (device, as passed to refine_eigvecs; n and o as there). Synchronous: call it after the
+ * stream has finished the solve (e.g. after a graph replay and a stream synchronisation). */
+int refeig_read_report(const void *work, int n, const refeig_opts *o, int *status,
+                       refeig_report *report);
 
 /* Complex Hermitian extension (Sec. 5 names the Hermitian case as future
  * work): the same iteration for A = A^H with complex X. A and X are complex

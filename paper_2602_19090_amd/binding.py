@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("xi", ctypes.c_double), ("theta", ctypes.c_double), ("ka_max", ctypes.c_int),
                 ("d_extra", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("kx_force", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("sparse_k", ctypes.c_int), ("vmode", ctypes.c_int), ("reserved_i", ctypes.c_int * 2),
+                ("sparse_k", ctypes.c_int), ("vmode", ctypes.c_int), ("plan", ctypes.c_int),
+                ("enqueue_only", ctypes.c_int),
                 ("group_tau", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 3)]
 
@@ -106,6 +107,8 @@ _lib.refeig_server_submit.argtypes = [_vp, _vp, _int, _vp, _int, _vp, _int, _dbl
                                       ctypes.POINTER(_int)]
 _lib.refeig_server_request_bytes.argtypes = [_int, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
 _lib.refeig_host_admission_sim.argtypes = [_int, _vp, _vp, _vp, _int, _sz, _vp, _vp]
+_lib.refeig_read_report.argtypes = [_vp, _int, ctypes.POINTER(Opts), ctypes.POINTER(_int),
+                                    ctypes.POINTER(Report)]
 _lib.refeig_server_wait.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(Report),
                                     ctypes.POINTER(_dbl)]
 _lib.refeig_server_destroy.argtypes = [_vp]
@@ -131,7 +134,8 @@ EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "
             "refeig_digits_to_e4m3", "refeig_batched_workspace_bytes",
             "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
             "refeig_server_destroy", "refeig_server_request_bytes", "refeig_host_admission_sim",
-            "refine_eigvecs_batched", "refeig_host_beta", "refeig_host_column_order",
+            "refine_eigvecs_batched", "refeig_read_report", "refeig_host_beta",
+            "refeig_host_column_order",
             "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
 
@@ -202,6 +206,17 @@ def refine_eigvecs_noalloc(A, X, D, target: float, opts: Opts | None = None, str
                                      ctypes.byref(opts) if opts is not None else None,
                                      _stream(stream), ctypes.byref(rep))
     return st, rep
+
+
+def read_report(work, n: int, opts: Opts | None = None):
+    """refeig_read_report: (status, report) of a solve enqueued with opts.enqueue_only on the
+    workspace `work` (call after the stream has finished it)."""
+    st, rep = _int(0), Report()
+    r = _lib.refeig_read_report(_ptr(work), int(n), ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(st), ctypes.byref(rep))
+    if r != 0:
+        raise ValueError(strerror(r))
+    return st.value, rep
 
 
 def colmajor_complex(M: np.ndarray, device="cuda"):

@@ -1,0 +1,674 @@
+// Device-side planning of the refinement iteration (see devplan.h). Every kernel here is a
+// single block of 1024 threads except the residue kernel; the arithmetic of the decisions is
+// the shared code of plan.h, so the plan matches the host orchestrator's.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+#include <cstdint>
+
+#include "../../include/refeig.h"
+#include "devplan.h"
+#include "plan.h"
+
+namespace refeig {
+
+namespace {
+
+constexpr int kPT = 1024;   // threads of a planning kernel
+
+// Block-wide reductions (every thread gets the result). s: shared scratch of >= 16 entries.
+__device__ double blk_max_d(double v, double *s) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = s[0];
+  for (int q = 1; q < kPT / 64; ++q) m = fmax(m, s[q]);
+  __syncthreads();
+  return m;
+}
+__device__ double blk_min_d(double v, double *s) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = s[0];
+  for (int q = 1; q < kPT / 64; ++q) m = fmin(m, s[q]);
+  __syncthreads();
+  return m;
+}
+__device__ int blk_max_i(int v, int *s) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int m = s[0];
+  for (int q = 1; q < kPT / 64; ++q) m = max(m, s[q]);
+  __syncthreads();
+  return m;
+}
+
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Bitonic sort of N2 (a power of two) entries (key, aux) ascending by (key, aux), in LDS.
+template <typename K>
+__device__ void bitonic(K *key, int *aux, int N2) {
+  for (int k = 2; k <= N2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < N2; i += kPT) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const K a = key[i], b = key[l];
+          const int ia = aux[i], ib = aux[l];
+          const bool gt = (a > b) || (a == b && ia > ib);
+          if (gt == up) {
+            key[i] = b;
+            key[l] = a;
+            aux[i] = ib;
+            aux[l] = ia;
+          }
+        }
+      }
+    }
+  __syncthreads();
+}
+
+// Block table of a tabled slice-GEMM launch from each tile's last diagonal dt[J] (LDS, ntile
+// tiles per side): groups of tiles with equal dt, largest first; (group, slot) combinations
+// ordered by pair count, most first (stable); within one, the XCD band order of
+// xcd_tile_order. Entry = row tile | column tile << 8 | slot << 16. Returns the entry count.
+struct TabScratch {
+  int gval[kMaxDiag + 2], gcnt[kMaxDiag + 2], goff[kMaxDiag + 2];
+  int rows[64];
+  int ng, ncombo;
+  int cg[kMaxDiag * kMaxDiag], cq[kMaxDiag * kMaxDiag], coff[kMaxDiag * kMaxDiag + 1];
+};
+__device__ int build_table(const int *dt, int ntile, int kl, int kr, int *tab, TabScratch &ts) {
+  if (threadIdx.x == 0) {
+    int dmax = 2;
+    for (int J = 0; J < ntile; ++J) dmax = max(dmax, dt[J]);
+    int ng = 0, nr = 0;
+    for (int v = dmax; v >= 2; --v) {
+      int c = 0;
+      for (int J = 0; J < ntile; ++J)
+        if (dt[J] == v) ts.rows[nr + c++] = J;
+      if (c) {
+        ts.gval[ng] = v;
+        ts.gcnt[ng] = c;
+        ts.goff[ng] = nr;
+        nr += c;
+        ++ng;
+      }
+    }
+    ts.ng = ng;
+    // combinations (group, slot), most pairs first, stable over (group, slot)
+    int nc = 0;
+    for (int np = kMaxDiag; np >= 1; --np)
+      for (int g = 0; g < ng; ++g)
+        for (int q = 0; q + 2 <= ts.gval[g]; ++q)
+          if (npairs_of(2 + q, kl, kr) == np) {
+            ts.cg[nc] = g;
+            ts.cq[nc] = q;
+            ++nc;
+          }
+    ts.ncombo = nc;
+    int off = 0;
+    for (int c = 0; c < nc; ++c) {
+      ts.coff[c] = off;
+      off += ts.gcnt[ts.cg[c]] * ntile;
+    }
+    ts.coff[nc] = off;
+  }
+  __syncthreads();
+  const int total = ts.coff[ts.ncombo];
+  for (int e = threadIdx.x; e < total; e += kPT) {
+    int lo = 0, hi = ts.ncombo - 1;   // the combination holding entry e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ts.coff[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int g = ts.cg[lo], q = ts.cq[lo];
+    int mi, nb;
+    xcd_tile_order(e - ts.coff[lo], ts.gcnt[g], ntile, mi, nb);
+    tab[e] = ts.rows[ts.goff[g] + mi] | (nb << 8) | (q << 16);
+  }
+  __syncthreads();
+  return total;
+}
+
+// Per-tile last diagonal from per-column cutoffs: dt = min(max(2, max over the tile's
+// columns < n), dallowed); every column of the tile (padding included) gets dt in dcut.
+// Returns the largest dt and the pair work in n x n x n products (tiles of tr rows).
+__device__ int tile_cutoffs_from_columns(int *dtile, const int *dcol_lds, int n, int npad, int tr,
+                                         int dallowed, int kl, int kr, int *dcut, double *pairs,
+                                         int *ired) {
+  const int nt = npad / tr;
+  for (int J = threadIdx.x; J < nt; J += kPT) {
+    int d = 2;
+    for (int j = J * tr; j < min((J + 1) * tr, n); ++j) d = max(d, dcol_lds[j]);
+    dtile[J] = min(d, dallowed);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < npad; j += kPT) dcut[j] = dtile[j / tr];
+  int dm = 2;
+  for (int J = threadIdx.x; J < nt; J += kPT) dm = max(dm, dtile[J]);
+  dm = blk_max_i(dm, ired);
+  if (threadIdx.x == 0) {
+    double pe = 0.0;
+    for (int J = 0; J < nt; ++J) {
+      int pr = 0;
+      for (int d = 2; d <= dtile[J]; ++d) pr += npairs_of(d, kl, kr);
+      pe += pr * (double)tr / npad;
+    }
+    *pairs = pe;
+  }
+  __syncthreads();
+  return dm;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- once per solve
+__global__ __launch_bounds__(kPT) void k_dp_init(PlanParams p, PlanBufs b) {
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  int em = -100000;
+  double h = 0.0;
+  for (int i = threadIdx.x; i < p.n; i += kPT) {
+    em = max(em, b.eA[i]);
+    if (b.mxA[i] != 0.0) h = fmax(h, ldexp(sqrt(b.ssA[i]), -b.eA[i]));
+  }
+  em = blk_max_i(em, ired);
+  h = blk_max_d(h, red);
+  if (threadIdx.x < kCrtMax) b.mods[threadIdx.x] = modulus(threadIdx.x);
+  if (threadIdx.x == 0) {
+    DevState &st = *b.st;
+    st.eA_max = em;
+    st.hA = h;
+    st.done = 0;
+    st.stop_status = 0;
+    st.iters_done = 0;
+    st.eps_prev = INFINITY;
+    for (int l = 0; l < kVLevels; ++l) {
+      st.ares_ka[l] = st.ares_n[l] = -1;
+      st.ares_dirty[l] = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- working column order
+// From the entry estimates D (natural order): gaps, the smallest gap and max |lambda|, and the
+// working order (gap descending, ties by eigenvalue ascending): colmap, gapsw.
+__global__ __launch_bounds__(kPT) void k_dp_order(PlanParams p, PlanBufs b) {
+  __shared__ double key[kDevSortMax];    // eigenvalues, then the gap keys (as 64-bit ints)
+  __shared__ int idx[kDevSortMax];       // sorted position -> column
+  __shared__ int rk[kDevSortMax];        // second sort: rank in eigenvalue order
+  __shared__ double red[16];
+  const int n = p.n, N2 = pow2_at_least(n);
+  int bad = 0;
+  for (int i = threadIdx.x; i < N2; i += kPT) {
+    double v = i < n ? b.D[i] : INFINITY;
+    if (i < n && !(fabs(v) <= DBL_MAX)) {
+      bad = 1;
+      v = 0.0;
+    }
+    key[i] = v;
+    idx[i] = i;
+  }
+  if (bad) atomicOr(b.flags, FLAG_NONFINITE);
+  bitonic<double>(key, idx, N2);
+  double lmax;
+  // gaps in eigenvalue order, kept in registers of the thread that owns the position (at
+  // most kDevSortMax / kPT per thread)
+  double gl[kDevSortMax / kPT];
+  double gm = INFINITY, lm = 0.0;
+#pragma unroll
+  for (int q = 0; q < kDevSortMax / kPT; ++q) {
+    const int pp = threadIdx.x + q * kPT;
+    gl[q] = INFINITY;
+    if (pp < n) {
+      const double dl = pp > 0 ? key[pp] - key[pp - 1] : INFINITY;
+      const double dr = pp + 1 < n ? key[pp + 1] - key[pp] : INFINITY;
+      gl[q] = fmin(dl, dr);
+      gm = fmin(gm, dr);
+      lm = fmax(lm, fabs(key[pp]));
+    }
+  }
+  gm = blk_min_d(gm, red);
+  lmax = blk_max_d(lm, red);
+  if (n == 1) {
+    gl[0] = 1.0;
+    gm = 1.0;
+  }
+  if (!(gm > 0.0) && threadIdx.x == 0) atomicOr(b.flags, FLAG_GAP);
+  __syncthreads();
+  // second sort: keys ~bits(g) ascending = g descending, ties by eigenvalue rank
+  unsigned long long *k2 = (unsigned long long *)key;
+#pragma unroll
+  for (int q = 0; q < kDevSortMax / kPT; ++q) {
+    const int pp = threadIdx.x + q * kPT;
+    if (pp < N2) {
+      k2[pp] = pp < n ? ~(unsigned long long)__double_as_longlong(gl[q]) : ~0ull;
+      rk[pp] = pp;
+    }
+  }
+  bitonic<unsigned long long>(k2, rk, N2);
+  for (int q = threadIdx.x; q < p.npad; q += kPT) {
+    if (q < n) {
+      const int r = rk[q];
+      b.colmap[q] = idx[r];
+      b.gapsw[q] = __longlong_as_double((long long)~k2[q]);
+    } else {
+      b.colmap[q] = q;
+      b.gapsw[q] = 0.0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    b.st->gmin = gm;
+    b.st->lmax = lmax;
+  }
+}
+
+// ---------------------------------------------------------------- beta, kx and the V plan
+__global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
+  __shared__ int hist[kBetaBins];
+  __shared__ int dcol[kDevSortMax];
+  __shared__ int dtile[64];
+  __shared__ int kab[kDevSortMax / 256], lvb[kDevSortMax / 256];
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  __shared__ int s_ok, s_kx;
+  __shared__ TabScratch ts;
+  DevState &st = *b.st;
+  DevIter &rep = st.rep[p.it < 32 ? p.it : 31];
+  const int n = p.n, npad = p.npad;
+  for (int q = threadIdx.x; q < kBetaBins; q += kPT) hist[q] = 0;
+  __syncthreads();
+  int extra = 0, exm = -100000;
+  double hx = 0.0;
+  for (int j = threadIdx.x; j < n; j += kPT) {
+    exm = max(exm, b.eX[j]);
+    if (b.mxX[j] == 0.0) continue;
+    atomicAdd(&hist[min(kBetaBins - 1, max(0, 2 * b.cX[j] + kBetaBias))], 1);
+    extra = max(extra, b.eX[j] - b.cX[j]);
+    hx = fmax(hx, ldexp(sqrt(b.ssX[j]), -b.eX[j]));
+  }
+  extra = blk_max_i(extra, ired);
+  exm = blk_max_i(exm, ired);
+  hx = blk_max_d(hx, red);
+  if (threadIdx.x == 0) {
+    int beta = 0, kx = 1;
+    beta_core(p.xi, p.delta_k, st.gmin, st.lmax, pow2_sum(hist), extra, &beta, &kx);
+    if (p.kx_force > 0) kx = p.kx_force;
+    st.beta = beta;
+    st.kx = kx;
+    st.eXmax = exm;
+    st.hX = hx;
+    s_kx = kx;
+    rep.beta = beta;
+    rep.kx = kx;
+    rep.delta = p.delta_k;
+  }
+  __syncthreads();
+  const int kx = s_kx;
+  const int eA_max = st.eA_max;
+  const int nb = npad / 256;
+  // ---- V by residues: A's digits per 256-column block, levels, moduli, floor check
+  if (threadIdx.x == 0) s_ok = 0;
+  __syncthreads();
+  if (p.crt) {
+    for (int q = threadIdx.x; q < nb; q += kPT) kab[q] = 1;
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kPT)
+      if (b.mxX[j] != 0.0)
+        atomicMax(&kab[j / 256], cut_ka(eA_max, p.lgrowth_a, b.eX[j], p.theta, p.delta_k,
+                                        b.gapsw[j], p.d_extra));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int ka_top = 1;
+      for (int q = 0; q < nb; ++q) {
+        kab[q] = min(kab[q], p.ka_max);
+        ka_top = max(ka_top, kab[q]);
+      }
+      const bool levels = npad >= 1024;
+      int ka_l[kVLevels] = {0, 0, 0, 0};
+      for (int q = 0; q < nb; ++q) {
+        lvb[q] = levels ? min(kVLevels - 1, (ka_top - kab[q]) / 2) : 0;
+        ka_l[lvb[q]] = max(ka_l[lvb[q]], kab[q]);
+      }
+      const double hbits = (st.hA > 0.0 && st.hX > 0.0) ? plan_log2(st.hA * st.hX * (1.0 + 1e-6))
+                                                        : -1.0;
+      int ok = 1;
+      for (int l = 0; l < kVLevels; ++l) {
+        st.ka_l[l] = ka_l[l];
+        st.N_l[l] = 0;
+        if (ka_l[l] > 0) {
+          const int N = crt_count(crt_need_bits(npad, ka_l[l], kx, hbits));
+          if (N < 0 || ka_l[l] > kCrtPlanes || kx > kCrtPlanes) ok = 0;
+          else st.N_l[l] = N;
+        }
+      }
+      st.ka_top = ka_top;
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (s_ok && threadIdx.x < kVLevels && st.ka_l[threadIdx.x] > 0)
+      crt_rec_build(st.N_l[threadIdx.x], st.ka_l[threadIdx.x], kx, st.recs[threadIdx.x]);
+    __syncthreads();
+    if (s_ok) {   // reconstruction floor against each column's share of delta
+      int fail = 0;
+      for (int j = threadIdx.x; j < n; j += kPT) {
+        if (b.mxX[j] == 0.0) continue;
+        const CrtRec &rl = st.recs[lvb[j / 256]];
+        const double fl = ldexp(rl.M[0], eA_max + b.eX[j] + rl.sh - 115);
+        if (!(fl <= 0.25 * p.theta * p.delta_k * b.gapsw[j])) fail = 1;
+      }
+      if (fail) atomicAnd(&s_ok, 0);
+    }
+    __syncthreads();
+  }
+  const int vres = s_ok;
+  if (vres) {
+    if (threadIdx.x == 0) res_weights_build(kx, st.N_l[0], st.wX);
+    if (threadIdx.x >= 1 && threadIdx.x <= kVLevels) {
+      const int l = threadIdx.x - 1;
+      const int ka = st.ka_l[l], N = st.N_l[l];
+      const bool dirty = ka > 0 && (ka != st.ares_ka[l] || N != st.ares_n[l]);
+      if (dirty) {
+        res_weights_build(ka, N, st.wA[l]);
+        st.ares_ka[l] = ka;
+        st.ares_n[l] = N;
+      }
+      st.ares_dirty[l] = dirty ? 1 : 0;
+    }
+    for (int q = threadIdx.x; q < nb; q += kPT) {
+      b.vblk[2 * q] = st.N_l[lvb[q]];
+      b.vblk[2 * q + 1] = lvb[q];
+    }
+    if (threadIdx.x == 0) {
+      double nsum = 0.0;
+      for (int q = 0; q < nb; ++q) nsum += st.N_l[lvb[q]];
+      rep.pv = nsum / nb;
+      rep.dv = st.ka_top + kx;
+      rep.lv = 1;
+      st.gemm_v[0] = kx;
+      st.gemm_v[1] = p.ka_max;
+      st.gemm_v[2] = 0;   // no slice table
+    }
+  } else {
+    for (int q = threadIdx.x; q < nb; q += kPT) {
+      b.vblk[2 * q] = 0;
+      b.vblk[2 * q + 1] = 0;
+    }
+    if (threadIdx.x < kVLevels) st.ares_dirty[threadIdx.x] = 0;
+    // ---- V by slices: per-column cutoffs, per-tile maxima, the block table
+    for (int j = threadIdx.x; j < npad; j += kPT)
+      dcol[j] = (j < n && b.mxX[j] != 0.0)
+                    ? cut_v(eA_max, p.lgrowth_a, kx, b.eX[j], p.theta, p.delta_k, b.gapsw[j],
+                            p.d_extra)
+                    : 2;
+    __syncthreads();
+    const int tr = npad >= 1024 ? 256 : 128;
+    const int dallowed = min(p.ka_max + 1, kx + p.ka_max);
+    double pairs = 0.0;
+    const int dv = tile_cutoffs_from_columns(dtile, dcol, n, npad, tr, dallowed, kx, p.ka_max,
+                                             b.dcut[0], &pairs, ired);
+    const int cnt = build_table(dtile, npad / tr, kx, p.ka_max, b.tab[0], ts);
+    if (threadIdx.x == 0) {
+      st.gemm_v[0] = kx;
+      st.gemm_v[1] = p.ka_max;
+      st.gemm_v[2] = cnt;
+      rep.pv = pairs;
+      rep.dv = dv;
+      rep.lv = 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st.vres = vres;
+    st.vslice = 1 - vres;
+    rep.vres = vres;
+  }
+}
+
+// ---------------------------------------------------------------- the W plan
+__global__ __launch_bounds__(kPT) void k_dp_wplan(PlanParams p, PlanBufs b) {
+  __shared__ double key[kDevSortMax];
+  __shared__ int idx[kDevSortMax];
+  __shared__ int dcol[kDevSortMax];
+  __shared__ int dtile[64];
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  __shared__ TabScratch ts;
+  DevState &st = *b.st;
+  DevIter &rep = st.rep[p.it < 32 ? p.it : 31];
+  const int n = p.n, npad = p.npad, N2 = pow2_at_least(n), kx = st.kx;
+  for (int i = threadIdx.x; i < N2; i += kPT) {
+    key[i] = i < n ? b.lam[i] : INFINITY;
+    idx[i] = i;
+  }
+  bitonic<double>(key, idx, N2);
+  // gaps of the Rayleigh quotients, to their working positions (held in wtol[npad + j])
+  double gm = INFINITY, lm = 0.0;
+  for (int pp = threadIdx.x; pp < n; pp += kPT) {
+    const double dl = pp > 0 ? key[pp] - key[pp - 1] : INFINITY;
+    const double dr = pp + 1 < n ? key[pp + 1] - key[pp] : INFINITY;
+    b.wtol[npad + idx[pp]] = fmin(dl, dr);
+    gm = fmin(gm, dr);
+    lm = fmax(lm, fabs(key[pp]));
+  }
+  gm = blk_min_d(gm, red);
+  lm = blk_max_d(lm, red);
+  if (n == 1) {
+    if (threadIdx.x == 0) b.wtol[npad] = 1.0;
+    gm = 1.0;
+  }
+  if (!(gm > 0.0) && threadIdx.x == 0) atomicOr(b.flags, FLAG_GAP);
+  __syncthreads();
+  for (int j = threadIdx.x; j < npad; j += kPT) {
+    if (j < n) {
+      const double g = b.wtol[npad + j];
+      b.wtol[j] = w_tight(p.delta_int, g, lm, p.theta, p.delta_k);
+      dcol[j] = b.resmax[j] != 0.0
+                    ? cut_w(st.eXmax, kx, p.lsqn, b.eR[j], p.theta, p.delta_k, g, p.d_extra)
+                    : 2;
+    } else {
+      dcol[j] = 2;
+    }
+  }
+  __syncthreads();
+  const int tr = npad >= 1024 ? 256 : 128;
+  const int dallowed = min(kKrMaxP + 1, kKrMaxP + kx);
+  double pairs = 0.0;
+  const int dw = tile_cutoffs_from_columns(dtile, dcol, n, npad, tr, dallowed, kKrMaxP, kx,
+                                           b.dcut[1], &pairs, ired);
+  const int cnt = build_table(dtile, npad / tr, kKrMaxP, kx, b.tab[1], ts);
+  if (threadIdx.x == 0) {
+    st.gmin_w = gm;
+    st.lmax_w = lm;
+    st.cx = cx_tile(kx, p.lsqn, p.theta, p.delta_k);
+    st.dmax_w = dallowed;
+    st.gemm_w[0] = kKrMaxP;
+    st.gemm_w[1] = kx;
+    st.gemm_w[2] = cnt;
+    rep.dw = dw;
+    rep.pw = pairs;   // replaced by the pairs under the tile cutoffs when they apply
+    rep.lw = 1;
+    rep.gmin = gm;
+    rep.lmax = lm;
+  }
+}
+
+// ---------------------------------------------------------------- the X^(1) E~ plan, stop test
+__global__ __launch_bounds__(kPT) void k_dp_uplan(PlanParams p, PlanBufs b) {
+  __shared__ int dcol[kDevSortMax];
+  __shared__ int dtile[64];
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  __shared__ TabScratch ts;
+  DevState &st = *b.st;
+  DevIter &rep = st.rep[p.it < 32 ? p.it : 31];
+  const int n = p.n, npad = p.npad, kx = st.kx;
+  double eps = 0.0;
+  for (int j = threadIdx.x; j < npad; j += kPT) {
+    if (j < n) {
+      eps = fmax(eps, b.emax[j]);
+      dcol[j] = b.emax[j] != 0.0
+                    ? cut_u(kx, p.lsqn, b.eE[j], p.theta, p.delta_k, b.wtol[j], p.d_extra)
+                    : 2;
+    } else {
+      dcol[j] = 2;
+    }
+  }
+  eps = blk_max_d(eps, red);
+  __syncthreads();
+  const int tr = npad >= 1024 ? 256 : 128;
+  const int dallowed = min(kKrMaxP + 1, kKrMaxP + kx);
+  double pairs = 0.0;
+  const int du = tile_cutoffs_from_columns(dtile, dcol, n, npad, tr, dallowed, kKrMaxP, kx,
+                                           b.dcut[2], &pairs, ired);
+  const int cnt = build_table(dtile, npad / tr, kKrMaxP, kx, b.tab[2], ts);
+  // W pairs computed under the per-tile cutoffs (the tile's diagonal, at most its launch's)
+  double pw = -1.0;
+  if (npad >= 1024 && b.tcut) {
+    const int T = npad / 256;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < T * T; q += kPT) {
+      const int dl = min(b.tcut[q], b.dcut[1][(q / T) * 256]);
+      int pr = 0;
+      for (int d = 2; d <= dl; ++d) pr += npairs_of(d, kKrMaxP, kx);
+      acc += pr;
+    }
+    // a sum of small integers: exact in any order
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kPT / 64; ++w) t += red[w];
+      pw = t / ((double)T * T);
+    }
+  }
+  if (threadIdx.x == 0) {
+    st.gemm_u[0] = kKrMaxP;
+    st.gemm_u[1] = kx;
+    st.gemm_u[2] = cnt;
+    rep.du = du;
+    rep.pu = pairs;
+    rep.lu = 1;
+    rep.eps = eps;
+    if (pw >= 0.0) rep.pw = pw;
+    const bool err = (*b.flags & kFlagsError) != 0;
+    if (!err) st.iters_done = p.it + 1;
+    if (err) {
+      st.done = 1;
+    } else if (!p.fixed) {
+      // the stop test: eps = max |E~| estimates the error of X^(1); the post-update error
+      // modelled by eq. (assume2) is eps^2 max|lambda| / (xi gap)
+      if (eps <= p.delta_int || eps * eps * st.lmax_w / (p.xi_stop * st.gmin_w) <= p.delta_int) {
+        st.done = 1;
+      } else if (p.it >= 1 && eps > 0.5 * st.eps_prev) {
+        // no quadratic decrease: the floor that the products' truncation leaves
+        st.done = 1;
+        if (eps > p.target) st.stop_status = REFEIG_NOT_CONVERGED;
+      } else if (p.it + 1 == p.iters) {
+        st.done = 1;
+        st.stop_status = REFEIG_NOT_CONVERGED;
+      }
+    }
+    st.eps_prev = eps;
+  }
+}
+
+// ---------------------------------------------------------------- residue planes
+__global__ __launch_bounds__(256) void k_residues_dev(const int8_t *__restrict__ planes,
+                                                      size_t pstride, size_t count,
+                                                      const ResWeights *__restrict__ w,
+                                                      int8_t *__restrict__ res,
+                                                      const int *__restrict__ gate) {
+  if (gate && *gate == 0) return;
+  constexpr int G = (kCrtPlanes + 3) / 4;
+  __shared__ int swp[kCrtMax][G];
+  __shared__ float sm[kCrtMax], srm[kCrtMax];
+  const int K = w->k, N = w->N;
+  for (int q = threadIdx.x; q < kCrtMax * G; q += 256) swp[q / G][q % G] = w->wp[q / G][q % G];
+  for (int q = threadIdx.x; q < kCrtMax; q += 256) {
+    sm[q] = (float)w->m[q];
+    srm[q] = w->rmf[q];
+  }
+  __syncthreads();
+  for (size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4; e < count;
+       e += (size_t)gridDim.x * 256 * 4) {
+    unsigned v[4 * G];
+#pragma unroll
+    for (int t = 0; t < 4 * G; ++t)
+      v[t] = (t < K) ? *(const unsigned *)(planes + (size_t)t * pstride + e) : 0u;
+    int dg[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+        dg[g][bb] = (int)(((v[4 * g] >> (8 * bb)) & 0xffu) |
+                          (((v[4 * g + 1] >> (8 * bb)) & 0xffu) << 8) |
+                          (((v[4 * g + 2] >> (8 * bb)) & 0xffu) << 16) |
+                          (((v[4 * g + 3] >> (8 * bb)) & 0xffu) << 24));
+    for (int q = 0; q < N; ++q) {
+      const float m = sm[q], rm = srm[q];
+      unsigned packed = 0u;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        int acc = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc = __builtin_amdgcn_sdot4(dg[g][bb], swp[q][g], acc, false);
+        const float a = (float)acc;
+        const int rr = (int)(a - m * rintf(a * rm));
+        packed |= ((unsigned)(rr & 0xff)) << (8 * bb);
+      }
+      *(unsigned *)(res + (size_t)q * pstride + e) = packed;
+    }
+  }
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_dp_init(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_init, dim3(1), dim3(kPT), 0, s, p, b);
+}
+void launch_dp_order(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_order, dim3(1), dim3(kPT), 0, s, p, b);
+}
+void launch_dp_vplan(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_vplan, dim3(1), dim3(kPT), 0, s, p, b);
+}
+void launch_dp_wplan(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_wplan, dim3(1), dim3(kPT), 0, s, p, b);
+}
+void launch_dp_uplan(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_uplan, dim3(1), dim3(kPT), 0, s, p, b);
+}
+void launch_residues_dev(const int8_t *planes, size_t pstride, size_t count, const ResWeights *w,
+                         int8_t *res, const int *gate, hipStream_t s) {
+  const size_t quads = count / 4;
+  size_t blocks = (quads + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_residues_dev, dim3((unsigned)blocks), dim3(256), 0, s, planes, pstride,
+                     count, w, res, gate);
+}
+void launch_fill_int(int *p, int n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+}  // namespace refeig

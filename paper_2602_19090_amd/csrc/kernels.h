@@ -10,7 +10,10 @@ constexpr int kMaxDiag = 32;   // pair diagonals per product
 constexpr int kEpiThreads = 1024;
 
 // Flags raised by kernels (bitwise OR into a device int).
-enum : int { FLAG_NONFINITE = 1, FLAG_TIE = 2, FLAG_RANGE = 4 };
+enum : int { FLAG_NONFINITE = 1, FLAG_TIE = 2, FLAG_RANGE = 4, FLAG_GAP = 8 };
+// Any of these ends a solve with an error; kernels that write X and D skip their work once one
+// is raised (the caller keeps the last completed iterate).
+constexpr int kFlagsError = FLAG_NONFINITE | FLAG_TIE | FLAG_RANGE | FLAG_GAP;
 
 struct DiagOrder {
   int q[kMaxDiag];  // launch position -> diagonal slot
@@ -36,10 +39,11 @@ void launch_row_nonzeros(const double *A, int lda, int n, int *kmax, hipStream_t
 //  planesT (optional): kT planes of the transposed layout, element (i, j) at i*cpad + j.
 // The grid covers the padded rpad x cpad area and writes zero digits outside.
 // colmap (device, may be null): column j is read from column colmap[j] of M.
+// kdev (device, may be null): the plane count k (and kT) read from device memory instead.
 void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
                        int8_t *planesT, size_t pstrideT, int kT, hipStream_t s,
-                       const int *colmap = nullptr);
+                       const int *colmap = nullptr, const int *kdev = nullptr);
 
 constexpr int kMaxRowBlocks = 64;
 struct RowBlocks {
@@ -73,11 +77,14 @@ void launch_digits_e4m3(const int8_t *in, uint8_t *out, size_t count, int *bad, 
 // The same products for npad >= 1024 in one launch of nblocks 256 x 256 blocks, block b
 // computing the tile and diagonal slot of tab[b] (device memory; L row block | R row block
 // << 8 | slot << 16, slot = d - d_min); the host orders the table. tcut as above.
+// dp (device, may be null): {kl, kr, table entries} read from device memory; blocks at or
+// beyond the entry count exit (the launch is sized for the largest table). npad < 1024: the
+// 128 x 128 kernel, table entries in units of its tiles.
 void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad,
                              int kl, int kr, int d_min, const int *tab, int nblocks, int32_t *C,
                              hipStream_t s, hipEvent_t ev_start = nullptr,
                              hipEvent_t ev_stop = nullptr, int kdim = 0,
-                             const int *tcut = nullptr);
+                             const int *tcut = nullptr, const int *dp = nullptr);
 // L rows per block tile of launch_slice_gemm for this npad.
 int gemm_tile_rows(int npad);
 
@@ -87,9 +94,11 @@ int gemm_tile_rows(int npad);
 // distance from each column's eigenvalue estimate to the nearest one of row block I;
 // cx = 7 + log2(1.5 kx) + log2(sqrt n) - log2(theta delta). T <= kMaxTileSide.
 constexpr int kMaxTileSide = 32;
+// cxp, dmaxp (device, may be null): cx and dmax read from device memory instead.
 void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
                          int n, int T, double cx, int dmax, int dextra, const double *tcol,
-                         const double *gcol, int *tcut, hipStream_t s);
+                         const double *gcol, int *tcut, hipStream_t s,
+                         const double *cxp = nullptr, const int *dmaxp = nullptr);
 
 // V epilogue fused with the column pass of Algorithm 1 (column j per block):
 //   V_ij = sum_d 2^(eA_i + eX_j - 7d) C_d(i, j)  (double-word),
@@ -142,15 +151,16 @@ struct CrtRec {
 // of stride npad^2 bytes, reduced mod m_q by the GEMM) instead of summed from slice diagonals.
 // recs (device): one record per level; vblk (device, may be null: level 0 for all): per
 // 256-column block, its slot count and level.
+// gate (device, may be null): the kernel does nothing while *gate == 0.
 void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec *recs, const int *vblk,
                       const int *eA, const int *eX, const double *X1, int n, double *lam,
                       double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rpl, int kr,
-                      int *flags, hipStream_t s);
+                      int *flags, hipStream_t s, const int *gate = nullptr);
 
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eA, const int *eX, const double *X1, int n, double *lam,
                   double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rplanes, int kr,
-                  int *flags, hipStream_t s);
+                  int *flags, hipStream_t s, const int *gate = nullptr);
 
 // W epilogue (column j per block): W_ij = sum_d 2^(eX_i + eR_j - 7d) C_d(i, j),
 //   e_ij = W_ij / (lambda_j - lambda_i) (difference of the double-word values),
@@ -188,12 +198,14 @@ void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const in
 
 // Update: X_ij = hi(TwoSum(X1_ij, U_ij)), U_ij = sum_d 2^(eE_j - 7d) C_d(i, j); column j
 // is written to column colmap[j] of X (colmap may be null).
+// errflags (device, may be null): nothing is written once an error flag is raised.
 void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s,
-                  const int *colmap = nullptr);
+                  const int *colmap = nullptr, const int *errflags = nullptr);
 
-// out[colmap[p]] = v[p] for p < n (colmap may be null).
-void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s);
+// out[colmap[p]] = v[p] for p < n (colmap may be null); nothing once *errflags holds an error.
+void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s,
+                    const int *errflags = nullptr);
 
 
 // ---- complex Hermitian case. Complex matrices are interleaved (re, im), column-major,

@@ -263,8 +263,13 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
                                                     int rpad, int cpad, double *__restrict__ trunc,
                                                     int ldt, int8_t *__restrict__ planesT,
                                                     size_t pstrideT, int kT,
-                                                    const int *__restrict__ colmap) {
+                                                    const int *__restrict__ colmap,
+                                                    const int *__restrict__ kdev) {
   __shared__ __attribute__((aligned(16))) int8_t sC[64 * kSplitRow];
+  if (kdev) {
+    k = *kdev;
+    kT = WITH_T ? k : 0;
+  }
   __shared__ __attribute__((aligned(16))) int8_t sR[WITH_T ? 64 * kSplitRow : 16];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int tid = threadIdx.x, ig = tid & 15, jg = tid >> 4;
@@ -353,14 +358,15 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
 void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
                        int8_t *planesT, size_t pstrideT, int kT, hipStream_t s,
-                       const int *colmap) {
+                       const int *colmap, const int *kdev) {
   dim3 grid(rpad / 64, cpad / 64);
   if (planesT && kT > 0)
     hipLaunchKernelGGL(k_split_cols<true>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
-                       pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT, colmap);
+                       pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT, colmap, kdev);
   else
     hipLaunchKernelGGL(k_split_cols<false>, grid, dim3(256), 0, s, M, ld, rows, cols, e, k, planes,
-                       pstride, rpad, cpad, trunc, ldt, (int8_t *)nullptr, (size_t)0, 0, colmap);
+                       pstride, rpad, cpad, trunc, ldt, (int8_t *)nullptr, (size_t)0, 0, colmap,
+                       kdev);
 }
 
 // ---------------------------------------------------------------- INT8 slice GEMM
@@ -376,13 +382,36 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
                                                        size_t pstride, int npad, int kdim,
                                                        int kl, int kr, int d_min, DiagOrder order,
                                                        int32_t *__restrict__ C, RowBlocks rb,
-                                                       int same, const int *__restrict__ mods) {
+                                                       int same, const int *__restrict__ mods,
+                                                       const int *__restrict__ tab,
+                                                       const int *__restrict__ dp,
+                                                       const int *__restrict__ vblk) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
-  const int tiles_n = npad / GBN;
-  const int m0 = rb.m[blockIdx.x / tiles_n] * GBM;
-  const int n0 = (blockIdx.x % tiles_n) * GBN;
-  const int slot = order.q[blockIdx.y];
+  int m0, n0, slot;
+  if (tab) {   // block table: row tile | column tile << 8 | slot << 16 (128 x 128 tiles)
+    if (dp) {
+      if ((int)blockIdx.x >= dp[2]) return;
+      kl = dp[0];
+      kr = dp[1];
+    }
+    const int ent = tab[blockIdx.x];
+    m0 = (ent & 0xff) * GBM;
+    n0 = ((ent >> 8) & 0xff) * GBN;
+    slot = ent >> 16;
+  } else {
+    const int tiles_n = npad / GBN;
+    m0 = rb.m[blockIdx.x / tiles_n] * GBM;
+    n0 = (blockIdx.x % tiles_n) * GBN;
+    slot = order.q[blockIdx.y];
+  }
+  // vblk (same-plane products, per 256-row block of L: slot count, level)
+  int roff = 0;
+  if (vblk) {
+    const int mb = m0 / 256;
+    if (slot >= vblk[2 * mb]) return;
+    roff = vblk[2 * mb + 1] * kCrtMax;
+  }
   const int d = d_min + slot;
   // same: slot q multiplies plane q + 1 of both operands (one pair); else the pairs of
   // diagonal d, planes (s, d - s)
@@ -407,7 +436,7 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
     const int p = t / KT, k0 = (t - p * KT) * GBK;
     const int s = s_lo + p;
     const int8_t *Lb = Lp + (size_t)(s - 1) * pstride;
-    const int8_t *Rb = Rp + (size_t)(rsum - s - 1) * pstride;
+    const int8_t *Rb = Rp + (size_t)(roff + rsum - s - 1) * pstride;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
@@ -541,10 +570,16 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
                                                            int same, const int *__restrict__ tcut,
                                                            const int *__restrict__ tab,
                                                            const int *__restrict__ mods,
-                                                           const int *__restrict__ vblk) {
+                                                           const int *__restrict__ vblk,
+                                                           const int *__restrict__ dp) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
   int m0, n0, slot;
+  if (dp) {   // device-planned table launch: sized for the largest table
+    if ((int)blockIdx.x >= dp[2]) return;
+    kl = dp[0];
+    kr = dp[1];
+  }
   if (tab) {   // block table: row block | column block << 8 | slot << 16
     const int ent = tab[blockIdx.x];
     m0 = (ent & 0xff) * HBM_;
@@ -781,16 +816,16 @@ void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int n
     hipExtLaunchKernelGGL(k_slice_gemm256d<true>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start,
                           ev_stop, 0, Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb,
                           (int)same_plane, tcut, (const int *)nullptr, (const int *)nullptr,
-                          (const int *)nullptr);
+                          (const int *)nullptr, (const int *)nullptr);
   else if (npad >= 1024)
-    hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
-                          Lp, Rp, pstride,
-                       npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane, tcut,
-                       (const int *)nullptr, mods, vblk);
+    hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(tiles, ndiag), dim3(256), 0, s, ev_start,
+                          ev_stop, 0, Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb,
+                          (int)same_plane, tcut, (const int *)nullptr, mods, vblk,
+                          (const int *)nullptr);
   else
     hipExtLaunchKernelGGL(k_slice_gemm, dim3(tiles, ndiag), dim3(256), 0, s, ev_start, ev_stop, 0,
-                          Lp, Rp, pstride, npad, kdim,
-                       kl, kr, d_min, o, C, rb, (int)same_plane, mods);
+                          Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, (int)same_plane,
+                          mods, (const int *)nullptr, (const int *)nullptr, vblk);
 }
 
 // FP8 E4M3 (sign, 4 exponent bits with bias 7, 3 mantissa bits): a nonzero |d| <= 15 is
@@ -825,16 +860,21 @@ int gemm_tile_rows(int npad) { return npad >= 1024 ? HBM_ : GBM; }
 void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad,
                              int kl, int kr, int d_min, const int *tab, int nblocks, int32_t *C,
                              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, int kdim,
-                             const int *tcut) {
+                             const int *tcut, const int *dp) {
   if (kdim <= 0) kdim = npad;
   if (nblocks <= 0) return;
   DiagOrder o;
   RowBlocks rb;
   rb.count = 0;
   for (int q = 0; q < kMaxDiag; ++q) o.q[q] = q;
-  hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
-                        Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0, tcut, tab,
-                        (const int *)nullptr, (const int *)nullptr);
+  if (npad >= 1024)
+    hipExtLaunchKernelGGL(k_slice_gemm256d<false>, dim3(nblocks, 1), dim3(256), 0, s, ev_start,
+                          ev_stop, 0, Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0,
+                          tcut, tab, (const int *)nullptr, (const int *)nullptr, dp);
+  else
+    hipExtLaunchKernelGGL(k_slice_gemm, dim3(nblocks, 1), dim3(256), 0, s, ev_start, ev_stop, 0,
+                          Lp, Rp, pstride, npad, kdim, kl, kr, d_min, o, C, rb, 0,
+                          (const int *)nullptr, tab, dp, (const int *)nullptr);
 }
 
 // Digit planes of one operand row j (an output column of a column epilogue): the values
@@ -966,8 +1006,10 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
-    int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk) {
+    int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
+    const int *__restrict__ gate) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
+  if (gate && *gate == 0) return;
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
@@ -1094,21 +1136,22 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
 template <int EPT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
-                    int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
+                    int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s,
+                    const int *gate) {
   hipLaunchKernelGGL((k_epi_v<EPT, false>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min,
                      ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags,
-                     (const CrtRec *)nullptr, (const int *)nullptr);
+                     (const CrtRec *)nullptr, (const int *)nullptr, gate);
 }
 
 void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec *recs, const int *vblk,
                       const int *eA, const int *eX, const double *X1, int n, double *lam,
                       double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rpl, int kr,
-                      int *flags, hipStream_t s) {
+                      int *flags, hipStream_t s, const int *gate) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
 #define EPI_V_CRT(E)                                                                          \
   hipLaunchKernelGGL((k_epi_v<E, true>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, 2, 1,   \
                      (const int *)nullptr, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr,  \
-                     flags, recs, vblk)
+                     flags, recs, vblk, gate)
   if (ept <= 1) EPI_V_CRT(1);
   else if (ept <= 2) EPI_V_CRT(2);
   else if (ept <= 4) EPI_V_CRT(4);
@@ -1180,12 +1223,13 @@ void launch_residues(const int8_t *planes, size_t pstride, size_t count, const R
 
 void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
-                  int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s) {
+                  int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s,
+                  const int *gate) {
   const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
-  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
-  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s);
+  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
+  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
+  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
+  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
 }
 
 // Slots of W entry (i, j) that hold diagonals to sum: up to the column's cutoff dcut[j] or,
@@ -1213,8 +1257,12 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
                                                       int T, double cx, int dmax, int dextra,
                                                       const double *__restrict__ tcol,
                                                       const double *__restrict__ gcol,
-                                                      int *__restrict__ tcut) {
+                                                      int *__restrict__ tcut,
+                                                      const double *__restrict__ cxp,
+                                                      const int *__restrict__ dmaxp) {
   __shared__ double v[256];
+  if (cxp) cx = *cxp;
+  if (dmaxp) dmax = *dmaxp;
   __shared__ int tm[kMaxTileSide];
   __shared__ int exb;
   const int I = blockIdx.x, tid = threadIdx.x;
@@ -1273,9 +1321,10 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
 
 void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
                          int n, int T, double cx, int dmax, int dextra, const double *tcol,
-                         const double *gcol, int *tcut, hipStream_t s) {
+                         const double *gcol, int *tcut, hipStream_t s, const double *cxp,
+                         const int *dmaxp) {
   hipLaunchKernelGGL(k_tile_cutoffs, dim3(T), dim3(256), 0, s, lam, eX, eR, resmax, n, T, cx,
-                     dmax, dextra, tcol, gcol, tcut);
+                     dmax, dextra, tcol, gcol, tcut, cxp, dmaxp);
 }
 
 // ---------------------------------------------------------------- W epilogue -> E~
@@ -1551,9 +1600,11 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
                                                const int *__restrict__ eE,
                                                const double *__restrict__ X1, int n,
                                                double *__restrict__ X, int ldx,
-                                               const int *__restrict__ colmap) {
+                                               const int *__restrict__ colmap,
+                                               const int *__restrict__ errflags) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
+  if (errflags && (*errflags & kFlagsError)) return;
   const size_t P = (size_t)npad * npad;
   const int32_t *Ccol = C + (size_t)j * npad;
   const int ej = eE[j];
@@ -1566,19 +1617,22 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
 
 void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s,
-                  const int *colmap) {
+                  const int *colmap, const int *errflags) {
   hipLaunchKernelGGL(k_epi_u, dim3((n + 255) / 256, n), dim3(256), 0, s, C, npad, d_min, ndiag, dcut,
-                     eE, X1, n, X, ldx, colmap);
+                     eE, X1, n, X, ldx, colmap, errflags);
 }
 
 __global__ void k_scatter(const double *__restrict__ v, const int *__restrict__ colmap, int n,
-                          double *__restrict__ out) {
+                          double *__restrict__ out, const int *__restrict__ errflags) {
+  if (errflags && (*errflags & kFlagsError)) return;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p < n) out[colmap ? colmap[p] : p] = v[p];
 }
 
-void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, v, colmap, n, out);
+void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s,
+                    const int *errflags) {
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, v, colmap, n, out,
+                     errflags);
 }
 
 

@@ -39,6 +39,8 @@
 #include "../../include/refeig.h"
 #include "kernels.h"
 #include "plain.h"
+#include "plan.h"
+#include "devplan.h"
 
 using namespace refeig;
 
@@ -82,6 +84,8 @@ struct Work {
   int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
   double *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
   double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
+  DevState *dst;   // device planning state
+  double *gapsw;   // entry gaps in working order (device planning)
 };
 
 int nslots(int ka, bool crt = false) {
@@ -156,6 +160,8 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.r = (double *)take(vd);
   t.resmax = (double *)take(vd);
   t.emax = (double *)take(vd);
+  t.dst = (DevState *)take(sizeof(DevState));
+  t.gapsw = (double *)take(vd);
   if (w) *w = t;
   return off;
 }
@@ -253,41 +259,6 @@ size_t carve_herm(int n, int ka, char *base, HermWork *w) {
   return off;
 }
 
-// ---- V by residues: moduli and reconstruction constants.
-// Odd, pairwise coprime moduli <= 255, largest first (greedy over 255, 253, ...).
-const std::vector<int> &crt_moduli() {
-  static const std::vector<int> mods = [] {
-    std::vector<int> v;
-    for (int m = 255; m >= 3 && (int)v.size() < kCrtMax; m -= 2) {
-      bool ok = true;
-      for (int x : v) {
-        int a = m, b = x;
-        while (b) {
-          int t = a % b;
-          a = b;
-          b = t;
-        }
-        if (a != 1) ok = false;
-      }
-      if (ok) v.push_back(m);
-    }
-    return v;
-  }();
-  return mods;
-}
-
-int inv_mod(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1)
-  int t = 0, nt = 1, r = m, nr = ((a % m) + m) % m;
-  while (nr) {
-    const int q = r / nr, tt = t - q * nt, rr = r - q * nr;
-    t = nt;
-    nt = tt;
-    r = nr;
-    nr = rr;
-  }
-  return t < 0 ? t + m : t;
-}
-
 // Residue weights of k digit planes for N odd moduli m_q <= 255: w_qt = 128^(k-1-t) mod m_q
 // in the symmetric range (|w| <= 127), also packed four planes to a dword for the dot4
 // products of the residue kernel.
@@ -315,93 +286,20 @@ void res_weights(int k, int N, const int *mods, ResWeights &rw) {
   }
 }
 
-// Plans V = P 2^(eA_i + eX_j - 7 (ka1 + kx)) with P = Ã X̃ (ka1 digits of A, kx of X^(1),
+// Plans V = P 2^(eA_i + eX_j - 7 (ka1 + kx)) with P = A~ X~ (ka1 digits of A, kx of X^(1),
 // reduction length npad): enough moduli that prod m_q > 4 2^hbits 128^(ka1 + kx) (so
-// |P| < M / 4), the digit weights of both residue passes and the triple-double constants.
+// |P| < M / 4), the digit weights of both residue passes and the reconstruction record.
 // False when more than kCrtMax moduli would be needed.
 // hbits (optional): log2 of a bound on ||a_i|| 2^-eA_i times ||x_j|| 2^-eX_j over all rows
-// and columns (Cauchy-Schwarz: |P_ij| <= ||Ã_i|| ||X̃_j|| <= 2^(hbits + 7 (ka1 + kx)));
+// and columns (Cauchy-Schwarz: |P_ij| <= ||A~_i|| ||X~_j|| <= 2^(hbits + 7 (ka1 + kx)));
 // log2(npad) (the bound for any input) when absent or larger.
 bool crt_plan(int npad, int ka1, int kx, ResWeights &wA, ResWeights &wX, CrtRec &rec,
               double hbits = -1.0) {
-  const std::vector<int> &mods = crt_moduli();
-  const double hb = (hbits >= 0.0 && hbits < std::log2((double)npad)) ? hbits
-                                                                      : std::log2((double)npad);
-  const double need = 2.0 + hb + 7.0 * (ka1 + kx);
-  double bits = 0.0;
-  int N = 0;
-  while (N < (int)mods.size() && bits <= need) bits += std::log2((double)mods[N++]);
-  if (bits <= need || ka1 > kCrtPlanes || kx > kCrtPlanes) return false;
-  rec.N = N;
-  rec.sh = -7 * (ka1 + kx);
-  res_weights(ka1, N, mods.data(), wA);
-  res_weights(kx, N, mods.data(), wX);
-  for (int q = 0; q < N; ++q) {
-    const int m = mods[q];
-    rec.m[q] = m;
-    rec.rm[q] = 1.0 / (double)m;
-    long long Mq = 1;   // (M / m_q) mod m_q
-    for (int l = 0; l < N; ++l)
-      if (l != q) Mq = Mq * (mods[l] % m) % m;
-    const double y = (double)inv_mod((int)Mq, m), md = (double)m;
-    const double u0 = y / md, r0 = std::fma(-u0, md, y);
-    const double u1 = r0 / md, r1 = std::fma(-u1, md, r0);
-    rec.u[q][0] = u0;
-    rec.u[q][1] = u1;
-    rec.u[q][2] = r1 / md;
-  }
-  // M = prod m_q as a double-word (relative error about N 2^-105: it only scales P / M, so
-  // V keeps a double-word's relative accuracy)
-  double a0 = 1.0, a1 = 0.0;
-  for (int q = 0; q < N; ++q) {
-    const double md = (double)mods[q];
-    const double p0 = a0 * md, e0 = std::fma(a0, md, -p0);
-    const double sl = e0 + a1 * md;
-    a0 = p0 + sl;
-    a1 = sl - (a0 - p0);
-  }
-  const double a2 = 0.0;
-  // pairs of slots (2t, 2t + 1) and their triple-double constants U_t = Y_t / M_t
-  rec.T = (N + 1) / 2;
-  for (int t = 0; t < rec.T; ++t) {
-    const int qa = 2 * t, qb = 2 * t + 1;
-    long long Mt = mods[qa];
-    if (qb < N) {
-      Mt *= mods[qb];
-      rec.pma[t] = (float)mods[qa];
-      rec.pmb[t] = (float)mods[qb];
-      rec.prmb[t] = 1.0f / (float)mods[qb];
-      rec.pinv[t] = (float)inv_mod(mods[qa] % mods[qb], mods[qb]);
-    }
-    long long rest = 1;   // (M / M_t) mod M_t
-    for (int l = 0; l < N; ++l)
-      if (l != qa && l != qb) rest = rest * (mods[l] % Mt) % Mt;
-    // Y_t = rest^-1 mod M_t (extended Euclid in 64-bit)
-    long long r0 = Mt, r1 = rest % Mt, t0 = 0, t1 = 1;
-    while (r1) {
-      const long long qq = r0 / r1, r2 = r0 - qq * r1, t2 = t0 - qq * t1;
-      r0 = r1;
-      r1 = r2;
-      t0 = t1;
-      t1 = t2;
-    }
-    const double Y = (double)(t0 < 0 ? t0 + Mt : t0), Md = (double)Mt;
-    const double v0 = Y / Md, q0 = std::fma(-v0, Md, Y);
-    const double v1 = q0 / Md, q1 = std::fma(-v1, Md, q0);
-    rec.U[t][0] = v0;
-    rec.U[t][1] = v1;
-    rec.U[t][2] = q1 / Md;
-    // limbs of Y_t / M_t by long division (every quotient and remainder exact: num < 2^50)
-    long long rem = (long long)Y;
-    for (int k = 0; k < kCrtLimbs; ++k) {
-      const long long num = rem << kCrtLimbBits;
-      rec.L[t][k] = (double)(num / Mt);
-      rem = num % Mt;
-    }
-  }
-  rec.M[0] = a0;
-  rec.M[1] = a1;
-  rec.M[2] = a2;
+  const int N = crt_count(crt_need_bits(npad, ka1, kx, hbits));
+  if (N < 0 || ka1 > kCrtPlanes || kx > kCrtPlanes) return false;
+  res_weights_build(ka1, N, wA);
+  res_weights_build(kx, N, wX);
+  crt_rec_build(N, ka1, kx, rec);
   return true;
 }
 
@@ -410,10 +308,6 @@ int ka_of(const refeig_opts *o) {
   return std::min(ka, kKaMaxLimit);
 }
 
-int npairs_of(int d, int kl, int kr) {
-  int lo = std::max(1, d - kr), hi = std::min(kl, d - 1);
-  return hi >= lo ? hi - lo + 1 : 0;
-}
 
 // Per-column pair cutoffs -> per GEMM tile (max over its columns, the block
 // computes those diagonals anyway), expanded back to every column and uploaded
@@ -458,24 +352,6 @@ bool plan_cutoffs(const std::vector<int> &dcol, int n, int npad, int kl, int kr,
 // XCDs (id mod 8), each with its own L2; with tiles_n a multiple of 8 each XCD owns a band
 // of column blocks and walks it in groups of up to 8 row blocks (the kernel's own order
 // without a table).
-void xcd_tile_order(int bid, int tiles_m, int tiles_n, int &mi, int &nb) {
-  if (tiles_n % 8 == 0) {
-    const int xcd = bid & 7, local = bid >> 3, cb = tiles_n >> 3;
-    const int rg = local / (8 * cb), rem = local - rg * 8 * cb;
-    const int gs = std::min(8, tiles_m - rg * 8);
-    mi = rg * 8 + rem % gs;
-    nb = xcd * cb + rem / gs;
-  } else if (tiles_m % 8 == 0) {
-    const int xcd = bid & 7, local = bid >> 3, rows = tiles_m >> 3;
-    mi = xcd + 8 * (local % rows);
-    nb = local / rows;
-  } else {
-    const int group = bid / (4 * tiles_n), first_m = group * 4;
-    const int gsz = std::min(tiles_m - first_m, 4), inb = bid - group * 4 * tiles_n;
-    mi = first_m + inb % gsz;
-    nb = inb / gsz;
-  }
-}
 
 // One launch per product (npad >= 1024): the blocks of every group and diagonal in one table,
 // the diagonals with the most pairs first, so blocks of all groups share the chip and the
@@ -776,7 +652,7 @@ double xi_of(const refeig_opts &o, int n) {
 // min(k, sqrt(n)) under the sparse rule.
 double lgrowth_of(const refeig_opts &o, int n) {
   const double sq = std::sqrt((double)n);
-  return std::log2(o.sparse_k > 0 ? std::min((double)o.sparse_k, sq) : sq);
+  return plan_log2(o.sparse_k > 0 ? std::min((double)o.sparse_k, sq) : sq);
 }
 
 // beta of Sec. 4.1 (floor form): beta = floor(log2((1/(0.75u)) sqrt(xi delta g / (L S)))),
@@ -785,21 +661,15 @@ double lgrowth_of(const refeig_opts &o, int n) {
 // rounding bound u*ufp(tau_j) of eq. (minamihata).
 void beta_rule(int n, double xi, double delta, double g, double L, const std::vector<int> &e,
                const std::vector<int> &c, const std::vector<double> &mx, int *beta, int *kx) {
-  double S = 0.0;
+  std::vector<int> hist(kBetaBins, 0);
   int extra = 0;
   for (int j = 0; j < n; ++j) {
     if (mx[j] == 0.0) continue;
-    S += std::ldexp(1.0, 2 * c[j]);
+    const int b = std::min(kBetaBins - 1, std::max(0, 2 * c[j] + kBetaBias));
+    ++hist[b];
     extra = std::max(extra, e[j] - c[j]);
   }
-  double q = ((xi * delta) * g) / (L * S);
-  double t = std::sqrt(q) / (0.75 * std::ldexp(1.0, -53));
-  int ex = 0;
-  (void)std::frexp(t, &ex);
-  *beta = ex - 1;
-  int num = 54 - *beta + extra;
-  int k = num <= 0 ? 1 : (num + 6) / 7;
-  *kx = std::min(std::max(k, 1), kKxMax);
+  beta_core(xi, delta, g, L, pow2_sum(hist.data()), extra, beta, kx);
 }
 
 // Working column order: by gap, widest first; ties (two columns share a gap) go by
@@ -862,7 +732,7 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
   const double delta_int = target / o.delta_safety;
   const double xi = xi_of(o, n);
   const double lgrowth_a = lgrowth_of(o, n);   // error growth of products of A's planes
-  const int alpha = (int)std::ceil((53.0 + std::log2((double)n)) / 2.0);
+  const int alpha = (int)std::ceil((53.0 + plan_log2((double)n)) / 2.0);
   const int b = 53 - alpha;  // bits per FP64 slice
   auto t_start = std::chrono::steady_clock::now();
   rocblas_handle hb = nullptr;
@@ -945,8 +815,8 @@ int refine_plain(const double *A, int lda, double *X, int ldx, double *D, int n,
     int dv = 2;
     for (int j = 0; j < n; ++j) {
       if (mxX[j] == 0.0) continue;
-      double need_bits = eA_max + eX[j] + b + std::log2(1.5 * kx) + lgrowth_a -
-                         std::log2(o.theta * delta_int * gaps[j]);
+      double need_bits = eA_max + eX[j] + b + plan_log2(1.5 * kx) + lgrowth_a -
+                         plan_log2(o.theta * delta_int * gaps[j]);
       dv = std::max(dv, (int)std::ceil(need_bits / b));
     }
     dv = std::min(dv + o.d_extra, kPlainKaMax + kx);
@@ -1068,7 +938,7 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
   const double delta = target / o.delta_safety;
   const double xi = xi_of(o, n);
   const double theta = o.theta;
-  const double lsq2n = 0.5 * std::log2(2.0 * n);   // statistical growth over 2n real terms
+  const double lsq2n = 0.5 * plan_log2(2.0 * n);   // statistical growth over 2n real terms
   auto t_start = std::chrono::steady_clock::now();
 
   int status = REFEIG_OK;
@@ -1149,10 +1019,10 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
     std::vector<int> dcol(npad, 2);
     {
-      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lsq2n;
+      const double c0 = eA_max + 7 + plan_log2(1.5 * kx) + lsq2n;
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
-        double nd = (c0 + eX[j] - std::log2(theta * delta * gaps[j])) / 7.0;
+        double nd = (c0 + eX[j] - plan_log2(theta * delta * gaps[j])) / 7.0;
         dcol[j] = std::max(2, (int)std::ceil(nd) + o.d_extra);
       }
     }
@@ -1176,11 +1046,11 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
     column_gaps(lam, gaps, &gmin, &lmax);
     if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
     {
-      const double c0 = eXmax + 7 + std::log2(1.5 * kx) + lsq2n;
+      const double c0 = eXmax + 7 + plan_log2(1.5 * kx) + lsq2n;
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (resmax[j] == 0.0) continue;
-        double nd = (c0 + eR[j] - std::log2(theta * delta * gaps[j])) / 7.0;
+        double nd = (c0 + eR[j] - plan_log2(theta * delta * gaps[j])) / 7.0;
         dcol[j] = std::max(2, (int)std::ceil(nd) + o.d_extra);
       }
     }
@@ -1204,12 +1074,12 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
     // ---- X <- X^(1) + X^(1) E~ (each column t_j times tighter for noise stability, as in
     // the real path; W here already keeps each column within theta delta g_j)
     {
-      const double c0 = 7 + std::log2(1.008 * kx) + lsq2n - std::log2(theta * delta);
+      const double c0 = 7 + plan_log2(1.008 * kx) + lsq2n - plan_log2(theta * delta);
       std::fill(dcol.begin(), dcol.end(), 2);
       for (int j = 0; j < n; ++j) {
         if (emax[j] == 0.0) continue;
         const double t = std::sqrt(delta * gaps[j] / (4.0 * lmax)) / (theta * delta);
-        const double need = (c0 + eE[j] - std::log2(std::min(1.0, t))) / 7.0;
+        const double need = (c0 + eE[j] - plan_log2(std::min(1.0, t))) / 7.0;
         dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
       }
     }
@@ -1278,6 +1148,269 @@ int refine_herm(const double *A, int lda, double *X, int ldx, double *D, int n, 
   }
   return cleanup(status);
 #undef STEP
+}
+
+// ---- device-planned solve: every decision of an iteration is made by the planning kernels
+// (devplan.hip) from values already on the device, so the host only enqueues.
+
+// Timing events, reused across calls (a call takes a set and returns it).
+struct EventPool {
+  std::mutex mu;
+  std::vector<hipEvent_t> free_;
+  std::vector<hipEvent_t> take(size_t k) {
+    std::vector<hipEvent_t> out;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      while (out.size() < k && !free_.empty()) {
+        out.push_back(free_.back());
+        free_.pop_back();
+      }
+    }
+    while (out.size() < k) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      out.push_back(e);
+    }
+    return out;
+  }
+  void give(std::vector<hipEvent_t> &ev) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto e : ev) free_.push_back(e);
+    ev.clear();
+  }
+};
+EventPool &event_pool() {
+  static EventPool *p = new EventPool();   // never destroyed: events live with the process
+  return *p;
+}
+
+constexpr int kEvPerIter = 18;   // as the host-planned solve: iteration, products, phases
+
+void fill_report_from_device(const DevState &st, int flags, int iters_enqueued,
+                             refeig_report *rep) {
+  const int k = std::min(st.iters_done, REFEIG_MAX_ITERS);
+  rep->iters = k;
+  for (int it = 0; it < k; ++it) {
+    const DevIter &r = st.rep[it];
+    rep->beta[it] = r.beta;
+    rep->kx[it] = r.kx;
+    rep->dv[it] = r.dv;
+    rep->dw[it] = r.dw;
+    rep->du[it] = r.du;
+    rep->eps[it] = r.eps;
+    rep->pairs_f[it][0] = r.pv;
+    rep->pairs_f[it][1] = r.pw;
+    rep->pairs_f[it][2] = r.pu;
+    rep->pairs_p[it][0] = (int)std::lround(r.pv);
+    rep->pairs_p[it][1] = (int)std::lround(r.pw);
+    rep->pairs_p[it][2] = (int)std::lround(r.pu);
+    rep->pairs[it] = (int)std::lround(r.pv + r.pw + r.pu);
+    rep->launches_p[it][0] = r.lv;
+    rep->launches_p[it][1] = r.lw;
+    rep->launches_p[it][2] = r.lu;
+    rep->vres[it] = r.vres;
+    rep->delta_it[it] = r.delta;
+    rep->min_gap = r.gmin;
+    rep->max_abs_lambda = r.lmax;
+  }
+  (void)flags;
+  (void)iters_enqueued;
+}
+
+int status_of(const DevState &st, int flags) {
+  if (flags & FLAG_NONFINITE) return REFEIG_E_NONFINITE;
+  if (flags & FLAG_RANGE) return REFEIG_E_RANGE;
+  if (flags & (FLAG_GAP | FLAG_TIE)) return REFEIG_E_GAP;
+  return st.stop_status;
+}
+
+// The solve with device planning (INT8 path, no grouping, no schedule). `work` holds at least
+// carve(n, ka_max, crt) bytes. enqueue_only: no wait and no event (fixed_iters > 0).
+int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n, double target,
+                  const refeig_opts &o, void *work, hipStream_t s, refeig_report *rep,
+                  bool enqueue_only) {
+  const int ka_max = ka_of(&o);
+  const bool crt = o.vmode == 1;
+  Work w;
+  carve(n, ka_max, (char *)work, &w, crt);
+  const int npad = w.npad;
+  const size_t P = w.P;
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  PlanParams pp;
+  pp.n = n;
+  pp.npad = npad;
+  pp.it = 0;
+  pp.iters = iters;
+  pp.fixed = o.fixed_iters > 0 ? 1 : 0;
+  pp.kx_force = o.kx_force;
+  pp.ka_max = ka_max;
+  pp.d_extra = o.d_extra;
+  pp.vmode = o.vmode;
+  pp.stop_rule = o.stop_rule;
+  pp.crt = crt ? 1 : 0;
+  pp.theta = o.theta;
+  pp.delta_int = target / o.delta_safety;
+  pp.delta_k = pp.delta_int;
+  pp.xi = xi_of(o, n);
+  pp.xi_stop = o.stop_rule == 1 ? 1.0 : pp.xi;
+  pp.lgrowth_a = lgrowth_of(o, n);
+  pp.lsqn = 0.5 * plan_log2((double)n);
+  pp.target = target;
+  PlanBufs pb;
+  pb.st = w.dst;
+  pb.D = D;
+  pb.colmap = w.colmap;
+  pb.gapsw = w.gapsw;
+  pb.eA = w.eA;
+  pb.mxA = w.mxA;
+  pb.ssA = w.ssA;
+  pb.eX = w.eX;
+  pb.cX = w.cX;
+  pb.mxX = w.mxX;
+  pb.ssX = w.ssX;
+  pb.lam = w.lam;
+  pb.eR = w.eR;
+  pb.resmax = w.resmax;
+  pb.eE = w.eE;
+  pb.emax = w.emax;
+  pb.wtol = w.wtol;
+  for (int q = 0; q < 3; ++q) {
+    pb.dcut[q] = w.dcut[q];
+    pb.tab[q] = w.tab[q];
+  }
+  pb.vblk = w.vblk;
+  pb.tcut = npad >= 1024 ? w.tcut : nullptr;
+  pb.flags = w.flags;
+  pb.mods = w.mods;
+  DevState *st = w.dst;
+  const int tr = gemm_tile_rows(npad), TT = npad / tr;
+  // launch sizes of the tabled products: the largest tables the cutoffs allow
+  const int maxv = TT * TT * ka_max;
+  const int maxw = TT * TT * kKrMax, maxu = TT * TT * kKeMax;
+  const int T256 = npad / 256;
+  std::vector<hipEvent_t> ev;
+  if (!enqueue_only) ev = event_pool().take((size_t)kEvPerIter * iters);
+  const bool timed = !enqueue_only && ev.size() == (size_t)kEvPerIter * iters;
+  auto E = [&](int it, int q) -> hipEvent_t { return timed ? ev[(size_t)it * kEvPerIter + q] : nullptr; };
+  auto rec = [&](int it, int q) {
+    if (timed) (void)hipEventRecord(E(it, q), s);
+  };
+  auto t_start = std::chrono::steady_clock::now();
+  // A: column exponents (= row exponents, A is symmetric) and its digit planes, once
+  launch_fill_int(w.flags, 1, 0, s);
+  launch_colstats(A, lda, n, n, npad, w.eA, w.cA, w.mxA, w.flags, s, nullptr, w.ssA);
+  launch_dp_init(pp, pb, s);
+  launch_split_cols(A, lda, n, n, w.eA, ka_max, w.AP, P, npad, npad, nullptr, 0, nullptr, 0, 0, s);
+  int it = 0, host_status = REFEIG_OK;
+  DevState hst;
+  int hflags = 0;
+  for (; it < iters; ++it) {
+    pp.it = it;
+    rec(it, 0);
+    launch_dp_order(pp, pb, s);
+    rec(it, 8);
+    launch_colstats(X, ldx, n, n, npad, w.eX, w.cX, w.mxX, w.flags, s, w.colmap, w.ssX);
+    rec(it, 9);
+    launch_dp_vplan(pp, pb, s);
+    rec(it, 10);
+    launch_split_cols(X, ldx, n, n, w.eX, kKxMax, w.XP, P, npad, npad, w.X1, n, w.XPT, P, kKxMax,
+                      s, w.colmap, &st->kx);
+    rec(it, 11);
+    rec(it, 12);
+    if (crt) {
+      for (int l = 0; l < kVLevels; ++l)
+        launch_residues_dev(w.AP, P, P, &st->wA[l], w.ARES + (size_t)l * kCrtMax * P,
+                            &st->ares_dirty[l], s);
+      launch_residues_dev(w.XP, P, P, &st->wX, w.XRES, &st->vres, s);
+      // one launch for all moduli: slots beyond a block's count (0 when V goes by slices) exit
+      launch_slice_gemm(w.XRES, w.ARES, P, npad, kCrtMax, kCrtMax, 2, kCrtMax, w.Cs, nullptr, s,
+                        E(it, 1), E(it, 2), 0, true, nullptr, w.mods, false, w.vblk);
+      launch_epi_v_crt(w.Cs, npad, st->recs, w.vblk, w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
+                       w.eR, w.resmax, w.RP, kKrMax, w.flags, s, &st->vres);
+    }
+    // V by slices (vmode 0, or where the reconstruction floor rules residues out): the table
+    // is empty otherwise
+    launch_slice_gemm_table(w.XP, w.AP, P, npad, kKxMax, ka_max, 2, w.tab[0], maxv, w.Cs, s,
+                            crt ? nullptr : E(it, 1), crt ? nullptr : E(it, 2), 0, nullptr,
+                            st->gemm_v);
+    launch_epi_v(w.Cs, npad, 2, kMaxDiag - 1, w.dcut[0], w.eA, w.eX, w.X1, n, w.lam, w.lam_lo, w.r,
+                 w.eR, w.resmax, w.RP, kKrMax, w.flags, s, &st->vslice);
+    rec(it, 13);
+    rec(it, 14);
+    launch_dp_wplan(pp, pb, s);
+    if (npad >= 1024)
+      launch_tile_cutoffs(w.lam, w.eX, w.eR, w.resmax, n, T256, 0.0, 2, o.d_extra, w.wtol,
+                          w.wtol + npad, w.tcut, s, &st->cx, &st->dmax_w);
+    launch_slice_gemm_table(w.RP, w.XP, P, npad, kKrMax, kKxMax, 2, w.tab[1], maxw, w.Cs, s,
+                            E(it, 3), E(it, 4), 0, npad >= 1024 ? w.tcut : nullptr, st->gemm_w);
+    launch_epi_w(w.Cs, npad, 2, kMaxDiag - 1, w.dcut[1], w.eX, w.eR, w.lam, w.lam_lo, w.r, n, w.eE,
+                 w.emax, w.EP, kKeMax, w.flags, s, 0.0, nullptr, nullptr, 0,
+                 npad >= 1024 ? w.tcut : nullptr);
+    rec(it, 15);
+    launch_dp_uplan(pp, pb, s);
+    rec(it, 16);
+    launch_slice_gemm_table(w.EP, w.XPT, P, npad, kKeMax, kKxMax, 2, w.tab[2], maxu, w.Cs, s,
+                            E(it, 5), E(it, 6), 0, nullptr, st->gemm_u);
+    launch_epi_u(w.Cs, npad, 2, kMaxDiag - 1, w.dcut[2], w.eE, w.X1, n, X, ldx, s, w.colmap,
+                 w.flags);
+    launch_scatter(w.lam, w.colmap, n, D, s, w.flags);
+    rec(it, 17);
+    rec(it, 7);
+    if (hipGetLastError() != hipSuccess) {
+      host_status = REFEIG_E_HIP;
+      break;
+    }
+    if (!pp.fixed) {   // the stop test's decision (one small read per iteration)
+      if (hipMemcpyAsync(&hst.done, &st->done, sizeof(int), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        host_status = REFEIG_E_HIP;
+        break;
+      }
+      if (hst.done) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (enqueue_only) return host_status;
+  if (host_status == REFEIG_OK) {
+    if (hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      host_status = REFEIG_E_HIP;
+  }
+  int status = host_status;
+  if (status == REFEIG_OK) status = status_of(hst, hflags);
+  if (rep && host_status == REFEIG_OK) {
+    fill_report_from_device(hst, hflags, it, rep);
+    if (timed)
+      for (int k = 0; k < std::min(hst.iters_done, REFEIG_MAX_ITERS); ++k) {
+        float t = 0, g1 = 0, g2 = 0, g3 = 0;
+        (void)hipEventElapsedTime(&t, E(k, 0), E(k, 7));
+        (void)hipEventElapsedTime(&g1, E(k, 1), E(k, 2));
+        (void)hipEventElapsedTime(&g2, E(k, 3), E(k, 4));
+        (void)hipEventElapsedTime(&g3, E(k, 5), E(k, 6));
+        rep->ms_iter[k] = t;
+        rep->ms_p[k][0] = g1;
+        rep->ms_p[k][1] = g2;
+        rep->ms_p[k][2] = g3;
+        rep->ms_gemm[k] = g1 + g2 + g3;
+        for (int q = 0; q < 5; ++q) {
+          float ph = 0;
+          (void)hipEventElapsedTime(&ph, E(k, 8 + 2 * q), E(k, 9 + 2 * q));
+          rep->ms_phase[k][q] = ph;
+        }
+      }
+  }
+  if (!ev.empty()) event_pool().give(ev);
+  if (rep) {
+    rep->status = status;
+    rep->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+  }
+  return status;
 }
 
 }  // namespace
@@ -1514,9 +1647,12 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       o.max_iter > REFEIG_MAX_ITERS || o.fixed_iters > REFEIG_MAX_ITERS)
     return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  if (o.mode == REFEIG_FP64_PLAIN)
+  if (o.mode == REFEIG_FP64_PLAIN && !o.enqueue_only)
     return refine_plain(A, lda, X, ldx, D, n, target, o, work, work_bytes, s, rep);
-  if (o.mode != REFEIG_OZAKI_INT8) return REFEIG_E_ARG;
+  if (o.mode != REFEIG_OZAKI_INT8 || o.plan < 0 || o.plan > 1) return REFEIG_E_ARG;
+  // device planning unless the options need the host (grouped correction, schedule)
+  const bool dev_plan = o.plan == 0 && o.group_tau == 0.0 && o.schedule == 0;
+  if (o.enqueue_only && !(dev_plan && o.fixed_iters > 0 && work)) return REFEIG_E_ARG;
   const int ka_max = ka_of(&o);
   const bool crt = o.vmode == 1;
   const size_t need = carve(n, ka_max, nullptr, nullptr, crt);
@@ -1528,6 +1664,15 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   } else if (work_bytes < need) {
     return REFEIG_E_NOMEM;
   }
+  if (dev_plan) {
+    const int st = refine_device(A, lda, X, ldx, D, n, target, o, work, s, rep,
+                                 o.enqueue_only != 0);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(work);
+    }
+    return st;
+  }
   Work w;
   carve(n, ka_max, (char *)work, &w, crt);
   const int npad = w.npad;
@@ -1535,7 +1680,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   const double delta_int = target / o.delta_safety;
   const double xi = xi_of(o, n);
   const double theta = o.theta;
-  const double lsqn = 0.5 * std::log2((double)n);
+  const double lsqn = 0.5 * plan_log2((double)n);
   const double lgrowth_a = lgrowth_of(o, n);   // error growth of products of A's planes
   auto t_start = std::chrono::steady_clock::now();
 
@@ -1662,14 +1807,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     int eXmax = -100000;
     for (int j = 0; j < n; ++j) eXmax = std::max(eXmax, eX[j]);
     std::vector<int> dcol(npad, 2), dhost;
-    {
-      const double c0 = eA_max + 7 + std::log2(1.5 * kx) + lgrowth_a;
-      for (int j = 0; j < n; ++j) {
-        if (mxX[j] == 0.0) continue;
-        double need = (c0 + eX[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
-        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
-      }
-    }
+    for (int j = 0; j < n; ++j)
+      if (mxX[j] != 0.0)
+        dcol[j] = cut_v(eA_max, lgrowth_a, kx, eX[j], theta, delta_k, gaps[j], o.d_extra);
     const int dv_allowed = std::min(ka_max + 1, kx + ka_max);
     const int ka = ka_max;
     CutPlan plan;
@@ -1687,9 +1827,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       std::vector<int> kab(nb, 1);
       for (int j = 0; j < n; ++j) {
         if (mxX[j] == 0.0) continue;
-        const double nd =
-            (eA_max + lgrowth_a + eX[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
-        kab[j / 256] = std::max(kab[j / 256], (int)std::ceil(nd) + o.d_extra);
+        kab[j / 256] = std::max(kab[j / 256], cut_ka(eA_max, lgrowth_a, eX[j], theta, delta_k,
+                                                     gaps[j], o.d_extra));
       }
       int ka_top = 1;
       for (int b = 0; b < nb; ++b) ka_top = std::max(ka_top, kab[b] = std::min(kab[b], ka_max));
@@ -1705,7 +1844,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       for (int j = 0; j < n; ++j)
         if (mxX[j] != 0.0) hX = std::max(hX, std::ldexp(std::sqrt(ssX[j]), -eX[j]));
       const double hbits =
-          (hA > 0.0 && hX > 0.0) ? std::log2(hA * hX * (1.0 + 1e-6)) : -1.0;
+          (hA > 0.0 && hX > 0.0) ? plan_log2(hA * hX * (1.0 + 1e-6)) : -1.0;
       ResWeights wA[kVLevels], wX, wXl;   // X's weights: level 0's (the most moduli)
       bool ok = true;
       for (int l = 0; l < kVLevels && ok; ++l)
@@ -1777,15 +1916,10 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     // ---- W = X^(1)T Res -> E~
     column_gaps(lam, gaps, &gmin, &lmax);
     if (!(gmin > 0.0)) return cleanup(REFEIG_E_GAP);
-    {
-      const double c0 = eXmax + 7 + std::log2(1.5 * kx) + lsqn;
-      std::fill(dcol.begin(), dcol.end(), 2);
-      for (int j = 0; j < n; ++j) {
-        if (resmax[j] == 0.0) continue;
-        double need = (c0 + eR[j] - std::log2(theta * delta_k * gaps[j])) / 7.0;
-        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
-      }
-    }
+    std::fill(dcol.begin(), dcol.end(), 2);
+    for (int j = 0; j < n; ++j)
+      if (resmax[j] != 0.0)
+        dcol[j] = cut_w(eXmax, kx, lsqn, eR[j], theta, delta_k, gaps[j], o.d_extra);
     // Noise stability: the W tiles far from column j's eigenvalue, and the product X^(1) E~,
     // leave an error of about nu_j = theta delta t_j along every eigenvector in column j of
     // the new X; the next iteration turns it into about nu_j^2 max|lambda| / g_j (the
@@ -1793,10 +1927,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     // internal delta. t_j = 1 unless g_j is tiny next to max|lambda| and delta is loose.
     bool tight = false;
     for (int j = 0; j < n; ++j) {
-      const double t = std::sqrt(delta_int * gaps[j] / (4.0 * lmax)) / (theta * delta_k);
-      wtolh[j] = std::min(1.0, t);
+      wtolh[j] = w_tight(delta_int, gaps[j], lmax, theta, delta_k);
       wtolh[npad + j] = gaps[j];
-      tight = tight || t < 1.0;
+      tight = tight || wtolh[j] < 1.0;
     }
     const int kR = kKrMax, kxw = kx;
     const int dw_allowed = std::min(kKrMax + 1, kR + kxw);
@@ -1811,7 +1944,7 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     if (npad >= 1024) {
       // on the device (nothing for the host to wait for); the pair count of the report is
       // read back after the iteration
-      const double cx = 7 + std::log2(1.5 * kx) + lsqn - std::log2(theta * delta_k);
+      const double cx = cx_tile(kx, lsqn, theta, delta_k);
       if (tight)
         STEP(hipMemcpyAsync(w.wtol, wtolh.data(), sizeof(double) * 2 * npad,
                             hipMemcpyHostToDevice, s));
@@ -1949,15 +2082,9 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
     double eps = 0.0;
     for (int j = 0; j < n; ++j) eps = std::max(eps, emax[j]);
     // ---- X <- X^(1) + X^(1) E~
-    {
-      const double c0 = 7 + std::log2(1.008 * kx) + lsqn - std::log2(theta * delta_k);
-      std::fill(dcol.begin(), dcol.end(), 2);
-      for (int j = 0; j < n; ++j) {
-        if (emax[j] == 0.0) continue;
-        const double need = (c0 + eE[j] - std::log2(wtolh[j])) / 7.0;
-        dcol[j] = std::max(2, (int)std::ceil(need) + o.d_extra);
-      }
-    }
+    std::fill(dcol.begin(), dcol.end(), 2);
+    for (int j = 0; j < n; ++j)
+      if (emax[j] != 0.0) dcol[j] = cut_u(kx, lsqn, eE[j], theta, delta_k, wtolh[j], o.d_extra);
     const int kE = kKeMax, kxu = kx;
     if (!plan_cutoffs(dcol, n, npad, kE, kxu, std::min(kKeMax + 1, kE + kxu), w.dcut[2], dhost, s,
                       plan))
@@ -2071,6 +2198,27 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
   }
   return cleanup(status);
 #undef STEP
+}
+
+int refeig_read_report(const void *work, int n, const refeig_opts *o_in, int *status,
+                       refeig_report *report) {
+  refeig_opts o;
+  if (o_in) o = *o_in;
+  else refeig_default_opts(&o);
+  if (!work || !status || n < 1 || n > kMaxN) return REFEIG_E_ARG;
+  Work w;
+  carve(n, ka_of(&o), (char *)work, &w, o.vmode == 1);
+  DevState hst;
+  int hflags = 0;
+  HIPCHK(hipMemcpy(&hst, w.dst, sizeof(DevState), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&hflags, w.flags, sizeof(int), hipMemcpyDeviceToHost));
+  *status = status_of(hst, hflags);
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    fill_report_from_device(hst, hflags, hst.iters_done, report);
+    report->status = *status;
+  }
+  return REFEIG_OK;
 }
 
 int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream, int *k) {
