@@ -21,6 +21,8 @@ struct DevIter {
 // The planning state, kept in the workspace across iterations.
 struct DevState {
   int done, stop_status, iters_done;
+  int skip;   // grouped batches: the solve had stopped when this iteration began
+
   int eA_max;
   double hA;
   // the current iteration

@@ -10,6 +10,7 @@
 #include "../../include/refeig.h"
 #include "devplan.h"
 #include "plan.h"
+#include "work.h"
 
 namespace refeig {
 
@@ -55,11 +56,16 @@ __device__ __forceinline__ int pow2_at_least(int n) {
   return p;
 }
 
-// Bitonic sort of N2 (a power of two) entries (key, aux) ascending by (key, aux), in LDS.
+// Bitonic sort of N2 (a power of two, <= kDevSortMax) entries (key, aux) ascending by (key,
+// aux), in LDS. Entry i belongs to thread i mod kPT; the exchanges at distance j < 64 pair
+// lanes of one wavefront and run in registers (shuffles, no barrier), the longer ones in LDS.
 template <typename K>
 __device__ void bitonic(K *key, int *aux, int N2) {
-  for (int k = 2; k <= N2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
+  constexpr int R = kDevSortMax / kPT;
+  const int lane = threadIdx.x & 63;
+  for (int k = 2; k <= N2; k <<= 1) {
+    int j = k >> 1;
+    for (; j >= 64; j >>= 1) {
       __syncthreads();
       for (int i = threadIdx.x; i < N2; i += kPT) {
         const int l = i ^ j;
@@ -77,6 +83,31 @@ __device__ void bitonic(K *key, int *aux, int N2) {
         }
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * kPT;
+      if (r * kPT >= N2) break;   // uniform over the block
+      K a = i < N2 ? key[i] : K(0);
+      int ia = i < N2 ? aux[i] : 0;
+      const bool up = (i & k) == 0;
+      for (int jj = j; jj > 0; jj >>= 1) {
+        const K b = __shfl_xor(a, jj);
+        const int ib = __shfl_xor(ia, jj);
+        const bool low = (lane & jj) == 0;   // this entry is the pair's lower index
+        // the pair (lower, upper) is out of order when lower > upper
+        const bool gt = low ? ((a > b) || (a == b && ia > ib)) : ((b > a) || (b == a && ib > ia));
+        if (gt == up) {
+          a = b;
+          ia = ib;
+        }
+      }
+      if (i < N2) {
+        key[i] = a;
+        aux[i] = ia;
+      }
+    }
+  }
   __syncthreads();
 }
 
@@ -177,7 +208,7 @@ __device__ int tile_cutoffs_from_columns(int *dtile, const int *dcol_lds, int n,
 }  // namespace
 
 // ---------------------------------------------------------------- once per solve
-__global__ __launch_bounds__(kPT) void k_dp_init(PlanParams p, PlanBufs b) {
+__device__ __forceinline__ void dp_init_body(PlanParams p, PlanBufs b) {
   __shared__ double red[16];
   __shared__ int ired[16];
   int em = -100000;
@@ -194,6 +225,7 @@ __global__ __launch_bounds__(kPT) void k_dp_init(PlanParams p, PlanBufs b) {
     st.eA_max = em;
     st.hA = h;
     st.done = 0;
+    st.skip = 0;
     st.stop_status = 0;
     st.iters_done = 0;
     st.eps_prev = INFINITY;
@@ -204,10 +236,14 @@ __global__ __launch_bounds__(kPT) void k_dp_init(PlanParams p, PlanBufs b) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_dp_init(PlanParams p, PlanBufs b) {
+  dp_init_body(p, b);
+}
+
 // ---------------------------------------------------------------- working column order
 // From the entry estimates D (natural order): gaps, the smallest gap and max |lambda|, and the
 // working order (gap descending, ties by eigenvalue ascending): colmap, gapsw.
-__global__ __launch_bounds__(kPT) void k_dp_order(PlanParams p, PlanBufs b) {
+__device__ __forceinline__ void dp_order_body(PlanParams p, PlanBufs b) {
   __shared__ double key[kDevSortMax];    // eigenvalues, then the gap keys (as 64-bit ints)
   __shared__ int idx[kDevSortMax];       // sorted position -> column
   __shared__ int rk[kDevSortMax];        // second sort: rank in eigenvalue order
@@ -277,8 +313,12 @@ __global__ __launch_bounds__(kPT) void k_dp_order(PlanParams p, PlanBufs b) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_dp_order(PlanParams p, PlanBufs b) {
+  dp_order_body(p, b);
+}
+
 // ---------------------------------------------------------------- beta, kx and the V plan
-__global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
+__device__ __forceinline__ void dp_vplan_body(PlanParams p, PlanBufs b) {
   __shared__ int hist[kBetaBins];
   __shared__ int dcol[kDevSortMax];
   __shared__ int dtile[64];
@@ -361,7 +401,17 @@ __global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
     }
     __syncthreads();
     if (s_ok && threadIdx.x < kVLevels && st.ka_l[threadIdx.x] > 0)
-      crt_rec_build(st.N_l[threadIdx.x], st.ka_l[threadIdx.x], kx, st.recs[threadIdx.x]);
+      crt_rec_head(st.N_l[threadIdx.x], st.ka_l[threadIdx.x], kx, st.recs[threadIdx.x]);
+    __syncthreads();
+    if (s_ok) {   // the per-modulus and per-pair fields, one thread each
+      constexpr int kPer = kCrtMax + kCrtMax / 2 + 1;
+      for (int i = threadIdx.x; i < kVLevels * kPer; i += kPT) {
+        const int l = i / kPer, r = i - l * kPer;
+        if (st.ka_l[l] <= 0) continue;
+        if (r < kCrtMax) crt_rec_modulus(r, st.recs[l]);
+        else crt_rec_pair(r - kCrtMax, st.recs[l]);
+      }
+    }
     __syncthreads();
     if (s_ok) {   // reconstruction floor against each column's share of delta
       int fail = 0;
@@ -377,17 +427,33 @@ __global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
   }
   const int vres = s_ok;
   if (vres) {
-    if (threadIdx.x == 0) res_weights_build(kx, st.N_l[0], st.wX);
-    if (threadIdx.x >= 1 && threadIdx.x <= kVLevels) {
-      const int l = threadIdx.x - 1;
+    // weights of X^(1)'s digits and of A's at each level whose digit or modulus count changed,
+    // one thread per modulus slot
+    __shared__ int s_dirty[kVLevels];
+    if (threadIdx.x < kVLevels) {
+      const int l = threadIdx.x;
       const int ka = st.ka_l[l], N = st.N_l[l];
-      const bool dirty = ka > 0 && (ka != st.ares_ka[l] || N != st.ares_n[l]);
-      if (dirty) {
-        res_weights_build(ka, N, st.wA[l]);
-        st.ares_ka[l] = ka;
-        st.ares_n[l] = N;
+      s_dirty[l] = ka > 0 && (ka != st.ares_ka[l] || N != st.ares_n[l]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (kVLevels + 1) * kCrtMax; i += kPT) {
+      const int l = i / kCrtMax - 1, q = i - (l + 1) * kCrtMax;
+      if (l < 0) res_weights_row(kx, st.N_l[0], q, st.wX);
+      else if (s_dirty[l]) res_weights_row(st.ka_l[l], st.N_l[l], q, st.wA[l]);
+    }
+    if (threadIdx.x == 0) {
+      st.wX.N = st.N_l[0];
+      st.wX.k = kx;
+    }
+    if (threadIdx.x < kVLevels) {
+      const int l = threadIdx.x;
+      if (s_dirty[l]) {
+        st.wA[l].N = st.N_l[l];
+        st.wA[l].k = st.ka_l[l];
+        st.ares_ka[l] = st.ka_l[l];
+        st.ares_n[l] = st.N_l[l];
       }
-      st.ares_dirty[l] = dirty ? 1 : 0;
+      st.ares_dirty[l] = s_dirty[l];
     }
     for (int q = threadIdx.x; q < nb; q += kPT) {
       b.vblk[2 * q] = st.N_l[lvb[q]];
@@ -438,8 +504,12 @@ __global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_dp_vplan(PlanParams p, PlanBufs b) {
+  dp_vplan_body(p, b);
+}
+
 // ---------------------------------------------------------------- the W plan
-__global__ __launch_bounds__(kPT) void k_dp_wplan(PlanParams p, PlanBufs b) {
+__device__ __forceinline__ void dp_wplan_body(PlanParams p, PlanBufs b) {
   __shared__ double key[kDevSortMax];
   __shared__ int idx[kDevSortMax];
   __shared__ int dcol[kDevSortMax];
@@ -506,8 +576,12 @@ __global__ __launch_bounds__(kPT) void k_dp_wplan(PlanParams p, PlanBufs b) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_dp_wplan(PlanParams p, PlanBufs b) {
+  dp_wplan_body(p, b);
+}
+
 // ---------------------------------------------------------------- the X^(1) E~ plan, stop test
-__global__ __launch_bounds__(kPT) void k_dp_uplan(PlanParams p, PlanBufs b) {
+__device__ __forceinline__ void dp_uplan_body(PlanParams p, PlanBufs b) {
   __shared__ int dcol[kDevSortMax];
   __shared__ int dtile[64];
   __shared__ double red[16];
@@ -588,12 +662,16 @@ __global__ __launch_bounds__(kPT) void k_dp_uplan(PlanParams p, PlanBufs b) {
   }
 }
 
+__global__ __launch_bounds__(kPT) void k_dp_uplan(PlanParams p, PlanBufs b) {
+  dp_uplan_body(p, b);
+}
+
 // ---------------------------------------------------------------- residue planes
-__global__ __launch_bounds__(256) void k_residues_dev(const int8_t *__restrict__ planes,
-                                                      size_t pstride, size_t count,
-                                                      const ResWeights *__restrict__ w,
-                                                      int8_t *__restrict__ res,
-                                                      const int *__restrict__ gate) {
+__device__ __forceinline__ void residues_dev_body(const int8_t *__restrict__ planes,
+                                                  size_t pstride, size_t count,
+                                                  const ResWeights *__restrict__ w,
+                                                  int8_t *__restrict__ res,
+                                                  const int *__restrict__ gate, int bid, int nblk) {
   if (gate && *gate == 0) return;
   constexpr int G = (kCrtPlanes + 3) / 4;
   __shared__ int swp[kCrtMax][G];
@@ -605,8 +683,8 @@ __global__ __launch_bounds__(256) void k_residues_dev(const int8_t *__restrict__
     srm[q] = w->rmf[q];
   }
   __syncthreads();
-  for (size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4; e < count;
-       e += (size_t)gridDim.x * 256 * 4) {
+  for (size_t e = ((size_t)bid * 256 + threadIdx.x) * 4; e < count;
+       e += (size_t)nblk * 256 * 4) {
     unsigned v[4 * G];
 #pragma unroll
     for (int t = 0; t < 4 * G; ++t)
@@ -637,9 +715,134 @@ __global__ __launch_bounds__(256) void k_residues_dev(const int8_t *__restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_residues_dev(const int8_t *__restrict__ planes,
+                                                      size_t pstride, size_t count,
+                                                      const ResWeights *__restrict__ w,
+                                                      int8_t *__restrict__ res,
+                                                      const int *__restrict__ gate) {
+  residues_dev_body(planes, pstride, count, w, res, gate, blockIdx.x, gridDim.x);
+}
+
 __global__ void k_fill_int(int *p, int n, int v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- grouped batches
+// The planning kernels over problems gp[first .. first + gridDim.x), one block each, the
+// iteration as an argument. Iteration it of a problem whose stop test has ended its solve is
+// skipped (DevState::skip, set by the order kernel; with fixed iterations every one runs, as
+// in a single call).
+__global__ __launch_bounds__(kPT) void k_dp_init_g(const GProb *__restrict__ gp, int first) {
+  const GProb &q = gp[first + blockIdx.x];
+  dp_init_body(q.pp, q.pb);
+}
+__device__ __forceinline__ PlanParams params_at(const GProb &q, int it) {
+  PlanParams p = q.pp;
+  p.it = it;
+  return p;
+}
+__global__ __launch_bounds__(kPT) void k_dp_order_g(const GProb *__restrict__ gp, int first,
+                                                    int it) {
+  const GProb &q = gp[first + blockIdx.x];
+  DevState &st = *q.pb.st;
+  const int stop = !q.pp.fixed && st.done;
+  if (threadIdx.x == 0) st.skip = stop;
+  if (stop) return;
+  dp_order_body(params_at(q, it), q.pb);
+}
+__global__ __launch_bounds__(kPT) void k_dp_vplan_g(const GProb *__restrict__ gp, int first,
+                                                    int it) {
+  const GProb &q = gp[first + blockIdx.x];
+  if (q.pb.st->skip) return;
+  dp_vplan_body(params_at(q, it), q.pb);
+}
+__global__ __launch_bounds__(kPT) void k_dp_wplan_g(const GProb *__restrict__ gp, int first,
+                                                    int it) {
+  const GProb &q = gp[first + blockIdx.x];
+  if (q.pb.st->skip) return;
+  dp_wplan_body(params_at(q, it), q.pb);
+}
+__global__ __launch_bounds__(kPT) void k_dp_uplan_g(const GProb *__restrict__ gp, int first,
+                                                    int it) {
+  const GProb &q = gp[first + blockIdx.x];
+  if (q.pb.st->skip) return;
+  dp_uplan_body(params_at(q, it), q.pb);
+}
+
+// Residue planes: which < kVLevels, A's digits at that level; which == kVLevels, X^(1)'s.
+__global__ __launch_bounds__(256) void k_residues_g(const GProb *__restrict__ gp, int first,
+                                                    int bpp, int which) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  DevState *st = q.pb.st;
+  if (st->skip) return;
+  const int lb = blockIdx.x % bpp;
+  if (which < kVLevels)
+    residues_dev_body(q.w.AP, q.P, q.P, &st->wA[which], q.w.ARES + (size_t)which * kCrtMax * q.P,
+                      &st->ares_dirty[which], lb, bpp);
+  else
+    residues_dev_body(q.w.XP, q.P, q.P, &st->wX, q.w.XRES, &st->vres, lb, bpp);
+}
+
+__global__ void k_flags_clear_g(const GProb *__restrict__ gp, int count) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g < count) gp[g].w.flags[0] = 0;
+}
+
+// Problems whose solve still runs (not done), into *out.
+__global__ __launch_bounds__(256) void k_count_running_g(const GProb *__restrict__ gp, int count,
+                                                         int *__restrict__ out) {
+  __shared__ int ws[4];
+  int c = 0;
+  for (int g = threadIdx.x; g < count; g += 256) c += gp[g].pb.st->done ? 0 : 1;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Each problem's planning state and error flags, gathered for one copy to the host: problem
+// g at out + g stride (the DevState, then the flags word).
+__global__ __launch_bounds__(256) void k_gather_state_g(const GProb *__restrict__ gp,
+                                                        char *__restrict__ out, size_t stride) {
+  const GProb &q = gp[blockIdx.x];
+  const int *src = (const int *)q.pb.st;
+  int *dst = (int *)(out + (size_t)blockIdx.x * stride);
+  constexpr int W = (int)(sizeof(DevState) / sizeof(int));
+  for (int i = threadIdx.x; i < W; i += 256) dst[i] = src[i];
+  if (threadIdx.x == 0) dst[W] = q.w.flags[0];
+}
+
+void launch_dp_init_g(const GProb *gp, int first, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_init_g, dim3(count), dim3(kPT), 0, s, gp, first);
+}
+void launch_dp_order_g(const GProb *gp, int first, int count, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_order_g, dim3(count), dim3(kPT), 0, s, gp, first, it);
+}
+void launch_dp_vplan_g(const GProb *gp, int first, int count, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_vplan_g, dim3(count), dim3(kPT), 0, s, gp, first, it);
+}
+void launch_dp_wplan_g(const GProb *gp, int first, int count, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_wplan_g, dim3(count), dim3(kPT), 0, s, gp, first, it);
+}
+void launch_dp_uplan_g(const GProb *gp, int first, int count, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_uplan_g, dim3(count), dim3(kPT), 0, s, gp, first, it);
+}
+void launch_residues_g(const GProb *gp, int first, int count, size_t P, int which,
+                       hipStream_t s) {
+  size_t bpp = (P / 4 + 255) / 256;
+  if (bpp > 1024) bpp = 1024;
+  hipLaunchKernelGGL(k_residues_g, dim3((unsigned)(count * bpp)), dim3(256), 0, s, gp, first,
+                     (int)bpp, which);
+}
+void launch_flags_clear_g(const GProb *gp, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_flags_clear_g, dim3((count + 255) / 256), dim3(256), 0, s, gp, count);
+}
+void launch_count_running_g(const GProb *gp, int count, int *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_running_g, dim3(1), dim3(256), 0, s, gp, count, out);
+}
+void launch_gather_state_g(const GProb *gp, int count, char *out, size_t stride, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_state_g, dim3(count), dim3(256), 0, s, gp, out, stride);
 }
 
 void launch_dp_init(const PlanParams &p, const PlanBufs &b, hipStream_t s) {
@@ -661,7 +864,7 @@ void launch_residues_dev(const int8_t *planes, size_t pstride, size_t count, con
                          int8_t *res, const int *gate, hipStream_t s) {
   const size_t quads = count / 4;
   size_t blocks = (quads + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 1024) blocks = 1024;
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_residues_dev, dim3((unsigned)blocks), dim3(256), 0, s, planes, pstride,
                      count, w, res, gate);

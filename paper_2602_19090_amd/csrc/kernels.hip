@@ -15,6 +15,7 @@
 // -ffp-contract=off: the error-free transformations (TwoSum, the exact product
 // via fma) must not be contracted or reassociated.
 #include "kernels.h"
+#include "work.h"
 #include <hip/hip_ext.h>
 
 #include <float.h>
@@ -171,12 +172,12 @@ __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
 }
 
 // ---------------------------------------------------------------- column statistics
-__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, int ld, int rows,
+__device__ __forceinline__ void colstats_body(const double *__restrict__ M, int ld, int rows,
                                                   int cols, int *e, int *c, double *mx,
                                                   int *flags, const int *__restrict__ colmap,
-                                                  double *ss) {
+                                                  double *ss, int bx) {
   __shared__ double scratch[4];
-  const int j = blockIdx.x;
+  const int j = bx;
   if (j >= cols) {
     if (threadIdx.x == 0) {
       e[j] = 0;
@@ -214,6 +215,13 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, 
     if (mx) mx[j] = m;
     if (m != 0.0 && (ee < -400 || ee > 400)) atomicOr(flags, FLAG_RANGE);
   }
+}
+
+__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ M, int ld, int rows,
+                                                  int cols, int *e, int *c, double *mx,
+                                                  int *flags, const int *__restrict__ colmap,
+                                                  double *ss) {
+  colstats_body(M, ld, rows, cols, e, c, mx, flags, colmap, ss, blockIdx.x);
 }
 
 // Nonzeros of column j of the symmetric A (= row j), block per column; the maximum goes
@@ -257,21 +265,21 @@ constexpr int kTStride = 80;   // LDS row stride of the complex splitter's trans
 // 64 x 64 tile is contiguous), 16 bytes per thread. Reads and the X^(1) writes take 32
 // contiguous bytes per thread and column.
 template <bool WITH_T>
-__global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M, int ld, int rows,
+__device__ __forceinline__ void split_cols_body(const double *__restrict__ M, int ld, int rows,
                                                     int cols, const int *__restrict__ e, int k,
                                                     int8_t *__restrict__ planes, size_t pstride,
                                                     int rpad, int cpad, double *__restrict__ trunc,
                                                     int ldt, int8_t *__restrict__ planesT,
                                                     size_t pstrideT, int kT,
                                                     const int *__restrict__ colmap,
-                                                    const int *__restrict__ kdev) {
+                                                    const int *__restrict__ kdev, int bx, int by) {
   __shared__ __attribute__((aligned(16))) int8_t sC[64 * kSplitRow];
   if (kdev) {
     k = *kdev;
     kT = WITH_T ? k : 0;
   }
   __shared__ __attribute__((aligned(16))) int8_t sR[WITH_T ? 64 * kSplitRow : 16];
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int i0 = bx * 64, j0 = by * 64;
   const int tid = threadIdx.x, ig = tid & 15, jg = tid >> 4;
   const int kk = (WITH_T && kT > k) ? kT : k;
   const int ib = i0 + 4 * ig;
@@ -355,6 +363,18 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M
   }
 }
 
+template <bool WITH_T>
+__global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ M, int ld, int rows,
+                                                    int cols, const int *__restrict__ e, int k,
+                                                    int8_t *__restrict__ planes, size_t pstride,
+                                                    int rpad, int cpad, double *__restrict__ trunc,
+                                                    int ldt, int8_t *__restrict__ planesT,
+                                                    size_t pstrideT, int kT,
+                                                    const int *__restrict__ colmap,
+                                                    const int *__restrict__ kdev) {
+  split_cols_body<WITH_T>(M, ld, rows, cols, e, k, planes, pstride, rpad, cpad, trunc, ldt, planesT, pstrideT, kT, colmap, kdev, blockIdx.x, blockIdx.y);
+}
+
 void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e, int k,
                        int8_t *planes, size_t pstride, int rpad, int cpad, double *trunc, int ldt,
                        int8_t *planesT, size_t pstrideT, int kT, hipStream_t s,
@@ -377,34 +397,17 @@ void launch_split_cols(const double *M, int ld, int rows, int cols, const int *e
 // registers while the current one feeds the matrix cores.
 constexpr int GBM = 128, GBN = 128, GBK = 128, GLDS = GBK + 16;
 
-__global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict__ Lp,
-                                                       const int8_t *__restrict__ Rp,
-                                                       size_t pstride, int npad, int kdim,
-                                                       int kl, int kr, int d_min, DiagOrder order,
-                                                       int32_t *__restrict__ C, RowBlocks rb,
-                                                       int same, const int *__restrict__ mods,
-                                                       const int *__restrict__ tab,
-                                                       const int *__restrict__ dp,
-                                                       const int *__restrict__ vblk) {
+// One 128 x 128 output tile (rows m0.., columns n0..) of slot `slot` (body of k_slice_gemm
+// and of the grouped persistent form).
+__device__ __forceinline__ void gemm128_item(const int8_t *__restrict__ Lp,
+                                             const int8_t *__restrict__ Rp, size_t pstride,
+                                             int npad, int kdim, int kl, int kr, int d_min,
+                                             int32_t *__restrict__ C, int same,
+                                             const int *__restrict__ mods,
+                                             const int *__restrict__ vblk, int m0, int n0,
+                                             int slot) {
   __shared__ __attribute__((aligned(16))) int8_t sL[GBM * GLDS];
   __shared__ __attribute__((aligned(16))) int8_t sR[GBN * GLDS];
-  int m0, n0, slot;
-  if (tab) {   // block table: row tile | column tile << 8 | slot << 16 (128 x 128 tiles)
-    if (dp) {
-      if ((int)blockIdx.x >= dp[2]) return;
-      kl = dp[0];
-      kr = dp[1];
-    }
-    const int ent = tab[blockIdx.x];
-    m0 = (ent & 0xff) * GBM;
-    n0 = ((ent >> 8) & 0xff) * GBN;
-    slot = ent >> 16;
-  } else {
-    const int tiles_n = npad / GBN;
-    m0 = rb.m[blockIdx.x / tiles_n] * GBM;
-    n0 = (blockIdx.x % tiles_n) * GBN;
-    slot = order.q[blockIdx.y];
-  }
   // vblk (same-plane products, per 256-row block of L: slot count, level)
   int roff = 0;
   if (vblk) {
@@ -499,6 +502,35 @@ __global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict_
       }
 }
 
+__global__ __launch_bounds__(256, 2) void k_slice_gemm(const int8_t *__restrict__ Lp,
+                                                       const int8_t *__restrict__ Rp,
+                                                       size_t pstride, int npad, int kdim,
+                                                       int kl, int kr, int d_min, DiagOrder order,
+                                                       int32_t *__restrict__ C, RowBlocks rb,
+                                                       int same, const int *__restrict__ mods,
+                                                       const int *__restrict__ tab,
+                                                       const int *__restrict__ dp,
+                                                       const int *__restrict__ vblk) {
+  int m0, n0, slot;
+  if (tab) {   // block table: row tile | column tile << 8 | slot << 16 (128 x 128 tiles)
+    if (dp) {
+      if ((int)blockIdx.x >= dp[2]) return;
+      kl = dp[0];
+      kr = dp[1];
+    }
+    const int ent = tab[blockIdx.x];
+    m0 = (ent & 0xff) * GBM;
+    n0 = ((ent >> 8) & 0xff) * GBN;
+    slot = ent >> 16;
+  } else {
+    const int tiles_n = npad / GBN;
+    m0 = rb.m[blockIdx.x / tiles_n] * GBM;
+    n0 = (blockIdx.x % tiles_n) * GBN;
+    slot = order.q[blockIdx.y];
+  }
+  gemm128_item(Lp, Rp, pstride, npad, kdim, kl, kr, d_min, C, same, mods, vblk, m0, n0, slot);
+}
+
 constexpr int HBM_ = 256, HGM = 4;
 
 // Block -> (row-block index, column offset) for the 256 x 256 kernel over a
@@ -560,37 +592,19 @@ __device__ __forceinline__ void wait_vm_lds_barrier() {
 // the INT8 form feeds to two v_mfma_i32_32x32x32_i8 (both operands see the same lane and byte
 // order of k, so the sum over k is unchanged). The FP32 sums are integers below 2^24 (exact)
 // and are stored as INT32 like the INT8 form's.
+// One 256 x 256 output tile (rows m0.., columns n0..) of slot `slot` (body of k_slice_gemm256d
+// and of the grouped persistent form).
 template <bool F8>
-__global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restrict__ Lp,
-                                                           const int8_t *__restrict__ Rp,
-                                                           size_t pstride, int npad, int kdim,
-                                                           int kl, int kr, int d_min,
-                                                           DiagOrder order,
-                                                           int32_t *__restrict__ C, RowBlocks rb,
-                                                           int same, const int *__restrict__ tcut,
-                                                           const int *__restrict__ tab,
-                                                           const int *__restrict__ mods,
-                                                           const int *__restrict__ vblk,
-                                                           const int *__restrict__ dp) {
+__device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
+                                             const int8_t *__restrict__ Rp, size_t pstride,
+                                             int npad, int kdim, int kl, int kr, int d_min,
+                                             int32_t *__restrict__ C, int same,
+                                             const int *__restrict__ tcut,
+                                             const int *__restrict__ mods,
+                                             const int *__restrict__ vblk, int m0, int n0,
+                                             int slot) {
   constexpr int S = DSTAGES;
   __shared__ __attribute__((aligned(1024))) int8_t ring[S * DSTAGE_BYTES];
-  int m0, n0, slot;
-  if (dp) {   // device-planned table launch: sized for the largest table
-    if ((int)blockIdx.x >= dp[2]) return;
-    kl = dp[0];
-    kr = dp[1];
-  }
-  if (tab) {   // block table: row block | column block << 8 | slot << 16
-    const int ent = tab[blockIdx.x];
-    m0 = (ent & 0xff) * HBM_;
-    n0 = ((ent >> 8) & 0xff) * HBM_;
-    slot = ent >> 16;
-  } else {
-    int mi;
-    tile_of_block(blockIdx.x, rb.count, npad / HBM_, mi, n0);
-    m0 = rb.m[mi] * HBM_;
-    slot = order.q[blockIdx.y];
-  }
   const int d = d_min + slot;
   // per-tile diagonal limit (tile = output column block m0 / 256, output row block n0 / 256):
   // the block's diagonal is not needed there, and nothing reads its slot
@@ -779,6 +793,39 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restr
         const int col = n0 + wn * 128 + y * 32 + (lane & 31);
         Cq[(size_t)row * npad + col] = (int32_t)acc[x][y][v];
       }
+}
+
+template <bool F8>
+__global__ __launch_bounds__(256, 1) void k_slice_gemm256d(const int8_t *__restrict__ Lp,
+                                                           const int8_t *__restrict__ Rp,
+                                                           size_t pstride, int npad, int kdim,
+                                                           int kl, int kr, int d_min,
+                                                           DiagOrder order,
+                                                           int32_t *__restrict__ C, RowBlocks rb,
+                                                           int same, const int *__restrict__ tcut,
+                                                           const int *__restrict__ tab,
+                                                           const int *__restrict__ mods,
+                                                           const int *__restrict__ vblk,
+                                                           const int *__restrict__ dp) {
+  int m0, n0, slot;
+  if (dp) {   // device-planned table launch: sized for the largest table
+    if ((int)blockIdx.x >= dp[2]) return;
+    kl = dp[0];
+    kr = dp[1];
+  }
+  if (tab) {   // block table: row block | column block << 8 | slot << 16
+    const int ent = tab[blockIdx.x];
+    m0 = (ent & 0xff) * HBM_;
+    n0 = ((ent >> 8) & 0xff) * HBM_;
+    slot = ent >> 16;
+  } else {
+    int mi;
+    tile_of_block(blockIdx.x, rb.count, npad / HBM_, mi, n0);
+    m0 = rb.m[mi] * HBM_;
+    slot = order.q[blockIdx.y];
+  }
+  gemm256_item<F8>(Lp, Rp, pstride, npad, kdim, kl, kr, d_min, C, same, tcut, mods, vblk, m0, n0,
+                   slot);
 }
 
 void launch_slice_gemm(const int8_t *Lp, const int8_t *Rp, size_t pstride, int npad, int kl,
@@ -1002,15 +1049,15 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
 }
 
 template <int EPT, bool CRT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_v(
+__device__ __forceinline__ void epi_v_body(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
     int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
-    const int *__restrict__ gate) {
+    const int *__restrict__ gate, int bx) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
   if (gate && *gate == 0) return;
-  const int j = blockIdx.x, tid = threadIdx.x;
+  const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
@@ -1133,6 +1180,16 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v(
   }
 }
 
+template <int EPT, bool CRT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_v(
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
+    double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
+    int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
+    const int *__restrict__ gate) {
+  epi_v_body<EPT, CRT>(C, npad, d_min, ndiag_all, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, recs, vblk, gate, blockIdx.x);
+}
+
 template <int EPT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
@@ -1250,7 +1307,7 @@ __device__ __forceinline__ int w_ndiag(const int *__restrict__ dcut, const int *
 // With tcol and gcol (per column, optional), g is replaced by max(gcol_j, tcol_j g): a column
 // whose own gap gcol_j is small takes its far tiles tcol_j <= 1 times tighter, never tighter
 // than its own gap (the column-wide rule).
-__global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__ lam,
+__device__ __forceinline__ void tile_cutoffs_body(const double *__restrict__ lam,
                                                       const int *__restrict__ eX,
                                                       const int *__restrict__ eR,
                                                       const double *__restrict__ resmax, int n,
@@ -1259,13 +1316,13 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
                                                       const double *__restrict__ gcol,
                                                       int *__restrict__ tcut,
                                                       const double *__restrict__ cxp,
-                                                      const int *__restrict__ dmaxp) {
+                                                      const int *__restrict__ dmaxp, int bx) {
   __shared__ double v[256];
   if (cxp) cx = *cxp;
   if (dmaxp) dmax = *dmaxp;
   __shared__ int tm[kMaxTileSide];
   __shared__ int exb;
-  const int I = blockIdx.x, tid = threadIdx.x;
+  const int I = bx, tid = threadIdx.x;
   const int i0 = I * 256, cnt = min(256, n - i0);
   v[tid] = (tid < cnt) ? lam[i0 + tid] : INFINITY;
   if (tid < T) tm[tid] = INT_MIN;
@@ -1319,6 +1376,19 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_tile_cutoffs(const double *__restrict__ lam,
+                                                      const int *__restrict__ eX,
+                                                      const int *__restrict__ eR,
+                                                      const double *__restrict__ resmax, int n,
+                                                      int T, double cx, int dmax, int dextra,
+                                                      const double *__restrict__ tcol,
+                                                      const double *__restrict__ gcol,
+                                                      int *__restrict__ tcut,
+                                                      const double *__restrict__ cxp,
+                                                      const int *__restrict__ dmaxp) {
+  tile_cutoffs_body(lam, eX, eR, resmax, n, T, cx, dmax, dextra, tcol, gcol, tcut, cxp, dmaxp, blockIdx.x);
+}
+
 void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const double *resmax,
                          int n, int T, double cx, int dmax, int dextra, const double *tcol,
                          const double *gcol, int *tcut, hipStream_t s, const double *cxp,
@@ -1329,14 +1399,14 @@ void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const 
 
 // ---------------------------------------------------------------- W epilogue -> E~
 template <int EPT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_w(
+__device__ __forceinline__ void epi_w_body(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
     double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
-    int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut) {
+    int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut, int bx) {
   __shared__ double scratch[2 * (kEpiThreads / 64)];
-  const int j = blockIdx.x, tid = threadIdx.x;
+  const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
@@ -1426,6 +1496,16 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_w(
     emax[j] = mr;
     if (!(mr <= DBL_MAX)) atomicOr(flags, FLAG_NONFINITE);
   }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_w(
+    const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
+    const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
+    const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
+    double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
+    int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut) {
+  epi_w_body<EPT>(C, npad, d_min, ndiag_all, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, blockIdx.x);
 }
 
 template <int EPT>
@@ -1595,14 +1675,14 @@ void launch_group_fix(const int32_t *C, int npad, int d_min, int ndiag, const in
 }
 
 // ---------------------------------------------------------------- update X <- X1 + X1 E~
-__global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, int npad, int d_min,
+__device__ __forceinline__ void epi_u_body(const int32_t *__restrict__ C, int npad, int d_min,
                                                int ndiag_all, const int *__restrict__ dcut,
                                                const int *__restrict__ eE,
                                                const double *__restrict__ X1, int n,
                                                double *__restrict__ X, int ldx,
                                                const int *__restrict__ colmap,
-                                               const int *__restrict__ errflags) {
-  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+                                               const int *__restrict__ errflags, int bx, int by) {
+  const int i = bx * 256 + threadIdx.x, j = by;
   if (i >= n) return;
   if (errflags && (*errflags & kFlagsError)) return;
   const size_t P = (size_t)npad * npad;
@@ -1615,6 +1695,16 @@ __global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, in
   X[(size_t)(colmap ? colmap[j] : j) * ldx + i] = X1[(size_t)j * n + i] + u;
 }
 
+__global__ __launch_bounds__(256) void k_epi_u(const int32_t *__restrict__ C, int npad, int d_min,
+                                               int ndiag_all, const int *__restrict__ dcut,
+                                               const int *__restrict__ eE,
+                                               const double *__restrict__ X1, int n,
+                                               double *__restrict__ X, int ldx,
+                                               const int *__restrict__ colmap,
+                                               const int *__restrict__ errflags) {
+  epi_u_body(C, npad, d_min, ndiag_all, dcut, eE, X1, n, X, ldx, colmap, errflags, blockIdx.x, blockIdx.y);
+}
+
 void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                   const int *eE, const double *X1, int n, double *X, int ldx, hipStream_t s,
                   const int *colmap, const int *errflags) {
@@ -1622,11 +1712,16 @@ void launch_epi_u(const int32_t *C, int npad, int d_min, int ndiag, const int *d
                      eE, X1, n, X, ldx, colmap, errflags);
 }
 
+__device__ __forceinline__ void scatter_body(const double *__restrict__ v, const int *__restrict__ colmap, int n,
+                          double *__restrict__ out, const int *__restrict__ errflags, int bx) {
+  if (errflags && (*errflags & kFlagsError)) return;
+  const int p = bx * 256 + threadIdx.x;
+  if (p < n) out[colmap ? colmap[p] : p] = v[p];
+}
+
 __global__ void k_scatter(const double *__restrict__ v, const int *__restrict__ colmap, int n,
                           double *__restrict__ out, const int *__restrict__ errflags) {
-  if (errflags && (*errflags & kFlagsError)) return;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p < n) out[colmap ? colmap[p] : p] = v[p];
+  scatter_body(v, colmap, n, out, errflags, blockIdx.x);
 }
 
 void launch_scatter(const double *v, const int *colmap, int n, double *out, hipStream_t s,
@@ -2098,6 +2193,292 @@ void launch_epi_u_c(const int32_t *Cr, const int32_t *Ci, int npad, int d_min, i
                     hipStream_t s, const int *colmap) {
   hipLaunchKernelGGL(k_epi_u_c, dim3((n + 255) / 256, n), dim3(256), 0, s, Cr, Ci, npad, d_min,
                      ndiag, dcut, eE, X1, n, X, ldx, colmap);
+}
+
+// ================================================================ grouped batches
+// A batch of independent solves runs as one launch per step and size class (problems of equal
+// npad, consecutive in gp): block b of such a launch serves problem first + b / bpp with the
+// local block index b % bpp, as the single-problem launch would. The products run as
+// persistent kernels over a work list of (problem, tile, slot) items built on the device from
+// each problem's plan. A problem whose solve has stopped (DevState::skip) does nothing.
+
+__global__ __launch_bounds__(256) void k_colstats_g(const GProb *__restrict__ gp, int first,
+                                                    int bpp, int of_x) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  const int j = blockIdx.x % bpp;
+  if (!of_x) {
+    colstats_body(q.A, q.lda, q.n, q.n, q.w.eA, q.w.cA, q.w.mxA, q.w.flags, nullptr, q.w.ssA, j);
+  } else {
+    if (q.pb.st->skip) return;
+    colstats_body(q.X, q.ldx, q.n, q.n, q.w.eX, q.w.cX, q.w.mxX, q.w.flags, q.w.colmap, q.w.ssX,
+                  j);
+  }
+}
+
+// WITH_T false: the planes of A (once per solve); true: X^(1), its planes in both layouts.
+template <bool WITH_T>
+__global__ __launch_bounds__(256) void k_split_g(const GProb *__restrict__ gp, int first, int gx) {
+  const int bpp = gx * gx;
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  const int lb = blockIdx.x % bpp, bx = lb % gx, by = lb / gx;
+  if constexpr (!WITH_T) {
+    split_cols_body<false>(q.A, q.lda, q.n, q.n, q.w.eA, q.ka, q.w.AP, q.P, q.npad, q.npad,
+                           nullptr, 0, nullptr, 0, 0, nullptr, nullptr, bx, by);
+  } else {
+    if (q.pb.st->skip) return;
+    split_cols_body<true>(q.X, q.ldx, q.n, q.n, q.w.eX, kKxMax, q.w.XP, q.P, q.npad, q.npad,
+                          q.w.X1, q.n, q.w.XPT, q.P, kKxMax, q.w.colmap, &q.pb.st->kx, bx, by);
+  }
+}
+
+template <int EPT, bool CRT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_v_g(const GProb *__restrict__ gp, int first,
+                                                         int bpp) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  const int j = blockIdx.x % bpp;
+  DevState *st = q.pb.st;
+  if (st->skip) return;
+  if constexpr (CRT)
+    epi_v_body<EPT, true>(q.w.Cs, q.npad, 2, 1, nullptr, q.w.eA, q.w.eX, q.w.X1, q.n, q.w.lam,
+                          q.w.lam_lo, q.w.r, q.w.eR, q.w.resmax, q.w.RP, kKrMax, q.w.flags,
+                          st->recs, q.w.vblk, &st->vres, j);
+  else
+    epi_v_body<EPT, false>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[0], q.w.eA, q.w.eX, q.w.X1,
+                           q.n, q.w.lam, q.w.lam_lo, q.w.r, q.w.eR, q.w.resmax, q.w.RP, kKrMax,
+                           q.w.flags, nullptr, nullptr, &st->vslice, j);
+}
+
+__global__ __launch_bounds__(256) void k_tile_cutoffs_g(const GProb *__restrict__ gp, int first,
+                                                        int bpp) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  DevState *st = q.pb.st;
+  if (st->skip) return;
+  tile_cutoffs_body(q.w.lam, q.w.eX, q.w.eR, q.w.resmax, q.n, q.npad / 256, 0.0, 2, q.pp.d_extra,
+                    q.w.wtol, q.w.wtol + q.npad, q.w.tcut, &st->cx, &st->dmax_w,
+                    blockIdx.x % bpp);
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_w_g(const GProb *__restrict__ gp, int first,
+                                                         int bpp) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  if (q.pb.st->skip) return;
+  epi_w_body<EPT>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[1], q.w.eX, q.w.eR, q.w.lam,
+                  q.w.lam_lo, q.w.r, q.n, q.w.eE, q.w.emax, q.w.EP, kKeMax, q.w.flags, 0.0,
+                  nullptr, nullptr, 0, q.npad >= 1024 ? q.w.tcut : nullptr, blockIdx.x % bpp);
+}
+
+__global__ __launch_bounds__(256) void k_epi_u_g(const GProb *__restrict__ gp, int first,
+                                                 int gx, int bpp) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  const int lb = blockIdx.x % bpp, bx = lb % gx, by = lb / gx;
+  if (by >= q.n || q.pb.st->skip) return;
+  epi_u_body(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[2], q.w.eE, q.w.X1, q.n, q.X, q.ldx,
+             q.w.colmap, q.w.flags, bx, by);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_g(const GProb *__restrict__ gp, int first,
+                                                   int bpp) {
+  const GProb &q = gp[first + blockIdx.x / bpp];
+  if (q.pb.st->skip) return;
+  scatter_body(q.w.lam, q.w.colmap, q.n, q.D, q.w.flags, blockIdx.x % bpp);
+}
+
+// Work items of one product over the problems gp[first .. first + count) (tile rows `tile`
+// each): item = {problem, row tile | column tile << 8 | slot << 16}. which: 0 V by residues
+// (the slots below each 256-row block's modulus count, when V goes by residues), 1 V by slices,
+// 2 W, 3 X^(1) E~ (each problem's block table). One block; also resets the item counter.
+__device__ __forceinline__ int items_of(const GProb &q, int which, int tile) {
+  const DevState &st = *q.pb.st;
+  if (st.skip) return 0;
+  if (which == 0) {
+    if (!st.vres) return 0;
+    const int TT = q.npad / tile;
+    int c = 0;
+    for (int mi = 0; mi < TT; ++mi) c += q.w.vblk[2 * ((mi * tile) >> 8)];
+    return c * TT;
+  }
+  return (which == 1 ? st.gemm_v : which == 2 ? st.gemm_w : st.gemm_u)[2];
+}
+
+__global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ gp, int first,
+                                                     int count, int which, int tile,
+                                                     int2 *__restrict__ items,
+                                                     int *__restrict__ total,
+                                                     int *__restrict__ ctr) {
+  __shared__ int off[1025];
+  __shared__ int wsum[16];
+  int base_off = 0;
+  for (int base = 0; base < count; base += 1024) {
+    const int k = base + (int)threadIdx.x;
+    const int c = k < count ? items_of(gp[first + k], which, tile) : 0;
+    // block-wide exclusive scan of c
+    int v = c;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(v, o);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) wsum[wv] = v;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; ++q) before += wsum[q];
+    off[threadIdx.x] = base_off + before + v - c;
+    if (threadIdx.x == 1023) off[1024] = base_off + before + v;
+    __syncthreads();
+    const int chunk = min(1024, count - base);
+    for (int kk = 0; kk < chunk; ++kk) {
+      const GProb &q = gp[first + base + kk];
+      const int o0 = off[kk], cnt = off[kk + 1] - o0;
+      const int g = first + base + kk;
+      if (which == 0) {
+        const int TT = q.npad / tile;
+        for (int e = threadIdx.x; e < cnt; e += 1024) {
+          const int ni = e % TT;
+          int r = e / TT, mi = 0;
+          for (; mi < TT; ++mi) {
+            const int cm = q.w.vblk[2 * ((mi * tile) >> 8)];
+            if (r < cm) break;
+            r -= cm;
+          }
+          items[o0 + e] = make_int2(g, mi | (ni << 8) | (r << 16));
+        }
+      } else {
+        const int *tab = q.w.tab[which - 1];
+        for (int e = threadIdx.x; e < cnt; e += 1024) items[o0 + e] = make_int2(g, tab[e]);
+      }
+    }
+    base_off = off[1024];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *total = base_off;
+    *ctr = 0;
+  }
+}
+
+// The products of a grouped batch: persistent blocks take items from the list in order (one
+// atomic counter) until it is exhausted.
+template <int TILE, int WHICH>
+__global__ __launch_bounds__(256, TILE == 256 ? 1 : 2) void k_gemm_g(
+    const GProb *__restrict__ gp, const int2 *__restrict__ items, const int *__restrict__ total,
+    int *__restrict__ ctr) {
+  __shared__ int s_w;
+  const int tot = *total;
+  for (;;) {
+    if (threadIdx.x == 0) s_w = atomicAdd(ctr, 1);
+    __syncthreads();
+    // uniform values (scalar registers), so the item's loop control stays scalar
+    const int w = __builtin_amdgcn_readfirstlane(s_w);
+    __syncthreads();   // every wave has read s_w and left the previous item's LDS
+    if (w >= tot) return;
+    const int2 it = items[w];
+    const GProb &q = gp[__builtin_amdgcn_readfirstlane(it.x)];
+    const DevState &st = *q.pb.st;
+    const int ent = __builtin_amdgcn_readfirstlane(it.y);
+    const int m0 = (ent & 0xff) * TILE, n0 = ((ent >> 8) & 0xff) * TILE, slot = ent >> 16;
+    const int8_t *Lp, *Rp;
+    int kl, kr, same = 0;
+    const int *mods = nullptr, *vblk = nullptr, *tcut = nullptr;
+    if constexpr (WHICH == 0) {
+      Lp = q.w.XRES;
+      Rp = q.w.ARES;
+      kl = kr = kCrtMax;
+      same = 1;
+      mods = q.w.mods;
+      vblk = q.w.vblk;
+    } else if constexpr (WHICH == 1) {
+      Lp = q.w.XP;
+      Rp = q.w.AP;
+      kl = st.gemm_v[0];
+      kr = st.gemm_v[1];
+    } else if constexpr (WHICH == 2) {
+      Lp = q.w.RP;
+      Rp = q.w.XP;
+      kl = st.gemm_w[0];
+      kr = st.gemm_w[1];
+      if (q.npad >= 1024) tcut = q.w.tcut;
+    } else {
+      Lp = q.w.EP;
+      Rp = q.w.XPT;
+      kl = st.gemm_u[0];
+      kr = st.gemm_u[1];
+    }
+    if constexpr (TILE == 256)
+      gemm256_item<false>(Lp, Rp, q.P, q.npad, q.npad, kl, kr, 2, q.w.Cs, same, tcut, mods, vblk,
+                          m0, n0, slot);
+    else
+      gemm128_item(Lp, Rp, q.P, q.npad, q.npad, kl, kr, 2, q.w.Cs, same, mods, vblk, m0, n0,
+                   slot);
+  }
+}
+
+void launch_colstats_g(const GProb *gp, int first, int count, int npad, bool of_x, hipStream_t s) {
+  hipLaunchKernelGGL(k_colstats_g, dim3(count * npad), dim3(256), 0, s, gp, first, npad,
+                     of_x ? 1 : 0);
+}
+void launch_split_g(const GProb *gp, int first, int count, int npad, bool of_x, hipStream_t s) {
+  const int gx = npad / 64;
+  if (of_x)
+    hipLaunchKernelGGL(k_split_g<true>, dim3(count * gx * gx), dim3(256), 0, s, gp, first, gx);
+  else
+    hipLaunchKernelGGL(k_split_g<false>, dim3(count * gx * gx), dim3(256), 0, s, gp, first, gx);
+}
+void launch_epi_v_g(const GProb *gp, int first, int count, int npad, bool crt, hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+  const dim3 grid(count * npad), blk(kEpiThreads);
+#define EPI_V_G(E)                                                                            \
+  do {                                                                                        \
+    if (crt) hipLaunchKernelGGL((k_epi_v_g<E, true>), grid, blk, 0, s, gp, first, npad);      \
+    else hipLaunchKernelGGL((k_epi_v_g<E, false>), grid, blk, 0, s, gp, first, npad);         \
+  } while (0)
+  // grouped batches hold npad <= kGroupMaxNpad (4 entries per thread at most)
+  if (ept <= 1) EPI_V_G(1);
+  else if (ept <= 2) EPI_V_G(2);
+  else EPI_V_G(4);
+#undef EPI_V_G
+}
+void launch_tile_cutoffs_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_cutoffs_g, dim3(count * (npad / 256)), dim3(256), 0, s, gp, first,
+                     npad / 256);
+}
+void launch_epi_w_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
+  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
+  const dim3 grid(count * npad), blk(kEpiThreads);
+  if (ept <= 1) hipLaunchKernelGGL(k_epi_w_g<1>, grid, blk, 0, s, gp, first, npad);
+  else if (ept <= 2) hipLaunchKernelGGL(k_epi_w_g<2>, grid, blk, 0, s, gp, first, npad);
+  else hipLaunchKernelGGL(k_epi_w_g<4>, grid, blk, 0, s, gp, first, npad);
+}
+void launch_epi_u_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
+  const int gx = npad / 256;
+  hipLaunchKernelGGL(k_epi_u_g, dim3(count * gx * npad), dim3(256), 0, s, gp, first, gx,
+                     gx * npad);
+}
+void launch_scatter_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_g, dim3(count * (npad / 256)), dim3(256), 0, s, gp, first,
+                     npad / 256);
+}
+void launch_worklist_g(const GProb *gp, int first, int count, int which, int tile, int2 *items,
+                       int *total, int *ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_worklist_g, dim3(1), dim3(1024), 0, s, gp, first, count, which, tile,
+                     items, total, ctr);
+}
+template <int TILE>
+static void gemm_g_t(const GProb *gp, int blocks, const int2 *items, const int *total, int *ctr,
+                     int which, hipStream_t s) {
+  const dim3 g(blocks), b(256);
+  switch (which) {
+    case 0: hipLaunchKernelGGL((k_gemm_g<TILE, 0>), g, b, 0, s, gp, items, total, ctr); break;
+    case 1: hipLaunchKernelGGL((k_gemm_g<TILE, 1>), g, b, 0, s, gp, items, total, ctr); break;
+    case 2: hipLaunchKernelGGL((k_gemm_g<TILE, 2>), g, b, 0, s, gp, items, total, ctr); break;
+    default: hipLaunchKernelGGL((k_gemm_g<TILE, 3>), g, b, 0, s, gp, items, total, ctr); break;
+  }
+}
+void launch_gemm_g(const GProb *gp, int tile, int blocks, const int2 *items, const int *total,
+                   int *ctr, int which, hipStream_t s) {
+  if (blocks <= 0) return;
+  if (tile == 256) gemm_g_t<256>(gp, blocks, items, total, ctr, which, s);
+  else gemm_g_t<128>(gp, blocks, items, total, ctr, which, s);
 }
 
 }  // namespace refeig

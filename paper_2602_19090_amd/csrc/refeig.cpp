@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
@@ -41,16 +42,13 @@
 #include "plain.h"
 #include "plan.h"
 #include "devplan.h"
+#include "work.h"
 
 using namespace refeig;
 
 namespace {
 
-constexpr int kMaxN = 8192;  // the column epilogues hold a whole column in registers
 constexpr int kKaMaxLimit = 18;
-constexpr int kKxMax = 9;
-constexpr int kKrMax = 12;
-constexpr int kKeMax = 12;
 
 #define HIPCHK(x)                                                        \
   do {                                                                   \
@@ -63,30 +61,6 @@ constexpr int kKeMax = 12;
 
 inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
-struct Work {
-  int n = 0, npad = 0, ka = 0;
-  size_t P = 0;
-  int8_t *AP, *XP, *XPT, *RP, *EP;
-  int8_t *ARES = nullptr, *XRES = nullptr;   // residue planes of the V product by residues
-  int32_t *Cs;
-  double *X1;
-  int *eA, *cA, *eX, *cX, *eR, *eE, *flags;
-  int *dcut[3];  // per-column last diagonal of V, W and X^(1) E~
-  int *colmap;   // working column p holds column colmap[p] of the caller's X
-  int *tcut;     // per-tile last diagonal of W (256 x 256 tiles)
-  int *mods;     // moduli of the residue product of V
-  CrtRec *recs;  // its reconstruction records, one per level (digit count of A)
-  int *vblk;     // per 256-column block of V: slot count, level
-  double *ssA, *ssX;   // column sums of squares of A and X (the residue product's bound)
-  double *wtol;        // per column: W tile tightening t_j, then the column's own gap g_j
-  int *tab[3];   // block tables of the V, W and X^(1) E~ products
-  // grouped correction: coupling list, pair list, member table, Ritz data
-  int *cpl, *g_pa, *g_pb, *g_col, *g_first, *g_k, *g_pos, *g_base;   // cpl: count, then pairs
-  double *g_gh, *g_gl, *g_w, *g_Y, *g_mu, *g_mul;
-  double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
-  DevState *dst;   // device planning state
-  double *gapsw;   // entry gaps in working order (device planning)
-};
 
 int nslots(int ka, bool crt = false) {
   return std::max(std::max(ka, kKrMax + kKxMax), crt ? kCrtMax : 0);
@@ -1224,30 +1198,20 @@ int status_of(const DevState &st, int flags) {
   return st.stop_status;
 }
 
-// The solve with device planning (INT8 path, no grouping, no schedule). `work` holds at least
-// carve(n, ka_max, crt) bytes. enqueue_only: no wait and no event (fixed_iters > 0).
-int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n, double target,
-                  const refeig_opts &o, void *work, hipStream_t s, refeig_report *rep,
-                  bool enqueue_only) {
-  const int ka_max = ka_of(&o);
-  const bool crt = o.vmode == 1;
-  Work w;
-  carve(n, ka_max, (char *)work, &w, crt);
-  const int npad = w.npad;
-  const size_t P = w.P;
-  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+// Scalars and device pointers the planning kernels of one solve read (iteration 0).
+PlanParams plan_params(int n, int npad, const refeig_opts &o, double target) {
   PlanParams pp;
   pp.n = n;
   pp.npad = npad;
   pp.it = 0;
-  pp.iters = iters;
+  pp.iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
   pp.fixed = o.fixed_iters > 0 ? 1 : 0;
   pp.kx_force = o.kx_force;
-  pp.ka_max = ka_max;
+  pp.ka_max = ka_of(&o);
   pp.d_extra = o.d_extra;
   pp.vmode = o.vmode;
   pp.stop_rule = o.stop_rule;
-  pp.crt = crt ? 1 : 0;
+  pp.crt = o.vmode == 1 ? 1 : 0;
   pp.theta = o.theta;
   pp.delta_int = target / o.delta_safety;
   pp.delta_k = pp.delta_int;
@@ -1256,6 +1220,9 @@ int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n
   pp.lgrowth_a = lgrowth_of(o, n);
   pp.lsqn = 0.5 * plan_log2((double)n);
   pp.target = target;
+  return pp;
+}
+PlanBufs plan_bufs(const Work &w, const double *D) {
   PlanBufs pb;
   pb.st = w.dst;
   pb.D = D;
@@ -1279,9 +1246,26 @@ int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n
     pb.tab[q] = w.tab[q];
   }
   pb.vblk = w.vblk;
-  pb.tcut = npad >= 1024 ? w.tcut : nullptr;
+  pb.tcut = w.npad >= 1024 ? w.tcut : nullptr;
   pb.flags = w.flags;
   pb.mods = w.mods;
+  return pb;
+}
+
+// The solve with device planning (INT8 path, no grouping, no schedule). `work` holds at least
+// carve(n, ka_max, crt) bytes. enqueue_only: no wait and no event (fixed_iters > 0).
+int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n, double target,
+                  const refeig_opts &o, void *work, hipStream_t s, refeig_report *rep,
+                  bool enqueue_only) {
+  const int ka_max = ka_of(&o);
+  const bool crt = o.vmode == 1;
+  Work w;
+  carve(n, ka_max, (char *)work, &w, crt);
+  const int npad = w.npad;
+  const size_t P = w.P;
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  PlanParams pp = plan_params(n, npad, o, target);
+  const PlanBufs pb = plan_bufs(w, D);
   DevState *st = w.dst;
   const int tr = gemm_tile_rows(npad), TT = npad / tr;
   // launch sizes of the tabled products: the largest tables the cutoffs allow
@@ -1411,6 +1395,276 @@ int refine_device(const double *A, int lda, double *X, int ldx, double *D, int n
             .count();
   }
   return status;
+}
+
+// ---- grouped batches: the solves of a batch advance together, one launch per step and size
+// class, the products as persistent kernels over a device-built work list of (problem, tile,
+// slot) items. Every problem's arithmetic is that of its single call (the same kernels' bodies
+// on the same plan), so its result is bit for bit the same.
+bool grouped_batch(const refeig_opts &o) {
+  return o.mode == REFEIG_OZAKI_INT8 && o.plan == 0 && o.group_tau == 0.0 && o.schedule == 0 &&
+         !o.enqueue_only;
+}
+
+// Workspaces of the problems run together: 16 GiB, or REFEIG_GROUP_CHUNK_MIB from the
+// environment (read at each call; the workspace query and the solve must see the same value).
+size_t group_chunk_bytes() {
+  const char *e = std::getenv("REFEIG_GROUP_CHUNK_MIB");
+  if (e) {
+    const long long m = std::atoll(e);
+    if (m > 0) return (size_t)m << 20;
+  }
+  return 16ull << 30;
+}
+
+size_t ws_rounded(int n, const refeig_opts &o) {
+  return (carve(n, ka_of(&o), nullptr, nullptr, o.vmode == 1) + 255) / 256 * 256;
+}
+// Work items a problem's products can ask for at most (tiles x slots).
+size_t item_cap(int n) {
+  const int npad = round_up(n, kTile), tt = npad / gemm_tile_rows(npad);
+  return (size_t)tt * tt * std::max(kCrtMax, kMaxDiag);
+}
+size_t stage_stride() { return (sizeof(DevState) + sizeof(int) + 255) / 256 * 256; }
+
+// The batch's own area (descriptors, work lists, counters, the state staging) for count
+// problems with icap items, then the region the problems' workspaces are carved from.
+struct GroupArea {
+  GProb *gp;
+  int2 *items;
+  int *cnt;     // [0..1] total, counter of the 256-tile list; [2..3] of the 128-tile one; [4]
+  char *stage;
+};
+size_t group_area(int count, size_t icap, char *base, GroupArea *ga) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  GroupArea g;
+  g.gp = (GProb *)take(sizeof(GProb) * (size_t)count);
+  g.items = (int2 *)take(sizeof(int2) * icap);
+  g.cnt = (int *)take(sizeof(int) * 8);
+  g.stage = take(stage_stride() * (size_t)count);
+  if (ga) *ga = g;
+  return off;
+}
+
+size_t grouped_bytes(int count, const int *n, const refeig_opts &o) {
+  size_t icap = 0, sum = 0, mx = 0;
+  for (int i = 0; i < count; ++i) {
+    const size_t w = ws_rounded(n[i], o);
+    sum += w;
+    mx = std::max(mx, w);
+    if (round_up(n[i], kTile) <= kGroupMaxNpad) icap += item_cap(n[i]);
+  }
+  return group_area(count, icap, nullptr, nullptr) +
+         std::min(sum, std::max(group_chunk_bytes(), mx));
+}
+
+// One chunk of a grouped batch: problems ids (npad descending, all <= kGroupMaxNpad), their
+// workspaces carved from `region`. Fills status[] and reports (may be null) of its problems.
+int run_chunk(const std::vector<int> &ids, const int *n, const double *const *A, const int *lda,
+              double *const *X, const int *ldx, double *const *D, const double *target,
+              const refeig_opts &o, const GroupArea &ga, char *region, hipStream_t s,
+              refeig_report *reports, std::vector<int> &status) {
+  const int G = (int)ids.size();
+  const int ka_max = ka_of(&o);
+  const bool crt = o.vmode == 1;
+  auto t_start = std::chrono::steady_clock::now();
+  std::vector<GProb> hp(G);
+  size_t off = 0;
+  for (int k = 0; k < G; ++k) {
+    const int i = ids[k];
+    GProb &q = hp[k];
+    carve(n[i], ka_max, region + off, &q.w, crt);
+    off += ws_rounded(n[i], o);
+    q.A = A[i];
+    q.X = X[i];
+    q.D = D[i];
+    q.lda = lda[i];
+    q.ldx = ldx[i];
+    q.n = n[i];
+    q.npad = q.w.npad;
+    q.ka = ka_max;
+    q.P = q.w.P;
+    q.pp = plan_params(n[i], q.npad, o, target[i]);
+    q.pb = plan_bufs(q.w, D[i]);
+  }
+  // size classes (runs of equal npad) and the two tile groups (256-row tiles first)
+  struct Cls {
+    int first, count, npad;
+  };
+  std::vector<Cls> cls;
+  for (int k = 0; k < G; ++k) {
+    if (cls.empty() || cls.back().npad != hp[k].npad) cls.push_back({k, 0, hp[k].npad});
+    ++cls.back().count;
+  }
+  int g256 = 0;
+  size_t cap256 = 0, cap128 = 0;
+  for (int k = 0; k < G; ++k) {
+    if (gemm_tile_rows(hp[k].npad) == 256) {
+      ++g256;
+      cap256 += item_cap(hp[k].n);
+    } else {
+      cap128 += item_cap(hp[k].n);
+    }
+  }
+  int2 *items256 = ga.items, *items128 = ga.items + cap256;
+  const int blocks256 = (int)std::min<size_t>(256, cap256);
+  const int blocks128 = (int)std::min<size_t>(512, cap128);
+  const GProb *gp = ga.gp;
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);   // nothing in flight reads hp after this returns
+    for (int k = 0; k < G; ++k) status[ids[k]] = st;
+    return st;
+  };
+  if (hipMemcpyAsync(ga.gp, hp.data(), sizeof(GProb) * G, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(REFEIG_E_HIP);
+  auto products = [&](int which) {
+    if (g256) {
+      launch_worklist_g(gp, 0, g256, which, 256, items256, ga.cnt, ga.cnt + 1, s);
+      launch_gemm_g(gp, 256, blocks256, items256, ga.cnt, ga.cnt + 1, which, s);
+    }
+    if (G > g256) {
+      launch_worklist_g(gp, g256, G - g256, which, 128, items128, ga.cnt + 2, ga.cnt + 3, s);
+      launch_gemm_g(gp, 128, blocks128, items128, ga.cnt + 2, ga.cnt + 3, which, s);
+    }
+  };
+  // once per solve: A's column statistics, the planning state, A's digit planes
+  launch_flags_clear_g(gp, G, s);
+  for (const Cls &c : cls) {
+    launch_colstats_g(gp, c.first, c.count, c.npad, false, s);
+    launch_dp_init_g(gp, c.first, c.count, s);
+    launch_split_g(gp, c.first, c.count, c.npad, false, s);
+  }
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  for (int it = 0; it < iters; ++it) {
+    for (const Cls &c : cls) launch_dp_order_g(gp, c.first, c.count, it, s);
+    for (const Cls &c : cls) launch_colstats_g(gp, c.first, c.count, c.npad, true, s);
+    for (const Cls &c : cls) launch_dp_vplan_g(gp, c.first, c.count, it, s);
+    for (const Cls &c : cls) launch_split_g(gp, c.first, c.count, c.npad, true, s);
+    if (crt) {
+      for (const Cls &c : cls)
+        for (int l = 0; l <= kVLevels; ++l)
+          launch_residues_g(gp, c.first, c.count, (size_t)c.npad * c.npad, l, s);
+      products(0);
+      for (const Cls &c : cls) launch_epi_v_g(gp, c.first, c.count, c.npad, true, s);
+    }
+    products(1);
+    for (const Cls &c : cls) launch_epi_v_g(gp, c.first, c.count, c.npad, false, s);
+    for (const Cls &c : cls) launch_dp_wplan_g(gp, c.first, c.count, it, s);
+    for (const Cls &c : cls)
+      if (c.npad >= 1024) launch_tile_cutoffs_g(gp, c.first, c.count, c.npad, s);
+    products(2);
+    for (const Cls &c : cls) launch_epi_w_g(gp, c.first, c.count, c.npad, s);
+    for (const Cls &c : cls) launch_dp_uplan_g(gp, c.first, c.count, it, s);
+    products(3);
+    for (const Cls &c : cls) launch_epi_u_g(gp, c.first, c.count, c.npad, s);
+    for (const Cls &c : cls) launch_scatter_g(gp, c.first, c.count, c.npad, s);
+    if (hipGetLastError() != hipSuccess) return fail(REFEIG_E_HIP);
+    if (o.fixed_iters <= 0 && it + 1 < iters) {   // stop once every solve has stopped
+      int running = 0;
+      launch_count_running_g(gp, G, ga.cnt + 4, s);
+      if (hipMemcpyAsync(&running, ga.cnt + 4, sizeof(int), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(REFEIG_E_HIP);
+      if (running == 0) break;
+    }
+  }
+  const size_t stride = stage_stride();
+  std::vector<char> stage(stride * G);
+  launch_gather_state_g(gp, G, ga.stage, stride, s);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(stage.data(), ga.stage, stride * G, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(REFEIG_E_HIP);
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+          .count();
+  for (int k = 0; k < G; ++k) {
+    DevState hst;
+    int hflags = 0;
+    std::memcpy(&hst, stage.data() + stride * k, sizeof(DevState));
+    std::memcpy(&hflags, stage.data() + stride * k + sizeof(DevState), sizeof(int));
+    const int st = status_of(hst, hflags);
+    status[ids[k]] = st;
+    if (reports) {
+      refeig_report *r = &reports[ids[k]];
+      fill_report_from_device(hst, hflags, iters, r);
+      r->status = st;
+      r->ms_total = ms;   // the chunk's wall time (its solves run together)
+    }
+  }
+  return REFEIG_OK;
+}
+
+bool opts_valid(const refeig_opts &o) {
+  return o.delta_safety >= 1.0 && o.theta > 0.0 && o.theta <= 1.0 && o.max_iter >= 1 &&
+         o.group_tau >= 0.0 && o.kx_force >= 0 && o.kx_force <= kKxMax && o.sparse_k >= 0 &&
+         o.schedule >= 0 && o.schedule <= 1 && o.vmode >= 0 && o.vmode <= 1 &&
+         o.max_iter <= REFEIG_MAX_ITERS && o.fixed_iters <= REFEIG_MAX_ITERS;
+}
+
+int refine_grouped(int count, const int *n, const double *const *A, const int *lda,
+                   double *const *X, const int *ldx, double *const *D, const double *target,
+                   const refeig_opts &o, char *work, size_t work_bytes, hipStream_t s,
+                   refeig_report *reports) {
+  std::vector<int> status(count, REFEIG_E_ARG);
+  if (reports) std::memset(reports, 0, sizeof(refeig_report) * count);
+  const bool ok_opts = opts_valid(o);
+  // problems run together (valid, npad <= kGroupMaxNpad) by npad descending, and the rest
+  std::vector<int> grouped, alone;
+  size_t icap = 0;
+  for (int i = 0; i < count; ++i) {
+    const bool valid = ok_opts && A[i] && X[i] && D[i] && n[i] >= 1 && n[i] <= kMaxN &&
+                       lda[i] >= n[i] && ldx[i] >= n[i] && target[i] > 0.0;
+    if (!valid) continue;
+    if (round_up(n[i], kTile) <= kGroupMaxNpad) {
+      grouped.push_back(i);
+      icap += item_cap(n[i]);
+    } else {
+      alone.push_back(i);
+    }
+  }
+  std::stable_sort(grouped.begin(), grouped.end(), [&](int a, int b) {
+    return round_up(n[a], kTile) > round_up(n[b], kTile);
+  });
+  GroupArea ga;
+  const size_t area = group_area(count, icap, work, &ga);
+  char *region = work + area;
+  const size_t room = std::min(work_bytes - area, std::max(group_chunk_bytes(), [&] {
+                                 size_t mx = 0;
+                                 for (int i = 0; i < count; ++i)
+                                   if (n[i] >= 1 && n[i] <= kMaxN)
+                                     mx = std::max(mx, ws_rounded(n[i], o));
+                                 return mx;
+                               }()));
+  // chunks of consecutive problems whose workspaces fit in the region together
+  size_t k = 0;
+  while (k < grouped.size()) {
+    std::vector<int> ids;
+    size_t used = 0;
+    while (k < grouped.size() && (ids.empty() || used + ws_rounded(n[grouped[k]], o) <= room)) {
+      used += ws_rounded(n[grouped[k]], o);
+      ids.push_back(grouped[k++]);
+    }
+    if (used > room) return REFEIG_E_NOMEM;
+    run_chunk(ids, n, A, lda, X, ldx, D, target, o, ga, region, s, reports, status);
+  }
+  for (int i : alone)
+    status[i] = refine_eigvecs(A[i], lda[i], X[i], ldx[i], D[i], n[i], target[i], &o, region,
+                               room, (refeig_stream_t)s, reports ? &reports[i] : nullptr);
+  int worst = REFEIG_OK;
+  for (int i = 0; i < count; ++i) {
+    if (reports && status[i] == REFEIG_E_ARG) reports[i].status = REFEIG_E_ARG;
+    if (status[i] < 0) return status[i];
+    if (status[i] != REFEIG_OK) worst = status[i];
+  }
+  return worst;
 }
 
 }  // namespace
@@ -2302,10 +2556,17 @@ int refeig_host_group_ritz(int k, const double *G_hi, const double *G_lo, const 
 
 int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes) {
   if (count < 1 || !n || !bytes) return REFEIG_E_ARG;
+  refeig_opts opts;
+  if (o) opts = *o;
+  else refeig_default_opts(&opts);
   int nmax = 0;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > kMaxN) return REFEIG_E_ARG;
     nmax = std::max(nmax, n[i]);
+  }
+  if (grouped_batch(opts)) {
+    *bytes = grouped_bytes(count, n, opts);
+    return *bytes ? REFEIG_OK : REFEIG_E_ARG;
   }
   size_t one = 0;
   const int st = refeig_workspace_bytes(nmax, o, &one);
@@ -2322,8 +2583,6 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
   size_t need = 0;
   int st = refeig_batched_workspace_bytes(count, n, o, &need);
   if (st != REFEIG_OK) return st;
-  const int lanes = std::min(count, REFEIG_BATCH_LANES);
-  const size_t slice = need / lanes;
   hipStream_t s = (hipStream_t)stream;
   bool own = false;
   if (!work) {
@@ -2333,6 +2592,20 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
   } else if (work_bytes < need) {
     return REFEIG_E_NOMEM;
   }
+  refeig_opts opts;
+  if (o) opts = *o;
+  else refeig_default_opts(&opts);
+  if (grouped_batch(opts)) {
+    const int st = refine_grouped(count, n, A, lda, X, ldx, D, target, opts, (char *)work, need,
+                                  s, reports);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(work);
+    }
+    return st;
+  }
+  const int lanes = std::min(count, REFEIG_BATCH_LANES);
+  const size_t slice = need / lanes;
   // lanes: own streams (default priority), joined to the caller's stream by events
   std::vector<hipStream_t> ls(lanes, nullptr);
   std::vector<hipEvent_t> le(lanes + 1, nullptr);
