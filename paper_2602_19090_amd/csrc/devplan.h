@@ -69,6 +69,8 @@ struct PlanBufs {
   const int *tcut;
   int *flags;
   int *mods;              // the moduli, all kCrtMax (for the residue store)
+  double *skey;           // the W plan's sorted Rayleigh quotients (n), reused by the next
+  int *sidx;              // iteration's order (their columns; D holds the same values then)
 };
 
 void launch_dp_init(const PlanParams &p, const PlanBufs &b, hipStream_t s);

@@ -112,63 +112,106 @@ __device__ void bitonic(K *key, int *aux, int N2) {
 }
 
 // Block table of a tabled slice-GEMM launch from each tile's last diagonal dt[J] (LDS, ntile
-// tiles per side): groups of tiles with equal dt, largest first; (group, slot) combinations
-// ordered by pair count, most first (stable); within one, the XCD band order of
-// xcd_tile_order. Entry = row tile | column tile << 8 | slot << 16. Returns the entry count.
+// tiles per side, 2 <= dt[J] <= kMaxDiag + 1): groups of tiles with equal dt, largest first;
+// (group, slot) combinations ordered by pair count, most first (stable); within one, the XCD
+// band order of xcd_tile_order. Entry = row tile | column tile << 8 | slot << 16. Returns the
+// entry count. The slots are ranked once by pair count (descending, stable); a run of slots
+// with equal counts is taken group by group, and in a group the slots q with q + 2 <= dt (a
+// prefix of the run, which holds ascending q): block (run r, group g) holds those
+// combinations' entries, and the blocks follow each other run by run, group by group.
+constexpr int kTabRuns = kMaxDiag;   // runs and groups a block index is formed from
 struct TabScratch {
+  int vcnt[kMaxDiag + 2], gidx[kMaxDiag + 2];
   int gval[kMaxDiag + 2], gcnt[kMaxDiag + 2], goff[kMaxDiag + 2];
   int rows[64];
-  int ng, ncombo;
-  int cg[kMaxDiag * kMaxDiag], cq[kMaxDiag * kMaxDiag], coff[kMaxDiag * kMaxDiag + 1];
+  int ng, nrun;
+  int np[kMaxDiag], qs[kMaxDiag], rstart[kMaxDiag + 1];
+  int boff[kTabRuns * kTabRuns + 1];
+  int wsum[kPT / 64];
 };
 __device__ int build_table(const int *dt, int ntile, int kl, int kr, int *tab, TabScratch &ts) {
-  if (threadIdx.x == 0) {
-    int dmax = 2;
-    for (int J = 0; J < ntile; ++J) dmax = max(dmax, dt[J]);
+  const int tid = threadIdx.x;
+  if (tid < kMaxDiag + 2) ts.vcnt[tid] = 0;
+  __syncthreads();
+  if (tid < ntile) atomicAdd(&ts.vcnt[dt[tid]], 1);
+  if (tid >= 64 && tid < 64 + kMaxDiag) ts.np[tid - 64] = npairs_of(2 + (tid - 64), kl, kr);
+  __syncthreads();
+  if (tid == 0) {   // groups, largest dt first
     int ng = 0, nr = 0;
-    for (int v = dmax; v >= 2; --v) {
-      int c = 0;
-      for (int J = 0; J < ntile; ++J)
-        if (dt[J] == v) ts.rows[nr + c++] = J;
-      if (c) {
+    for (int v = kMaxDiag + 1; v >= 2; --v)
+      if (ts.vcnt[v]) {
         ts.gval[ng] = v;
-        ts.gcnt[ng] = c;
+        ts.gcnt[ng] = ts.vcnt[v];
         ts.goff[ng] = nr;
-        nr += c;
+        ts.gidx[v] = ng;
+        nr += ts.vcnt[v];
         ++ng;
       }
-    }
     ts.ng = ng;
-    // combinations (group, slot), most pairs first, stable over (group, slot)
-    int nc = 0;
-    for (int np = kMaxDiag; np >= 1; --np)
-      for (int g = 0; g < ng; ++g)
-        for (int q = 0; q + 2 <= ts.gval[g]; ++q)
-          if (npairs_of(2 + q, kl, kr) == np) {
-            ts.cg[nc] = g;
-            ts.cq[nc] = q;
-            ++nc;
-          }
-    ts.ncombo = nc;
-    int off = 0;
-    for (int c = 0; c < nc; ++c) {
-      ts.coff[c] = off;
-      off += ts.gcnt[ts.cg[c]] * ntile;
-    }
-    ts.coff[nc] = off;
+  }
+  if (tid >= 64 && tid < 64 + kMaxDiag) {   // rank of slot q: more pairs first, then q
+    const int q = tid - 64, v = ts.np[q];
+    int rk = 0;
+    for (int k = 0; k < kMaxDiag; ++k) rk += (ts.np[k] > v || (ts.np[k] == v && k < q)) ? 1 : 0;
+    ts.qs[rk] = q;
   }
   __syncthreads();
-  const int total = ts.coff[ts.ncombo];
-  for (int e = threadIdx.x; e < total; e += kPT) {
-    int lo = 0, hi = ts.ncombo - 1;   // the combination holding entry e
+  if (tid < ntile) {   // tile J's place in its group (ascending J)
+    const int v = dt[tid];
+    int rk = 0;
+    for (int J = 0; J < tid; ++J) rk += dt[J] == v ? 1 : 0;
+    ts.rows[ts.goff[ts.gidx[v]] + rk] = tid;
+  }
+  if (tid == 64) {   // runs of equal pair counts (those with pairs)
+    int nrun = 0;
+    for (int k = 0; k < kMaxDiag; ++k) {
+      if (ts.np[ts.qs[k]] < 1) break;
+      if (k == 0 || ts.np[ts.qs[k]] != ts.np[ts.qs[k - 1]]) ts.rstart[nrun++] = k;
+    }
+    int end = 0;
+    while (end < kMaxDiag && ts.np[ts.qs[end]] >= 1) ++end;
+    ts.rstart[nrun] = end;
+    ts.nrun = nrun;
+  }
+  __syncthreads();
+  // block (r, g) = thread r kTabRuns + g: its entry count, then an exclusive scan in that order
+  int sz = 0;
+  {
+    const int r = tid / kTabRuns, g = tid % kTabRuns;
+    if (r < ts.nrun && g < ts.ng) {
+      int c = 0;
+      for (int k = ts.rstart[r]; k < ts.rstart[r + 1]; ++k) c += ts.qs[k] + 2 <= ts.gval[g] ? 1 : 0;
+      sz = c * ts.gcnt[g] * ntile;
+    }
+  }
+  static_assert(kTabRuns * kTabRuns == kPT, "one thread per (run, group) block");
+  const int lane = tid & 63, wv = tid >> 6;
+  int v = sz;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) ts.wsum[wv] = v;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wv; ++w) before += ts.wsum[w];
+  ts.boff[tid] = before + v - sz;
+  if (tid == kPT - 1) ts.boff[kPT] = before + v;
+  __syncthreads();
+  const int total = ts.boff[kPT];
+  for (int e = tid; e < total; e += kPT) {
+    int lo = 0, hi = kPT - 1;   // the last block starting at or before e (it holds e)
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (ts.coff[mid] <= e) lo = mid;
+      if (ts.boff[mid] <= e) lo = mid;
       else hi = mid - 1;
     }
-    const int g = ts.cg[lo], q = ts.cq[lo];
+    const int r = lo / kTabRuns, g = lo % kTabRuns;
+    const int per = ts.gcnt[g] * ntile, local = e - ts.boff[lo];
+    const int k = local / per, within = local - k * per;
+    const int q = ts.qs[ts.rstart[r] + k];
     int mi, nb;
-    xcd_tile_order(e - ts.coff[lo], ts.gcnt[g], ntile, mi, nb);
+    xcd_tile_order(within, ts.gcnt[g], ntile, mi, nb);
     tab[e] = ts.rows[ts.goff[g] + mi] | (nb << 8) | (q << 16);
   }
   __syncthreads();
@@ -249,18 +292,31 @@ __device__ __forceinline__ void dp_order_body(PlanParams p, PlanBufs b) {
   __shared__ int rk[kDevSortMax];        // second sort: rank in eigenvalue order
   __shared__ double red[16];
   const int n = p.n, N2 = pow2_at_least(n);
-  int bad = 0;
-  for (int i = threadIdx.x; i < N2; i += kPT) {
-    double v = i < n ? b.D[i] : INFINITY;
-    if (i < n && !(fabs(v) <= DBL_MAX)) {
-      bad = 1;
-      v = 0.0;
+  // after the first iteration, D holds the last W plan's Rayleigh quotients, already sorted
+  // (unless an error stopped the update; ties, gap 0, are an error either way)
+  __shared__ int s_reuse;
+  if (threadIdx.x == 0) s_reuse = p.it > 0 && !(*b.flags & kFlagsError);
+  __syncthreads();
+  if (s_reuse) {
+    for (int i = threadIdx.x; i < N2; i += kPT) {
+      key[i] = i < n ? b.skey[i] : INFINITY;
+      idx[i] = i < n ? b.sidx[i] : i;
     }
-    key[i] = v;
-    idx[i] = i;
+    __syncthreads();
+  } else {
+    int bad = 0;
+    for (int i = threadIdx.x; i < N2; i += kPT) {
+      double v = i < n ? b.D[i] : INFINITY;
+      if (i < n && !(fabs(v) <= DBL_MAX)) {
+        bad = 1;
+        v = 0.0;
+      }
+      key[i] = v;
+      idx[i] = i;
+    }
+    if (bad) atomicOr(b.flags, FLAG_NONFINITE);
+    bitonic<double>(key, idx, N2);
   }
-  if (bad) atomicOr(b.flags, FLAG_NONFINITE);
-  bitonic<double>(key, idx, N2);
   double lmax;
   // gaps in eigenvalue order, kept in registers of the thread that owns the position (at
   // most kDevSortMax / kPT per thread)
@@ -344,9 +400,25 @@ __device__ __forceinline__ void dp_vplan_body(PlanParams p, PlanBufs b) {
   extra = blk_max_i(extra, ired);
   exm = blk_max_i(exm, ired);
   hx = blk_max_d(hx, red);
+  // the histogram's nonzero bins as bit masks, so the sum below visits only those (in the
+  // ascending order of pow2_sum)
+  __shared__ unsigned long long nzm[kBetaBins / 64];
+  if (threadIdx.x < kBetaBins / 64) {
+    unsigned long long m = 0ull;
+    for (int k = 0; k < 64; ++k)
+      if (hist[64 * threadIdx.x + k]) m |= 1ull << k;
+    nzm[threadIdx.x] = m;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    double S = 0.0;
+    for (int w = 0; w < kBetaBins / 64; ++w)
+      for (unsigned long long m = nzm[w]; m; m &= m - 1) {
+        const int bb = 64 * w + __ffsll((long long)m) - 1;
+        S += (double)hist[bb] * ldexp(1.0, bb - kBetaBias);
+      }
     int beta = 0, kx = 1;
-    beta_core(p.xi, p.delta_k, st.gmin, st.lmax, pow2_sum(hist), extra, &beta, &kx);
+    beta_core(p.xi, p.delta_k, st.gmin, st.lmax, S, extra, &beta, &kx);
     if (p.kx_force > 0) kx = p.kx_force;
     st.beta = beta;
     st.kx = kx;
@@ -525,6 +597,12 @@ __device__ __forceinline__ void dp_wplan_body(PlanParams p, PlanBufs b) {
     idx[i] = i;
   }
   bitonic<double>(key, idx, N2);
+  // the sorted quotients and their columns: after this iteration D holds exactly these values
+  // (the update scatters them), so the next iteration's order needs no sort of D
+  for (int pp = threadIdx.x; pp < n; pp += kPT) {
+    b.skey[pp] = key[pp];
+    b.sidx[pp] = b.colmap[idx[pp]];
+  }
   // gaps of the Rayleigh quotients, to their working positions (held in wtol[npad + j])
   double gm = INFINITY, lm = 0.0;
   for (int pp = threadIdx.x; pp < n; pp += kPT) {

@@ -924,17 +924,41 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
                           (const int *)nullptr, tab, dp, (const int *)nullptr);
 }
 
+// Threads and entries per thread of the column epilogues (one block per output column):
+// up to npad = 1024 one entry per thread and npad threads (npad is a multiple of 256), above
+// it 1024 threads and npad / 1024 entries each. The single and grouped launches use the same
+// shapes, so their reductions group the column's entries alike.
+#define EPI_DISPATCH(npad, M)        \
+  do {                               \
+    if ((npad) <= 256) M(1, 256);    \
+    else if ((npad) <= 512) M(1, 512);  \
+    else if ((npad) <= 768) M(1, 768);  \
+    else if ((npad) <= 1024) M(1, 1024); \
+    else if ((npad) <= 2048) M(2, 1024); \
+    else if ((npad) <= 4096) M(4, 1024); \
+    else M(8, 1024);                 \
+  } while (0)
+#define EPI_DISPATCH_G(npad, M)      \
+  do {                               \
+    if ((npad) <= 256) M(1, 256);    \
+    else if ((npad) <= 512) M(1, 512);  \
+    else if ((npad) <= 768) M(1, 768);  \
+    else if ((npad) <= 1024) M(1, 1024); \
+    else if ((npad) <= 2048) M(2, 1024); \
+    else M(4, 1024);                 \
+  } while (0)
+
 // Digit planes of one operand row j (an output column of a column epilogue): the values
-// v (EPT per thread, row i = tid + kEpiThreads q; zero beyond n) with column maximum ms,
+// v (EPT per thread, row i = tid + NT q; zero beyond n) with column maximum ms,
 // exponent exp_above(ms), written K-blocked for rows i < npad.
-template <int EPT>
+template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double ms, int j, int npad,
                                                  int8_t *__restrict__ planes, int k) {
   const size_t P = (size_t)npad * npad;
   const int ee = exp_above(ms);
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = threadIdx.x + kEpiThreads * q;
+    const int i = threadIdx.x + NT * q;
     if (i < npad) {
       const double a = v[q];
       double y = ldexp(fabs(a), -ee);
@@ -956,7 +980,7 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
 // leave s0 exactly), then V = (P / M) M 2^(scale) as a double-word (vh, vl). Moduli are the
 // outer loop, and the next modulus's slot is loaded while this one is added; s0 and s1 live
 // in vh and vl until the end.
-template <int EPT>
+template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size_t P, int n,
                                            int tid, const CrtRec &rec, const int (&scale)[EPT],
                                            double (&vh)[EPT], double (&vl)[EPT]) {
@@ -967,7 +991,7 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
   int ca[EPT], cb[EPT], na[EPT], nb[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
 #pragma unroll
     for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
     ca[q] = (i < n) ? Ccol[i] : 0;
@@ -982,7 +1006,7 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
       const bool pn = qa + 3 < rec.N;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        const int i = tid + kEpiThreads * q;
+        const int i = tid + NT * q;
         na[q] = (i < n) ? Ca[i] : 0;
         nb[q] = (i < n && pn) ? Ca[P + i] : 0;
       }
@@ -1048,20 +1072,20 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
   }
 }
 
-template <int EPT, bool CRT>
+template <int EPT, bool CRT, int NT = kEpiThreads>
 __device__ __forceinline__ void epi_v_body(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
     int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
     const int *__restrict__ gate, int bx) {
-  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  __shared__ double scratch[2 * (NT / 64)];
   if (gate && *gate == 0) return;
   const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
-      const int i = tid + kEpiThreads * q;
+      const int i = tid + NT * q;
       if (i < npad)
         for (int t = 0; t < kr; ++t) Rpl[t * P + kb_off(j, i, npad)] = 0;
     }
@@ -1075,7 +1099,7 @@ __device__ __forceinline__ void epi_v_body(
   int eiq[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     vh[q] = vl[q] = 0.0;
     eiq[q] = (i < n) ? eA[i] + ej : 0;
   }
@@ -1085,14 +1109,14 @@ __device__ __forceinline__ void epi_v_body(
     int sc[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
-    crt_column<EPT>((const int8_t *)C + (size_t)j * npad, P, n, tid, rec, sc, vh, vl);
+    crt_column<EPT, NT>((const int8_t *)C + (size_t)j * npad, P, n, tid, rec, sc, vh, vl);
   } else {
   // slice sum, smallest scale first; diagonals outermost, and the next diagonal's values
   // are loaded while this one is summed, so each thread keeps 2 EPT loads in flight
   int32_t cv[EPT], cn[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
   }
 #pragma unroll 1
@@ -1101,7 +1125,7 @@ __device__ __forceinline__ void epi_v_body(
       const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        const int i = tid + kEpiThreads * q;
+        const int i = tid + NT * q;
         cn[q] = (i < n) ? Cn[i] : 0;
       }
     }
@@ -1120,7 +1144,7 @@ __device__ __forceinline__ void epi_v_body(
   ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     if (i < n) {
       fast_two_sum(vh[q], vl[q], vh[q], vl[q]);
       const double x = xcol[i];
@@ -1131,8 +1155,8 @@ __device__ __forceinline__ void epi_v_body(
       sv = dd_add_prod(sv, p, pe + x * vl[q]);
     }
   }
-  sx = block_dd_sum<kEpiThreads>(sx, scratch);
-  sv = block_dd_sum<kEpiThreads>(sv, scratch);
+  sx = block_dd_sum<NT>(sx, scratch);
+  sv = block_dd_sum<NT>(sv, scratch);
   // r_j = 1 - x^T x,  lambda_j = x^T v / (1 - r_j)
   ddv rj = dd_add(ddv{1.0, 0.0}, ddv{-sx.h, -sx.l});
   ddv den = dd_add(ddv{1.0, 0.0}, ddv{-rj.h, -rj.l});
@@ -1142,7 +1166,7 @@ __device__ __forceinline__ void epi_v_body(
   double rmax = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     if (i < n) {
       double p, pe, s, e;
       const double x = xcol[i];
@@ -1153,11 +1177,11 @@ __device__ __forceinline__ void epi_v_body(
       rmax = fmax(rmax, fabs(res));
     }
   }
-  rmax = block_max<kEpiThreads>(rmax, scratch);
+  rmax = block_max<NT>(rmax, scratch);
   const int er = exp_above(rmax);
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     if (i < npad) {
       const double a = (i < n) ? vh[q] : 0.0;
       double y = ldexp(fabs(a), -er);
@@ -1180,22 +1204,23 @@ __device__ __forceinline__ void epi_v_body(
   }
 }
 
-template <int EPT, bool CRT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_v(
+template <int EPT, bool CRT, int NT>
+__global__ __launch_bounds__(NT) void k_epi_v(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eA, const int *__restrict__ eX, const double *__restrict__ X1, int n,
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
     int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
     const int *__restrict__ gate) {
-  epi_v_body<EPT, CRT>(C, npad, d_min, ndiag_all, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, recs, vblk, gate, blockIdx.x);
+  epi_v_body<EPT, CRT, NT>(C, npad, d_min, ndiag_all, dcut, eA, eX, X1, n, lam, lam_lo, r, eR,
+                           resmax, Rpl, kr, flags, recs, vblk, gate, blockIdx.x);
 }
 
-template <int EPT>
+template <int EPT, int NT>
 static void epi_v_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                     int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s,
                     const int *gate) {
-  hipLaunchKernelGGL((k_epi_v<EPT, false>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min,
+  hipLaunchKernelGGL((k_epi_v<EPT, false, NT>), dim3(npad), dim3(NT), 0, s, C, npad, d_min,
                      ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags,
                      (const CrtRec *)nullptr, (const int *)nullptr, gate);
 }
@@ -1204,15 +1229,11 @@ void launch_epi_v_crt(const int32_t *C, int npad, const CrtRec *recs, const int 
                       const int *eA, const int *eX, const double *X1, int n, double *lam,
                       double *lam_lo, double *r, int *eR, double *resmax, int8_t *Rpl, int kr,
                       int *flags, hipStream_t s, const int *gate) {
-  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-#define EPI_V_CRT(E)                                                                          \
-  hipLaunchKernelGGL((k_epi_v<E, true>), dim3(npad), dim3(kEpiThreads), 0, s, C, npad, 2, 1,   \
+#define EPI_V_CRT(E, T)                                                                       \
+  hipLaunchKernelGGL((k_epi_v<E, true, T>), dim3(npad), dim3(T), 0, s, C, npad, 2, 1,          \
                      (const int *)nullptr, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr,  \
                      flags, recs, vblk, gate)
-  if (ept <= 1) EPI_V_CRT(1);
-  else if (ept <= 2) EPI_V_CRT(2);
-  else if (ept <= 4) EPI_V_CRT(4);
-  else EPI_V_CRT(8);
+  EPI_DISPATCH(npad, EPI_V_CRT);
 #undef EPI_V_CRT
 }
 
@@ -1282,11 +1303,11 @@ void launch_epi_v(const int32_t *C, int npad, int d_min, int ndiag, const int *d
                   const int *eA, const int *eX, const double *X1, int n, double *lam, double *lam_lo, double *r,
                   int *eR, double *resmax, int8_t *Rpl, int kr, int *flags, hipStream_t s,
                   const int *gate) {
-  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_v_t<1>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
-  else if (ept <= 2) epi_v_t<2>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
-  else if (ept <= 4) epi_v_t<4>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
-  else epi_v_t<8>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, flags, s, gate);
+#define EPI_V(E, T)                                                                          \
+  epi_v_t<E, T>(C, npad, d_min, ndiag, dcut, eA, eX, X1, n, lam, lam_lo, r, eR, resmax, Rpl, kr, \
+                flags, s, gate)
+  EPI_DISPATCH(npad, EPI_V);
+#undef EPI_V
 }
 
 // Slots of W entry (i, j) that hold diagonals to sum: up to the column's cutoff dcut[j] or,
@@ -1398,19 +1419,19 @@ void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const 
 }
 
 // ---------------------------------------------------------------- W epilogue -> E~
-template <int EPT>
+template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void epi_w_body(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
     double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
     int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut, int bx) {
-  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  __shared__ double scratch[2 * (NT / 64)];
   const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   if (j >= n) {
     for (int q = 0; q < EPT; ++q) {
-      const int i = tid + kEpiThreads * q;
+      const int i = tid + NT * q;
       if (i < npad)
         for (int t = 0; t < ke; ++t) Epl[t * P + kb_off(j, i, npad)] = 0;
     }
@@ -1425,7 +1446,7 @@ __device__ __forceinline__ void epi_w_body(
   int eiq[EPT], ndq[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     wq[q] = 0.0;
     eiq[q] = (i < n) ? eX[i] + ej : 0;
     ndq[q] = w_ndiag(dcut, tcut, T, ndiag_all, d_min, i, j);
@@ -1434,7 +1455,7 @@ __device__ __forceinline__ void epi_w_body(
   int32_t cv[EPT], cn[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
   }
 #pragma unroll 1
@@ -1443,7 +1464,7 @@ __device__ __forceinline__ void epi_w_body(
       const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        const int i = tid + kEpiThreads * q;
+        const int i = tid + NT * q;
         cn[q] = (i < n) ? Cn[i] : 0;
       }
     }
@@ -1457,7 +1478,7 @@ __device__ __forceinline__ void epi_w_body(
   int tie = 0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = tid + NT * q;
     ev[q] = 0.0;
     if (i < n) {
       const int ei = eX[i];
@@ -1488,9 +1509,9 @@ __device__ __forceinline__ void epi_w_body(
     }
   }
   if (tie) atomicOr(flags, FLAG_TIE);
-  ms = block_max<kEpiThreads>(ms, scratch);
-  mr = block_max<kEpiThreads>(mr, scratch);
-  write_col_planes<EPT>(ev, ms, j, npad, Epl, ke);
+  ms = block_max<NT>(ms, scratch);
+  mr = block_max<NT>(mr, scratch);
+  write_col_planes<EPT, NT>(ev, ms, j, npad, Epl, ke);
   if (tid == 0) {
     eE[j] = exp_above(ms);
     emax[j] = mr;
@@ -1498,23 +1519,24 @@ __device__ __forceinline__ void epi_w_body(
   }
 }
 
-template <int EPT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_w(
+template <int EPT, int NT>
+__global__ __launch_bounds__(NT) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
     double *emax, int8_t *__restrict__ Epl, int ke, int *flags, double tau, int *cpl_count,
     int *cpl_pairs, int cpl_cap, const int *__restrict__ tcut) {
-  epi_w_body<EPT>(C, npad, d_min, ndiag_all, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, blockIdx.x);
+  epi_w_body<EPT, NT>(C, npad, d_min, ndiag_all, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl,
+                      ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, blockIdx.x);
 }
 
-template <int EPT>
+template <int EPT, int NT>
 static void epi_w_t(const int32_t *C, int npad, int d_min, int ndiag, const int *dcut,
                     const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n,
                     int *eE, double *emax, int8_t *Epl, int ke, int *flags, double tau,
                     int *cpl_count, int *cpl_pairs, int cpl_cap, const int *tcut,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_w<EPT>, dim3(npad), dim3(kEpiThreads), 0, s, C, npad, d_min, ndiag, dcut,
+  hipLaunchKernelGGL((k_epi_w<EPT, NT>), dim3(npad), dim3(NT), 0, s, C, npad, d_min, ndiag, dcut,
                      eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs,
                      cpl_cap, tcut);
 }
@@ -1523,11 +1545,11 @@ void launch_epi_w(const int32_t *C, int npad, int d_min, int ndiag, const int *d
                   const int *eX, const int *eR, const double *lam, const double *lam_lo, const double *r, int n, int *eE,
                   double *emax, int8_t *Epl, int ke, int *flags, hipStream_t s, double tau,
                   int *cpl_count, int *cpl_pairs, int cpl_cap, const int *tcut) {
-  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  if (ept <= 1) epi_w_t<1>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
-  else if (ept <= 2) epi_w_t<2>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
-  else if (ept <= 4) epi_w_t<4>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
-  else epi_w_t<8>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, tau, cpl_count, cpl_pairs, cpl_cap, tcut, s);
+#define EPI_W(E, T)                                                                          \
+  epi_w_t<E, T>(C, npad, d_min, ndiag, dcut, eX, eR, lam, lam_lo, r, n, eE, emax, Epl, ke, flags, \
+                tau, cpl_count, cpl_pairs, cpl_cap, tcut, s)
+  EPI_DISPATCH(npad, EPI_W);
+#undef EPI_W
 }
 
 // ---------------------------------------------------------------- grouped correction
@@ -2231,19 +2253,19 @@ __global__ __launch_bounds__(256) void k_split_g(const GProb *__restrict__ gp, i
   }
 }
 
-template <int EPT, bool CRT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_v_g(const GProb *__restrict__ gp, int first,
+template <int EPT, bool CRT, int NT>
+__global__ __launch_bounds__(NT) void k_epi_v_g(const GProb *__restrict__ gp, int first,
                                                          int bpp) {
   const GProb &q = gp[first + blockIdx.x / bpp];
   const int j = blockIdx.x % bpp;
   DevState *st = q.pb.st;
   if (st->skip) return;
   if constexpr (CRT)
-    epi_v_body<EPT, true>(q.w.Cs, q.npad, 2, 1, nullptr, q.w.eA, q.w.eX, q.w.X1, q.n, q.w.lam,
+    epi_v_body<EPT, true, NT>(q.w.Cs, q.npad, 2, 1, nullptr, q.w.eA, q.w.eX, q.w.X1, q.n, q.w.lam,
                           q.w.lam_lo, q.w.r, q.w.eR, q.w.resmax, q.w.RP, kKrMax, q.w.flags,
                           st->recs, q.w.vblk, &st->vres, j);
   else
-    epi_v_body<EPT, false>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[0], q.w.eA, q.w.eX, q.w.X1,
+    epi_v_body<EPT, false, NT>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[0], q.w.eA, q.w.eX, q.w.X1,
                            q.n, q.w.lam, q.w.lam_lo, q.w.r, q.w.eR, q.w.resmax, q.w.RP, kKrMax,
                            q.w.flags, nullptr, nullptr, &st->vslice, j);
 }
@@ -2258,12 +2280,12 @@ __global__ __launch_bounds__(256) void k_tile_cutoffs_g(const GProb *__restrict_
                     blockIdx.x % bpp);
 }
 
-template <int EPT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_w_g(const GProb *__restrict__ gp, int first,
+template <int EPT, int NT>
+__global__ __launch_bounds__(NT) void k_epi_w_g(const GProb *__restrict__ gp, int first,
                                                          int bpp) {
   const GProb &q = gp[first + blockIdx.x / bpp];
   if (q.pb.st->skip) return;
-  epi_w_body<EPT>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[1], q.w.eX, q.w.eR, q.w.lam,
+  epi_w_body<EPT, NT>(q.w.Cs, q.npad, 2, kMaxDiag - 1, q.w.dcut[1], q.w.eX, q.w.eR, q.w.lam,
                   q.w.lam_lo, q.w.r, q.n, q.w.eE, q.w.emax, q.w.EP, kKeMax, q.w.flags, 0.0,
                   nullptr, nullptr, 0, q.npad >= 1024 ? q.w.tcut : nullptr, blockIdx.x % bpp);
 }
@@ -2327,13 +2349,13 @@ __global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ g
     if (threadIdx.x == 1023) off[1024] = base_off + before + v;
     __syncthreads();
     const int chunk = min(1024, count - base);
-    for (int kk = 0; kk < chunk; ++kk) {
+    for (int kk = wv; kk < chunk; kk += 16) {   // one problem per wavefront at a time
       const GProb &q = gp[first + base + kk];
       const int o0 = off[kk], cnt = off[kk + 1] - o0;
       const int g = first + base + kk;
       if (which == 0) {
         const int TT = q.npad / tile;
-        for (int e = threadIdx.x; e < cnt; e += 1024) {
+        for (int e = lane; e < cnt; e += 64) {
           const int ni = e % TT;
           int r = e / TT, mi = 0;
           for (; mi < TT; ++mi) {
@@ -2345,7 +2367,7 @@ __global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ g
         }
       } else {
         const int *tab = q.w.tab[which - 1];
-        for (int e = threadIdx.x; e < cnt; e += 1024) items[o0 + e] = make_int2(g, tab[e]);
+        for (int e = lane; e < cnt; e += 64) items[o0 + e] = make_int2(g, tab[e]);
       }
     }
     base_off = off[1024];
@@ -2425,17 +2447,14 @@ void launch_split_g(const GProb *gp, int first, int count, int npad, bool of_x, 
     hipLaunchKernelGGL(k_split_g<false>, dim3(count * gx * gx), dim3(256), 0, s, gp, first, gx);
 }
 void launch_epi_v_g(const GProb *gp, int first, int count, int npad, bool crt, hipStream_t s) {
-  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  const dim3 grid(count * npad), blk(kEpiThreads);
-#define EPI_V_G(E)                                                                            \
-  do {                                                                                        \
-    if (crt) hipLaunchKernelGGL((k_epi_v_g<E, true>), grid, blk, 0, s, gp, first, npad);      \
-    else hipLaunchKernelGGL((k_epi_v_g<E, false>), grid, blk, 0, s, gp, first, npad);         \
+  const dim3 grid(count * npad);
+#define EPI_V_G(E, T)                                                                            \
+  do {                                                                                           \
+    if (crt) hipLaunchKernelGGL((k_epi_v_g<E, true, T>), grid, dim3(T), 0, s, gp, first, npad);  \
+    else hipLaunchKernelGGL((k_epi_v_g<E, false, T>), grid, dim3(T), 0, s, gp, first, npad);     \
   } while (0)
   // grouped batches hold npad <= kGroupMaxNpad (4 entries per thread at most)
-  if (ept <= 1) EPI_V_G(1);
-  else if (ept <= 2) EPI_V_G(2);
-  else EPI_V_G(4);
+  EPI_DISPATCH_G(npad, EPI_V_G);
 #undef EPI_V_G
 }
 void launch_tile_cutoffs_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
@@ -2443,11 +2462,10 @@ void launch_tile_cutoffs_g(const GProb *gp, int first, int count, int npad, hipS
                      npad / 256);
 }
 void launch_epi_w_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
-  const int ept = (npad + kEpiThreads - 1) / kEpiThreads;
-  const dim3 grid(count * npad), blk(kEpiThreads);
-  if (ept <= 1) hipLaunchKernelGGL(k_epi_w_g<1>, grid, blk, 0, s, gp, first, npad);
-  else if (ept <= 2) hipLaunchKernelGGL(k_epi_w_g<2>, grid, blk, 0, s, gp, first, npad);
-  else hipLaunchKernelGGL(k_epi_w_g<4>, grid, blk, 0, s, gp, first, npad);
+  const dim3 grid(count * npad);
+#define EPI_W_G(E, T) hipLaunchKernelGGL((k_epi_w_g<E, T>), grid, dim3(T), 0, s, gp, first, npad)
+  EPI_DISPATCH_G(npad, EPI_W_G);
+#undef EPI_W_G
 }
 void launch_epi_u_g(const GProb *gp, int first, int count, int npad, hipStream_t s) {
   const int gx = npad / 256;

@@ -136,6 +136,8 @@ size_t carve(int n, int ka, char *base, Work *w, bool crt = false) {
   t.emax = (double *)take(vd);
   t.dst = (DevState *)take(sizeof(DevState));
   t.gapsw = (double *)take(vd);
+  t.skey = (double *)take(vd);
+  t.sidx = (int *)take(vi);
   if (w) *w = t;
   return off;
 }
@@ -1249,6 +1251,8 @@ PlanBufs plan_bufs(const Work &w, const double *D) {
   pb.tcut = w.npad >= 1024 ? w.tcut : nullptr;
   pb.flags = w.flags;
   pb.mods = w.mods;
+  pb.skey = w.skey;
+  pb.sidx = w.sidx;
   return pb;
 }
 

@@ -41,6 +41,8 @@ struct Work {
   double *mxA, *mxX, *lam, *lam_lo, *r, *resmax, *emax;
   DevState *dst;   // device planning state
   double *gapsw;   // entry gaps in working order (device planning)
+  double *skey;    // the last W plan's Rayleigh quotients in ascending order (device planning)
+  int *sidx;       // ... and the column of each
 };
 
 // One problem of a grouped batch (device memory, one entry per problem). pp.it is not used:
