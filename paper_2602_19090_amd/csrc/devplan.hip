@@ -57,58 +57,90 @@ __device__ __forceinline__ int pow2_at_least(int n) {
 }
 
 // Bitonic sort of N2 (a power of two, <= kDevSortMax) entries (key, aux) ascending by (key,
-// aux), in LDS. Entry i belongs to thread i mod kPT; the exchanges at distance j < 64 pair
-// lanes of one wavefront and run in registers (shuffles, no barrier), the longer ones in LDS.
-template <typename K>
-__device__ void bitonic(K *key, int *aux, int N2) {
-  constexpr int R = kDevSortMax / kPT;
+// aux), in LDS. Entry i belongs to thread i mod kPT (R = N2 / kPT entries per thread, at
+// least 1). The exchanges at distance j < 64 pair lanes of one wavefront and run in registers
+// (shuffles, no barrier); the longer ones go through LDS, each thread loading all its pairs
+// before it compares and stores them, so the R independent exchanges overlap.
+template <typename K, int R>
+__device__ void bitonic_r(K *key, int *aux, int N2) {
   const int lane = threadIdx.x & 63;
   for (int k = 2; k <= N2; k <<= 1) {
     int j = k >> 1;
     for (; j >= 64; j >>= 1) {
       __syncthreads();
-      for (int i = threadIdx.x; i < N2; i += kPT) {
-        const int l = i ^ j;
-        if (l > i) {
+      K a[R], bv[R];
+      int ia[R], ib[R];
+      bool act[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + r * kPT, l = i ^ j;
+        act[r] = i < N2 && l > i;
+        if (act[r]) {
+          a[r] = key[i];
+          bv[r] = key[l];
+          ia[r] = aux[i];
+          ib[r] = aux[l];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + r * kPT, l = i ^ j;
+        if (act[r]) {
           const bool up = (i & k) == 0;
-          const K a = key[i], b = key[l];
-          const int ia = aux[i], ib = aux[l];
-          const bool gt = (a > b) || (a == b && ia > ib);
+          const bool gt = (a[r] > bv[r]) || (a[r] == bv[r] && ia[r] > ib[r]);
           if (gt == up) {
-            key[i] = b;
-            key[l] = a;
-            aux[i] = ib;
-            aux[l] = ia;
+            key[i] = bv[r];
+            key[l] = a[r];
+            aux[i] = ib[r];
+            aux[l] = ia[r];
           }
         }
       }
     }
     __syncthreads();
+    K a[R];
+    int ia[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = threadIdx.x + r * kPT;
-      if (r * kPT >= N2) break;   // uniform over the block
-      K a = i < N2 ? key[i] : K(0);
-      int ia = i < N2 ? aux[i] : 0;
-      const bool up = (i & k) == 0;
-      for (int jj = j; jj > 0; jj >>= 1) {
-        const K b = __shfl_xor(a, jj);
-        const int ib = __shfl_xor(ia, jj);
-        const bool low = (lane & jj) == 0;   // this entry is the pair's lower index
+      a[r] = i < N2 ? key[i] : K(0);
+      ia[r] = i < N2 ? aux[i] : 0;
+    }
+    for (int jj = j; jj > 0; jj >>= 1) {
+      const bool low = (lane & jj) == 0;   // this entry is the pair's lower index
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + r * kPT;
+        const bool up = (i & k) == 0;
+        const K b = __shfl_xor(a[r], jj);
+        const int ib = __shfl_xor(ia[r], jj);
         // the pair (lower, upper) is out of order when lower > upper
-        const bool gt = low ? ((a > b) || (a == b && ia > ib)) : ((b > a) || (b == a && ib > ia));
+        const bool gt = low ? ((a[r] > b) || (a[r] == b && ia[r] > ib))
+                            : ((b > a[r]) || (b == a[r] && ib > ia[r]));
         if (gt == up) {
-          a = b;
-          ia = ib;
+          a[r] = b;
+          ia[r] = ib;
         }
       }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * kPT;
       if (i < N2) {
-        key[i] = a;
-        aux[i] = ia;
+        key[i] = a[r];
+        aux[i] = ia[r];
       }
     }
   }
   __syncthreads();
+}
+template <typename K>
+__device__ void bitonic(K *key, int *aux, int N2) {
+  static_assert(kDevSortMax == 8 * kPT, "entries per thread: 1, 2, 4 or 8");
+  if (N2 <= kPT) bitonic_r<K, 1>(key, aux, N2);
+  else if (N2 <= 2 * kPT) bitonic_r<K, 2>(key, aux, N2);
+  else if (N2 <= 4 * kPT) bitonic_r<K, 4>(key, aux, N2);
+  else bitonic_r<K, 8>(key, aux, N2);
 }
 
 // Block table of a tabled slice-GEMM launch from each tile's last diagonal dt[J] (LDS, ntile
@@ -437,7 +469,10 @@ __device__ __forceinline__ void dp_vplan_body(PlanParams p, PlanBufs b) {
   if (threadIdx.x == 0) s_ok = 0;
   __syncthreads();
   if (p.crt) {
+    __shared__ double lgm[kCrtMax];   // log2 of each modulus
     for (int q = threadIdx.x; q < nb; q += kPT) kab[q] = 1;
+    if (threadIdx.x >= 64 && threadIdx.x < 64 + kCrtMax)
+      lgm[threadIdx.x - 64] = plan_log2((double)modulus(threadIdx.x - 64));
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += kPT)
       if (b.mxX[j] != 0.0)
@@ -463,7 +498,7 @@ __device__ __forceinline__ void dp_vplan_body(PlanParams p, PlanBufs b) {
         st.ka_l[l] = ka_l[l];
         st.N_l[l] = 0;
         if (ka_l[l] > 0) {
-          const int N = crt_count(crt_need_bits(npad, ka_l[l], kx, hbits));
+          const int N = crt_count_lg(crt_need_bits(npad, ka_l[l], kx, hbits), lgm);
           if (N < 0 || ka_l[l] > kCrtPlanes || kx > kCrtPlanes) ok = 0;
           else st.N_l[l] = N;
         }
@@ -620,12 +655,13 @@ __device__ __forceinline__ void dp_wplan_body(PlanParams p, PlanBufs b) {
   }
   if (!(gm > 0.0) && threadIdx.x == 0) atomicOr(b.flags, FLAG_GAP);
   __syncthreads();
+  const double cw0 = cut_w_c0(st.eXmax, kx, p.lsqn);
   for (int j = threadIdx.x; j < npad; j += kPT) {
     if (j < n) {
       const double g = b.wtol[npad + j];
       b.wtol[j] = w_tight(p.delta_int, g, lm, p.theta, p.delta_k);
       dcol[j] = b.resmax[j] != 0.0
-                    ? cut_w(st.eXmax, kx, p.lsqn, b.eR[j], p.theta, p.delta_k, g, p.d_extra)
+                    ? cut_w_from(cw0, b.eR[j], p.theta, p.delta_k, g, p.d_extra)
                     : 2;
     } else {
       dcol[j] = 2;
@@ -669,12 +705,11 @@ __device__ __forceinline__ void dp_uplan_body(PlanParams p, PlanBufs b) {
   DevIter &rep = st.rep[p.it < 32 ? p.it : 31];
   const int n = p.n, npad = p.npad, kx = st.kx;
   double eps = 0.0;
+  const double cu0 = cut_u_c0(kx, p.lsqn, p.theta, p.delta_k);
   for (int j = threadIdx.x; j < npad; j += kPT) {
     if (j < n) {
       eps = fmax(eps, b.emax[j]);
-      dcol[j] = b.emax[j] != 0.0
-                    ? cut_u(kx, p.lsqn, b.eE[j], p.theta, p.delta_k, b.wtol[j], p.d_extra)
-                    : 2;
+      dcol[j] = b.emax[j] != 0.0 ? cut_u_from(cu0, b.eE[j], b.wtol[j], p.d_extra) : 2;
     } else {
       dcol[j] = 2;
     }
@@ -745,22 +780,14 @@ __global__ __launch_bounds__(kPT) void k_dp_uplan(PlanParams p, PlanBufs b) {
 }
 
 // ---------------------------------------------------------------- residue planes
-__device__ __forceinline__ void residues_dev_body(const int8_t *__restrict__ planes,
-                                                  size_t pstride, size_t count,
-                                                  const ResWeights *__restrict__ w,
-                                                  int8_t *__restrict__ res,
-                                                  const int *__restrict__ gate, int bid, int nblk) {
-  if (gate && *gate == 0) return;
-  constexpr int G = (kCrtPlanes + 3) / 4;
-  __shared__ int swp[kCrtMax][G];
-  __shared__ float sm[kCrtMax], srm[kCrtMax];
-  const int K = w->k, N = w->N;
-  for (int q = threadIdx.x; q < kCrtMax * G; q += 256) swp[q / G][q % G] = w->wp[q / G][q % G];
-  for (int q = threadIdx.x; q < kCrtMax; q += 256) {
-    sm[q] = (float)w->m[q];
-    srm[q] = w->rmf[q];
-  }
-  __syncthreads();
+// G: groups of four digit planes (K <= 4 G), a template so that the loads and the byte dot
+// products of absent groups are not issued.
+template <int G>
+__device__ __forceinline__ void residues_dev_loop(const int8_t *__restrict__ planes,
+                                                  size_t pstride, size_t count, int K, int N,
+                                                  const int (*swp)[(kCrtPlanes + 3) / 4],
+                                                  const float *sm, const float *srm,
+                                                  int8_t *__restrict__ res, int bid, int nblk) {
   for (size_t e = ((size_t)bid * 256 + threadIdx.x) * 4; e < count;
        e += (size_t)nblk * 256 * 4) {
     unsigned v[4 * G];
@@ -790,6 +817,32 @@ __device__ __forceinline__ void residues_dev_body(const int8_t *__restrict__ pla
       }
       *(unsigned *)(res + (size_t)q * pstride + e) = packed;
     }
+  }
+}
+
+__device__ __forceinline__ void residues_dev_body(const int8_t *__restrict__ planes,
+                                                  size_t pstride, size_t count,
+                                                  const ResWeights *__restrict__ w,
+                                                  int8_t *__restrict__ res,
+                                                  const int *__restrict__ gate, int bid, int nblk) {
+  if (gate && *gate == 0) return;
+  constexpr int G = (kCrtPlanes + 3) / 4;
+  __shared__ int swp[kCrtMax][G];
+  __shared__ float sm[kCrtMax], srm[kCrtMax];
+  const int K = w->k, N = w->N;
+  for (int q = threadIdx.x; q < kCrtMax * G; q += 256) swp[q / G][q % G] = w->wp[q / G][q % G];
+  for (int q = threadIdx.x; q < kCrtMax; q += 256) {
+    sm[q] = (float)w->m[q];
+    srm[q] = w->rmf[q];
+  }
+  __syncthreads();
+  static_assert(G == 5, "digit planes up to 18: groups 1..5");
+  switch ((K + 3) / 4) {
+    case 1: residues_dev_loop<1>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
+    case 2: residues_dev_loop<2>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
+    case 3: residues_dev_loop<3>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
+    case 4: residues_dev_loop<4>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
+    default: residues_dev_loop<5>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
   }
 }
 
@@ -909,7 +962,7 @@ void launch_dp_uplan_g(const GProb *gp, int first, int count, int it, hipStream_
 void launch_residues_g(const GProb *gp, int first, int count, size_t P, int which,
                        hipStream_t s) {
   size_t bpp = (P / 4 + 255) / 256;
-  if (bpp > 1024) bpp = 1024;
+  if (bpp > 2048) bpp = 2048;
   hipLaunchKernelGGL(k_residues_g, dim3((unsigned)(count * bpp)), dim3(256), 0, s, gp, first,
                      (int)bpp, which);
 }
@@ -942,7 +995,7 @@ void launch_residues_dev(const int8_t *planes, size_t pstride, size_t count, con
                          int8_t *res, const int *gate, hipStream_t s) {
   const size_t quads = count / 4;
   size_t blocks = (quads + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
+  if (blocks > 2048) blocks = 2048;
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_residues_dev, dim3((unsigned)blocks), dim3(256), 0, s, planes, pstride,
                      count, w, res, gate);

@@ -987,51 +987,63 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
   // F = sum_t c_t U_t mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |c_t| < 2^15, so
   // c_t L[t][k] is an integer below 2^49 and at most 14 of them sum below 2^52.9: every limb
   // sum is exact. Truncating U_t to 136 bits moves F by at most 14 2^15 2^-136 = 2^-117.2.
+  // the record's per-term constants, staged in LDS (every thread reads all of them)
+  constexpr int kT = kCrtMax / 2 + 1;
+  __shared__ double sL[kT * kCrtLimbs];
+  __shared__ float sma[kT], smb[kT], sinv[kT], srmb[kT];
+  for (int e = threadIdx.x; e < kT * kCrtLimbs; e += NT) sL[e] = rec.L[e / kCrtLimbs][e % kCrtLimbs];
+  for (int e = threadIdx.x; e < kCrtMax / 2; e += NT) {
+    sma[e] = rec.pma[e];
+    smb[e] = rec.pmb[e];
+    sinv[e] = rec.pinv[e];
+    srmb[e] = rec.prmb[e];
+  }
+  const int T = rec.T, N = rec.N;
+  __syncthreads();
   double a[EPT][kCrtLimbs];
-  int ca[EPT], cb[EPT], na[EPT], nb[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
+  for (int q = 0; q < EPT; ++q)
 #pragma unroll
     for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
-    ca[q] = (i < n) ? Ccol[i] : 0;
-    cb[q] = (i < n && rec.N > 1) ? Ccol[P + i] : 0;
-  }
+  // the slots are loaded kPD terms at a time (all of them when a thread holds one entry), so
+  // each thread keeps up to 2 kPD EPT loads in flight; the terms are added in order
+  constexpr int kPD = EPT >= 8 ? 1 : (16 / EPT < kCrtMax / 2 ? 16 / EPT : kCrtMax / 2);
 #pragma unroll 1
-  for (int t = 0; t < rec.T; ++t) {
-    const int qa = 2 * t, qb = 2 * t + 1;   // qb == N: a single last slot
-    const bool pair = qb < rec.N;
-    if (t + 1 < rec.T) {   // next term's slots
-      const int8_t *Ca = Ccol + (size_t)(qa + 2) * P;
-      const bool pn = qa + 3 < rec.N;
+  for (int t0 = 0; t0 < T; t0 += kPD) {
+    int ca[kPD][EPT], cb[kPD][EPT];
+#pragma unroll
+    for (int u = 0; u < kPD; ++u) {
+      const int t = t0 + u;
+      const int8_t *Ca = Ccol + (size_t)(2 * t) * P;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int i = tid + NT * q;
-        na[q] = (i < n) ? Ca[i] : 0;
-        nb[q] = (i < n && pn) ? Ca[P + i] : 0;
+        ca[u][q] = (t < T && i < n) ? Ca[i] : 0;
+        cb[u][q] = (t < T && 2 * t + 1 < N && i < n) ? Ca[P + i] : 0;
       }
     }
-    double L[kCrtLimbs];
 #pragma unroll
-    for (int k = 0; k < kCrtLimbs; ++k) L[k] = rec.L[t][k];
-    const float ma = pair ? rec.pma[t] : 0.0f, mb = pair ? rec.pmb[t] : 1.0f;
-    const float inv = pair ? rec.pinv[t] : 0.0f, rmb = pair ? rec.prmb[t] : 0.0f;
+    for (int u = 0; u < kPD; ++u) {
+      const int t = t0 + u;
+      if (t >= T) break;
+      const bool pair = 2 * t + 1 < N;   // else a single last slot
+      double L[kCrtLimbs];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15
-      double rq = (double)ca[q];
-      if (pair) {
-        const float d = (float)(cb[q] - ca[q]) * inv;   // |d| < 2^16, exact
-        const float tt = d - mb * rintf(d * rmb);
-        rq = (double)ca[q] + (double)ma * (double)tt;
+      for (int k = 0; k < kCrtLimbs; ++k) L[k] = sL[t * kCrtLimbs + k];
+      const float ma = pair ? sma[t] : 0.0f, mb = pair ? smb[t] : 1.0f;
+      const float inv = pair ? sinv[t] : 0.0f, rmb = pair ? srmb[t] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15
+        double rq = (double)ca[u][q];
+        if (pair) {
+          const float d = (float)(cb[u][q] - ca[u][q]) * inv;   // |d| < 2^16, exact
+          const float tt = d - mb * rintf(d * rmb);
+          rq = (double)ca[u][q] + (double)ma * (double)tt;
+        }
+#pragma unroll
+        for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
       }
-#pragma unroll
-      for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
-    }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      ca[q] = na[q];
-      cb[q] = nb[q];
     }
   }
   static_assert(kCrtLimbs == 4 && kCrtLimbBits == 34, "limb scales below are written for 4 x 34");
@@ -1111,34 +1123,62 @@ __device__ __forceinline__ void epi_v_body(
     for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
     crt_column<EPT, NT>((const int8_t *)C + (size_t)j * npad, P, n, tid, rec, sc, vh, vl);
   } else {
-  // slice sum, smallest scale first; diagonals outermost, and the next diagonal's values
-  // are loaded while this one is summed, so each thread keeps 2 EPT loads in flight
-  int32_t cv[EPT], cn[EPT];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
-    cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
-  }
-#pragma unroll 1
-  for (int qq = ndiag - 1; qq >= 0; --qq) {
-    if (qq > 0) {
-      const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = tid + NT * q;
-        cn[q] = (i < n) ? Cn[i] : 0;
-      }
-    }
+  // slice sum, smallest scale first; with few entries per thread the diagonals' values are
+  // loaded kPD at a time, with many the next diagonal is loaded while this one is summed
+  if constexpr (EPT >= 4) {
+    int32_t cv[EPT], cn[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const double tv = ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
-      double s, e;
-      two_sum(vh[q], tv, s, e);
-      vh[q] = s;
-      vl[q] += e;
+      const int i = tid + NT * q;
+      cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
     }
+#pragma unroll 1
+    for (int qq = ndiag - 1; qq >= 0; --qq) {
+      if (qq > 0) {
+        const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+        for (int q = 0; q < EPT; ++q) {
+          const int i = tid + NT * q;
+          cn[q] = (i < n) ? Cn[i] : 0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const double tv = ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+        double s, e;
+        two_sum(vh[q], tv, s, e);
+        vh[q] = s;
+        vl[q] += e;
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+    }
+  } else {
+  constexpr int kPD = 16 / EPT;
+#pragma unroll 1
+  for (int c0 = ndiag - 1; c0 >= 0; c0 -= kPD) {
+    int32_t cv[kPD][EPT];
+#pragma unroll
+    for (int u = 0; u < kPD; ++u)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int i = tid + NT * q, qq = c0 - u;
+        cv[u][q] = (qq >= 0 && i < n) ? Ccol[(size_t)qq * P + i] : 0;
+      }
+#pragma unroll
+    for (int u = 0; u < kPD; ++u) {
+      const int qq = c0 - u;
+      if (qq < 0) break;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const double tv = ldexp((double)cv[u][q], eiq[q] - 7 * (d_min + qq));
+        double s, e;
+        two_sum(vh[q], tv, s, e);
+        vh[q] = s;
+        vl[q] += e;
+      }
+    }
+  }
   }
   }
   ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
@@ -1451,28 +1491,52 @@ __device__ __forceinline__ void epi_w_body(
     eiq[q] = (i < n) ? eX[i] + ej : 0;
     ndq[q] = w_ndiag(dcut, tcut, T, ndiag_all, d_min, i, j);
   }
-  // as in the V epilogue: the next diagonal is loaded while this one is summed
-  int32_t cv[EPT], cn[EPT];
+  // as in the V epilogue: with few entries per thread the diagonals' values are loaded kPD
+  // at a time; with many, the next diagonal is loaded while this one is summed
+  if constexpr (EPT >= 4) {
+    int32_t cv[EPT], cn[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
-    cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
-  }
+    for (int q = 0; q < EPT; ++q) {
+      const int i = tid + NT * q;
+      cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
+    }
 #pragma unroll 1
-  for (int qq = ndiag - 1; qq >= 0; --qq) {
-    if (qq > 0) {
-      const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
+    for (int qq = ndiag - 1; qq >= 0; --qq) {
+      if (qq > 0) {
+        const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const int i = tid + NT * q;
+          cn[q] = (i < n) ? Cn[i] : 0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+    }
+  } else {
+  constexpr int kPD = 16 / EPT;
+#pragma unroll 1
+  for (int c0 = ndiag - 1; c0 >= 0; c0 -= kPD) {
+    int32_t cv[kPD][EPT];
+#pragma unroll
+    for (int u = 0; u < kPD; ++u)
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        const int i = tid + NT * q;
-        cn[q] = (i < n) ? Cn[i] : 0;
+        const int i = tid + NT * q, qq = c0 - u;
+        cv[u][q] = (qq >= 0 && i < n) ? Ccol[(size_t)qq * P + i] : 0;
       }
+#pragma unroll
+    for (int u = 0; u < kPD; ++u) {
+      const int qq = c0 - u;
+      if (qq < 0) break;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        if (qq < ndq[q]) wq[q] += ldexp((double)cv[u][q], eiq[q] - 7 * (d_min + qq));
     }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q)
-      if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+  }
   }
   double ms = 0.0, mr = 0.0;
   int tie = 0;
@@ -1711,9 +1775,19 @@ __device__ __forceinline__ void epi_u_body(const int32_t *__restrict__ C, int np
   const int32_t *Ccol = C + (size_t)j * npad;
   const int ej = eE[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
+  // the diagonals' values loaded 16 at a time, added smallest scale first
   double u = 0.0;
-  for (int qq = ndiag - 1; qq >= 0; --qq)
-    u += ldexp((double)Ccol[(size_t)qq * P + i], ej - 7 * (d_min + qq));
+#pragma unroll 1
+  for (int c0 = ndiag - 1; c0 >= 0; c0 -= 16) {
+    int32_t cv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cv[k] = c0 - k >= 0 ? Ccol[(size_t)(c0 - k) * P + i] : 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (c0 - k < 0) break;
+      u += ldexp((double)cv[k], ej - 7 * (d_min + c0 - k));
+    }
+  }
   X[(size_t)(colmap ? colmap[j] : j) * ldx + i] = X1[(size_t)j * n + i] + u;
 }
 

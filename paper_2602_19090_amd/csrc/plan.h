@@ -110,25 +110,36 @@ RF_HD int cut_ka(int eA_max, double lgrowth, int eXj, double theta, double delta
   const double nd = ((double)eA_max + lgrowth + (double)eXj - plan_log2(theta * delta * g)) / 7.0;
   return (int)ceil(nd) + dextra;
 }
-// W = X^(1)T Res, column j (eR_j the residual column's exponent).
-RF_HD int cut_w(int eXmax, int kx, double lsqn, int eRj, double theta, double delta, double g,
-                int dextra) {
-  const double c0 = (double)eXmax + 7.0 + plan_log2(1.5 * kx) + lsqn;
+// W = X^(1)T Res, column j (eR_j the residual column's exponent); the column-independent
+// part c0 = cut_w_c0(...) may be formed once per iteration.
+RF_HD double cut_w_c0(int eXmax, int kx, double lsqn) {
+  return (double)eXmax + 7.0 + plan_log2(1.5 * kx) + lsqn;
+}
+RF_HD int cut_w_from(double c0, int eRj, double theta, double delta, double g, int dextra) {
   const double need = (c0 + (double)eRj - plan_log2(theta * delta * g)) / 7.0;
   const int d = (int)ceil(need) + dextra;
   return d > 2 ? d : 2;
+}
+RF_HD int cut_w(int eXmax, int kx, double lsqn, int eRj, double theta, double delta, double g,
+                int dextra) {
+  return cut_w_from(cut_w_c0(eXmax, kx, lsqn), eRj, theta, delta, g, dextra);
 }
 // The per-tile W cutoff's constant: 7 + log2(1.5 kx) + lsqn - log2(theta delta).
 RF_HD double cx_tile(int kx, double lsqn, double theta, double delta) {
   return 7.0 + plan_log2(1.5 * kx) + lsqn - plan_log2(theta * delta);
 }
 // X^(1) E~, column j (eE_j the exponent of E~'s column, t_j its noise tightening).
-RF_HD int cut_u(int kx, double lsqn, int eEj, double theta, double delta, double tj,
-                int dextra) {
-  const double c0 = 7.0 + plan_log2(1.008 * kx) + lsqn - plan_log2(theta * delta);
+RF_HD double cut_u_c0(int kx, double lsqn, double theta, double delta) {
+  return 7.0 + plan_log2(1.008 * kx) + lsqn - plan_log2(theta * delta);
+}
+RF_HD int cut_u_from(double c0, int eEj, double tj, int dextra) {
   const double need = (c0 + (double)eEj - plan_log2(tj)) / 7.0;
   const int d = (int)ceil(need) + dextra;
   return d > 2 ? d : 2;
+}
+RF_HD int cut_u(int kx, double lsqn, int eEj, double theta, double delta, double tj,
+                int dextra) {
+  return cut_u_from(cut_u_c0(kx, lsqn, theta, delta), eEj, tj, dextra);
 }
 // Noise tightening of column j (the reading of the paper's cut bound for loose targets):
 // t_j = min(1, sqrt(delta_int g_j / (4 L)) / (theta delta_k)).
@@ -143,6 +154,13 @@ RF_HD int crt_count(double need_bits) {
   double bits = 0.0;
   int N = 0;
   while (N < kCrtMax && bits <= need_bits) bits += plan_log2((double)modulus(N++));
+  return bits > need_bits ? N : -1;
+}
+// The same with lg[q] = plan_log2(modulus(q)) given (the same sums in the same order).
+RF_HD int crt_count_lg(double need_bits, const double *lg) {
+  double bits = 0.0;
+  int N = 0;
+  while (N < kCrtMax && bits <= need_bits) bits += lg[N++];
   return bits > need_bits ? N : -1;
 }
 // Bits the moduli must exceed for ka1 digits of A, kx of X^(1), reduction length npad and
