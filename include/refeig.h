@@ -225,25 +225,55 @@ int refine_eigvecs_herm(const double *A, int lda, double *X, int ldx, double *D,
                         double target_fwd_err, const refeig_opts *o, void *work,
                         size_t work_bytes, refeig_stream_t stream, refeig_report *report);
 
-/* Batched form of refine_eigvecs for `count` independent problems (the
- * serving and many-small-matrices workloads of Sec. 4's setting, one matrix
- * per request). Host arrays of length count hold each problem's order n[i],
- * device pointers A[i], X[i], D[i], leading dimensions and target_fwd_err[i];
- * o applies to all. Problems run concurrently on up to REFEIG_BATCH_LANES
- * internal streams, each with its own slice of the workspace; the caller's
- * stream is joined to them on entry and exit. Every problem's result is bit
- * for bit what refine_eigvecs returns for it alone. work: device buffer of
- * work_bytes >= refeig_batched_workspace_bytes, or NULL (the library allocates
- * and frees it). reports (host, count entries, may be NULL) receive each
- * problem's report and status. Returns REFEIG_OK when every problem did, else
- * the first negative per-problem status, else REFEIG_NOT_CONVERGED;
- * REFEIG_E_ARG for count < 1 or a NULL array. */
+/* Batched form of refine_eigvecs for `count` independent problems (the many-small-matrices
+ * workload, one matrix per problem). Host arrays of length count hold each problem's order
+ * n[i], device pointers A[i], X[i], D[i], leading dimensions and target_fwd_err[i]; o applies
+ * to all. With device planning (o->plan == 0, group_tau == 0, schedule == 0: the defaults) the
+ * solves advance together as a grouped batch: every step of an iteration is one launch per
+ * group of problems with equal padded order, and the three products run as persistent kernels
+ * over a device-built list of (problem, tile, slot) items. Problems run in chunks whose
+ * workspaces total at most 16 GiB (the environment variable REFEIG_GROUP_CHUNK_MIB, read at each
+ * call, overrides; the workspace query and the solve must see the same value); a problem whose
+ * padded order exceeds 4096 runs alone after the chunks. With other options the problems run
+ * concurrently on up to REFEIG_BATCH_LANES internal streams, each with its own slice of the
+ * workspace. Either way every problem's result is bit for bit what refine_eigvecs returns for it
+ * alone. work: device buffer of work_bytes >= refeig_batched_workspace_bytes(count, n, o), or
+ * NULL (the library allocates and frees it). reports (host, count entries, may be NULL) receive
+ * each problem's report and status (a grouped problem's ms_total is its chunk's wall time and
+ * its per-iteration times are not taken). Returns REFEIG_OK when every problem did, else the
+ * first negative per-problem status, else REFEIG_NOT_CONVERGED; REFEIG_E_ARG for count < 1 or a
+ * NULL array (a problem with bad arguments of its own gets REFEIG_E_ARG in its report). */
 #define REFEIG_BATCH_LANES 8
 int refeig_batched_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes);
 int refine_eigvecs_batched(int count, const int *n, const double *const *A, const int *lda,
                            double *const *X, const int *ldx, double *const *D,
                            const double *target_fwd_err, const refeig_opts *o, void *work,
                            size_t work_bytes, refeig_stream_t stream, refeig_report *reports);
+
+/* A grouped batch captured once in a HIP graph and replayed, for callers that refine batches of
+ * the same shapes again and again (fixed_iters > 0 and device planning: grouped execution as
+ * refine_eigvecs_batched, in one chunk; every padded order at most 4096). refeig_batch_create
+ * (synchronous) carves the problems' workspaces from work (device, work_bytes >=
+ * refeig_batch_workspace_bytes), uploads their descriptors and captures every launch of the solve
+ * (all fixed_iters iterations) on an internal stream into a HIP graph; the arrays it takes are
+ * those of refine_eigvecs_batched and the device buffers must stay allocated, at the same
+ * addresses, until refeig_batch_destroy. refeig_batch_launch replays the graph on `stream` (NULL =
+ * default): X and D are refined in place from whatever they hold when the replay runs, so the
+ * caller rewrites them between replays (on that stream) to refine new data. refeig_batch_results
+ * waits for the last replay and fills status[count] and reports (host, may be NULL); it returns
+ * REFEIG_OK when every problem did, else the first negative status, else REFEIG_NOT_CONVERGED.
+ * Each replay's results are bit for bit those of refine_eigvecs_batched (and of single calls).
+ * REFEIG_E_ARG: options outside the above, bad arguments; REFEIG_E_NOMEM: work too small;
+ * REFEIG_E_HIP: the capture or instantiation failed. Replays of one batch must not overlap. */
+typedef struct refeig_batch refeig_batch;
+int refeig_batch_workspace_bytes(int count, const int *n, const refeig_opts *o, size_t *bytes);
+int refeig_batch_create(int count, const int *n, const double *const *A, const int *lda,
+                        double *const *X, const int *ldx, double *const *D,
+                        const double *target_fwd_err, const refeig_opts *o, void *work,
+                        size_t work_bytes, refeig_batch **batch);
+int refeig_batch_launch(refeig_batch *batch, refeig_stream_t stream);
+int refeig_batch_results(refeig_batch *batch, int *status, refeig_report *reports);
+int refeig_batch_destroy(refeig_batch *batch);
 
 const char *refeig_strerror(int status);
 

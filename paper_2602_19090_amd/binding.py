@@ -118,6 +118,13 @@ _lib.refeig_batched_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts),
 _lib.refine_eigvecs_batched.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.POINTER(Opts), _vp, _sz, _vp, _vp]
 
+_lib.refeig_batch_workspace_bytes.argtypes = [_int, _vp, ctypes.POINTER(Opts), ctypes.POINTER(_sz)]
+_lib.refeig_batch_create.argtypes = [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     ctypes.POINTER(Opts), _vp, _sz, ctypes.POINTER(_vp)]
+_lib.refeig_batch_launch.argtypes = [_vp, _vp]
+_lib.refeig_batch_results.argtypes = [_vp, _vp, _vp]
+_lib.refeig_batch_destroy.argtypes = [_vp]
+
 _lib.refeig_row_nonzeros.argtypes = [_vp, _int, _int, _vp, ctypes.POINTER(_int)]
 _lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                                   ctypes.POINTER(_int), ctypes.POINTER(_int)]
@@ -135,6 +142,8 @@ EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "
             "refeig_server_create", "refeig_server_submit", "refeig_server_wait",
             "refeig_server_destroy", "refeig_server_request_bytes", "refeig_host_admission_sim",
             "refine_eigvecs_batched", "refeig_read_report", "refeig_host_beta",
+            "refeig_batch_workspace_bytes", "refeig_batch_create", "refeig_batch_launch",
+            "refeig_batch_results", "refeig_batch_destroy",
             "refeig_host_column_order",
             "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
@@ -286,6 +295,65 @@ def refine_eigvecs_batched(As, Xs, Ds, targets, opts: Opts | None = None, work=N
                                      ctypes.byref(opts) if opts is not None else None, _ptr(work),
                                      wb, _stream(stream), c(reps))
     return st, list(reps)
+
+
+def batch_workspace_bytes(ns, opts: Opts | None = None) -> int:
+    arr = (ctypes.c_int * len(ns))(*[int(v) for v in ns])
+    out = _sz(0)
+    st = _lib.refeig_batch_workspace_bytes(len(ns), ctypes.cast(arr, _vp),
+                                           ctypes.byref(opts) if opts is not None else None,
+                                           ctypes.byref(out))
+    if st != 0:
+        raise ValueError(strerror(st))
+    return out.value
+
+
+class Batch:
+    """A grouped batch captured in a HIP graph (refeig_batch_*): created once over lists of
+    (A, X, D) tensors (as refine_eigvecs_batched; fixed_iters > 0), replayed with launch(),
+    results() -> (status, [status per problem], [report per problem]). The tensors and the
+    workspace are kept alive by this object until close()."""
+
+    def __init__(self, As, Xs, Ds, targets, opts: Opts, work=None):
+        import torch
+        count = len(As)
+        assert len(Xs) == len(Ds) == len(targets) == count
+        ns = [D.numel() for D in Ds]
+        for A, X, n in zip(As, Xs, ns):
+            assert A.is_cuda and X.is_cuda and A.is_contiguous() and X.is_contiguous()
+            assert tuple(A.shape) == (n, n) and tuple(X.shape) == (n, n)
+        if work is None:
+            work = torch.empty(batch_workspace_bytes(ns, opts), dtype=torch.uint8, device="cuda")
+        self._keep = (list(As), list(Xs), list(Ds), work)
+        ci, cp = ctypes.c_int * count, ctypes.c_void_p * count
+        self._n = ci(*ns)
+        A_a, X_a, D_a = (cp(*[t.data_ptr() for t in ts]) for ts in (As, Xs, Ds))
+        t_a = (ctypes.c_double * count)(*[float(t) for t in targets])
+        c = lambda a: ctypes.cast(a, _vp)
+        self._h = _vp()
+        self.count = count
+        st = _lib.refeig_batch_create(count, c(self._n), c(A_a), c(self._n), c(X_a), c(self._n),
+                                      c(D_a), c(t_a), ctypes.byref(opts), _ptr(work),
+                                      work.numel() * work.element_size(), ctypes.byref(self._h))
+        if st != 0:
+            raise ValueError(strerror(st))
+
+    def launch(self, stream=None):
+        st = _lib.refeig_batch_launch(self._h, _stream(stream))
+        if st != 0:
+            raise RuntimeError(strerror(st))
+
+    def results(self):
+        sts = (ctypes.c_int * self.count)()
+        reps = (Report * self.count)()
+        st = _lib.refeig_batch_results(self._h, ctypes.cast(sts, _vp), ctypes.cast(reps, _vp))
+        return st, list(sts), list(reps)
+
+    def close(self):
+        if self._h:
+            _lib.refeig_batch_destroy(self._h)
+            self._h = _vp()
+            self._keep = None
 
 
 class Server:

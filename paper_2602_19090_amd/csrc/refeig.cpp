@@ -1468,20 +1468,32 @@ size_t grouped_bytes(int count, const int *n, const refeig_opts &o) {
 }
 
 // One chunk of a grouped batch: problems ids (npad descending, all <= kGroupMaxNpad), their
-// workspaces carved from `region`. Fills status[] and reports (may be null) of its problems.
-int run_chunk(const std::vector<int> &ids, const int *n, const double *const *A, const int *lda,
-              double *const *X, const int *ldx, double *const *D, const double *target,
-              const refeig_opts &o, const GroupArea &ga, char *region, hipStream_t s,
-              refeig_report *reports, std::vector<int> &status) {
-  const int G = (int)ids.size();
+// workspaces carved from `region`. prepare_chunk fills the host descriptors and the launch
+// shapes, enqueue_chunk enqueues the solve (with fixed iterations it never waits, so it can be
+// captured), collect_chunk gathers the planning states and fills statuses and reports.
+struct ChunkPlan {
+  struct Cls {
+    int first, count, npad;
+  };
+  std::vector<int> ids;
+  std::vector<GProb> hp;   // host copy of the descriptors (uploaded to ga.gp)
+  std::vector<Cls> cls;
+  int G = 0, g256 = 0, blocks256 = 0, blocks128 = 0;
+  size_t cap256 = 0;
+};
+
+void prepare_chunk(ChunkPlan &cp, const std::vector<int> &ids, const int *n,
+                   const double *const *A, const int *lda, double *const *X, const int *ldx,
+                   double *const *D, const double *target, const refeig_opts &o, char *region) {
+  cp.ids = ids;
+  cp.G = (int)ids.size();
   const int ka_max = ka_of(&o);
   const bool crt = o.vmode == 1;
-  auto t_start = std::chrono::steady_clock::now();
-  std::vector<GProb> hp(G);
+  cp.hp.assign(cp.G, GProb());
   size_t off = 0;
-  for (int k = 0; k < G; ++k) {
+  for (int k = 0; k < cp.G; ++k) {
     const int i = ids[k];
-    GProb &q = hp[k];
+    GProb &q = cp.hp[k];
     carve(n[i], ka_max, region + off, &q.w, crt);
     off += ws_rounded(n[i], o);
     q.A = A[i];
@@ -1496,114 +1508,146 @@ int run_chunk(const std::vector<int> &ids, const int *n, const double *const *A,
     q.pp = plan_params(n[i], q.npad, o, target[i]);
     q.pb = plan_bufs(q.w, D[i]);
   }
-  // size classes (runs of equal npad) and the two tile groups (256-row tiles first)
-  struct Cls {
-    int first, count, npad;
-  };
-  std::vector<Cls> cls;
-  for (int k = 0; k < G; ++k) {
-    if (cls.empty() || cls.back().npad != hp[k].npad) cls.push_back({k, 0, hp[k].npad});
-    ++cls.back().count;
+  cp.cls.clear();
+  for (int k = 0; k < cp.G; ++k) {
+    if (cp.cls.empty() || cp.cls.back().npad != cp.hp[k].npad)
+      cp.cls.push_back({k, 0, cp.hp[k].npad});
+    ++cp.cls.back().count;
   }
-  int g256 = 0;
-  size_t cap256 = 0, cap128 = 0;
-  for (int k = 0; k < G; ++k) {
-    if (gemm_tile_rows(hp[k].npad) == 256) {
-      ++g256;
-      cap256 += item_cap(hp[k].n);
+  size_t cap128 = 0;
+  cp.g256 = 0;
+  cp.cap256 = 0;
+  for (int k = 0; k < cp.G; ++k) {
+    if (gemm_tile_rows(cp.hp[k].npad) == 256) {
+      ++cp.g256;
+      cp.cap256 += item_cap(cp.hp[k].n);
     } else {
-      cap128 += item_cap(hp[k].n);
+      cap128 += item_cap(cp.hp[k].n);
     }
   }
-  int2 *items256 = ga.items, *items128 = ga.items + cap256;
-  const int blocks256 = (int)std::min<size_t>(256, cap256);
-  const int blocks128 = (int)std::min<size_t>(512, cap128);
+  cp.blocks256 = (int)std::min<size_t>(256, cp.cap256);
+  cp.blocks128 = (int)std::min<size_t>(512, cap128);
+}
+
+// Enqueues iterations it0 .. it1 - 1 (it0 == 0 also enqueues the once-per-solve steps); with
+// gather, the planning states are gathered into ga.stage at the end.
+void enqueue_chunk(const ChunkPlan &cp, const GroupArea &ga, const refeig_opts &o, int it0,
+                   int it1, bool gather, hipStream_t s) {
   const GProb *gp = ga.gp;
-  auto fail = [&](int st) {
-    (void)hipStreamSynchronize(s);   // nothing in flight reads hp after this returns
-    for (int k = 0; k < G; ++k) status[ids[k]] = st;
-    return st;
-  };
-  if (hipMemcpyAsync(ga.gp, hp.data(), sizeof(GProb) * G, hipMemcpyHostToDevice, s) != hipSuccess)
-    return fail(REFEIG_E_HIP);
+  const int G = cp.G, g256 = cp.g256;
+  int2 *items256 = ga.items, *items128 = ga.items + cp.cap256;
   auto products = [&](int which) {
     if (g256) {
       launch_worklist_g(gp, 0, g256, which, 256, items256, ga.cnt, ga.cnt + 1, s);
-      launch_gemm_g(gp, 256, blocks256, items256, ga.cnt, ga.cnt + 1, which, s);
+      launch_gemm_g(gp, 256, cp.blocks256, items256, ga.cnt, ga.cnt + 1, which, s);
     }
     if (G > g256) {
       launch_worklist_g(gp, g256, G - g256, which, 128, items128, ga.cnt + 2, ga.cnt + 3, s);
-      launch_gemm_g(gp, 128, blocks128, items128, ga.cnt + 2, ga.cnt + 3, which, s);
+      launch_gemm_g(gp, 128, cp.blocks128, items128, ga.cnt + 2, ga.cnt + 3, which, s);
     }
   };
-  // once per solve: A's column statistics, the planning state, A's digit planes
-  launch_flags_clear_g(gp, G, s);
-  for (const Cls &c : cls) {
-    launch_colstats_g(gp, c.first, c.count, c.npad, false, s);
-    launch_dp_init_g(gp, c.first, c.count, s);
-    launch_split_g(gp, c.first, c.count, c.npad, false, s);
+  if (it0 == 0) {   // once per solve: A's column statistics, the planning state, A's planes
+    launch_flags_clear_g(gp, G, s);
+    for (const auto &c : cp.cls) {
+      launch_colstats_g(gp, c.first, c.count, c.npad, false, s);
+      launch_dp_init_g(gp, c.first, c.count, s);
+      launch_split_g(gp, c.first, c.count, c.npad, false, s);
+    }
   }
-  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
-  for (int it = 0; it < iters; ++it) {
-    for (const Cls &c : cls) launch_dp_order_g(gp, c.first, c.count, it, s);
-    for (const Cls &c : cls) launch_colstats_g(gp, c.first, c.count, c.npad, true, s);
-    for (const Cls &c : cls) launch_dp_vplan_g(gp, c.first, c.count, it, s);
-    for (const Cls &c : cls) launch_split_g(gp, c.first, c.count, c.npad, true, s);
-    if (crt) {
-      for (const Cls &c : cls)
+  for (int it = it0; it < it1; ++it) {
+    for (const auto &c : cp.cls) launch_dp_order_g(gp, c.first, c.count, it, s);
+    for (const auto &c : cp.cls) launch_colstats_g(gp, c.first, c.count, c.npad, true, s);
+    for (const auto &c : cp.cls) launch_dp_vplan_g(gp, c.first, c.count, it, s);
+    for (const auto &c : cp.cls) launch_split_g(gp, c.first, c.count, c.npad, true, s);
+    if (o.vmode == 1) {
+      for (const auto &c : cp.cls)
         for (int l = 0; l <= kVLevels; ++l)
           launch_residues_g(gp, c.first, c.count, (size_t)c.npad * c.npad, l, s);
       products(0);
-      for (const Cls &c : cls) launch_epi_v_g(gp, c.first, c.count, c.npad, true, s);
+      for (const auto &c : cp.cls) launch_epi_v_g(gp, c.first, c.count, c.npad, true, s);
     }
     products(1);
-    for (const Cls &c : cls) launch_epi_v_g(gp, c.first, c.count, c.npad, false, s);
-    for (const Cls &c : cls) launch_dp_wplan_g(gp, c.first, c.count, it, s);
-    for (const Cls &c : cls)
+    for (const auto &c : cp.cls) launch_epi_v_g(gp, c.first, c.count, c.npad, false, s);
+    for (const auto &c : cp.cls) launch_dp_wplan_g(gp, c.first, c.count, it, s);
+    for (const auto &c : cp.cls)
       if (c.npad >= 1024) launch_tile_cutoffs_g(gp, c.first, c.count, c.npad, s);
     products(2);
-    for (const Cls &c : cls) launch_epi_w_g(gp, c.first, c.count, c.npad, s);
-    for (const Cls &c : cls) launch_dp_uplan_g(gp, c.first, c.count, it, s);
+    for (const auto &c : cp.cls) launch_epi_w_g(gp, c.first, c.count, c.npad, s);
+    for (const auto &c : cp.cls) launch_dp_uplan_g(gp, c.first, c.count, it, s);
     products(3);
-    for (const Cls &c : cls) launch_epi_u_g(gp, c.first, c.count, c.npad, s);
-    for (const Cls &c : cls) launch_scatter_g(gp, c.first, c.count, c.npad, s);
-    if (hipGetLastError() != hipSuccess) return fail(REFEIG_E_HIP);
-    if (o.fixed_iters <= 0 && it + 1 < iters) {   // stop once every solve has stopped
-      int running = 0;
-      launch_count_running_g(gp, G, ga.cnt + 4, s);
-      if (hipMemcpyAsync(&running, ga.cnt + 4, sizeof(int), hipMemcpyDeviceToHost, s) !=
-              hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return fail(REFEIG_E_HIP);
-      if (running == 0) break;
-    }
+    for (const auto &c : cp.cls) launch_epi_u_g(gp, c.first, c.count, c.npad, s);
+    for (const auto &c : cp.cls) launch_scatter_g(gp, c.first, c.count, c.npad, s);
   }
+  if (gather) launch_gather_state_g(gp, G, ga.stage, stage_stride(), s);
+}
+
+// Statuses and reports from ga.stage (filled by enqueue_chunk's gather; the caller has waited).
+int collect_chunk(const ChunkPlan &cp, const GroupArea &ga, double ms, refeig_report *reports,
+                  int *status) {
   const size_t stride = stage_stride();
-  std::vector<char> stage(stride * G);
-  launch_gather_state_g(gp, G, ga.stage, stride, s);
-  if (hipGetLastError() != hipSuccess ||
-      hipMemcpyAsync(stage.data(), ga.stage, stride * G, hipMemcpyDeviceToHost, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail(REFEIG_E_HIP);
-  const double ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
-          .count();
-  for (int k = 0; k < G; ++k) {
+  std::vector<char> stage(stride * cp.G);
+  if (hipMemcpy(stage.data(), ga.stage, stride * cp.G, hipMemcpyDeviceToHost) != hipSuccess)
+    return REFEIG_E_HIP;
+  for (int k = 0; k < cp.G; ++k) {
     DevState hst;
     int hflags = 0;
     std::memcpy(&hst, stage.data() + stride * k, sizeof(DevState));
     std::memcpy(&hflags, stage.data() + stride * k + sizeof(DevState), sizeof(int));
     const int st = status_of(hst, hflags);
-    status[ids[k]] = st;
+    status[cp.ids[k]] = st;
     if (reports) {
-      refeig_report *r = &reports[ids[k]];
-      fill_report_from_device(hst, hflags, iters, r);
+      refeig_report *r = &reports[cp.ids[k]];
+      std::memset(r, 0, sizeof(*r));
+      fill_report_from_device(hst, hflags, 0, r);
       r->status = st;
       r->ms_total = ms;   // the chunk's wall time (its solves run together)
     }
   }
   return REFEIG_OK;
+}
+
+int run_chunk(const std::vector<int> &ids, const int *n, const double *const *A, const int *lda,
+              double *const *X, const int *ldx, double *const *D, const double *target,
+              const refeig_opts &o, const GroupArea &ga, char *region, hipStream_t s,
+              refeig_report *reports, std::vector<int> &status) {
+  auto t_start = std::chrono::steady_clock::now();
+  ChunkPlan cp;
+  prepare_chunk(cp, ids, n, A, lda, X, ldx, D, target, o, region);
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);   // nothing in flight reads cp.hp after this returns
+    for (int k = 0; k < cp.G; ++k) status[ids[k]] = st;
+    return st;
+  };
+  if (hipMemcpyAsync(ga.gp, cp.hp.data(), sizeof(GProb) * cp.G, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return fail(REFEIG_E_HIP);
+  const int iters = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  if (o.fixed_iters > 0) {
+    enqueue_chunk(cp, ga, o, 0, iters, true, s);
+    if (hipGetLastError() != hipSuccess) return fail(REFEIG_E_HIP);
+  } else {
+    for (int it = 0; it < iters; ++it) {
+      enqueue_chunk(cp, ga, o, it, it + 1, false, s);
+      if (hipGetLastError() != hipSuccess) return fail(REFEIG_E_HIP);
+      if (it + 1 < iters) {   // stop once every solve has stopped
+        int running = 0;
+        launch_count_running_g(ga.gp, cp.G, ga.cnt + 4, s);
+        if (hipMemcpyAsync(&running, ga.cnt + 4, sizeof(int), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return fail(REFEIG_E_HIP);
+        if (running == 0) break;
+      }
+    }
+    launch_gather_state_g(ga.gp, cp.G, ga.stage, stage_stride(), s);
+  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(REFEIG_E_HIP);
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+          .count();
+  const int st = collect_chunk(cp, ga, ms, reports, status.data());
+  return st == REFEIG_OK ? REFEIG_OK : fail(st);
 }
 
 bool opts_valid(const refeig_opts &o) {
@@ -2654,6 +2698,124 @@ int refine_eigvecs_batched(int count, const int *n, const double *const *A, cons
     if (status[i] != REFEIG_OK) worst = status[i];
   }
   return worst;
+}
+
+
+// ---- a grouped batch captured once in a HIP graph and replayed
+struct refeig_batch {
+  int count = 0;
+  refeig_opts o;
+  ChunkPlan cp;
+  GroupArea ga;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+  bool launched = false;
+};
+
+static int batch_need(int count, const int *n, const refeig_opts &o, size_t *icap, size_t *sum) {
+  if (count < 1 || !n) return REFEIG_E_ARG;
+  if (!grouped_batch(o) || o.fixed_iters < 1 || !opts_valid(o)) return REFEIG_E_ARG;
+  *icap = 0;
+  *sum = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kMaxN || round_up(n[i], kTile) > kGroupMaxNpad) return REFEIG_E_ARG;
+    *icap += item_cap(n[i]);
+    *sum += ws_rounded(n[i], o);
+  }
+  return REFEIG_OK;
+}
+
+int refeig_batch_workspace_bytes(int count, const int *n, const refeig_opts *o_in,
+                                 size_t *bytes) {
+  refeig_opts o;
+  if (o_in) o = *o_in;
+  else refeig_default_opts(&o);
+  size_t icap = 0, sum = 0;
+  if (!bytes) return REFEIG_E_ARG;
+  const int st = batch_need(count, n, o, &icap, &sum);
+  if (st != REFEIG_OK) return st;
+  *bytes = group_area(count, icap, nullptr, nullptr) + sum;
+  return REFEIG_OK;
+}
+
+int refeig_batch_create(int count, const int *n, const double *const *A, const int *lda,
+                        double *const *X, const int *ldx, double *const *D,
+                        const double *target, const refeig_opts *o_in, void *work,
+                        size_t work_bytes, refeig_batch **out) {
+  if (!out) return REFEIG_E_ARG;
+  *out = nullptr;
+  refeig_opts o;
+  if (o_in) o = *o_in;
+  else refeig_default_opts(&o);
+  size_t icap = 0, sum = 0;
+  int st = batch_need(count, n, o, &icap, &sum);
+  if (st != REFEIG_OK) return st;
+  if (!A || !lda || !X || !ldx || !D || !target || !work) return REFEIG_E_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!A[i] || !X[i] || !D[i] || lda[i] < n[i] || ldx[i] < n[i] || !(target[i] > 0.0))
+      return REFEIG_E_ARG;
+  const size_t area = group_area(count, icap, nullptr, nullptr);
+  if (work_bytes < area + sum) return REFEIG_E_NOMEM;
+  std::vector<int> ids(count);
+  for (int i = 0; i < count; ++i) ids[i] = i;
+  std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+    return round_up(n[a], kTile) > round_up(n[b], kTile);
+  });
+  auto *b = new refeig_batch();
+  b->count = count;
+  b->o = o;
+  group_area(count, icap, (char *)work, &b->ga);
+  prepare_chunk(b->cp, ids, n, A, lda, X, ldx, D, target, o, (char *)work + area);
+  hipStream_t cs = nullptr;
+  bool ok = hipMemcpy(b->ga.gp, b->cp.hp.data(), sizeof(GProb) * b->cp.G,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    enqueue_chunk(b->cp, b->ga, o, 0, o.fixed_iters, true, cs);
+    ok = hipStreamEndCapture(cs, &b->graph) == hipSuccess &&
+         hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!ok) {
+    refeig_batch_destroy(b);
+    return REFEIG_E_HIP;
+  }
+  *out = b;
+  return REFEIG_OK;
+}
+
+int refeig_batch_launch(refeig_batch *b, refeig_stream_t stream) {
+  if (!b || !b->exec) return REFEIG_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipGraphLaunch(b->exec, s));
+  b->last = s;
+  b->launched = true;
+  return REFEIG_OK;
+}
+
+int refeig_batch_results(refeig_batch *b, int *status, refeig_report *reports) {
+  if (!b || !status || !b->launched) return REFEIG_E_ARG;
+  HIPCHK(hipStreamSynchronize(b->last));
+  std::vector<int> st(b->count, REFEIG_E_HIP);
+  const int r = collect_chunk(b->cp, b->ga, 0.0, reports, st.data());
+  if (r != REFEIG_OK) return r;
+  int worst = REFEIG_OK;
+  for (int i = 0; i < b->count; ++i) {
+    status[i] = st[i];
+    if (st[i] < 0 && worst >= 0) worst = st[i];
+    else if (st[i] != REFEIG_OK && worst == REFEIG_OK) worst = st[i];
+  }
+  return worst;
+}
+
+int refeig_batch_destroy(refeig_batch *b) {
+  if (!b) return REFEIG_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return REFEIG_OK;
 }
 
 }  // extern "C"

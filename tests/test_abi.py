@@ -91,3 +91,16 @@ def test_binding_lists_every_declared_symbol():
     """binding.EXPORTED names exactly the functions the header declares."""
     from paper_2602_19090_amd import binding as rb
     assert sorted(rb.EXPORTED) == _declared()
+
+
+def test_graph_batch_rejects_bad_options_without_a_gpu():
+    """refeig_batch_workspace_bytes is host-only: it refuses options the captured batch cannot
+    run (no fixed iteration count, host planning, a padded order above 4096)."""
+    from paper_2602_19090_amd import binding as rb
+    with pytest.raises(ValueError):
+        rb.batch_workspace_bytes([64, 100], rb.default_opts())
+    with pytest.raises(ValueError):
+        rb.batch_workspace_bytes([64, 100], rb.default_opts(fixed_iters=2, plan=1))
+    with pytest.raises(ValueError):
+        rb.batch_workspace_bytes([64, 4200], rb.default_opts(fixed_iters=2))
+    assert rb.batch_workspace_bytes([64, 100], rb.default_opts(fixed_iters=2)) > 0

@@ -123,3 +123,42 @@ def test_grouped_with_a_large_member_and_errors():
         assert r.status == s_st, (k, r.status, s_st)
         if s_st >= 0:
             assert np.array_equal(X.cpu().numpy(), Xs) and np.array_equal(D.cpu().numpy(), Ds)
+
+
+def test_graph_captured_batch_replays():
+    """A grouped batch captured once in a HIP graph (refeig_batch_*, 3 fixed iterations) and
+    replayed three times, its inputs rewritten by eager copies between the replays: every
+    replay gives bit for bit what refine_eigvecs_batched gives, statuses and plans included."""
+    import torch
+    rb = _rb()
+    probs, targets = _mix()
+    opts = rb.default_opts(fixed_iters=3)
+    ref = [_to_dev(p) for p in probs]
+    st, rreps = rb.refine_eigvecs_batched([d[0] for d in ref], [d[1] for d in ref],
+                                          [d[2] for d in ref], targets, opts)
+    torch.cuda.synchronize()
+    assert st == rb.REFEIG_OK
+    dev = [_to_dev(p) for p in probs]
+    X0 = [d[1].clone() for d in dev]
+    D0 = [d[2].clone() for d in dev]
+    print("batch workspace", rb.batch_workspace_bytes([p.n for p in probs], opts) >> 20, "MiB",
+          flush=True)
+    b = rb.Batch([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev], targets, opts)
+    try:
+        for rep in range(3):
+            for (A, X, D), x0, d0 in zip(dev, X0, D0):
+                X.copy_(x0)
+                D.copy_(d0)
+            torch.cuda.synchronize()
+            b.launch()
+            st, sts, reps = b.results()
+            assert st == rb.REFEIG_OK and all(s == rb.REFEIG_OK for s in sts), (rep, sts)
+            for k, ((A, X, D), (Ar, Xr, Dr), r, rr) in enumerate(zip(dev, ref, reps, rreps)):
+                assert r.iters == rr.iters == 3
+                assert list(r.beta[:3]) == list(rr.beta[:3]) and list(r.kx[:3]) == list(rr.kx[:3])
+                assert np.array_equal(X.cpu().numpy(), Xr.cpu().numpy()), (rep, k, probs[k].n)
+                assert np.array_equal(D.cpu().numpy(), Dr.cpu().numpy()), (rep, k, probs[k].n)
+            print(f"replay {rep + 1}: bit-identical", flush=True)
+    finally:
+        b.close()
+
