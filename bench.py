@@ -338,6 +338,7 @@ def config4_leg(count):
         assert st == rb.REFEIG_OK, rb.strerror(st)
         log(f"config 4 batch {rep + 1}: {times[-1] * 1e3:.1f} ms")
     t = float(np.median(times))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     X_last = [x.clone() for x in Xs]
     # the same batch captured once in a HIP graph and replayed (inputs rewritten between replays)
     graph = None
@@ -386,7 +387,9 @@ def config4_leg(count):
                          "achieved_padded": ops_pad / t / 1e12,
                          "frac_padded": ops_pad / t / 1e12 / INT8_PEAK_TOPS,
                          "note": "whole-batch time; ops = pair products x 2 n^3 (padded: npad^3)"},
-            "graph": graph}
+            "graph": graph,
+            "product_tiles": {str(m): rb.tile_cache_lookup(arch, m)[1]
+                              for m in sorted({-(-q.n // 256) * 256 for q in probs})}}
 
 
 def serve_leg(rates, nreq, pool_size=256, lanes=4, budget_gib=64.0):

@@ -351,6 +351,19 @@ int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA
 int refeig_host_admission_sim(int count, const double *t_arr, const size_t *bytes,
                               const double *dur, int lanes, size_t budget, double *t_start,
                               size_t *offset);
+/* Host-only: the product tile that grouped batches use for padded order npad on device
+ * architecture arch (e.g. "gfx950"), as the tile cache holds it. Grouped batches run orders
+ * from 1024 on the 256-row tile or, each entry of the 256-row plan split in four, on the
+ * 128-row tile; both give the same results. The first batch that meets an order times both on
+ * synthetic planes (in its own workspace) and records the faster in the cache, a JSON object
+ * {"<arch>:<npad>": tile} in the file REFEIG_TUNE_CACHE names (else
+ * $XDG_CACHE_HOME/refeig/tiles.json, else $HOME/.cache/refeig/tiles.json). REFEIG_TUNE=0 skips
+ * the timing (cached choice, else 256); REFEIG_TILE=128 or 256 fixes the tile for every order.
+ * *tile receives the cached tile (128 below npad 1024); returns REFEIG_OK when the cache holds
+ * the order, REFEIG_NOT_CONVERGED when it does not (*tile = 256, the default), REFEIG_E_ARG
+ * for bad arguments. */
+int refeig_tile_cache_lookup(const char *arch, int npad, int *tile);
+
 /* Working column order of an iteration: columns by the gap of their eigenvalue
  * estimate to its nearest neighbour, widest first, ties by eigenvalue.
  * order[p] = the column placed at working position p (host arrays of n). */

@@ -125,6 +125,7 @@ _lib.refeig_batch_launch.argtypes = [_vp, _vp]
 _lib.refeig_batch_results.argtypes = [_vp, _vp, _vp]
 _lib.refeig_batch_destroy.argtypes = [_vp]
 
+_lib.refeig_tile_cache_lookup.argtypes = [ctypes.c_char_p, _int, ctypes.POINTER(_int)]
 _lib.refeig_row_nonzeros.argtypes = [_vp, _int, _int, _vp, ctypes.POINTER(_int)]
 _lib.refeig_host_beta.argtypes = [_int, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                                   ctypes.POINTER(_int), ctypes.POINTER(_int)]
@@ -143,7 +144,7 @@ EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "
             "refeig_server_destroy", "refeig_server_request_bytes", "refeig_host_admission_sim",
             "refine_eigvecs_batched", "refeig_read_report", "refeig_host_beta",
             "refeig_batch_workspace_bytes", "refeig_batch_create", "refeig_batch_launch",
-            "refeig_batch_results", "refeig_batch_destroy",
+            "refeig_batch_results", "refeig_batch_destroy", "refeig_tile_cache_lookup",
             "refeig_host_column_order",
             "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
 
@@ -418,6 +419,15 @@ def host_admission_sim(t_arr, nbytes, dur, lanes: int, budget: int):
     st = _lib.refeig_host_admission_sim(len(t), _np_ptr(t), _np_ptr(b), _np_ptr(d), int(lanes),
                                         int(budget), _np_ptr(ts), _np_ptr(off))
     return st, ts, off
+
+
+def tile_cache_lookup(arch: str, npad: int):
+    """refeig_tile_cache_lookup: (cached, tile) for padded order npad on arch."""
+    t = _int(0)
+    st = _lib.refeig_tile_cache_lookup(arch.encode(), int(npad), ctypes.byref(t))
+    if st < 0:
+        raise ValueError(strerror(st))
+    return st == 0, t.value
 
 
 def row_nonzeros(A, stream=None) -> int:

@@ -2384,6 +2384,13 @@ __global__ __launch_bounds__(256) void k_scatter_g(const GProb *__restrict__ gp,
 // each): item = {problem, row tile | column tile << 8 | slot << 16}. which: 0 V by residues
 // (the slots below each 256-row block's modulus count, when V goes by residues), 1 V by slices,
 // 2 W, 3 X^(1) E~ (each problem's block table). One block; also resets the item counter.
+// A problem planned on 256-row tiles (npad >= 1024) and run on the 128-row tile splits each
+// block-table entry into its four 128-row quarters (split = 4); the slot values do not depend on
+// the tile, so the choice never changes a result.
+__device__ __forceinline__ int tab_split(const GProb &q, int tile) {
+  const int tr = q.npad >= 1024 ? 256 : 128;
+  return (tr / tile) * (tr / tile);
+}
 __device__ __forceinline__ int items_of(const GProb &q, int which, int tile) {
   const DevState &st = *q.pb.st;
   if (st.skip) return 0;
@@ -2394,7 +2401,7 @@ __device__ __forceinline__ int items_of(const GProb &q, int which, int tile) {
     for (int mi = 0; mi < TT; ++mi) c += q.w.vblk[2 * ((mi * tile) >> 8)];
     return c * TT;
   }
-  return (which == 1 ? st.gemm_v : which == 2 ? st.gemm_w : st.gemm_u)[2];
+  return (which == 1 ? st.gemm_v : which == 2 ? st.gemm_w : st.gemm_u)[2] * tab_split(q, tile);
 }
 
 __global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ gp, int first,
@@ -2441,7 +2448,15 @@ __global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ g
         }
       } else {
         const int *tab = q.w.tab[which - 1];
-        for (int e = lane; e < cnt; e += 64) items[o0 + e] = make_int2(g, tab[e]);
+        if (tab_split(q, tile) == 1) {
+          for (int e = lane; e < cnt; e += 64) items[o0 + e] = make_int2(g, tab[e]);
+        } else {
+          for (int e = lane; e < cnt; e += 64) {
+            const int ent = tab[e >> 2], sub = e & 3;
+            const int r = 2 * (ent & 0xff) + (sub & 1), c = 2 * ((ent >> 8) & 0xff) + (sub >> 1);
+            items[o0 + e] = make_int2(g, r | (c << 8) | ((ent >> 16) << 16));
+          }
+        }
       }
     }
     base_off = off[1024];
@@ -2500,13 +2515,32 @@ __global__ __launch_bounds__(256, TILE == 256 ? 1 : 2) void k_gemm_g(
       kl = st.gemm_u[0];
       kr = st.gemm_u[1];
     }
-    if constexpr (TILE == 256)
+    if constexpr (TILE == 256) {
       gemm256_item<false>(Lp, Rp, q.P, q.npad, q.npad, kl, kr, 2, q.w.Cs, same, tcut, mods, vblk,
                           m0, n0, slot);
-    else
+    } else {
+      // a quarter of a 256-row tile obeys that tile's W cutoff
+      if (tcut && 2 + slot > tcut[(m0 >> 8) * (q.npad >> 8) + (n0 >> 8)]) continue;
       gemm128_item(Lp, Rp, q.P, q.npad, q.npad, kl, kr, 2, q.w.Cs, same, mods, vblk, m0, n0,
                    slot);
+    }
   }
+}
+
+__global__ void k_fill_hash_i8(int8_t *__restrict__ p, size_t n, unsigned seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    unsigned h = (unsigned)i * 2654435761u ^ seed;   // multiplicative hash, then xorshift mixing
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = (int8_t)((int)(h % 255u) - 127);
+  }
+}
+void launch_fill_hash_i8(int8_t *p, size_t n, unsigned seed, hipStream_t s) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_fill_hash_i8, dim3((unsigned)blocks), dim3(256), 0, s, p, n, seed);
 }
 
 void launch_colstats_g(const GProb *gp, int first, int count, int npad, bool of_x, hipStream_t s) {

@@ -31,6 +31,11 @@
 #include <unordered_map>
 #include <queue>
 #include <map>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <thread>
 #include <time.h>
 #include <vector>
@@ -1425,8 +1430,8 @@ size_t ws_rounded(int n, const refeig_opts &o) {
   return (carve(n, ka_of(&o), nullptr, nullptr, o.vmode == 1) + 255) / 256 * 256;
 }
 // Work items a problem's products can ask for at most (tiles x slots).
-size_t item_cap(int n) {
-  const int npad = round_up(n, kTile), tt = npad / gemm_tile_rows(npad);
+size_t item_cap(int n) {   // on the 128-row tile, which bounds the 256-row one as well
+  const int tt = round_up(n, kTile) / 128;
   return (size_t)tt * tt * std::max(kCrtMax, kMaxDiag);
 }
 size_t stage_stride() { return (sizeof(DevState) + sizeof(int) + 255) / 256 * 256; }
@@ -1465,6 +1470,208 @@ size_t grouped_bytes(int count, const int *n, const refeig_opts &o) {
   }
   return group_area(count, icap, nullptr, nullptr) +
          std::min(sum, std::max(group_chunk_bytes(), mx));
+}
+
+// ---- product tile of grouped batches: the 256-row tile or, split in four, the 128-row one for
+// padded orders from 1024 (below 1024 the plan itself is on 128-row tiles). Either gives the
+// same results; the choice is timed once per padded order on synthetic planes and kept in an
+// on-disk cache (one JSON object, "<arch>:<npad>": tile), REFEIG_TUNE_CACHE naming the file
+// (else $XDG_CACHE_HOME/refeig/tiles.json, else $HOME/.cache/refeig/tiles.json).
+// REFEIG_TUNE=0 takes the cached choice or the 256-row default without timing anything.
+std::mutex g_tile_mu;
+std::map<std::string, int> g_tile;   // "<cache file>|<arch>:<npad>" -> tile, this process
+
+std::string tile_cache_path() {
+  const char *e = std::getenv("REFEIG_TUNE_CACHE");
+  if (e && *e) return e;
+  const char *x = std::getenv("XDG_CACHE_HOME");
+  const char *h = std::getenv("HOME");
+  std::string base = (x && *x) ? std::string(x) : (h && *h) ? std::string(h) + "/.cache" : "/tmp";
+  return base + "/refeig/tiles.json";
+}
+std::map<std::string, int> read_tile_cache(const std::string &path) {
+  std::map<std::string, int> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while ((i = t.find('"', i)) != std::string::npos) {   // "key": value pairs
+    const size_t j = t.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = t.substr(i + 1, j - i - 1);
+    size_t k = t.find(':', j);
+    if (k == std::string::npos) break;
+    const int v = std::atoi(t.c_str() + k + 1);
+    if (v == 128 || v == 256) out[key] = v;
+    i = j + 1;
+  }
+  return out;
+}
+void write_tile_cache(const std::string &path, const std::map<std::string, int> &m) {
+  for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
+    (void)mkdir(path.substr(0, p).c_str(), 0755);
+  const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+  {
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{";
+    bool first = true;
+    for (const auto &kv : m) {
+      f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": " << kv.second;
+      first = false;
+    }
+    f << "\n}\n";
+  }
+  (void)std::rename(tmp.c_str(), path.c_str());
+}
+std::string device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> known;   // device -> architecture name
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = known.find(d);
+  if (it != known.end()) return it->second;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, d) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  return known[d] = a.substr(0, a.find(':'));
+}
+std::string tile_key(int npad) {
+  return tile_cache_path() + "|" + device_arch() + ":" + std::to_string(npad);
+}
+int gtile_of(int npad) {
+  if (npad < 1024) return 128;
+  const char *f = std::getenv("REFEIG_TILE");   // 128 or 256: a fixed choice (A/B, tests)
+  if (f && (std::atoi(f) == 128 || std::atoi(f) == 256)) return std::atoi(f);
+  const std::string key = tile_key(npad);
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tile.find(key);
+  return it == g_tile.end() ? 256 : it->second;
+}
+
+// Time the W-type product of two synthetic problems of order npad (12 x 8 digit planes, all
+// tiles, slots 0..11) on both tiles; scratch: device memory the solve has not started to use.
+// Returns the faster tile, or 0 when the scratch is too small or a call failed.
+int time_tiles(int npad, char *scratch, size_t bytes, hipStream_t s) {
+  const size_t P = (size_t)npad * npad;
+  const int TT = npad / 256, nslot = 12, G = 2;
+  const int ntab = TT * TT * nslot;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char *p = scratch + off;
+    off += (b + 255) / 256 * 256;
+    return p;
+  };
+  int8_t *Lp = (int8_t *)take(P * 12), *Rp = (int8_t *)take(P * 8);
+  int32_t *Cs[G];
+  for (int g = 0; g < G; ++g) Cs[g] = (int32_t *)take(P * 4 * nslot);
+  int *tab = (int *)take(sizeof(int) * ntab);
+  int *tcut = (int *)take(sizeof(int) * TT * TT);
+  DevState *st = (DevState *)take(sizeof(DevState) * G);
+  GProb *gp = (GProb *)take(sizeof(GProb) * G);
+  int2 *items = (int2 *)take(sizeof(int2) * (size_t)ntab * 4 * G);
+  int *cnt = (int *)take(sizeof(int) * 4);
+  if (off > bytes) return 0;
+  std::vector<int> htab(ntab), htc(TT * TT, kMaxDiag + 1);
+  for (int q = 0, e = 0; q < nslot; ++q)
+    for (int r = 0; r < TT; ++r)
+      for (int c = 0; c < TT; ++c) htab[e++] = r | (c << 8) | (q << 16);
+  std::vector<DevState> hst(G);
+  std::memset(hst.data(), 0, sizeof(DevState) * G);
+  for (auto &d : hst) {
+    d.gemm_w[0] = kKrMax;
+    d.gemm_w[1] = 8;
+    d.gemm_w[2] = ntab;
+  }
+  std::vector<GProb> hp(G);
+  std::memset((void *)hp.data(), 0, sizeof(GProb) * G);
+  for (int g = 0; g < G; ++g) {
+    GProb &q = hp[g];
+    q.n = q.npad = npad;
+    q.P = P;
+    q.w.RP = Lp;
+    q.w.XP = Rp;
+    q.w.Cs = Cs[g];
+    q.w.tab[1] = tab;
+    q.w.tcut = tcut;
+    q.pb.st = st + g;
+  }
+  launch_fill_hash_i8(Lp, P * 12, 0x9e3779b9u, s);
+  launch_fill_hash_i8(Rp, P * 8, 0x7f4a7c15u, s);
+  if (hipMemcpyAsync(tab, htab.data(), sizeof(int) * ntab, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(tcut, htc.data(), sizeof(int) * TT * TT, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(st, hst.data(), sizeof(DevState) * G, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 0;
+  float best[2] = {1e30f, 1e30f};
+  const int tiles[2] = {256, 128};
+  bool ok = true;
+  for (int v = 0; v < 2 && ok; ++v) {
+    for (auto &q : hp) q.gtile = tiles[v];
+    ok = hipMemcpyAsync(gp, hp.data(), sizeof(GProb) * G, hipMemcpyHostToDevice, s) ==
+         hipSuccess;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+      launch_worklist_g(gp, 0, G, 2, tiles[v], items, cnt, cnt + 1, s);
+      ok = hipEventRecord(e0, s) == hipSuccess;
+      launch_gemm_g(gp, tiles[v], tiles[v] == 256 ? 256 : 512, items, cnt, cnt + 1, 2, s);
+      float ms = 0.0f;
+      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (ok) best[v] = std::min(best[v], ms);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok || hipStreamSynchronize(s) != hipSuccess) return 0;
+  return best[1] < best[0] ? 128 : 256;
+}
+
+// The tile of every padded order from 1024 in npads: from this process's choices, else the
+// cache, else timed (REFEIG_TUNE != 0) and stored in the cache.
+void ensure_tiles(const std::vector<int> &npads, char *scratch, size_t bytes, hipStream_t s) {
+  std::vector<int> need;
+  {
+    std::vector<std::pair<int, std::string>> keys;
+    for (int np : npads)
+      if (np >= 1024) keys.emplace_back(np, tile_key(np));
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    for (const auto &k : keys)
+      if (!g_tile.count(k.second) && std::find(need.begin(), need.end(), k.first) == need.end())
+        need.push_back(k.first);
+  }
+  const char *f = std::getenv("REFEIG_TILE");
+  if (need.empty() || (f && (std::atoi(f) == 128 || std::atoi(f) == 256))) return;
+  const char *tune = std::getenv("REFEIG_TUNE");
+  const bool timing = !(tune && std::atoi(tune) == 0);
+  const std::string path = tile_cache_path(), arch = device_arch();
+  std::map<std::string, int> cache = read_tile_cache(path);
+  bool dirty = false;
+  for (int np : need) {
+    const std::string key = arch + ":" + std::to_string(np);
+    int t = 256;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      t = it->second;
+    } else if (timing) {
+      const int r = time_tiles(np, scratch, bytes, s);
+      if (r) {
+        t = r;
+        cache[key] = r;
+        dirty = true;
+      }
+    }
+    const std::string pk = tile_key(np);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile[pk] = t;
+  }
+  if (dirty) write_tile_cache(path, cache);
 }
 
 // One chunk of a grouped batch: problems ids (npad descending, all <= kGroupMaxNpad), their
@@ -1507,6 +1714,7 @@ void prepare_chunk(ChunkPlan &cp, const std::vector<int> &ids, const int *n,
     q.P = q.w.P;
     q.pp = plan_params(n[i], q.npad, o, target[i]);
     q.pb = plan_bufs(q.w, D[i]);
+    q.gtile = gtile_of(q.npad);
   }
   cp.cls.clear();
   for (int k = 0; k < cp.G; ++k) {
@@ -1518,7 +1726,7 @@ void prepare_chunk(ChunkPlan &cp, const std::vector<int> &ids, const int *n,
   cp.g256 = 0;
   cp.cap256 = 0;
   for (int k = 0; k < cp.G; ++k) {
-    if (gemm_tile_rows(cp.hp[k].npad) == 256) {
+    if (cp.hp[k].gtile == 256) {
       ++cp.g256;
       cp.cap256 += item_cap(cp.hp[k].n);
     } else {
@@ -1678,9 +1886,6 @@ int refine_grouped(int count, const int *n, const double *const *A, const int *l
       alone.push_back(i);
     }
   }
-  std::stable_sort(grouped.begin(), grouped.end(), [&](int a, int b) {
-    return round_up(n[a], kTile) > round_up(n[b], kTile);
-  });
   GroupArea ga;
   const size_t area = group_area(count, icap, work, &ga);
   char *region = work + area;
@@ -1691,6 +1896,18 @@ int refine_grouped(int count, const int *n, const double *const *A, const int *l
                                      mx = std::max(mx, ws_rounded(n[i], o));
                                  return mx;
                                }()));
+  // product tiles (the region is free until the first chunk), then the problems ordered with
+  // the 256-row tile's first, each tile group by npad descending
+  {
+    std::vector<int> npads;
+    for (int i : grouped) npads.push_back(round_up(n[i], kTile));
+    ensure_tiles(npads, region, room, s);
+  }
+  std::stable_sort(grouped.begin(), grouped.end(), [&](int a, int b) {
+    const int pa = round_up(n[a], kTile), pb = round_up(n[b], kTile);
+    const int ta = gtile_of(pa), tb = gtile_of(pb);
+    return ta != tb ? ta > tb : pa > pb;
+  });
   // chunks of consecutive problems whose workspaces fit in the region together
   size_t k = 0;
   while (k < grouped.size()) {
@@ -2523,6 +2740,18 @@ int refeig_read_report(const void *work, int n, const refeig_opts *o_in, int *st
   return REFEIG_OK;
 }
 
+int refeig_tile_cache_lookup(const char *arch, int npad, int *tile) {
+  if (!arch || !tile || npad < 1) return REFEIG_E_ARG;
+  if (npad < 1024) {
+    *tile = 128;
+    return REFEIG_OK;
+  }
+  const auto m = read_tile_cache(tile_cache_path());
+  const auto it = m.find(std::string(arch) + ":" + std::to_string(npad));
+  *tile = it == m.end() ? 256 : it->second;
+  return it == m.end() ? REFEIG_NOT_CONVERGED : REFEIG_OK;
+}
+
 int refeig_row_nonzeros(const double *A, int lda, int n, refeig_stream_t stream, int *k) {
   if (!A || !k || n < 1 || lda < n) return REFEIG_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -2757,10 +2986,15 @@ int refeig_batch_create(int count, const int *n, const double *const *A, const i
       return REFEIG_E_ARG;
   const size_t area = group_area(count, icap, nullptr, nullptr);
   if (work_bytes < area + sum) return REFEIG_E_NOMEM;
-  std::vector<int> ids(count);
-  for (int i = 0; i < count; ++i) ids[i] = i;
+  std::vector<int> ids(count), npads(count);
+  for (int i = 0; i < count; ++i) {
+    ids[i] = i;
+    npads[i] = round_up(n[i], kTile);
+  }
+  ensure_tiles(npads, (char *)work + area, work_bytes - area, nullptr);
   std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
-    return round_up(n[a], kTile) > round_up(n[b], kTile);
+    const int ta = gtile_of(npads[a]), tb = gtile_of(npads[b]);
+    return ta != tb ? ta > tb : npads[a] > npads[b];
   });
   auto *b = new refeig_batch();
   b->count = count;

@@ -51,6 +51,7 @@ struct GProb {
   const double *A;
   double *X, *D;
   int lda, ldx, n, npad, ka;
+  int gtile;   // rows of the product tile the grouped kernels use (128, or 256 when npad >= 1024)
   size_t P;
   Work w;
   PlanParams pp;
@@ -73,6 +74,9 @@ void launch_worklist_g(const GProb *gp, int first, int count, int which, int til
                        int *total, int *ctr, hipStream_t s);
 void launch_gemm_g(const GProb *gp, int tile, int blocks, const int2 *items, const int *total,
                    int *ctr, int which, hipStream_t s);
+// Fill n bytes with digits in [-127, 127] from a hash of the index and seed (the tile tuner's
+// synthetic planes).
+void launch_fill_hash_i8(int8_t *p, size_t n, unsigned seed, hipStream_t s);
 void launch_dp_init_g(const GProb *gp, int first, int count, hipStream_t s);
 void launch_dp_order_g(const GProb *gp, int first, int count, int it, hipStream_t s);
 void launch_dp_vplan_g(const GProb *gp, int first, int count, int it, hipStream_t s);

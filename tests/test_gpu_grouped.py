@@ -162,3 +162,30 @@ def test_graph_captured_batch_replays():
     finally:
         b.close()
 
+
+
+def test_tile_choice_does_not_change_results(tmp_path):
+    """Orders from 1024 run on the 256-row tile or on the 128-row tile with each entry of the
+    256-row plan split in four: the batch is bit-identical to single calls either way. Then a
+    batch with timing enabled on an empty cache records a choice for each of its orders."""
+    rb = _rb()
+    probs, targets = _mix()
+    opts = rb.default_opts(fixed_iters=3)
+    singles = _singles(probs, targets, opts)
+    for t in ("128", "256"):
+        os.environ["REFEIG_TILE"] = t
+        try:
+            print("tile", t, flush=True)
+            _check_batch(probs, targets, opts, singles)
+        finally:
+            del os.environ["REFEIG_TILE"]
+    cache = tmp_path / "tiles.json"
+    os.environ["REFEIG_TUNE_CACHE"] = str(cache)
+    try:
+        _check_batch(probs[:4], targets[:4], opts, singles[:4])   # orders 40, 1000, 130, 1024
+        import json
+        got = json.loads(cache.read_text())
+        print("tuned:", got, flush=True)
+        assert any(k.endswith(":1024") for k in got) and all(v in (128, 256) for v in got.values())
+    finally:
+        del os.environ["REFEIG_TUNE_CACHE"]
