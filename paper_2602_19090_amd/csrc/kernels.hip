@@ -925,15 +925,15 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
 }
 
 // Threads and entries per thread of the column epilogues (one block per output column):
-// up to npad = 1024 one entry per thread and npad threads (npad is a multiple of 256), above
-// it 1024 threads and npad / 1024 entries each. The single and grouped launches use the same
-// shapes, so their reductions group the column's entries alike.
+// up to npad = 1024, 256 threads with npad / 256 entries each (rounded up to 1, 2 or 4), so a
+// CU holds several columns' blocks at once and their latencies overlap; above it 1024 threads
+// and npad / 1024 entries each. The single and grouped launches use the same shapes, so their
+// reductions group the column's entries alike.
 #define EPI_DISPATCH(npad, M)        \
   do {                               \
     if ((npad) <= 256) M(1, 256);    \
-    else if ((npad) <= 512) M(1, 512);  \
-    else if ((npad) <= 768) M(1, 768);  \
-    else if ((npad) <= 1024) M(1, 1024); \
+    else if ((npad) <= 512) M(2, 256);  \
+    else if ((npad) <= 1024) M(4, 256); \
     else if ((npad) <= 2048) M(2, 1024); \
     else if ((npad) <= 4096) M(4, 1024); \
     else M(8, 1024);                 \
@@ -941,9 +941,8 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
 #define EPI_DISPATCH_G(npad, M)      \
   do {                               \
     if ((npad) <= 256) M(1, 256);    \
-    else if ((npad) <= 512) M(1, 512);  \
-    else if ((npad) <= 768) M(1, 768);  \
-    else if ((npad) <= 1024) M(1, 1024); \
+    else if ((npad) <= 512) M(2, 256);  \
+    else if ((npad) <= 1024) M(4, 256); \
     else if ((npad) <= 2048) M(2, 1024); \
     else M(4, 1024);                 \
   } while (0)
