@@ -392,6 +392,28 @@ def config4_leg(count):
                               for m in sorted({-(-q.n // 256) * 256 for q in probs})}}
 
 
+def ceiling_leg(rb, achieved_tops, seconds=0.6):
+    """Matrix-core ceiling for the product's instruction mix (refeig_mfma_ceiling): the INT8
+    rate and shader clock of the product's K-stage issued back to back on changing operands,
+    with operands in registers, read from LDS, and with the LDS ring's writes and a barrier
+    per stage; the product's achieved rate as a fraction of each."""
+    out = {}
+    names = ("registers", "lds_reads", "lds_ring")
+    for v, name in enumerate(names):
+        st, ms, pops, ghz = rb.mfma_ceiling(v, seconds)
+        if st != rb.REFEIG_OK:
+            return {"status": rb.strerror(st)}
+        out[name] = {"pops": pops, "clock_ghz": ghz, "ms": ms}
+        log(f"MFMA ceiling ({name}): {pops:.3f} POP/s at {ghz:.2f} GHz")
+    for name in names:
+        out[name]["product_frac"] = achieved_tops / 1e3 / out[name]["pops"]
+    out["note"] = ("one block of 4 waves per CU issuing the product's K-stage (32 "
+                   "v_mfma_i32_32x32x32_i8 per wave) for about %.1f s on changing operands; "
+                   "product_frac = the dominant product kernel's achieved rate / this rate"
+                   % seconds)
+    return out
+
+
 def serve_leg(rates, nreq, pool_size=256, lanes=4, budget_gib=64.0):
     """Serving (config 5): requests arrive as a Poisson process and draw a problem from a
     pool (n = round(exp(U(ln 128, ln 8192))), cond 10^U(4,12), target from {1e-8, 1e-11,
@@ -552,6 +574,8 @@ def main():
                          "future work) at order N (4096: a matrix unitarily similar, by exact "
                          "phases 1, i, -1, -i, to the config-2 matrix of order 4096, whose X_true "
                          "columns are stored)")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the matrix-core ceiling probe")
     ap.add_argument("--calibrate", action="store_true",
                     help="run one elementwise kernel of known traffic (for profiler byte counters)")
     args = ap.parse_args()
@@ -797,6 +821,9 @@ def main():
             grouped = {"group_tau": args.group_tau, "ms_to_target": None,
                        "fwd_err_per_iter": gerrs, "groups_per_iter": ggroups}
 
+    ceiling = None
+    if not args.no_ceiling and roofline is not None:
+        ceiling = ceiling_leg(rb, roofline["achieved"])
     herm = None
     if args.herm > 0:
         herm = herm_leg(args.herm, target, args)
@@ -825,6 +852,8 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "fp64_plain": plain,
         "planning": planning,
     }
+    if ceiling is not None:
+        out["mfma_ceiling"] = ceiling
     if batch is not None:
         out["config4_batched"] = batch
     if grouped is not None:

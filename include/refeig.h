@@ -464,6 +464,23 @@ int refeig_slice_gemm_fp8(const uint8_t *Lp8, const uint8_t *Rp8, size_t plane_s
                           int kl, int kr, int d_min, int ndiag, int32_t *C,
                           refeig_stream_t stream);
 
+/* Measurement entry point, not part of the method: the matrix-core ceiling of the current GPU
+ * for the slice product's instruction mix, the figure the product's achieved INT8 rate is
+ * read against beside the published dense peak (the product is the cost that dominates,
+ * Sec. 4). One block of 4 waves per CU issues the product's K-stage (32
+ * v_mfma_i32_32x32x32_i8 per wave over a 128 x 128 wave tile) back to back for about
+ * `seconds` (0 < seconds <= 10) on operands that change every stage:
+ *   variant 0: operands in registers;
+ *   variant 1: operands read from LDS as the product reads them;
+ *   variant 2: variant 1 plus the LDS writes of the operand ring and a barrier per stage.
+ * Outputs (host pointers): *ms the last run's time, *pops its INT8 rate in 10^15 operations
+ * per second (2 per multiply-add), *ghz the shader clock over that run (s_memtime cycles over
+ * the constant-rate s_memrealtime time, averaged over the blocks). Allocates and frees a few
+ * KB of device memory; synchronous on `stream`. REFEIG_E_ARG for a bad variant, time or NULL
+ * output; REFEIG_E_NOMEM / REFEIG_E_HIP on runtime failures. */
+int refeig_mfma_ceiling(int variant, double seconds, refeig_stream_t stream, double *ms,
+                        double *pops, double *ghz);
+
 #ifdef __cplusplus
 }
 #endif

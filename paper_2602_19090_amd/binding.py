@@ -102,6 +102,8 @@ _lib.refeig_residue_planes.argtypes = [_vp, _sz, _sz, _int, _int, _vp, _vp, _vp]
 _lib.refeig_residue_gemm.argtypes = [_vp, _vp, _sz, _int, _int, _vp, _vp, _vp, _vp]
 _lib.refeig_slice_gemm_fp8.argtypes = [_vp, _vp, _sz, _int, _int, _int, _int, _int, _vp, _vp]
 _lib.refeig_digits_to_e4m3.argtypes = [_vp, _vp, _sz, _vp]
+_lib.refeig_mfma_ceiling.argtypes = [_int, _dbl, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
+                                     ctypes.POINTER(_dbl)]
 _lib.refeig_server_create.argtypes = [_int, _sz, ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
 _lib.refeig_server_submit.argtypes = [_vp, _vp, _int, _vp, _int, _vp, _int, _dbl, _vp,
                                       ctypes.POINTER(_int)]
@@ -146,7 +148,8 @@ EXPORTED = ["refeig_default_opts", "refeig_workspace_bytes", "refine_eigvecs", "
             "refeig_batch_workspace_bytes", "refeig_batch_create", "refeig_batch_launch",
             "refeig_batch_results", "refeig_batch_destroy", "refeig_tile_cache_lookup",
             "refeig_host_column_order",
-            "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros"]
+            "refeig_host_crt_plan", "refeig_host_group_ritz", "refeig_row_nonzeros",
+            "refeig_mfma_ceiling"]
 
 
 def _stream(stream=None):
@@ -529,6 +532,15 @@ def digits_to_e4m3(D, stream=None):
     codes = torch.empty(D.shape, dtype=torch.uint8, device=D.device)
     st = _lib.refeig_digits_to_e4m3(_ptr(D), _ptr(codes), D.numel(), _stream(stream))
     return st, codes
+
+
+def mfma_ceiling(variant: int, seconds: float = 1.0, stream=None):
+    """refeig_mfma_ceiling: (status, ms, INT8 POP/s, shader clock GHz) of the matrix-core probe
+    (variant 0: operands in registers, 1: from LDS, 2: LDS reads, writes and a barrier)."""
+    ms, pops, ghz = _dbl(), _dbl(), _dbl()
+    st = _lib.refeig_mfma_ceiling(variant, seconds, _stream(stream), ctypes.byref(ms),
+                                  ctypes.byref(pops), ctypes.byref(ghz))
+    return st, ms.value, pops.value, ghz.value
 
 
 def slice_gemm_fp8(Lp8, Rp8, npad: int, kl: int, kr: int, d_min: int, ndiag: int, stream=None):

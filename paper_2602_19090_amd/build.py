@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librefeig.so")
-SOURCES = ["kernels.hip", "plain.hip", "devplan.hip", "refeig.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "plain.hip", "devplan.hip", "refeig.cpp", "noalloc.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
