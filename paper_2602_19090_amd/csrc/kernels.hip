@@ -587,6 +587,16 @@ __device__ __forceinline__ void wait_vm_lds_barrier() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
+// Four 16-byte-per-lane DMA loads of 16 rows (1 KB) each, 1 KB apart both in global memory and
+// in LDS: the immediate offset of the instruction moves both addresses.
+__device__ __forceinline__ void dma_rows4(const int8_t *g, int8_t *l) {
+  typedef void __attribute__((address_space(3))) *lds_ptr;
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_ptr)l, 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_ptr)l, 16, 1024, 0);
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_ptr)l, 16, 2048, 0);
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_ptr)l, 16, 3072, 0);
+}
+
 // F8: the planes hold FP8 E4M3 bytes of small integer digits (|digit| <= 15) instead of
 // INT8 digits; one v_mfma_f32_32x32x64_f8f6f4 takes the two 32-deep halves of a stage that
 // the INT8 form feeds to two v_mfma_i32_32x32x32_i8 (both operands see the same lane and byte
@@ -636,26 +646,34 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][c][v] = 0;
 
-  // this lane's share of a stage: wave w fills rows [64w, 64w + 64) of both
-  // operands, 16 rows per instruction; lane -> row 16i + lane/4, position lane%4
+  // this lane's share of a stage: wave w fills rows [64w, 64w + 64) of both operands, 16 rows
+  // per instruction; lane -> row 16i + lane/4, chunk position lane%4, which holds chunk
+  // (lane%4) ^ ((row >> 2) & 3) of the row (the same for the four instructions, 16i being a
+  // multiple of 4). The four instructions differ by 16 rows = 1 KB both in the plane and in the
+  // ring, which their immediate offset carries, so one address serves all four.
   const int lrow = lane >> 2, lpos = lane & 3;
+  const int loff = (wave * 64 + lrow) * DBK + 16 * (lpos ^ ((lrow >> 2) & 3));
+  // issue stream: stages are issued in order; the next one is K-block ik of pair s_lo + ip,
+  // whose K-blocks of this tile's rows start at lsrc / rsrc (K-blocks of a plane are
+  // npad * 64 bytes apart; the next pair's L plane follows, its R plane precedes)
+  const size_t kstride = (size_t)npad * DBK;
+  const int8_t *lpair = Lp + (size_t)(s_lo - 1) * pstride + (size_t)m0 * DBK;
+  const int8_t *rpair = Rp + (size_t)(roff + rsum - s_lo - 1) * pstride + (size_t)n0 * DBK;
+  const int8_t *lsrc = lpair, *rsrc = rpair;
+  int ik = 0;
+  auto advance = [&]() {
+    const bool wrap = ++ik == KT;
+    ik = wrap ? 0 : ik;
+    lpair = wrap ? lpair + pstride : lpair;
+    rpair = wrap ? rpair - pstride : rpair;
+    lsrc = wrap ? lpair : lsrc + kstride;
+    rsrc = wrap ? rpair : rsrc + kstride;
+  };
   auto issue = [&](int tt) {
-    const int p = tt / KT, k0 = (tt - p * KT) * DBK;
-    const int s = s_lo + p;
-    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride + kb_off(m0, k0, npad);
-    const int8_t *Rb = Rp + (size_t)(roff + rsum - s - 1) * pstride + kb_off(n0, k0, npad);
-    int8_t *st = ring + (tt % S) * DSTAGE_BYTES;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wave * 64 + i * 16 + lrow;
-      const int chunk = lpos ^ ((row >> 2) & 3);
-      __builtin_amdgcn_global_load_lds((const void *)(Lb + row * 64 + chunk * 16),
-                                       (void __attribute__((address_space(3))) *)(st + (wave * 64 + i * 16) * DBK),
-                                       16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void *)(Rb + row * 64 + chunk * 16),
-                                       (void __attribute__((address_space(3))) *)(st + 256 * DBK + (wave * 64 + i * 16) * DBK),
-                                       16, 0, 0);
-    }
+    int8_t *st = ring + (tt % S) * DSTAGE_BYTES + wave * 64 * DBK;
+    dma_rows4(lsrc + loff, st);
+    dma_rows4(rsrc + loff, st + 256 * DBK);
+    advance();
   };
   // fragment offsets within a stage: row r, 16-byte chunk c -> r*64 + 16*(c ^ ((r>>2)&3))
   int fa_off[2][4], fb_off[2][4];
@@ -698,8 +716,49 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
   // tt+S-1, read stage tt+1 into the other register set, and run the MFMAs of
   // stage tt. Steady stages (tt+S-1 < T) are branch-free so the scheduler can
   // interleave the three instruction streams.
+  // Steady INT8 stage in 8 chunks, fenced so they keep this order: chunk g runs 4 of the 32
+  // MFMAs of stage tt, issues DMA instruction g of stage tt+S-1 (L rows for g < 4, R rows
+  // after) and reads fragment g of both operands of stage tt+1. With one wavefront per SIMD,
+  // issue is in program order, so spreading the memory instructions over the MFMAs keeps
+  // the matrix core fed while they issue.
+  auto chunk = [&](auto G, const v4i (&ca)[2][4], const v4i (&cb)[2][4], v4i (&na)[2][4],
+                   v4i (&nb)[2][4], const int8_t *lg, const int8_t *rg, int8_t *dst,
+                   const int8_t *sb) {
+    constexpr int g = decltype(G)::value;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = 4 * g + j, ks = m >> 4, x = (m >> 2) & 3, y = m & 3;
+      acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[ks][x], cb[ks][y], acc[x][y], 0, 0, 0);
+    }
+    typedef void __attribute__((address_space(3))) *lds_ptr;
+    if constexpr (g < 4)
+      __builtin_amdgcn_global_load_lds((const void *)lg, (lds_ptr)dst, 16, g * 1024, 0);
+    else
+      __builtin_amdgcn_global_load_lds((const void *)rg, (lds_ptr)(dst + 256 * DBK), 16,
+                                       (g - 4) * 1024, 0);
+    na[g >> 2][g & 3] = *(const v4i *)(sb + fa_off[g >> 2][g & 3]);
+    nb[g >> 2][g & 3] = *(const v4i *)(sb + fb_off[g >> 2][g & 3]);
+    if constexpr (g == 7) advance();
+    __builtin_amdgcn_sched_barrier(0);
+  };
   auto stage = [&](auto steady, int tt, v4i (&ca)[2][4], v4i (&cb)[2][4], v4i (&na)[2][4],
                    v4i (&nb)[2][4]) {
+    if constexpr (!F8 && decltype(steady)::value) {
+      wait_vm_lds_barrier<8 * (S - 3)>();
+      __builtin_amdgcn_sched_barrier(0);
+      int8_t *dst = ring + ((tt + S - 1) % S) * DSTAGE_BYTES + wave * 64 * DBK;
+      const int8_t *lg = lsrc + loff, *rg = rsrc + loff;
+      const int8_t *sb = ring + ((tt + 1) % S) * DSTAGE_BYTES;
+      chunk(std::integral_constant<int, 0>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 1>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 2>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 3>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 4>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 5>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 6>(), ca, cb, na, nb, lg, rg, dst, sb);
+      chunk(std::integral_constant<int, 7>(), ca, cb, na, nb, lg, rg, dst, sb);
+      return;
+    }
     if constexpr (decltype(steady)::value) {
       wait_vm_lds_barrier<8 * (S - 3)>();
       issue(tt + S - 1);
@@ -742,13 +801,17 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
             acc[x][y] =
                 __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[ks][x], cb[ks][y], acc[x][y], 0, 0, 0);
       if constexpr (decltype(steady)::value) {
-        // per 4 MFMAs: one DMA instruction and two fragment reads
+        // per 4 MFMAs: one DMA instruction, two fragment reads and up to five scalar or vector
+        // ALU instructions (addresses, the issue stream's pointers), so that a wave with one
+        // wavefront per SIMD never issues a run of them while its matrix core idles
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
           __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
           __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x006, 3, 0);
           __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
           __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x006, 2, 0);
         }
       }
     }
