@@ -146,7 +146,7 @@ __device__ void bitonic(K *key, int *aux, int N2) {
 // Block table of a tabled slice-GEMM launch from each tile's last diagonal dt[J] (LDS, ntile
 // tiles per side, 2 <= dt[J] <= kMaxDiag + 1): groups of tiles with equal dt, largest first;
 // (group, slot) combinations ordered by pair count, most first (stable); within one, the XCD
-// band order of xcd_tile_order. Entry = row tile | column tile << 8 | slot << 16. Returns the
+// XCD order of xcd_tile_order. Entry = row tile | column tile << 8 | slot << 16. Returns the
 // entry count. The slots are ranked once by pair count (descending, stable); a run of slots
 // with equal counts is taken group by group, and in a group the slots q with q + 2 <= dt (a
 // prefix of the run, which holds ascending q): block (run r, group g) holds those

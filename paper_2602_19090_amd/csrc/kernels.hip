@@ -537,19 +537,20 @@ constexpr int HBM_ = 256, HGM = 4;
 // launch of tiles_m row blocks x tiles_n column blocks. Blocks are dispatched
 // round-robin over the 8 XCDs (block id mod 8), and each XCD has its own L2, so
 // the blocks one XCD runs at once should form a compact patch that shares
-// operand panels. With tiles_n a multiple of 8 each XCD owns a column band;
-// else with tiles_m a multiple of 8 it takes row blocks x, x + 8, ...; otherwise
-// blocks walk groups of 4 row blocks.
+// operand panels. With tiles_n a multiple of 8 XCD x owns the column blocks x,
+// 15 - x, 16 + x, ...; else with tiles_m a multiple of 8 it takes row blocks x, x + 8, ...;
+// otherwise blocks walk groups of 4 row blocks.
 __device__ __forceinline__ void tile_of_block(int bid, int tiles_m, int tiles_n, int &mi, int &n0) {
   if (tiles_n % 8 == 0) {
-    // XCD x owns the column band [x cb, (x + 1) cb) and walks it in groups of up
-    // to 8 row blocks: its ~32 resident blocks form an 8 x 4 patch.
+    // XCD x owns column blocks x, 15 - x, 16 + x, ... and walks them in groups of up to 8 row
+    // blocks: its ~32 resident blocks form an 8 x 4 patch (as xcd_tile_order)
     const int xcd = bid & 7, local = bid >> 3;
     const int cb = tiles_n >> 3;
     const int rg = local / (8 * cb), rem = local - rg * 8 * cb;
     const int gs = min(8, tiles_m - rg * 8);
+    const int c = rem / gs;
     mi = rg * 8 + rem % gs;
-    n0 = (xcd * cb + rem / gs) * HBM_;
+    n0 = (8 * c + ((c & 1) ? 7 - xcd : xcd)) * HBM_;
   } else if (tiles_m % 8 == 0) {
     const int xcd = bid & 7, local = bid >> 3;
     const int rows = tiles_m >> 3;

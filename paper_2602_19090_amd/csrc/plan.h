@@ -302,16 +302,19 @@ RF_HD void crt_rec_build(int N, int ka1, int kx, CrtRec &rec) {
 
 // Block -> (row block, column block) of a launch over tiles_m row blocks x tiles_n column
 // blocks: blocks go round-robin to the 8 XCDs (id mod 8), each with its own L2; with tiles_n
-// a multiple of 8 each XCD owns a band of column blocks and walks it in groups of up to 8 row
-// blocks.
+// a multiple of 8 XCD x owns one column block of each group of 8, x in even groups and 7 - x
+// in odd ones (x, 15 - x, 16 + x, ...: its R operand stays in its L2), and walks them in
+// groups of up to 8 row blocks. Spread rather than contiguous column sets keep the XCDs' work
+// even when the work per tile drifts along the columns (per-tile cutoffs do).
 RF_HD void xcd_tile_order(int bid, int tiles_m, int tiles_n, int &mi, int &nb) {
   if (tiles_n % 8 == 0) {
     const int xcd = bid & 7, local = bid >> 3, cb = tiles_n >> 3;
     const int rg = local / (8 * cb), rem = local - rg * 8 * cb;
     const int left = tiles_m - rg * 8;
     const int gs = left < 8 ? left : 8;
+    const int c = rem / gs;
     mi = rg * 8 + rem % gs;
-    nb = xcd * cb + rem / gs;
+    nb = 8 * c + ((c & 1) ? 7 - xcd : xcd);
   } else if (tiles_m % 8 == 0) {
     const int xcd = bid & 7, local = bid >> 3, rows = tiles_m >> 3;
     mi = xcd + 8 * (local % rows);

@@ -330,9 +330,9 @@ bool plan_cutoffs(const std::vector<int> &dcol, int n, int npad, int kl, int kr,
 // One launch per group; ev_start is taken by the first dispatch, ev_stop by the last.
 // Block order of the 256 x 256 kernel within one (group, diagonal): a launch-local block
 // id -> (index into the group's row blocks, column block). Blocks go round-robin to the 8
-// XCDs (id mod 8), each with its own L2; with tiles_n a multiple of 8 each XCD owns a band
-// of column blocks and walks it in groups of up to 8 row blocks (the kernel's own order
-// without a table).
+// XCDs (id mod 8), each with its own L2; with tiles_n a multiple of 8 XCD x owns the column
+// blocks x, 15 - x, 16 + x, ... and walks them in groups of up to 8 row blocks (the kernel's
+// own order without a table).
 
 // One launch per product (npad >= 1024): the blocks of every group and diagonal in one table,
 // the diagonals with the most pairs first, so blocks of all groups share the chip and the
@@ -2649,6 +2649,14 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
                 nbw, live);
         for (int q = 1; q <= kKrMax; ++q)
           if (by_pairs_all[q]) fprintf(stderr, " %d:%d/%d", q, by_pairs[q], by_pairs_all[q]);
+        // live pair work by XCD (blocks go to XCDs round robin by index)
+        double xw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (size_t e = 0; e < htab[1].size(); ++e) {
+          const int v = htab[1][e], J = v & 0xff, I = (v >> 8) & 0xff, d = 2 + (v >> 16);
+          if (d <= tcut[(size_t)J * T + I]) xw[e % 8] += npairs_of(d, kR, kxw);
+        }
+        fprintf(stderr, "; live pair-blocks by XCD:");
+        for (int x = 0; x < 8; ++x) fprintf(stderr, " %.0f", xw[x]);
         fprintf(stderr, "\n");
       }
     }
