@@ -580,12 +580,18 @@ __device__ __forceinline__ void tile_of_block(int bid, int tiles_m, int tiles_n,
 constexpr int DBK = 64, DSTAGES = 4, DSTAGE_BYTES = 2 * 256 * DBK;
 
 // Wait until at most N vector-memory operations of this wave are outstanding,
-// then barrier; the memory clobber keeps LDS reads on their side of it.
-// Also waits for this wave's LDS reads, so no wave still reads a slot that the
-// DMA issued after the barrier overwrites.
+// then barrier. Also waits for this wave's LDS reads, so no wave still reads a slot
+// that the DMA issued after the barrier overwrites. Written with the builtins (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 left at 7, lgkmcnt 11:8 at 0) so
+// that the compiler's own wait insertion knows what has completed here; the
+// scheduling fences keep memory instructions on their side.
 template <int N>
 __device__ __forceinline__ void wait_vm_lds_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+  static_assert(N >= 0 && N < 64, "vmcnt has 6 bits");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Four 16-byte-per-lane DMA loads of 16 rows (1 KB) each, 1 KB apart both in global memory and
@@ -717,15 +723,24 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
   // tt+S-1, read stage tt+1 into the other register set, and run the MFMAs of
   // stage tt. Steady stages (tt+S-1 < T) are branch-free so the scheduler can
   // interleave the three instruction streams.
-  // Steady INT8 stage in 8 chunks, fenced so they keep this order: chunk g runs 4 of the 32
-  // MFMAs of stage tt, issues DMA instruction g of stage tt+S-1 (L rows for g < 4, R rows
-  // after) and reads fragment g of both operands of stage tt+1. With one wavefront per SIMD,
-  // issue is in program order, so spreading the memory instructions over the MFMAs keeps
-  // the matrix core fed while they issue.
+  // Steady INT8 stage in 8 chunks, fenced so they keep this order: chunk g reads its share of
+  // the 16 fragments of stage tt+1 (3, 3, 3, 3, 2, 2, 0, 0 of the sequence A0 B0 A1 B1 ...),
+  // runs 4 of the 32 MFMAs of stage tt and issues DMA instruction g of stage tt+S-1 (L rows
+  // for g < 4, R rows after). With one wavefront per SIMD, issue is in program order, so
+  // spreading the memory instructions over the MFMAs keeps the matrix core fed while they
+  // issue, and the last reads land two chunks before the next stage's wait.
   auto chunk = [&](auto G, const v4i (&ca)[2][4], const v4i (&cb)[2][4], v4i (&na)[2][4],
                    v4i (&nb)[2][4], const int8_t *lg, const int8_t *rg, int8_t *dst,
                    const int8_t *sb) {
     constexpr int g = decltype(G)::value;
+    constexpr int rlo = g < 4 ? 3 * g : g < 6 ? 12 + 2 * (g - 4) : 16;
+    constexpr int rhi = g < 4 ? 3 * g + 3 : g < 6 ? 14 + 2 * (g - 4) : 16;
+#pragma unroll
+    for (int r = rlo; r < rhi; ++r) {
+      const int f = r >> 1;
+      if (r & 1) nb[f >> 2][f & 3] = *(const v4i *)(sb + fb_off[f >> 2][f & 3]);
+      else na[f >> 2][f & 3] = *(const v4i *)(sb + fa_off[f >> 2][f & 3]);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int m = 4 * g + j, ks = m >> 4, x = (m >> 2) & 3, y = m & 3;
@@ -737,8 +752,6 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
     else
       __builtin_amdgcn_global_load_lds((const void *)rg, (lds_ptr)(dst + 256 * DBK), 16,
                                        (g - 4) * 1024, 0);
-    na[g >> 2][g & 3] = *(const v4i *)(sb + fa_off[g >> 2][g & 3]);
-    nb[g >> 2][g & 3] = *(const v4i *)(sb + fb_off[g >> 2][g & 3]);
     if constexpr (g == 7) advance();
     __builtin_amdgcn_sched_barrier(0);
   };
