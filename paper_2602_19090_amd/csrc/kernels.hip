@@ -1024,28 +1024,118 @@ void launch_slice_gemm_table(const int8_t *Lp, const int8_t *Rp, size_t pstride,
     else M(4, 1024);                 \
   } while (0)
 
+// Rows of a column epilogue's thread: EPT consecutive rows i = EPT tid + q (EPT divides 64,
+// so they share one 64-row K-block), so the thread's entries of one slot are one vector load
+// and its digits of one plane one vector store. A thread's rows are all below npad or none.
+template <int EPT>
+__device__ __forceinline__ int erow(int tid, int q) {
+  return EPT * tid + q;
+}
+// EPT consecutive values at p (aligned to their total size), integers sign-extended from int8
+template <int EPT>
+__device__ __forceinline__ void load_i8v(const int8_t *__restrict__ p, int (&v)[EPT]) {
+  if constexpr (EPT == 8) {
+    const uint2 w = *(const uint2 *)p;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = (int)(int8_t)(w.x >> (8 * e));
+      v[4 + e] = (int)(int8_t)(w.y >> (8 * e));
+    }
+  } else if constexpr (EPT == 4) {
+    const uint32_t w = *(const uint32_t *)p;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (int)(int8_t)(w >> (8 * e));
+  } else if constexpr (EPT == 2) {
+    const uint32_t w = *(const uint16_t *)p;
+    v[0] = (int)(int8_t)w;
+    v[1] = (int)(int8_t)(w >> 8);
+  } else {
+    v[0] = p[0];
+  }
+}
+template <int EPT>
+__device__ __forceinline__ void load_i32v(const int32_t *__restrict__ p, int32_t (&v)[EPT]) {
+  if constexpr (EPT >= 4) {
+#pragma unroll
+    for (int h = 0; h < EPT / 4; ++h) {
+      const int4 w = ((const int4 *)p)[h];
+      v[4 * h] = w.x;
+      v[4 * h + 1] = w.y;
+      v[4 * h + 2] = w.z;
+      v[4 * h + 3] = w.w;
+    }
+  } else if constexpr (EPT == 2) {
+    const int2 w = *(const int2 *)p;
+    v[0] = w.x;
+    v[1] = w.y;
+  } else {
+    v[0] = p[0];
+  }
+}
+template <int EPT>
+__device__ __forceinline__ void load_f64v(const double *__restrict__ p, double (&v)[EPT]) {
+  if constexpr (EPT >= 2) {
+#pragma unroll
+    for (int h = 0; h < EPT / 2; ++h) {
+      const double2 w = ((const double2 *)p)[h];
+      v[2 * h] = w.x;
+      v[2 * h + 1] = w.y;
+    }
+  } else {
+    v[0] = p[0];
+  }
+}
+// the low bytes of d[0..EPT) packed in order and stored at p (aligned to EPT bytes)
+template <int EPT>
+__device__ __forceinline__ void store_i8v(int8_t *__restrict__ p, const int (&d)[EPT]) {
+  if constexpr (EPT == 8) {
+    uint2 w = {0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      w.x |= ((uint32_t)d[e] & 255u) << (8 * e);
+      w.y |= ((uint32_t)d[4 + e] & 255u) << (8 * e);
+    }
+    *(uint2 *)p = w;
+  } else if constexpr (EPT == 4) {
+    uint32_t w = 0u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w |= ((uint32_t)d[e] & 255u) << (8 * e);
+    *(uint32_t *)p = w;
+  } else if constexpr (EPT == 2) {
+    *(uint16_t *)p = (uint16_t)(((uint32_t)d[0] & 255u) | (((uint32_t)d[1] & 255u) << 8));
+  } else {
+    p[0] = (int8_t)d[0];
+  }
+}
+
 // Digit planes of one operand row j (an output column of a column epilogue): the values
-// v (EPT per thread, row i = tid + NT q; zero beyond n) with column maximum ms,
+// v (EPT per thread, rows erow(tid, q); zero beyond n) with column maximum ms,
 // exponent exp_above(ms), written K-blocked for rows i < npad.
 template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double ms, int j, int npad,
                                                  int8_t *__restrict__ planes, int k) {
   const size_t P = (size_t)npad * npad;
+  const int i0 = erow<EPT>(threadIdx.x, 0);
+  if (i0 >= npad) return;
   const int ee = exp_above(ms);
+  double y[EPT];
+  int sg[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = threadIdx.x + NT * q;
-    if (i < npad) {
-      const double a = v[q];
-      double y = ldexp(fabs(a), -ee);
-      const int sg = (a < 0.0) ? -1 : 1;
-      for (int t = 0; t < k; ++t) {
-        double t128 = y * 128.0;
-        double dgt = floor(t128);
-        y = t128 - dgt;
-        planes[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
-      }
+    y[q] = ldexp(fabs(v[q]), -ee);
+    sg[q] = (v[q] < 0.0) ? -1 : 1;
+  }
+  int8_t *dst = planes + kb_off(j, i0, npad);
+  for (int t = 0; t < k; ++t) {
+    int d[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double t128 = y[q] * 128.0;
+      const double dgt = floor(t128);
+      y[q] = t128 - dgt;
+      d[q] = sg[q] * (int)dgt;
     }
+    store_i8v<EPT>(dst + (size_t)t * P, d);
   }
 }
 
@@ -1058,8 +1148,10 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
 // in vh and vl until the end.
 template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size_t P, int n,
-                                           int tid, const CrtRec &rec, const int (&scale)[EPT],
-                                           double (&vh)[EPT], double (&vl)[EPT]) {
+                                           int npad, int tid, const CrtRec &rec,
+                                           const int (&scale)[EPT], double (&vh)[EPT],
+                                           double (&vl)[EPT]) {
+  const int i0 = erow<EPT>(tid, 0);
   // F = sum_t c_t U_t mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |c_t| < 2^15, so
   // c_t L[t][k] is an integer below 2^49 and at most 14 of them sum below 2^52.9: every limb
   // sum is exact. Truncating U_t to 136 bits moves F by at most 14 2^15 2^-136 = 2^-117.2.
@@ -1081,27 +1173,46 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
   for (int q = 0; q < EPT; ++q)
 #pragma unroll
     for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
-  // the slots are loaded kPD terms at a time (all of them when a thread holds one entry), so
-  // each thread keeps up to 2 kPD EPT loads in flight; the terms are added in order
-  constexpr int kPD = EPT >= 8 ? 1 : (16 / EPT < kCrtMax / 2 ? 16 / EPT : kCrtMax / 2);
-#pragma unroll 1
-  for (int t0 = 0; t0 < T; t0 += kPD) {
-    int ca[kPD][EPT], cb[kPD][EPT];
+  // The slots' EPT bytes per thread are one packed load each (loadw); kD pairs of slots are
+  // in flight, in a ring of packed words unpacked where they are used; terms in order.
+  constexpr int kD = EPT >= 8 ? 3 : EPT >= 4 ? 6 : 8;
+  const bool live = i0 < npad;
+  auto loadw = [&](int s) -> uint2 {
+    uint2 w = {0u, 0u};
+    if (!live) return w;
+    const int8_t *p = Ccol + (size_t)s * P + i0;
+    if constexpr (EPT == 8) w = *(const uint2 *)p;
+    else if constexpr (EPT == 4) w.x = *(const uint32_t *)p;
+    else if constexpr (EPT == 2) w.x = *(const uint16_t *)p;
+    else w.x = (uint8_t)p[0];
+    return w;
+  };
+  auto unpack = [&](uint2 w, int (&v)[EPT]) {
 #pragma unroll
-    for (int u = 0; u < kPD; ++u) {
-      const int t = t0 + u;
-      const int8_t *Ca = Ccol + (size_t)(2 * t) * P;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = tid + NT * q;
-        ca[u][q] = (t < T && i < n) ? Ca[i] : 0;
-        cb[u][q] = (t < T && 2 * t + 1 < N && i < n) ? Ca[P + i] : 0;
-      }
+    for (int q = 0; q < EPT; ++q) {
+      const uint32_t word = q < 4 ? w.x : w.y;
+      v[q] = (i0 + q < n) ? (int)(int8_t)(word >> (8 * (q & 3))) : 0;
     }
+  };
+  uint2 ra[kD], rb[kD];
 #pragma unroll
-    for (int u = 0; u < kPD; ++u) {
+  for (int u = 0; u < kD; ++u) {
+    ra[u] = u < T ? loadw(2 * u) : uint2{0u, 0u};
+    rb[u] = (u < T && 2 * u + 1 < N) ? loadw(2 * u + 1) : uint2{0u, 0u};
+  }
+#pragma unroll 1
+  for (int t0 = 0; t0 < T; t0 += kD) {
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
       const int t = t0 + u;
       if (t >= T) break;
+      int ca[EPT], cb[EPT];
+      unpack(ra[u], ca);
+      unpack(rb[u], cb);
+      // refill this ring place with pair t + kD
+      const int tn = t + kD;
+      ra[u] = tn < T ? loadw(2 * tn) : uint2{0u, 0u};
+      rb[u] = (tn < T && 2 * tn + 1 < N) ? loadw(2 * tn + 1) : uint2{0u, 0u};
       const bool pair = 2 * t + 1 < N;   // else a single last slot
       double L[kCrtLimbs];
 #pragma unroll
@@ -1111,11 +1222,11 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15
-        double rq = (double)ca[u][q];
+        double rq = (double)ca[q];
         if (pair) {
-          const float d = (float)(cb[u][q] - ca[u][q]) * inv;   // |d| < 2^16, exact
+          const float d = (float)(cb[q] - ca[q]) * inv;   // |d| < 2^16, exact
           const float tt = d - mb * rintf(d * rmb);
-          rq = (double)ca[u][q] + (double)ma * (double)tt;
+          rq = (double)ca[q] + (double)ma * (double)tt;
         }
 #pragma unroll
         for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
@@ -1171,25 +1282,31 @@ __device__ __forceinline__ void epi_v_body(
   if (gate && *gate == 0) return;
   const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
+  const int i0 = erow<EPT>(tid, 0);
+  const bool live = i0 < npad;   // the thread's rows exist in the padded order
   if (j >= n) {
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + NT * q;
-      if (i < npad)
-        for (int t = 0; t < kr; ++t) Rpl[t * P + kb_off(j, i, npad)] = 0;
-    }
+    double z[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) z[q] = 0.0;
+    write_col_planes<EPT, NT>(z, 0.0, j, npad, Rpl, kr);
     return;
   }
   const int ej = eX[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
-  const int32_t *Ccol = C + (size_t)j * npad;
+  const int32_t *Ccol = C + (size_t)j * npad + i0;
   const double *xcol = X1 + (size_t)j * n;
   double vh[EPT], vl[EPT];
   int eiq[EPT];
+  {
+    int ea[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
-    vh[q] = vl[q] = 0.0;
-    eiq[q] = (i < n) ? eA[i] + ej : 0;
+    for (int q = 0; q < EPT; ++q) ea[q] = 0;
+    if (live) load_i32v<EPT>(eA + i0, ea);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      vh[q] = vl[q] = 0.0;
+      eiq[q] = (i0 + q < n) ? ea[q] + ej : 0;
+    }
   }
   if constexpr (CRT) {
     // the record of this column's level (per 256-column block: slot count, level)
@@ -1197,26 +1314,27 @@ __device__ __forceinline__ void epi_v_body(
     int sc[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) sc[q] = eiq[q] + rec.sh;
-    crt_column<EPT, NT>((const int8_t *)C + (size_t)j * npad, P, n, tid, rec, sc, vh, vl);
+    crt_column<EPT, NT>((const int8_t *)C + (size_t)j * npad, P, n, npad, tid, rec, sc, vh, vl);
   } else {
   // slice sum, smallest scale first; with few entries per thread the diagonals' values are
   // loaded kPD at a time, with many the next diagonal is loaded while this one is summed
   if constexpr (EPT >= 4) {
     int32_t cv[EPT], cn[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + NT * q;
-      cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
-    }
+    for (int q = 0; q < EPT; ++q) cv[q] = 0;
+    if (live && ndiag > 0) load_i32v<EPT>(Ccol + (size_t)(ndiag - 1) * P, cv);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+      if (i0 + q >= n) cv[q] = 0;
 #pragma unroll 1
     for (int qq = ndiag - 1; qq >= 0; --qq) {
       if (qq > 0) {
-        const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
 #pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-          const int i = tid + NT * q;
-          cn[q] = (i < n) ? Cn[i] : 0;
-        }
+        for (int q = 0; q < EPT; ++q) cn[q] = 0;
+        if (live) load_i32v<EPT>(Ccol + (size_t)(qq - 1) * P, cn);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+          if (i0 + q >= n) cn[q] = 0;
       }
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
@@ -1235,12 +1353,15 @@ __device__ __forceinline__ void epi_v_body(
   for (int c0 = ndiag - 1; c0 >= 0; c0 -= kPD) {
     int32_t cv[kPD][EPT];
 #pragma unroll
-    for (int u = 0; u < kPD; ++u)
+    for (int u = 0; u < kPD; ++u) {
+      const int qq = c0 - u;
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = tid + NT * q, qq = c0 - u;
-        cv[u][q] = (qq >= 0 && i < n) ? Ccol[(size_t)qq * P + i] : 0;
-      }
+      for (int q = 0; q < EPT; ++q) cv[u][q] = 0;
+      if (qq >= 0 && live) load_i32v<EPT>(Ccol + (size_t)qq * P, cv[u]);
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        if (i0 + q >= n) cv[u][q] = 0;
+    }
 #pragma unroll
     for (int u = 0; u < kPD; ++u) {
       const int qq = c0 - u;
@@ -1257,10 +1378,12 @@ __device__ __forceinline__ void epi_v_body(
   }
   }
   }
+  // the column of X^(1) is read where it is used (holding the thread's slice of it in
+  // registers across the reductions costs spills)
   ddv sx = {0.0, 0.0}, sv = {0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
+    const int i = i0 + q;
     if (i < n) {
       fast_two_sum(vh[q], vl[q], vh[q], vl[q]);
       const double x = xcol[i];
@@ -1282,7 +1405,7 @@ __device__ __forceinline__ void epi_v_body(
   double rmax = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
+    const int i = i0 + q;
     if (i < n) {
       double p, pe, s, e;
       const double x = xcol[i];
@@ -1291,25 +1414,13 @@ __device__ __forceinline__ void epi_v_body(
       const double res = s + (((e + vl[q]) - pe) - x * ljd.l);
       vh[q] = res;
       rmax = fmax(rmax, fabs(res));
+    } else {
+      vh[q] = 0.0;
     }
   }
   rmax = block_max<NT>(rmax, scratch);
   const int er = exp_above(rmax);
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
-    if (i < npad) {
-      const double a = (i < n) ? vh[q] : 0.0;
-      double y = ldexp(fabs(a), -er);
-      const int sg = (a < 0.0) ? -1 : 1;
-      for (int t = 0; t < kr; ++t) {
-        double t128 = y * 128.0;
-        double dgt = floor(t128);
-        y = t128 - dgt;
-        Rpl[t * P + kb_off(j, i, npad)] = (int8_t)(sg * (int)dgt);
-      }
-    }
-  }
+  write_col_planes<EPT, NT>(vh, rmax, j, npad, Rpl, kr);
   if (tid == 0) {
     lam[j] = lj;
     lam_lo[j] = ljd.l;
@@ -1545,52 +1656,68 @@ __device__ __forceinline__ void epi_w_body(
   __shared__ double scratch[2 * (NT / 64)];
   const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
+  const int i0 = erow<EPT>(tid, 0);
+  const bool live = i0 < npad;   // the thread's rows exist in the padded order
   if (j >= n) {
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + NT * q;
-      if (i < npad)
-        for (int t = 0; t < ke; ++t) Epl[t * P + kb_off(j, i, npad)] = 0;
-    }
+    double z[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) z[q] = 0.0;
+    write_col_planes<EPT, NT>(z, 0.0, j, npad, Epl, ke);
     return;
   }
   const int ej = eR[j];
   const double lj = lam[j], ljl = lam_lo[j];
   const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
-  const int32_t *Ccol = C + (size_t)j * npad;
+  const int32_t *Ccol = C + (size_t)j * npad + i0;
   const int T = npad >> 8;
-  double ev[EPT], wq[EPT];
-  int eiq[EPT], ndq[EPT];
+  double ev[EPT], wq[EPT], lmv[EPT], llv[EPT];
+  int eiq[EPT], ndq[EPT], exv[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
+    exv[q] = 0;
+    lmv[q] = llv[q] = 0.0;
+  }
+  if (live) {   // values of rows >= n are not used
+    load_i32v<EPT>(eX + i0, exv);
+    load_f64v<EPT>(lam + i0, lmv);
+    load_f64v<EPT>(lam_lo + i0, llv);
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int i = i0 + q;
     wq[q] = 0.0;
-    eiq[q] = (i < n) ? eX[i] + ej : 0;
+    eiq[q] = (i < n) ? exv[q] + ej : 0;
     ndq[q] = w_ndiag(dcut, tcut, T, ndiag_all, d_min, i, j);
   }
   // as in the V epilogue: with few entries per thread the diagonals' values are loaded kPD
-  // at a time; with many, the next diagonal is loaded while this one is summed
+  // at a time; with many, kD diagonals are in flight in a ring (smallest scale first)
   if constexpr (EPT >= 4) {
-    int32_t cv[EPT], cn[EPT];
+    constexpr int kD = 3;
+    int32_t ring[kD][EPT];
+    auto loadd = [&](int qq, int32_t (&v)[EPT]) {
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + NT * q;
-      cv[q] = (i < n && ndiag > 0) ? Ccol[(size_t)(ndiag - 1) * P + i] : 0;
-    }
-#pragma unroll 1
-    for (int qq = ndiag - 1; qq >= 0; --qq) {
-      if (qq > 0) {
-        const int32_t *Cn = Ccol + (size_t)(qq - 1) * P;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-          const int i = tid + NT * q;
-          cn[q] = (i < n) ? Cn[i] : 0;
-        }
-      }
+      for (int q = 0; q < EPT; ++q) v[q] = 0;
+      if (qq >= 0 && live) load_i32v<EPT>(Ccol + (size_t)qq * P, v);
 #pragma unroll
       for (int q = 0; q < EPT; ++q)
-        if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+        if (i0 + q >= n) v[q] = 0;
+    };
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) cv[q] = cn[q];
+    for (int u = 0; u < kD; ++u) loadd(ndiag - 1 - u, ring[u]);
+#pragma unroll 1
+    for (int c0 = ndiag - 1; c0 >= 0; c0 -= kD) {
+#pragma unroll
+      for (int u = 0; u < kD; ++u) {
+        const int qq = c0 - u;
+        if (qq < 0) break;
+        int32_t cv[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) cv[q] = ring[u][q];
+        loadd(qq - kD, ring[u]);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+          if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+      }
     }
   } else {
   constexpr int kPD = 16 / EPT;
@@ -1598,12 +1725,15 @@ __device__ __forceinline__ void epi_w_body(
   for (int c0 = ndiag - 1; c0 >= 0; c0 -= kPD) {
     int32_t cv[kPD][EPT];
 #pragma unroll
-    for (int u = 0; u < kPD; ++u)
+    for (int u = 0; u < kPD; ++u) {
+      const int qq = c0 - u;
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = tid + NT * q, qq = c0 - u;
-        cv[u][q] = (qq >= 0 && i < n) ? Ccol[(size_t)qq * P + i] : 0;
-      }
+      for (int q = 0; q < EPT; ++q) cv[u][q] = 0;
+      if (qq >= 0 && live) load_i32v<EPT>(Ccol + (size_t)qq * P, cv[u]);
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        if (i0 + q >= n) cv[u][q] = 0;
+    }
 #pragma unroll
     for (int u = 0; u < kPD; ++u) {
       const int qq = c0 - u;
@@ -1618,16 +1748,16 @@ __device__ __forceinline__ void epi_w_body(
   int tie = 0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + NT * q;
+    const int i = i0 + q;
     ev[q] = 0.0;
     if (i < n) {
-      const int ei = eX[i];
+      const int ei = exv[q];
       const double w = wq[q];
       double e;
       if (i == j) {
         e = 0.5 * r[j];
       } else {
-        const double den = dd_diff(lj, ljl, lam[i], lam_lo[i]);
+        const double den = dd_diff(lj, ljl, lmv[q], llv[q]);
         if (den == 0.0) {
           tie = 1;
           e = 0.0;
@@ -1771,7 +1901,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_group_fix(
   int tie = 0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int i = tid + kEpiThreads * q;
+    const int i = erow<EPT>(tid, q);
     ev[q] = 0.0;
     if (i < n) {
       int in = -1;
