@@ -2677,7 +2677,7 @@ __global__ __launch_bounds__(1024) void k_worklist_g(const GProb *__restrict__ g
 // The products of a grouped batch: persistent blocks take items from the list in order (one
 // atomic counter) until it is exhausted.
 template <int TILE, int WHICH>
-__global__ __launch_bounds__(256, TILE == 256 ? 1 : 2) void k_gemm_g(
+__global__ __launch_bounds__(256, TILE == 256 ? 1 : 3) void k_gemm_g(
     const GProb *__restrict__ gp, const int2 *__restrict__ items, const int *__restrict__ total,
     int *__restrict__ ctr) {
   __shared__ int s_w;

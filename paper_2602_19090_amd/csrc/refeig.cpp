@@ -1620,7 +1620,7 @@ int time_tiles(int npad, char *scratch, size_t bytes, hipStream_t s) {
     for (int rep = 0; rep < 3 && ok; ++rep) {
       launch_worklist_g(gp, 0, G, 2, tiles[v], items, cnt, cnt + 1, s);
       ok = hipEventRecord(e0, s) == hipSuccess;
-      launch_gemm_g(gp, tiles[v], tiles[v] == 256 ? 256 : 512, items, cnt, cnt + 1, 2, s);
+      launch_gemm_g(gp, tiles[v], tiles[v] == 256 ? 256 : 768, items, cnt, cnt + 1, 2, s);
       float ms = 0.0f;
       ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
            hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
@@ -1734,7 +1734,7 @@ void prepare_chunk(ChunkPlan &cp, const std::vector<int> &ids, const int *n,
     }
   }
   cp.blocks256 = (int)std::min<size_t>(256, cp.cap256);
-  cp.blocks128 = (int)std::min<size_t>(512, cap128);
+  cp.blocks128 = (int)std::min<size_t>(768, cap128);   // three blocks per CU
 }
 
 // Enqueues iterations it0 .. it1 - 1 (it0 == 0 also enqueues the once-per-solve steps); with
