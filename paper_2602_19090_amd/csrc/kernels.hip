@@ -1118,22 +1118,20 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
   const int i0 = erow<EPT>(threadIdx.x, 0);
   if (i0 >= npad) return;
   const int ee = exp_above(ms);
+  // digits of the signed value: truncation toward zero gives each digit the value's sign and
+  // the magnitude floor(|.|) would, and leaves a remainder of the same sign (all exact)
   double y[EPT];
-  int sg[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    y[q] = ldexp(fabs(v[q]), -ee);
-    sg[q] = (v[q] < 0.0) ? -1 : 1;
-  }
+  for (int q = 0; q < EPT; ++q) y[q] = ldexp(v[q], -ee);
   int8_t *dst = planes + kb_off(j, i0, npad);
   for (int t = 0; t < k; ++t) {
     int d[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const double t128 = y[q] * 128.0;
-      const double dgt = floor(t128);
+      const double dgt = trunc(t128);
       y[q] = t128 - dgt;
-      d[q] = sg[q] * (int)dgt;
+      d[q] = (int)dgt;
     }
     store_i8v<EPT>(dst + (size_t)t * P, d);
   }
@@ -1187,11 +1185,12 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
     else w.x = (uint8_t)p[0];
     return w;
   };
+  // (rows >= n carry the zero padding's residues; their results are discarded by the caller)
   auto unpack = [&](uint2 w, int (&v)[EPT]) {
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const uint32_t word = q < 4 ? w.x : w.y;
-      v[q] = (i0 + q < n) ? (int)(int8_t)(word >> (8 * (q & 3))) : 0;
+      v[q] = (int)(int8_t)(word >> (8 * (q & 3)));
     }
   };
   uint2 ra[kD], rb[kD];
@@ -1213,21 +1212,21 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
       const int tn = t + kD;
       ra[u] = tn < T ? loadw(2 * tn) : uint2{0u, 0u};
       rb[u] = (tn < T && 2 * tn + 1 < N) ? loadw(2 * tn + 1) : uint2{0u, 0u};
-      const bool pair = 2 * t + 1 < N;   // else a single last slot
+      const bool pair = 2 * t + 1 < N;   // else a single last slot (its r_b loads as 0)
       double L[kCrtLimbs];
 #pragma unroll
       for (int k = 0; k < kCrtLimbs; ++k) L[k] = sL[t * kCrtLimbs + k];
+      // a single slot takes m_a = 0, m_a^-1 = 0: c = r_a
       const float ma = pair ? sma[t] : 0.0f, mb = pair ? smb[t] : 1.0f;
       const float inv = pair ? sinv[t] : 0.0f, rmb = pair ? srmb[t] : 0.0f;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15
-        double rq = (double)ca[q];
-        if (pair) {
-          const float d = (float)(cb[q] - ca[q]) * inv;   // |d| < 2^16, exact
-          const float tt = d - mb * rintf(d * rmb);
-          rq = (double)ca[q] + (double)ma * (double)tt;
-        }
+        // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15;
+        // every step is exact in FP32: |d| < 2^16, |tt| <= m_b / 2, |c| < 2^16
+        const float fa = (float)ca[q], fb = (float)cb[q];
+        const float d = (fb - fa) * inv;
+        const float tt = fmaf(-mb, rintf(d * rmb), d);
+        const double rq = (double)fmaf(ma, tt, fa);
 #pragma unroll
         for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
       }
