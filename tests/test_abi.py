@@ -58,6 +58,17 @@ def test_host_only_entry_points(lib):
         rb.herm_workspace_bytes(4097)
 
 
+def test_mfma_probe_rejects_bad_arguments_without_a_gpu():
+    """refeig_mfma_ceiling checks its arguments before any HIP call."""
+    import ctypes
+    from paper_2602_19090_amd import binding as rb
+    out = [ctypes.c_double() for _ in range(3)]
+    for variant, seconds in ((3, 0.1), (-1, 0.1), (0, 0.0), (0, 11.0)):
+        st = rb._lib.refeig_mfma_ceiling(variant, seconds, None, *[ctypes.byref(o) for o in out])
+        assert st == rb.REFEIG_E_ARG, (variant, seconds, st)
+    assert rb._lib.refeig_mfma_ceiling(0, 0.1, None, None, None, None) == rb.REFEIG_E_ARG
+
+
 def _c_layout(struct, fields):
     """sizeof and offsetof of a header struct, from a C program that gcc builds."""
     import subprocess

@@ -153,3 +153,17 @@ def test_slice_gemm_rejects_overflow_and_bad_args():
     assert st == rb.REFEIG_E_ARG
     st, _ = rb.slice_gemm(Lp, Lp, 256, 2, 2, 2, 4)        # diagonal 5 > kl + kr
     assert st == rb.REFEIG_E_ARG
+
+
+def test_mfma_ceiling_probe():
+    """The matrix-core probe runs and reports a rate and clock in the hardware's range: at most
+    the dense INT8 peak (5.0 POP/s at 2.4 GHz), the clock below the nominal 2.4 GHz."""
+    from paper_2602_19090_amd import binding as rb
+    for variant in (0, 1, 2):
+        st, ms, pops, ghz = rb.mfma_ceiling(variant, 0.05)
+        print("variant", variant, "ms", round(ms, 2), "POP/s", round(pops, 3), "GHz", round(ghz, 3),
+              flush=True)
+        assert st == rb.REFEIG_OK
+        assert 0.3 < pops <= 5.0 and 0.5 < ghz <= 2.5 and ms > 0.0
+        # the rate cannot exceed what the reported clock allows (1024 SIMDs x 2048 ops/cycle)
+        assert pops <= 1024 * 2048 * ghz * 1e9 / 1e15 * 1.02
