@@ -35,6 +35,18 @@ __device__ __forceinline__ size_t kb_off(int m, int k, int rows) {
   return ((size_t)(k >> 6) * rows + m) * 64 + (k & 63);
 }
 
+// Global-memory view of a pointer that the compiler cannot place itself (pointers read from a
+// descriptor are generic): loads and stores through it are global, not flat, instructions, so
+// they count in vmcnt only and an LDS wait does not also wait for them.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 // ---------------------------------------------------------------- scalar helpers
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
   s = a + b;
@@ -435,19 +447,35 @@ __device__ __forceinline__ void gemm128_item(const int8_t *__restrict__ Lp,
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
 
   v4i gL[4], gR[4];
-  auto load = [&](int t) {
-    const int p = t / KT, k0 = (t - p * KT) * GBK;
-    const int s = s_lo + p;
-    const int8_t *Lb = Lp + (size_t)(s - 1) * pstride;
-    const int8_t *Rb = Rp + (size_t)(roff + rsum - s - 1) * pstride;
+  // thread's 16 bytes h of a stage: row c/8, bytes 16 (c%8) of the stage's 128 (c = tid + 256h),
+  // i.e. K-block (c%8)/4 of the stage at kb_off(row, 16 (c%4)): a fixed offset from the stage's
+  // first K-block. Stages are loaded in order: the next is K-block 2 ik of pair s_lo + ip,
+  // whose first K-block starts at lsrc / rsrc (the next pair's L plane follows, R precedes).
+  uint32_t hoff[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
+    hoff[h] = (uint32_t)((col >> 6) * npad * 64 + row * 64 + (col & 63));
+  }
+  const size_t kstride = (size_t)npad * GBK;   // two 64-deep K-blocks
+  const int8_t *lpair = Lp + (size_t)(s_lo - 1) * pstride + (size_t)m0 * 64;
+  const int8_t *rpair = Rp + (size_t)(roff + rsum - s_lo - 1) * pstride + (size_t)n0 * 64;
+  const int8_t *lsrc = lpair, *rsrc = rpair;
+  int ik = 0;
+  auto load = [&]() {
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      const int c = tid + 256 * h, row = c >> 3, col = (c & 7) * 16;
-      gL[h] = *(const v4i *)(Lb + kb_off(m0 + row, k0 + col, npad));
-      gR[h] = *(const v4i *)(Rb + kb_off(n0 + row, k0 + col, npad));
+      gL[h] = *gview((const v4i *)(lsrc + hoff[h]));
+      gR[h] = *gview((const v4i *)(rsrc + hoff[h]));
     }
+    const bool wrap = ++ik == KT;
+    ik = wrap ? 0 : ik;
+    lpair = wrap ? lpair + pstride : lpair;
+    rpair = wrap ? rpair - pstride : rpair;
+    lsrc = wrap ? lpair : lsrc + kstride;
+    rsrc = wrap ? rpair : rsrc + kstride;
   };
-  if (npairs > 0) load(0);
+  if (npairs > 0) load();
   for (int t = 0; t < T; ++t) {
     __syncthreads();
 #pragma unroll
@@ -457,7 +485,7 @@ __device__ __forceinline__ void gemm128_item(const int8_t *__restrict__ Lp,
       *(v4i *)(sR + row * GLDS + col) = gR[h];
     }
     __syncthreads();
-    if (t + 1 < T) load(t + 1);
+    if (t + 1 < T) load();
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 32) {
       v4i a[2], b[2];
@@ -474,7 +502,7 @@ __device__ __forceinline__ void gemm128_item(const int8_t *__restrict__ Lp,
     }
   }
   if (mods) {   // residue products: the slot's value mod m_slot as INT8 (as the 256 kernel)
-    int8_t *Cq8 = (int8_t *)C + (size_t)slot * npad * npad;
+    auto Cq8 = gview_w((int8_t *)C + (size_t)slot * npad * npad);
     const double m = (double)mods[slot], rm = 1.0 / m;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -489,7 +517,7 @@ __device__ __forceinline__ void gemm128_item(const int8_t *__restrict__ Lp,
         }
     return;
   }
-  int32_t *Cq = C + (size_t)slot * npad * npad;
+  auto Cq = gview_w(C + (size_t)slot * npad * npad);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -844,7 +872,7 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
     if (tt + 1 < T) stage(Tail(), tt + 1, fA[1], fB[1], fA[0], fB[0]);
   }
   if (!F8 && mods) {   // residue products: store the slot's value mod m_slot (|r| <= 127) as INT8
-    int8_t *Cq8 = (int8_t *)C + (size_t)slot * npad * npad;
+    auto Cq8 = gview_w((int8_t *)C + (size_t)slot * npad * npad);
     const double m = (double)mods[slot], rm = 1.0 / m;
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -859,7 +887,7 @@ __device__ __forceinline__ void gemm256_item(const int8_t *__restrict__ Lp,
         }
     return;
   }
-  int32_t *Cq = C + (size_t)slot * npad * npad;
+  auto Cq = gview_w(C + (size_t)slot * npad * npad);
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
