@@ -1060,25 +1060,28 @@ __device__ __forceinline__ int erow(int tid, int q) {
   return EPT * tid + q;
 }
 // EPT consecutive values at p (aligned to their total size), integers sign-extended from int8
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <int EPT>
 __device__ __forceinline__ void load_i8v(const int8_t *__restrict__ p, int (&v)[EPT]) {
   if constexpr (EPT == 8) {
-    const uint2 w = *(const uint2 *)p;
+    const u32x2 w = *gview((const u32x2 *)p);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       v[e] = (int)(int8_t)(w.x >> (8 * e));
       v[4 + e] = (int)(int8_t)(w.y >> (8 * e));
     }
   } else if constexpr (EPT == 4) {
-    const uint32_t w = *(const uint32_t *)p;
+    const uint32_t w = *gview((const uint32_t *)p);
 #pragma unroll
     for (int e = 0; e < 4; ++e) v[e] = (int)(int8_t)(w >> (8 * e));
   } else if constexpr (EPT == 2) {
-    const uint32_t w = *(const uint16_t *)p;
+    const uint32_t w = *gview((const uint16_t *)p);
     v[0] = (int)(int8_t)w;
     v[1] = (int)(int8_t)(w >> 8);
   } else {
-    v[0] = p[0];
+    v[0] = *gview(p);
   }
 }
 template <int EPT>
@@ -1086,18 +1089,18 @@ __device__ __forceinline__ void load_i32v(const int32_t *__restrict__ p, int32_t
   if constexpr (EPT >= 4) {
 #pragma unroll
     for (int h = 0; h < EPT / 4; ++h) {
-      const int4 w = ((const int4 *)p)[h];
+      const v4i w = gview((const v4i *)p)[h];
       v[4 * h] = w.x;
       v[4 * h + 1] = w.y;
       v[4 * h + 2] = w.z;
       v[4 * h + 3] = w.w;
     }
   } else if constexpr (EPT == 2) {
-    const int2 w = *(const int2 *)p;
+    const i32x2 w = *gview((const i32x2 *)p);
     v[0] = w.x;
     v[1] = w.y;
   } else {
-    v[0] = p[0];
+    v[0] = *gview(p);
   }
 }
 template <int EPT>
@@ -1105,34 +1108,34 @@ __device__ __forceinline__ void load_f64v(const double *__restrict__ p, double (
   if constexpr (EPT >= 2) {
 #pragma unroll
     for (int h = 0; h < EPT / 2; ++h) {
-      const double2 w = ((const double2 *)p)[h];
+      const f64x2 w = gview((const f64x2 *)p)[h];
       v[2 * h] = w.x;
       v[2 * h + 1] = w.y;
     }
   } else {
-    v[0] = p[0];
+    v[0] = *gview(p);
   }
 }
 // the low bytes of d[0..EPT) packed in order and stored at p (aligned to EPT bytes)
 template <int EPT>
 __device__ __forceinline__ void store_i8v(int8_t *__restrict__ p, const int (&d)[EPT]) {
   if constexpr (EPT == 8) {
-    uint2 w = {0u, 0u};
+    u32x2 w = {0u, 0u};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       w.x |= ((uint32_t)d[e] & 255u) << (8 * e);
       w.y |= ((uint32_t)d[4 + e] & 255u) << (8 * e);
     }
-    *(uint2 *)p = w;
+    *gview_w((u32x2 *)p) = w;
   } else if constexpr (EPT == 4) {
     uint32_t w = 0u;
 #pragma unroll
     for (int e = 0; e < 4; ++e) w |= ((uint32_t)d[e] & 255u) << (8 * e);
-    *(uint32_t *)p = w;
+    *gview_w((uint32_t *)p) = w;
   } else if constexpr (EPT == 2) {
-    *(uint16_t *)p = (uint16_t)(((uint32_t)d[0] & 255u) | (((uint32_t)d[1] & 255u) << 8));
+    *gview_w((uint16_t *)p) = (uint16_t)(((uint32_t)d[0] & 255u) | (((uint32_t)d[1] & 255u) << 8));
   } else {
-    p[0] = (int8_t)d[0];
+    *gview_w(p) = (int8_t)d[0];
   }
 }
 
@@ -1207,10 +1210,14 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
     uint2 w = {0u, 0u};
     if (!live) return w;
     const int8_t *p = Ccol + (size_t)s * P + i0;
-    if constexpr (EPT == 8) w = *(const uint2 *)p;
-    else if constexpr (EPT == 4) w.x = *(const uint32_t *)p;
-    else if constexpr (EPT == 2) w.x = *(const uint16_t *)p;
-    else w.x = (uint8_t)p[0];
+    if constexpr (EPT == 8) {
+      const u32x2 v2 = *gview((const u32x2 *)p);
+      w.x = v2.x;
+      w.y = v2.y;
+    }
+    else if constexpr (EPT == 4) w.x = *gview((const uint32_t *)p);
+    else if constexpr (EPT == 2) w.x = *gview((const uint16_t *)p);
+    else w.x = (uint8_t)*gview(p);
     return w;
   };
   // (rows >= n carry the zero padding's residues; their results are discarded by the caller)
@@ -1413,7 +1420,7 @@ __device__ __forceinline__ void epi_v_body(
     const int i = i0 + q;
     if (i < n) {
       fast_two_sum(vh[q], vl[q], vh[q], vl[q]);
-      const double x = xcol[i];
+      const double x = *gview(xcol + i);
       double p, pe;
       two_prod(x, x, p, pe);
       sx = dd_add_prod(sx, p, pe);
@@ -1435,7 +1442,7 @@ __device__ __forceinline__ void epi_v_body(
     const int i = i0 + q;
     if (i < n) {
       double p, pe, s, e;
-      const double x = xcol[i];
+      const double x = *gview(xcol + i);
       two_prod(x, lj, p, pe);
       two_sum(vh[q], -p, s, e);
       const double res = s + (((e + vl[q]) - pe) - x * ljd.l);
