@@ -332,13 +332,12 @@ int refeig_host_beta(int n, const double *lam, const int *e, const int *c, const
  * solver builds it: *N moduli (odd, pairwise coprime, <= 255, largest first)
  * with prod m_q > 4 npad 128^(ka1 + kx); digit weights wA[q*18 + t] =
  * 128^(ka1-1-t) mod m_q and wX[q*18 + t] = 128^(kx-1-t) mod m_q in the
- * symmetric range; the reconstruction sums (N + 1) / 2 terms, term t for the
- * moduli 2t and 2t + 1 (the last one alone when N is odd) with modulus M_t:
- * U[3t..3t+2] = Y_t / M_t as a triple-double, Y_t = (M / M_t)^-1 mod M_t;
- * L[4t..4t+3] = the 34-bit limbs of Y_t / M_t, floor(Y_t / M_t 2^(34(k+1))) mod
- * 2^34 for k = 0..3 (integers in doubles; the V epilogue sums c_t L[t][k]);
+ * symmetric range; the reconstruction sums N terms, one per modulus:
+ * U[3q..3q+2] = y_q / m_q as a triple-double, y_q = (M / m_q)^-1 mod m_q;
+ * L[4q..4q+3] = the 34-bit limbs of y_q / m_q, floor(y_q / m_q 2^(34(k+1))) mod
+ * 2^34 for k = 0..3 (integers in doubles; the V epilogue sums r_q L[q][k]);
  * M[0..2] = prod m_q (double-word, M[2] = 0). Arrays hold 28 moduli
- * (moduli: 28, wA, wX: 28*18, U: 14*3, L: 14*4 entries).
+ * (moduli: 28, wA, wX: 28*18, U: 28*3, L: 28*4 entries).
  * Returns REFEIG_E_ARG when more than 28 moduli would be needed. */
 int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA, int *wX,
                          double *U, double *L, double *M);

@@ -462,14 +462,14 @@ def host_beta(lam, e, c, mx, target, opts: Opts | None = None):
 
 def host_crt_plan(npad: int, ka1: int, kx: int):
     """The residue-product plan of V (refeig_host_crt_plan): dict with moduli, wA, wX (N x 18),
-    U ((N + 1) / 2 x 3, per reconstruction term), L ((N + 1) / 2 x 4, the 34-bit limbs of the
-    same terms) and M (3)."""
+    U (N x 3, y_q / m_q per modulus), L (N x 4, the 34-bit limbs of the same fractions) and
+    M (3)."""
     N = _int(0)
     mods = np.zeros(28, dtype=np.int32)
     wA = np.zeros(28 * 18, dtype=np.int32)
     wX = np.zeros(28 * 18, dtype=np.int32)
-    u = np.zeros(42)
-    lim = np.zeros(56)
+    u = np.zeros(84)
+    lim = np.zeros(112)
     M = np.zeros(3)
     st = _lib.refeig_host_crt_plan(int(npad), int(ka1), int(kx), ctypes.byref(N), _np_ptr(mods),
                                    _np_ptr(wA), _np_ptr(wX), _np_ptr(u), _np_ptr(lim), _np_ptr(M))
@@ -477,7 +477,7 @@ def host_crt_plan(npad: int, ka1: int, kx: int):
         raise ValueError(strerror(st))
     n = N.value
     return {"moduli": mods[:n].tolist(), "wA": wA.reshape(28, 18)[:n], "wX": wX.reshape(28, 18)[:n],
-            "U": u.reshape(14, 3)[:(n + 1) // 2], "L": lim.reshape(14, 4)[:(n + 1) // 2], "M": M}
+            "U": u.reshape(28, 3)[:n], "L": lim.reshape(28, 4)[:n], "M": M}
 
 
 def host_column_order(lam):

@@ -510,13 +510,11 @@ __device__ __forceinline__ void dp_vplan_body(PlanParams p, PlanBufs b) {
     if (s_ok && threadIdx.x < kVLevels && st.ka_l[threadIdx.x] > 0)
       crt_rec_head(st.N_l[threadIdx.x], st.ka_l[threadIdx.x], kx, st.recs[threadIdx.x]);
     __syncthreads();
-    if (s_ok) {   // the per-modulus and per-pair fields, one thread each
-      constexpr int kPer = kCrtMax + kCrtMax / 2 + 1;
-      for (int i = threadIdx.x; i < kVLevels * kPer; i += kPT) {
-        const int l = i / kPer, r = i - l * kPer;
+    if (s_ok) {   // the per-modulus fields, one thread each
+      for (int i = threadIdx.x; i < kVLevels * kCrtMax; i += kPT) {
+        const int l = i / kCrtMax, r = i - l * kCrtMax;
         if (st.ka_l[l] <= 0) continue;
-        if (r < kCrtMax) crt_rec_modulus(r, st.recs[l]);
-        else crt_rec_pair(r - kCrtMax, st.recs[l]);
+        crt_rec_modulus(r, st.recs[l]);
       }
     }
     __syncthreads();

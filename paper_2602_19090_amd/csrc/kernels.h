@@ -135,17 +135,10 @@ struct CrtRec {
   double rm[kCrtMax];             // fl(1 / m_q)
   double u[kCrtMax][3];           // y_q / m_q in triple-double, y_q = (M / m_q)^-1 mod m_q
   double M[3];                    // M = prod m_q in triple-double
-  // The epilogue combines slots 2t and 2t + 1 into one residue modulo m_2t m_2t+1 (exactly,
-  // in FP32: (r_b - r_a) inv_t stays below 2^24) and sums T terms c_t U_t, U_t = Y_t / M_t,
-  // Y_t = (M / M_t)^-1 mod M_t; an odd last slot is a term of its own.
-  int T;
-  float pinv[kCrtMax / 2];        // m_2t^-1 mod m_2t+1
-  float pmb[kCrtMax / 2], prmb[kCrtMax / 2];   // m_2t+1 and fl32(1 / m_2t+1)
-  float pma[kCrtMax / 2];         // m_2t
-  double U[kCrtMax / 2 + 1][3];   // triple-double
-  // U_t truncated to kCrtLimbs limbs of kCrtLimbBits bits: U_t ~ sum_k L[t][k] 2^(-34 (k + 1)),
-  // each L an integer below 2^34 held exactly in a double (what the epilogue sums)
-  double L[kCrtMax / 2 + 1][kCrtLimbs];
+  // The epilogue sums the N terms r_q u_q (r_q = the product mod m_q, symmetric) with u_q
+  // truncated to kCrtLimbs limbs of kCrtLimbBits bits: u_q ~ sum_k L[q][k] 2^(-34 (k + 1)),
+  // each L an integer below 2^34 held exactly in a double
+  double L[kCrtMax][kCrtLimbs];
 };
 // V epilogue as launch_epi_v, with V rebuilt from the residues of the products (INT8 slot q
 // of stride npad^2 bytes, reduced mod m_q by the GEMM) instead of summed from slice diagonals.

@@ -1169,42 +1169,34 @@ __device__ __forceinline__ void write_col_planes(const double (&v)[EPT], double 
 }
 
 // ---------------------------------------------------------------- V epilogue + column pass
-// Triple-double reconstruction of P from its residues c_q = C_q mod m_q (symmetric), for
-// the EPT rows of a thread: P / M = frac(sum_q c_q u_q) in [-1/2, 1/2), kept as
-// s0 + s1 + s2 (absolute error about 2^-150: every product is split exactly, integer parts
-// leave s0 exactly), then V = (P / M) M 2^(scale) as a double-word (vh, vl). Moduli are the
-// outer loop, and the next modulus's slot is loaded while this one is added; s0 and s1 live
-// in vh and vl until the end.
+// Reconstruction of P from its residues r_q = C_q mod m_q (symmetric), for the EPT rows of a
+// thread: P / M = frac(sum_q r_q u_q) in [-1/2, 1/2), summed exactly in four 34-bit
+// fixed-point limbs (u_q truncated to 136 bits, an error of at most 2^-124.2), carried into
+// s0 + s1 + s2, then V = (P / M) M 2^(scale) as a double-word (vh, vl); with the double-word
+// products by M the absolute error stays below 2^-115 M (the planner's floor).
 template <int EPT, int NT = kEpiThreads>
 __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size_t P, int n,
                                            int npad, int tid, const CrtRec &rec,
                                            const int (&scale)[EPT], double (&vh)[EPT],
                                            double (&vl)[EPT]) {
   const int i0 = erow<EPT>(tid, 0);
-  // F = sum_t c_t U_t mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |c_t| < 2^15, so
-  // c_t L[t][k] is an integer below 2^49 and at most 14 of them sum below 2^52.9: every limb
-  // sum is exact. Truncating U_t to 136 bits moves F by at most 14 2^15 2^-136 = 2^-117.2.
-  // the record's per-term constants, staged in LDS (every thread reads all of them)
-  constexpr int kT = kCrtMax / 2 + 1;
-  __shared__ double sL[kT * kCrtLimbs];
-  __shared__ float sma[kT], smb[kT], sinv[kT], srmb[kT];
-  for (int e = threadIdx.x; e < kT * kCrtLimbs; e += NT) sL[e] = rec.L[e / kCrtLimbs][e % kCrtLimbs];
-  for (int e = threadIdx.x; e < kCrtMax / 2; e += NT) {
-    sma[e] = rec.pma[e];
-    smb[e] = rec.pmb[e];
-    sinv[e] = rec.pinv[e];
-    srmb[e] = rec.prmb[e];
-  }
-  const int T = rec.T, N = rec.N;
+  // F = sum_q r_q u_q mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |r_q| <= 127, so
+  // r_q L[q][k] is an integer below 2^41 and at most 28 of them sum below 2^45.9: every limb
+  // sum is exact. Truncating u_q to 136 bits moves F by at most 28 127 2^-136 = 2^-124.2.
+  // The record's limbs, staged in LDS (every thread reads all of them).
+  __shared__ double sL[kCrtMax * kCrtLimbs];
+  for (int e = threadIdx.x; e < kCrtMax * kCrtLimbs; e += NT)
+    sL[e] = rec.L[e / kCrtLimbs][e % kCrtLimbs];
+  const int N = rec.N;
   __syncthreads();
   double a[EPT][kCrtLimbs];
 #pragma unroll
   for (int q = 0; q < EPT; ++q)
 #pragma unroll
     for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
-  // The slots' EPT bytes per thread are one packed load each (loadw); kD pairs of slots are
-  // in flight, in a ring of packed words unpacked where they are used; terms in order.
-  constexpr int kD = EPT >= 8 ? 3 : EPT >= 4 ? 6 : 8;
+  // A slot's EPT bytes per thread are one packed load (loadw); kD slots are in flight, in a
+  // ring of packed words unpacked where they are used; terms in order of the moduli.
+  constexpr int kD = EPT >= 8 ? 6 : EPT >= 4 ? 8 : 12;
   const bool live = i0 < npad;
   auto loadw = [&](int s) -> uint2 {
     uint2 w = {0u, 0u};
@@ -1220,50 +1212,28 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
     else w.x = (uint8_t)*gview(p);
     return w;
   };
-  // (rows >= n carry the zero padding's residues; their results are discarded by the caller)
-  auto unpack = [&](uint2 w, int (&v)[EPT]) {
+  uint2 ring[kD];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const uint32_t word = q < 4 ? w.x : w.y;
-      v[q] = (int)(int8_t)(word >> (8 * (q & 3)));
-    }
-  };
-  uint2 ra[kD], rb[kD];
-#pragma unroll
-  for (int u = 0; u < kD; ++u) {
-    ra[u] = u < T ? loadw(2 * u) : uint2{0u, 0u};
-    rb[u] = (u < T && 2 * u + 1 < N) ? loadw(2 * u + 1) : uint2{0u, 0u};
-  }
+  for (int u = 0; u < kD; ++u) ring[u] = u < N ? loadw(u) : uint2{0u, 0u};
 #pragma unroll 1
-  for (int t0 = 0; t0 < T; t0 += kD) {
+  for (int q0 = 0; q0 < N; q0 += kD) {
 #pragma unroll
     for (int u = 0; u < kD; ++u) {
-      const int t = t0 + u;
-      if (t >= T) break;
-      int ca[EPT], cb[EPT];
-      unpack(ra[u], ca);
-      unpack(rb[u], cb);
-      // refill this ring place with pair t + kD
-      const int tn = t + kD;
-      ra[u] = tn < T ? loadw(2 * tn) : uint2{0u, 0u};
-      rb[u] = (tn < T && 2 * tn + 1 < N) ? loadw(2 * tn + 1) : uint2{0u, 0u};
-      const bool pair = 2 * t + 1 < N;   // else a single last slot (its r_b loads as 0)
+      const int q = q0 + u;
+      if (q >= N) break;
+      const uint2 w = ring[u];
+      // refill this ring place with slot q + kD
+      ring[u] = q + kD < N ? loadw(q + kD) : uint2{0u, 0u};
       double L[kCrtLimbs];
 #pragma unroll
-      for (int k = 0; k < kCrtLimbs; ++k) L[k] = sL[t * kCrtLimbs + k];
-      // a single slot takes m_a = 0, m_a^-1 = 0: c = r_a
-      const float ma = pair ? sma[t] : 0.0f, mb = pair ? smb[t] : 1.0f;
-      const float inv = pair ? sinv[t] : 0.0f, rmb = pair ? srmb[t] : 0.0f;
+      for (int k = 0; k < kCrtLimbs; ++k) L[k] = sL[q * kCrtLimbs + k];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        // residue modulo m_a m_b: c = r_a + m_a ((r_b - r_a) m_a^-1 mod m_b), |c| < 2^15;
-        // every step is exact in FP32: |d| < 2^16, |tt| <= m_b / 2, |c| < 2^16
-        const float fa = (float)ca[q], fb = (float)cb[q];
-        const float d = (fb - fa) * inv;
-        const float tt = fmaf(-mb, rintf(d * rmb), d);
-        const double rq = (double)fmaf(ma, tt, fa);
+      for (int e = 0; e < EPT; ++e) {
+        // rows >= n carry the zero padding's residues; their results are discarded
+        const uint32_t word = e < 4 ? w.x : w.y;
+        const double rq = (double)(int)(int8_t)(word >> (8 * (e & 3)));
 #pragma unroll
-        for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = fma(rq, L[k], a[q][k]);
+        for (int k = 0; k < kCrtLimbs; ++k) a[e][k] = fma(rq, L[k], a[e][k]);
       }
     }
   }

@@ -214,13 +214,11 @@ RF_HD void res_weights_build(int k, int N, ResWeights &rw) {
 }
 
 // Reconstruction record of N moduli for ka1 digits of A and kx of X^(1): V = P 2^(eA_i +
-// eX_j + sh), sh = -7 (ka1 + kx); M = prod m_q (double-word); per modulus y_q / m_q
-// (triple-double, y_q = (M / m_q)^-1 mod m_q); slots paired (2t, 2t + 1) into residues mod
-// M_t = m_2t m_2t+1 with Y_t = (M / M_t)^-1 mod M_t, U_t = Y_t / M_t as a triple-double and as
-// kCrtLimbs limbs of kCrtLimbBits bits (long division, exact in 64-bit integers).
-// crt_rec_head fills the shared fields and clears the rest; after it, crt_rec_modulus (one
-// q < kCrtMax) and crt_rec_pair (one t <= kCrtMax / 2) write disjoint fields and may run in
-// parallel; crt_rec_build runs the three in order.
+// eX_j + sh), sh = -7 (ka1 + kx); M = prod m_q (double-word); per modulus u_q = y_q / m_q
+// (triple-double, y_q = (M / m_q)^-1 mod m_q) and its kCrtLimbs limbs of kCrtLimbBits bits
+// (long division, exact in 64-bit integers): P / M = sum_q r_q u_q mod 1.
+// crt_rec_head fills the shared fields; after it, crt_rec_modulus (one q < kCrtMax each)
+// writes disjoint fields and may run in parallel; crt_rec_build runs them in order.
 RF_HD void crt_rec_head(int N, int ka1, int kx, CrtRec &rec) {
   rec.N = N;
   rec.sh = -7 * (ka1 + kx);
@@ -232,7 +230,6 @@ RF_HD void crt_rec_head(int N, int ka1, int kx, CrtRec &rec) {
     a0 = p0 + sl;
     a1 = sl - (a0 - p0);
   }
-  rec.T = (N + 1) / 2;
   rec.M[0] = a0;
   rec.M[1] = a1;
   rec.M[2] = 0.0;
@@ -242,62 +239,29 @@ RF_HD void crt_rec_modulus(int q, CrtRec &rec) {
   rec.m[q] = q < N ? modulus(q) : 1;
   rec.rm[q] = q < N ? 1.0 / (double)rec.m[q] : 0.0;
   rec.u[q][0] = rec.u[q][1] = rec.u[q][2] = 0.0;
+  for (int k = 0; k < kCrtLimbs; ++k) rec.L[q][k] = 0.0;
   if (q >= N) return;
   const int m = modulus(q);
   unsigned Mq = 1;   // (M / m_q) mod m_q; products below 2^16
   for (int l = 0; l < N; ++l)
     if (l != q) Mq = Mq * ((unsigned)modulus(l) % (unsigned)m) % (unsigned)m;
-  const double y = (double)inv_mod_i((int)Mq, m), md = (double)m;
+  const int yi = inv_mod_i((int)Mq, m);
+  const double y = (double)yi, md = (double)m;
   const double u0 = y / md, r0 = fma(-u0, md, y);
   const double u1 = r0 / md, r1 = fma(-u1, md, r0);
   rec.u[q][0] = u0;
   rec.u[q][1] = u1;
   rec.u[q][2] = r1 / md;
-}
-RF_HD void crt_rec_pair(int t, CrtRec &rec) {
-  const int N = rec.N;
-  if (t < kCrtMax / 2) rec.pinv[t] = rec.pmb[t] = rec.prmb[t] = rec.pma[t] = 0.0f;
-  for (int k = 0; k < 3; ++k) rec.U[t][k] = 0.0;
-  for (int k = 0; k < kCrtLimbs; ++k) rec.L[t][k] = 0.0;
-  if (t >= (N + 1) / 2) return;
-  const int qa = 2 * t, qb = 2 * t + 1;
-  long long Mt = modulus(qa);
-  if (qb < N) {
-    Mt *= modulus(qb);
-    rec.pma[t] = (float)modulus(qa);
-    rec.pmb[t] = (float)modulus(qb);
-    rec.prmb[t] = 1.0f / (float)modulus(qb);
-    rec.pinv[t] = (float)inv_mod_i(modulus(qa) % modulus(qb), modulus(qb));
-  }
-  const unsigned Mtu = (unsigned)Mt;   // below 2^16
-  unsigned rest = 1;                   // (M / M_t) mod M_t; products below 2^32
-  for (int l = 0; l < N; ++l)
-    if (l != qa && l != qb) rest = rest * ((unsigned)modulus(l) % Mtu) % Mtu;
-  int r0 = (int)Mtu, r1 = (int)(rest % Mtu), t0 = 0, t1 = 1;   // Y_t = rest^-1 mod M_t
-  while (r1) {
-    const int qq = r0 / r1, r2 = r0 - qq * r1, t2 = t0 - qq * t1;
-    r0 = r1;
-    r1 = r2;
-    t0 = t1;
-    t1 = t2;
-  }
-  const double Y = (double)(t0 < 0 ? t0 + (int)Mtu : t0), Md = (double)Mt;
-  const double v0 = Y / Md, q0 = fma(-v0, Md, Y);
-  const double v1 = q0 / Md, q1 = fma(-v1, Md, q0);
-  rec.U[t][0] = v0;
-  rec.U[t][1] = v1;
-  rec.U[t][2] = q1 / Md;
-  unsigned long long rem = (unsigned long long)(t0 < 0 ? t0 + (int)Mtu : t0);
-  for (int k = 0; k < kCrtLimbs; ++k) {   // rem < M_t < 2^16: num < 2^(16 + limb bits)
+  unsigned long long rem = (unsigned long long)yi;   // < m < 2^8: num < 2^(8 + limb bits)
+  for (int k = 0; k < kCrtLimbs; ++k) {
     const unsigned long long num = rem << kCrtLimbBits;
-    rec.L[t][k] = (double)(num / Mtu);
-    rem = num % Mtu;
+    rec.L[q][k] = (double)(num / (unsigned)m);
+    rem = num % (unsigned)m;
   }
 }
 RF_HD void crt_rec_build(int N, int ka1, int kx, CrtRec &rec) {
   crt_rec_head(N, ka1, kx, rec);
   for (int q = 0; q < kCrtMax; ++q) crt_rec_modulus(q, rec);
-  for (int t = 0; t < kCrtMax / 2 + 1; ++t) crt_rec_pair(t, rec);
 }
 
 // Block -> (row block, column block) of a launch over tiles_m row blocks x tiles_n column

@@ -2369,8 +2369,8 @@ int refine_eigvecs(const double *A, int lda, double *X, int ldx, double *D, int 
       for (int l = 0; l < kVLevels && ok; ++l)
         if (ka_l[l] > 0) ok = crt_plan(npad, ka_l[l], kx, wA[l], l == 0 ? wX : wXl, rec[l],
                                        hbits);
-      // The reconstruction resolves P to within 2^-115 M (four 34-bit limbs of at most 14
-      // terms), so V_ij carries up to 2^(eA_max + eX_j + sh - 115) M of it. Where that is not
+      // The reconstruction resolves P to within 2^-115 M (the 34-bit limbs of at most 28
+      // terms lose at most 2^-124.2 M, the double-word products by M the rest), so V_ij carries up to 2^(eA_max + eX_j + sh - 115) M of it. Where that is not
       // well inside column j's share theta delta gap_j, this iteration forms V by slices.
       for (int j = 0; ok && j < n; ++j) {
         if (mxX[j] == 0.0) continue;
@@ -2807,10 +2807,10 @@ int refeig_host_crt_plan(int npad, int ka1, int kx, int *N, int *moduli, int *wA
       wX[q * kCrtPlanes + t] = x.w[q][t];
     }
   }
-  for (int t = 0; t < rec.T; ++t)
-    for (int c = 0; c < 3; ++c) U[3 * t + c] = rec.U[t][c];
-  for (int t = 0; t < rec.T; ++t)
-    for (int k = 0; k < kCrtLimbs; ++k) L[kCrtLimbs * t + k] = rec.L[t][k];
+  for (int q = 0; q < rec.N; ++q)
+    for (int c = 0; c < 3; ++c) U[3 * q + c] = rec.u[q][c];
+  for (int q = 0; q < rec.N; ++q)
+    for (int k = 0; k < kCrtLimbs; ++k) L[kCrtLimbs * q + k] = rec.L[q][k];
   for (int c = 0; c < 3; ++c) M[c] = rec.M[c];
   return REFEIG_OK;
 }
