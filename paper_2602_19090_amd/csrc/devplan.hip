@@ -625,11 +625,39 @@ __device__ __forceinline__ void dp_wplan_body(PlanParams p, PlanBufs b) {
   DevState &st = *b.st;
   DevIter &rep = st.rep[p.it < 32 ? p.it : 31];
   const int n = p.n, npad = p.npad, N2 = pow2_at_least(n), kx = st.kx;
-  for (int i = threadIdx.x; i < N2; i += kPT) {
-    key[i] = i < n ? b.lam[i] : INFINITY;
-    idx[i] = i;
+  // After the first iteration the quotients usually keep the previous iteration's order: take
+  // them in that order (its columns, through the inverse of this iteration's working order,
+  // held in dcol until the cutoffs below) and sort only if they are not strictly ascending
+  // there. Distinct keys have one sorted order, so both ways give the same key and idx.
+  __shared__ int s_sorted;
+  if (threadIdx.x == 0) s_sorted = p.it > 0 && !(*b.flags & kFlagsError);
+  __syncthreads();
+  if (s_sorted) {
+    for (int q = threadIdx.x; q < n; q += kPT) dcol[b.colmap[q]] = q;
+    __syncthreads();
+    for (int r = threadIdx.x; r < N2; r += kPT) {
+      if (r < n) {
+        const int pw = dcol[b.sidx[r]];
+        key[r] = b.lam[pw];
+        idx[r] = pw;
+      } else {
+        key[r] = INFINITY;
+        idx[r] = r;
+      }
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int r = threadIdx.x; r + 1 < n; r += kPT) bad |= !(key[r] < key[r + 1]);
+    if (bad) s_sorted = 0;   // every writer writes the same value
+    __syncthreads();
   }
-  bitonic<double>(key, idx, N2);
+  if (!s_sorted) {
+    for (int i = threadIdx.x; i < N2; i += kPT) {
+      key[i] = i < n ? b.lam[i] : INFINITY;
+      idx[i] = i;
+    }
+    bitonic<double>(key, idx, N2);
+  }
   // the sorted quotients and their columns: after this iteration D holds exactly these values
   // (the update scatters them), so the next iteration's order needs no sort of D
   for (int pp = threadIdx.x; pp < n; pp += kPT) {
