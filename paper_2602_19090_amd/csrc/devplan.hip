@@ -376,15 +376,54 @@ __device__ __forceinline__ void dp_order_body(PlanParams p, PlanBufs b) {
   __syncthreads();
   // second sort: keys ~bits(g) ascending = g descending, ties by eigenvalue rank
   unsigned long long *k2 = (unsigned long long *)key;
+  auto fill_k2 = [&]() {
 #pragma unroll
-  for (int q = 0; q < kDevSortMax / kPT; ++q) {
-    const int pp = threadIdx.x + q * kPT;
-    if (pp < N2) {
-      k2[pp] = pp < n ? ~(unsigned long long)__double_as_longlong(gl[q]) : ~0ull;
-      rk[pp] = pp;
+    for (int q = 0; q < kDevSortMax / kPT; ++q) {
+      const int pp = threadIdx.x + q * kPT;
+      if (pp < N2) {
+        k2[pp] = pp < n ? ~(unsigned long long)__double_as_longlong(gl[q]) : ~0ull;
+        rk[pp] = pp;
+      }
     }
+  };
+  fill_k2();
+  // After the first iteration the gaps usually keep the previous working order (b.colmap,
+  // not yet rewritten): put the keys in that order and sort only if (key, rank) is not
+  // strictly ascending there. The comparator orders by (key, rank), so the sorted order is
+  // unique and both ways give the same keys and ranks.
+  __shared__ int s_sorted;
+  if (threadIdx.x == 0) s_sorted = s_reuse;
+  __syncthreads();
+  if (s_sorted) {
+    constexpr int kE = kDevSortMax / kPT;
+    int rq[kE];
+    unsigned long long kq[kE];
+    for (int r = threadIdx.x; r < n; r += kPT) rk[idx[r]] = r;   // column -> rank
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int pp = threadIdx.x + q * kPT;
+      rq[q] = pp < n ? rk[b.colmap[pp]] : pp;
+      kq[q] = pp < n ? k2[rq[q]] : ~0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int pp = threadIdx.x + q * kPT;
+      if (pp < N2) {
+        k2[pp] = kq[q];
+        rk[pp] = rq[q];
+      }
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int pp = threadIdx.x; pp + 1 < n; pp += kPT)
+      bad |= !(k2[pp] < k2[pp + 1] || (k2[pp] == k2[pp + 1] && rk[pp] < rk[pp + 1]));
+    if (bad) s_sorted = 0;   // every writer writes the same value
+    __syncthreads();
+    if (!s_sorted) fill_k2();
   }
-  bitonic<unsigned long long>(k2, rk, N2);
+  if (!s_sorted) bitonic<unsigned long long>(k2, rk, N2);
   for (int q = threadIdx.x; q < p.npad; q += kPT) {
     if (q < n) {
       const int r = rk[q];
