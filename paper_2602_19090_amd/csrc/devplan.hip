@@ -876,8 +876,9 @@ __device__ __forceinline__ void residues_dev_loop(const int8_t *__restrict__ pla
         int acc = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) acc = __builtin_amdgcn_sdot4(dg[g][bb], swp[q][g], acc, false);
+        // |acc| < 2^17: a - m rint(a / m) is exact in FP32 (one rounding-free fma)
         const float a = (float)acc;
-        const int rr = (int)(a - m * rintf(a * rm));
+        const int rr = (int)fmaf(-m, rintf(a * rm), a);
         packed |= ((unsigned)(rr & 0xff)) << (8 * bb);
       }
       *(unsigned *)(res + (size_t)q * pstride + e) = packed;
