@@ -111,7 +111,7 @@ void launch_tile_cutoffs(const double *lam, const int *eX, const int *eR, const 
 // Chinese remainder theorem.
 constexpr int kCrtMax = 28;   // moduli at most (over 200 bits of product)
 constexpr int kVLevels = 4;   // digit counts of A (levels) in one residue product of V
-constexpr int kCrtLimbs = 4, kCrtLimbBits = 34;   // limbs of the CRT fractions U_t
+constexpr int kCrtLimbs = 4, kCrtLimbBits = 34;   // limbs of the CRT fractions y_q / m_q
 constexpr int kCrtPlanes = 18;
 struct ResWeights {
   int N, k;
