@@ -161,26 +161,73 @@ __device__ __forceinline__ double block_max(double v, double *scratch) {
   __syncthreads();
   if ((threadIdx.x & 63) == 0) scratch[w] = v;
   __syncthreads();
-  double m = scratch[0];
+  // over the waves' maxima: lane l takes wave l mod NW's, then an xor butterfly
+  constexpr int NW = NT / 64;
+  static_assert(NW >= 1 && NW <= 64 && (NW & (NW - 1)) == 0, "power-of-two wave count");
+  double m = scratch[threadIdx.x & (NW - 1)];
 #pragma unroll
-  for (int q = 1; q < NT / 64; ++q) m = fmax(m, scratch[q]);
+  for (int o = NW / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
   return m;
 }
-// Block-wide double-word sum in a fixed order (deterministic).
+// Across the waves of a block: lane l of every wave takes partial l mod NW from scratch (stride
+// 2 doubles) and the lanes combine them by an xor butterfly.
+template <int NW>
+__device__ __forceinline__ ddv cross_wave_dd_sum(const double *scratch, int stride) {
+  const int q = threadIdx.x & (NW - 1);
+  ddv v = {scratch[stride * q], scratch[stride * q + 1]};
+#pragma unroll
+  for (int o = NW / 2; o > 0; o >>= 1) {
+    ddv w = {__shfl_xor(v.h, o), __shfl_xor(v.l, o)};
+    v = dd_add(v, w);
+  }
+  return v;
+}
+// Block-wide double-word sums in a fixed order (deterministic); every thread gets the result.
+// Within a wave and then over the waves' partials the terms meet in xor butterflies: dd_add is
+// commutative, so every lane ends with the same value, after log2(NT) additions instead of a
+// serial pass over the waves. scratch: >= 2 (one sum) or 4 (two sums) doubles per wave.
 template <int NT>
 __device__ __forceinline__ ddv block_dd_sum(ddv v, double *scratch) {
+  constexpr int NW = NT / 64;
+  static_assert(NW >= 1 && NW <= 64 && (NW & (NW - 1)) == 0, "power-of-two wave count");
   v = wave_dd_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    scratch[2 * w] = v.h;
-    scratch[2 * w + 1] = v.l;
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      scratch[2 * w] = v.h;
+      scratch[2 * w + 1] = v.l;
+    }
+    __syncthreads();
+    return cross_wave_dd_sum<NW>(scratch, 2);
   }
-  __syncthreads();
-  ddv s = {scratch[0], scratch[1]};
+}
+template <int NT>
+__device__ __forceinline__ void block_dd_sum2(ddv &a, ddv &b, double *scratch) {
+  constexpr int NW = NT / 64;
+  static_assert(NW >= 1 && NW <= 64 && (NW & (NW - 1)) == 0, "power-of-two wave count");
 #pragma unroll
-  for (int q = 1; q < NT / 64; ++q) s = dd_add(s, ddv{scratch[2 * q], scratch[2 * q + 1]});
-  return s;
+  for (int o = 32; o > 0; o >>= 1) {
+    const ddv wa = {__shfl_xor(a.h, o), __shfl_xor(a.l, o)};
+    const ddv wb = {__shfl_xor(b.h, o), __shfl_xor(b.l, o)};
+    a = dd_add(a, wa);
+    b = dd_add(b, wb);
+  }
+  if constexpr (NW > 1) {
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      scratch[4 * w] = a.h;
+      scratch[4 * w + 1] = a.l;
+      scratch[4 * w + 2] = b.h;
+      scratch[4 * w + 3] = b.l;
+    }
+    __syncthreads();
+    a = cross_wave_dd_sum<NW>(scratch, 4);
+    b = cross_wave_dd_sum<NW>(scratch + 2, 4);
+  }
 }
 
 // ---------------------------------------------------------------- column statistics
@@ -1282,7 +1329,7 @@ __device__ __forceinline__ void epi_v_body(
     double *lam, double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
     int kr, int *flags, const CrtRec *__restrict__ recs, const int *__restrict__ vblk,
     const int *__restrict__ gate, int bx) {
-  __shared__ double scratch[2 * (NT / 64)];
+  __shared__ double scratch[4 * (NT / 64)];
   if (gate && *gate == 0) return;
   const int j = bx, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
@@ -1398,8 +1445,7 @@ __device__ __forceinline__ void epi_v_body(
       sv = dd_add_prod(sv, p, pe + x * vl[q]);
     }
   }
-  sx = block_dd_sum<NT>(sx, scratch);
-  sv = block_dd_sum<NT>(sv, scratch);
+  block_dd_sum2<NT>(sx, sv, scratch);
   // r_j = 1 - x^T x,  lambda_j = x^T v / (1 - r_j)
   ddv rj = dd_add(ddv{1.0, 0.0}, ddv{-sx.h, -sx.l});
   ddv den = dd_add(ddv{1.0, 0.0}, ddv{-rj.h, -rj.l});
@@ -2248,7 +2294,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v_c(
     const int *__restrict__ eX, const double *__restrict__ X1, int n, double *lam,
     double *lam_lo, double *r, int *eR, double *resmax, int8_t *__restrict__ Rpl,
     int8_t *__restrict__ Rpl2, int kr, int *flags) {
-  __shared__ double scratch[2 * (kEpiThreads / 64)];
+  __shared__ double scratch[4 * (kEpiThreads / 64)];
   const int j = blockIdx.x, tid = threadIdx.x;
   const size_t P = (size_t)npad * npad;
   double rr[EPT], ri[EPT];
@@ -2311,8 +2357,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_v_c(
       sv = dd_add_prod(sv, p, pe + x.y * vil[q]);
     }
   }
-  sx = block_dd_sum<kEpiThreads>(sx, scratch);
-  sv = block_dd_sum<kEpiThreads>(sv, scratch);
+  block_dd_sum2<kEpiThreads>(sx, sv, scratch);
   ddv rj = dd_add(ddv{1.0, 0.0}, ddv{-sx.h, -sx.l});
   ddv den = dd_add(ddv{1.0, 0.0}, ddv{-rj.h, -rj.l});
   const ddv ljd = dd_div_to_dd(sv, den);
