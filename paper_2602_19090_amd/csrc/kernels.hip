@@ -1230,25 +1230,18 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
   // F = sum_q r_q u_q mod 1 in kCrtLimbs fixed-point limbs of 34 bits: |r_q| <= 127, so
   // r_q L[q][k] is an integer below 2^41 and at most 28 of them sum below 2^45.9: every limb
   // sum is exact. Truncating u_q to 136 bits moves F by at most 28 127 2^-136 = 2^-124.2.
-  // The record's limbs, staged in LDS (every thread reads all of them).
-  __shared__ double sL[kCrtMax * kCrtLimbs];
-  for (int e = threadIdx.x; e < kCrtMax * kCrtLimbs; e += NT)
-    sL[e] = rec.L[e / kCrtLimbs][e % kCrtLimbs];
-  const int N = rec.N;
-  __syncthreads();
-  double a[EPT][kCrtLimbs];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q)
-#pragma unroll
-    for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
   // A slot's EPT bytes per thread are one packed load (loadw); kD slots are in flight, in a
-  // ring of packed words unpacked where they are used; terms in order of the moduli.
+  // ring of packed words unpacked where they are used; terms in order of the moduli. The
+  // ring's first fill does not wait for the record: the residue buffer holds at least
+  // kCrtMax > kD slots, so its first kD slots exist whatever N is (those past N are unused).
   constexpr int kD = EPT >= 8 ? 6 : EPT >= 4 ? 8 : 12;
-  const bool live = i0 < npad;
+  static_assert(kD < kCrtMax, "the first ring fill reads slots below kCrtMax");
+  // threads past the padded order read row 0 (no branch around the loads); all their rows
+  // are >= n, so what they sum is discarded like the padding rows' results
+  const int8_t *Crow = Ccol + (i0 < npad ? i0 : 0);
   auto loadw = [&](int s) -> uint2 {
     uint2 w = {0u, 0u};
-    if (!live) return w;
-    const int8_t *p = Ccol + (size_t)s * P + i0;
+    const int8_t *p = Crow + (size_t)s * P;
     if constexpr (EPT == 8) {
       const u32x2 v2 = *gview((const u32x2 *)p);
       w.x = v2.x;
@@ -1259,18 +1252,39 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
     else w.x = (uint8_t)*gview(p);
     return w;
   };
+  // The record's limbs, staged in LDS (every thread reads all of them); their loads go out
+  // before the ring's, so that storing them waits for them alone.
+  __shared__ double sL[kCrtMax * kCrtLimbs];
+  constexpr int kLper = (kCrtMax * kCrtLimbs + NT - 1) / NT;
+  double lv[kLper];
+#pragma unroll
+  for (int t = 0; t < kLper; ++t) {
+    const int e = threadIdx.x + t * NT;
+    lv[t] = e < kCrtMax * kCrtLimbs ? rec.L[e / kCrtLimbs][e % kCrtLimbs] : 0.0;
+  }
   uint2 ring[kD];
 #pragma unroll
-  for (int u = 0; u < kD; ++u) ring[u] = u < N ? loadw(u) : uint2{0u, 0u};
-#pragma unroll 1
-  for (int q0 = 0; q0 < N; q0 += kD) {
+  for (int u = 0; u < kD; ++u) ring[u] = loadw(u);
 #pragma unroll
-    for (int u = 0; u < kD; ++u) {
-      const int q = q0 + u;
-      if (q >= N) break;
-      const uint2 w = ring[u];
-      // refill this ring place with slot q + kD
-      ring[u] = q + kD < N ? loadw(q + kD) : uint2{0u, 0u};
+  for (int t = 0; t < kLper; ++t) {
+    const int e = threadIdx.x + t * NT;
+    if (e < kCrtMax * kCrtLimbs) sL[e] = lv[t];
+  }
+  const int N = rec.N;
+  __syncthreads();
+  double a[EPT][kCrtLimbs];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q)
+#pragma unroll
+    for (int k = 0; k < kCrtLimbs; ++k) a[q][k] = 0.0;
+  // All kCrtMax places of the sum are unrolled: the loads are unconditional (past the last
+  // slot, slot N - 1 again, which hits the cache), so the memory-counter waits stay exact
+  // with kD loads in flight; the terms themselves are skipped past N.
+#pragma unroll
+  for (int q = 0; q < kCrtMax; ++q) {
+    const uint2 w = ring[q % kD];
+    ring[q % kD] = loadw(min(q + kD, N - 1));
+    if (q < N) {
       double L[kCrtLimbs];
 #pragma unroll
       for (int k = 0; k < kCrtLimbs; ++k) L[k] = sL[q * kCrtLimbs + k];
@@ -1717,28 +1731,17 @@ __device__ __forceinline__ void epi_w_body(
   }
   const int ej = eR[j];
   const double lj = lam[j], ljl = lam_lo[j];
-  const int ndiag = dcut ? min(ndiag_all, dcut[j] - d_min + 1) : ndiag_all;
   const int32_t *Ccol = C + (size_t)j * npad + i0;
   const int T = npad >> 8;
-  double ev[EPT], wq[EPT], lmv[EPT], llv[EPT];
-  int eiq[EPT], ndq[EPT], exv[EPT];
+  // the rows of a thread lie in one 256-row tile, so they share one diagonal count; the
+  // diagonals past it were not computed for that tile and are neither loaded nor summed
+  const int nd = live ? w_ndiag(dcut, tcut, T, ndiag_all, d_min, i0, j) : 0;
+  // W_ij = 2^(eX_i + eR_j) sum_d C_d 2^(-7 d): the sum runs in units of 2^(eX_i + eR_j)
+  // (power-of-two scalings, so the roundings are those of the scaled sum); rows >= n sum
+  // whatever the padding holds (finite integers) and are not used
+  double wq[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    exv[q] = 0;
-    lmv[q] = llv[q] = 0.0;
-  }
-  if (live) {   // values of rows >= n are not used
-    load_i32v<EPT>(eX + i0, exv);
-    load_f64v<EPT>(lam + i0, lmv);
-    load_f64v<EPT>(lam_lo + i0, llv);
-  }
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = i0 + q;
-    wq[q] = 0.0;
-    eiq[q] = (i < n) ? exv[q] + ej : 0;
-    ndq[q] = w_ndiag(dcut, tcut, T, ndiag_all, d_min, i, j);
-  }
+  for (int q = 0; q < EPT; ++q) wq[q] = 0.0;
   // as in the V epilogue: with few entries per thread the diagonals' values are loaded kPD
   // at a time; with many, kD diagonals are in flight in a ring (smallest scale first)
   if constexpr (EPT >= 4) {
@@ -1747,15 +1750,12 @@ __device__ __forceinline__ void epi_w_body(
     auto loadd = [&](int qq, int32_t (&v)[EPT]) {
 #pragma unroll
       for (int q = 0; q < EPT; ++q) v[q] = 0;
-      if (qq >= 0 && live) load_i32v<EPT>(Ccol + (size_t)qq * P, v);
-#pragma unroll
-      for (int q = 0; q < EPT; ++q)
-        if (i0 + q >= n) v[q] = 0;
+      if (qq >= 0) load_i32v<EPT>(Ccol + (size_t)qq * P, v);
     };
 #pragma unroll
-    for (int u = 0; u < kD; ++u) loadd(ndiag - 1 - u, ring[u]);
+    for (int u = 0; u < kD; ++u) loadd(nd - 1 - u, ring[u]);
 #pragma unroll 1
-    for (int c0 = ndiag - 1; c0 >= 0; c0 -= kD) {
+    for (int c0 = nd - 1; c0 >= 0; c0 -= kD) {
 #pragma unroll
       for (int u = 0; u < kD; ++u) {
         const int qq = c0 - u;
@@ -1764,36 +1764,40 @@ __device__ __forceinline__ void epi_w_body(
 #pragma unroll
         for (int q = 0; q < EPT; ++q) cv[q] = ring[u][q];
         loadd(qq - kD, ring[u]);
+        const double sc = ldexp(1.0, -7 * (d_min + qq));
 #pragma unroll
-        for (int q = 0; q < EPT; ++q)
-          if (qq < ndq[q]) wq[q] += ldexp((double)cv[q], eiq[q] - 7 * (d_min + qq));
+        for (int q = 0; q < EPT; ++q) wq[q] = fma((double)cv[q], sc, wq[q]);
       }
     }
   } else {
   constexpr int kPD = 16 / EPT;
 #pragma unroll 1
-  for (int c0 = ndiag - 1; c0 >= 0; c0 -= kPD) {
+  for (int c0 = nd - 1; c0 >= 0; c0 -= kPD) {
     int32_t cv[kPD][EPT];
 #pragma unroll
     for (int u = 0; u < kPD; ++u) {
       const int qq = c0 - u;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) cv[u][q] = 0;
-      if (qq >= 0 && live) load_i32v<EPT>(Ccol + (size_t)qq * P, cv[u]);
-#pragma unroll
-      for (int q = 0; q < EPT; ++q)
-        if (i0 + q >= n) cv[u][q] = 0;
+      if (qq >= 0) load_i32v<EPT>(Ccol + (size_t)qq * P, cv[u]);
     }
 #pragma unroll
     for (int u = 0; u < kPD; ++u) {
       const int qq = c0 - u;
       if (qq < 0) break;
+      const double sc = ldexp(1.0, -7 * (d_min + qq));
 #pragma unroll
-      for (int q = 0; q < EPT; ++q)
-        if (qq < ndq[q]) wq[q] += ldexp((double)cv[u][q], eiq[q] - 7 * (d_min + qq));
+      for (int q = 0; q < EPT; ++q) wq[q] = fma((double)cv[u][q], sc, wq[q]);
     }
   }
   }
+  int exv[EPT];
+  double ev[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) exv[q] = 0;
+  if (live) load_i32v<EPT>(eX + i0, exv);   // values of rows >= n are not used
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) wq[q] = ldexp(wq[q], exv[q] + ej);
   double ms = 0.0, mr = 0.0;
   int tie = 0;
 #pragma unroll
@@ -1807,7 +1811,7 @@ __device__ __forceinline__ void epi_w_body(
       if (i == j) {
         e = 0.5 * r[j];
       } else {
-        const double den = dd_diff(lj, ljl, lmv[q], llv[q]);
+        const double den = dd_diff(lj, ljl, *gview(lam + i), *gview(lam_lo + i));
         if (den == 0.0) {
           tie = 1;
           e = 0.0;
@@ -1840,7 +1844,7 @@ __device__ __forceinline__ void epi_w_body(
 }
 
 template <int EPT, int NT>
-__global__ __launch_bounds__(NT) void k_epi_w(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
     const int *__restrict__ eX, const int *__restrict__ eR, const double *__restrict__ lam,
     const double *__restrict__ lam_lo, const double *__restrict__ r, int n, int *eE,
