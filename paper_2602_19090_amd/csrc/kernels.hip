@@ -1283,7 +1283,7 @@ __device__ __forceinline__ void crt_column(const int8_t *__restrict__ Ccol, size
 #pragma unroll
   for (int q = 0; q < kCrtMax; ++q) {
     const uint2 w = ring[q % kD];
-    ring[q % kD] = loadw(min(q + kD, N - 1));
+    ring[q % kD] = loadw(max(min(q + kD, N - 1), 0));
     if (q < N) {
       double L[kCrtLimbs];
 #pragma unroll
