@@ -1843,6 +1843,8 @@ __device__ __forceinline__ void epi_w_body(
   }
 }
 
+// At most 64 VGPRs (8 waves per SIMD): two 1024-thread blocks share a CU, so one block's
+// loads and barriers overlap the other's arithmetic.
 template <int EPT, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_epi_w(
     const int32_t *__restrict__ C, int npad, int d_min, int ndiag_all, const int *__restrict__ dcut,
