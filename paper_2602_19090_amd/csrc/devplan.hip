@@ -851,7 +851,7 @@ template <int G>
 __device__ __forceinline__ void residues_dev_loop(const int8_t *__restrict__ planes,
                                                   size_t pstride, size_t count, int K, int N,
                                                   const int (*swp)[(kCrtPlanes + 3) / 4],
-                                                  const float *sm, const float *srm,
+                                                  const int *snm, const int *sm22, const float *srm,
                                                   int8_t *__restrict__ res, int bid, int nblk) {
   for (size_t e = ((size_t)bid * 256 + threadIdx.x) * 4; e < count;
        e += (size_t)nblk * 256 * 4) {
@@ -868,20 +868,28 @@ __device__ __forceinline__ void residues_dev_loop(const int8_t *__restrict__ pla
                           (((v[4 * g + 1] >> (8 * bb)) & 0xffu) << 8) |
                           (((v[4 * g + 2] >> (8 * bb)) & 0xffu) << 16) |
                           (((v[4 * g + 3] >> (8 * bb)) & 0xffu) << 24));
-    for (int q = 0; q < N; ++q) {
-      const float m = sm[q], rm = srm[q];
-      unsigned packed = 0u;
+    int8_t *out = res + e;
+    for (int q = 0; q < N; ++q, out += pstride) {
+      const int nm = snm[q], m22 = sm22[q];
+      const float rm = srm[q];
+      int rr[4];
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
         int acc = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) acc = __builtin_amdgcn_sdot4(dg[g][bb], swp[q][g], acc, false);
-        // |acc| < 2^17: a - m rint(a / m) is exact in FP32 (one rounding-free fma)
-        const float a = (float)acc;
-        const int rr = (int)fmaf(-m, rintf(a * rm), a);
-        packed |= ((unsigned)(rr & 0xff)) << (8 * bb);
+        // |acc| <= 18 127^2 < 2^19, so acc rm_q is within 2^-13 of acc / m_q, which is at
+        // least 1 / (2 m_q) > 2^-9 from a half-integer (m_q odd): acc rm_q + 1.5 2^23 rounded
+        // once is the float 1.5 2^23 + q with q = rint(acc / m_q). The low 24 bits of its
+        // pattern are 2^22 + q (bit 23 clear), so acc - m_q q = (acc + m_q 2^22) -
+        // m_q (2^22 + q) is one signed 24-bit multiply-add
+        const int bits = __float_as_int(fmaf((float)acc, rm, 0x1.8p23f));
+        rr[bb] = __mul24(bits, nm) + (acc + m22);
       }
-      *(unsigned *)(res + (size_t)q * pstride + e) = packed;
+      // the low bytes of the four residues, in order
+      const unsigned lo = __builtin_amdgcn_perm((unsigned)rr[1], (unsigned)rr[0], 0x0c0c0400u);
+      const unsigned hi = __builtin_amdgcn_perm((unsigned)rr[3], (unsigned)rr[2], 0x04000c0cu);
+      *(unsigned *)out = lo | hi;
     }
   }
 }
@@ -894,21 +902,23 @@ __device__ __forceinline__ void residues_dev_body(const int8_t *__restrict__ pla
   if (gate && *gate == 0) return;
   constexpr int G = (kCrtPlanes + 3) / 4;
   __shared__ int swp[kCrtMax][G];
-  __shared__ float sm[kCrtMax], srm[kCrtMax];
+  __shared__ int snm[kCrtMax], sm22[kCrtMax];   // -m_q and m_q 2^22
+  __shared__ float srm[kCrtMax];
   const int K = w->k, N = w->N;
   for (int q = threadIdx.x; q < kCrtMax * G; q += 256) swp[q / G][q % G] = w->wp[q / G][q % G];
   for (int q = threadIdx.x; q < kCrtMax; q += 256) {
-    sm[q] = (float)w->m[q];
+    snm[q] = -w->m[q];
+    sm22[q] = w->m[q] << 22;
     srm[q] = w->rmf[q];
   }
   __syncthreads();
   static_assert(G == 5, "digit planes up to 18: groups 1..5");
   switch ((K + 3) / 4) {
-    case 1: residues_dev_loop<1>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
-    case 2: residues_dev_loop<2>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
-    case 3: residues_dev_loop<3>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
-    case 4: residues_dev_loop<4>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
-    default: residues_dev_loop<5>(planes, pstride, count, K, N, swp, sm, srm, res, bid, nblk); break;
+    case 1: residues_dev_loop<1>(planes, pstride, count, K, N, swp, snm, sm22, srm, res, bid, nblk); break;
+    case 2: residues_dev_loop<2>(planes, pstride, count, K, N, swp, snm, sm22, srm, res, bid, nblk); break;
+    case 3: residues_dev_loop<3>(planes, pstride, count, K, N, swp, snm, sm22, srm, res, bid, nblk); break;
+    case 4: residues_dev_loop<4>(planes, pstride, count, K, N, swp, snm, sm22, srm, res, bid, nblk); break;
+    default: residues_dev_loop<5>(planes, pstride, count, K, N, swp, snm, sm22, srm, res, bid, nblk); break;
   }
 }
 
