@@ -582,7 +582,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the refinement of one matrix is not sharded "
-              "across GPUs in this build (--gpus 1).", file=sys.stderr)
+              "across GPUs (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
