@@ -1754,18 +1754,18 @@ void enqueue_chunk(const ChunkPlan &cp, const GroupArea &ga, const refeig_opts &
       launch_gemm_g(gp, 128, cp.blocks128, items128, ga.cnt + 2, ga.cnt + 3, which, s);
     }
   };
+  // The planning kernels take one block per problem whatever its order, so each runs as one
+  // launch over the whole batch; the other steps are one launch per size class.
   if (it0 == 0) {   // once per solve: A's column statistics, the planning state, A's planes
     launch_flags_clear_g(gp, G, s);
-    for (const auto &c : cp.cls) {
-      launch_colstats_g(gp, c.first, c.count, c.npad, false, s);
-      launch_dp_init_g(gp, c.first, c.count, s);
-      launch_split_g(gp, c.first, c.count, c.npad, false, s);
-    }
+    for (const auto &c : cp.cls) launch_colstats_g(gp, c.first, c.count, c.npad, false, s);
+    launch_dp_init_g(gp, 0, G, s);
+    for (const auto &c : cp.cls) launch_split_g(gp, c.first, c.count, c.npad, false, s);
   }
   for (int it = it0; it < it1; ++it) {
-    for (const auto &c : cp.cls) launch_dp_order_g(gp, c.first, c.count, it, s);
+    launch_dp_order_g(gp, 0, G, it, s);
     for (const auto &c : cp.cls) launch_colstats_g(gp, c.first, c.count, c.npad, true, s);
-    for (const auto &c : cp.cls) launch_dp_vplan_g(gp, c.first, c.count, it, s);
+    launch_dp_vplan_g(gp, 0, G, it, s);
     for (const auto &c : cp.cls) launch_split_g(gp, c.first, c.count, c.npad, true, s);
     if (o.vmode == 1) {
       for (const auto &c : cp.cls)
@@ -1776,12 +1776,12 @@ void enqueue_chunk(const ChunkPlan &cp, const GroupArea &ga, const refeig_opts &
     }
     products(1);
     for (const auto &c : cp.cls) launch_epi_v_g(gp, c.first, c.count, c.npad, false, s);
-    for (const auto &c : cp.cls) launch_dp_wplan_g(gp, c.first, c.count, it, s);
+    launch_dp_wplan_g(gp, 0, G, it, s);
     for (const auto &c : cp.cls)
       if (c.npad >= 1024) launch_tile_cutoffs_g(gp, c.first, c.count, c.npad, s);
     products(2);
     for (const auto &c : cp.cls) launch_epi_w_g(gp, c.first, c.count, c.npad, s);
-    for (const auto &c : cp.cls) launch_dp_uplan_g(gp, c.first, c.count, it, s);
+    launch_dp_uplan_g(gp, 0, G, it, s);
     products(3);
     for (const auto &c : cp.cls) launch_epi_u_g(gp, c.first, c.count, c.npad, s);
     for (const auto &c : cp.cls) launch_scatter_g(gp, c.first, c.count, c.npad, s);
